@@ -1,0 +1,272 @@
+"""Plain FP64 direct-DFT model of the PSF path and its analytic gradient.
+
+TEST INFRASTRUCTURE ONLY: imported by tests/, the smoke check and the
+benchmark's CPU baseline; never by the product path.
+
+What it computes follows the paper (Desdoigts et al., "Differentiable optics
+with dLux I", arXiv 2406.08703):
+
+* Section 3, aperture listing: a basis optic whose optical path difference
+  is a linear combination of Zernike terms over a grey transmission, with
+  the field normalised to unit power;
+* Section 3, propagation paragraph: Fraunhofer propagation to the focal
+  plane by a two-sided matrix Fourier transform, one product per side;
+  summed incoherently over wavelengths and stars; pixel response applied
+  by multiplication;
+* Section 4: a per-pixel Poisson log-likelihood plus a chi-squared prior on
+  the pixel response, differentiated with respect to star positions,
+  fluxes, Zernike coefficients and every pixel-response value.
+
+The MFT is a direct DFT evaluated at arbitrary output coordinates, so the
+oracle is that definition written out with explicit DFT matrices (no FFT),
+one PSF at a time, in FP64. Readings where the paper is silent
+(normalisation, centring, sign of the kernel, binning, intra-pixel kernel,
+prior form, chi-squared data term, bicubic map) are listed in the design doc.
+
+Pins (tests/test_oracle_pins.py): brute-force DFT, FFT equivalence,
+Parseval, Airy and annular-Airy closed forms, shift theorem, piston and
+even-mode invariances, adjoint dot product, Euler identity for the flux
+gradient, library log-pmf/log-pdf for the loss, matrix-form binning, and
+central finite differences of every gradient block.
+Parity unpinned beyond finite differences: the bicubic map term and the
+chi-squared data term (definitions, not results).
+"""
+from __future__ import annotations
+
+from dataclasses import dataclass
+
+import numpy as np
+
+TWO_PI = 2.0 * np.pi
+
+
+@dataclass
+class OracleProblem:
+    """Static inputs of one problem, promoted to FP64."""
+    n_pupil: int
+    n_focal: int
+    oversample: int
+    diameter: float
+    focal_pixel: float
+    wavelengths: np.ndarray
+    weights: np.ndarray
+    transmission: np.ndarray          # [Ni, Ni]
+    zbasis: np.ndarray                # [Nz, Ni, Ni]
+    map_basis: np.ndarray | None = None   # [Ni, n_map]
+    intrapixel: np.ndarray | None = None  # [Q, Q]
+
+    @staticmethod
+    def from_arrays(n_pupil, n_focal, oversample, diameter, focal_pixel, wavelengths, weights,
+                    transmission, zbasis, map_basis=None, intrapixel=None) -> "OracleProblem":
+        f64 = lambda a: None if a is None else np.asarray(a, dtype=np.float64)
+        return OracleProblem(int(n_pupil), int(n_focal), int(oversample), float(diameter), float(focal_pixel),
+                             f64(wavelengths), f64(weights), f64(transmission), f64(zbasis),
+                             f64(map_basis), f64(intrapixel))
+
+    @property
+    def n_det(self) -> int:
+        return self.n_focal // self.oversample
+
+    @property
+    def dx(self) -> float:
+        return self.diameter / self.n_pupil
+
+
+def pixel_grid(n: int, pitch: float) -> np.ndarray:
+    """Pixel-centred sample coordinates ``(i - (n-1)/2) * pitch``."""
+    return (np.arange(n) - (n - 1) / 2.0) * pitch
+
+
+def dft_matrix(x: np.ndarray, u: np.ndarray, lam: float) -> np.ndarray:
+    """M[l, n] = exp(-2 pi i x_n u_l / lambda): one side of the two-sided MFT (Section 3)."""
+    return np.exp(-1j * TWO_PI * np.outer(u, x) / lam)
+
+
+def focal_field(P, x, y, u, v, lam, scale):
+    """E[k, l] = scale * sum_{m,n} P[m, n] exp(-2 pi i (y_m v_k + x_n u_l) / lambda).
+
+    The two matrix products of Section 3's propagation paragraph:
+    ``E = scale * My @ P @ Mx.T``. ``scale`` is dx*du/lambda for the model.
+    """
+    return scale * (dft_matrix(y, v, lam) @ P @ dft_matrix(x, u, lam).T)
+
+
+def focal_field_adjoint(Y, x, y, u, v, lam, scale):
+    """Adjoint of ``focal_field`` in P: ``scale * My^H @ Y @ conj(Mx)``."""
+    return scale * (dft_matrix(y, v, lam).conj().T @ Y @ dft_matrix(x, u, lam).conj())
+
+
+def opd_map(zbasis, coeffs, map_basis=None, phase_map=None):
+    """OPD = sum_j c_j Z_j (Section 3, basis optic), plus the bicubic map B C B^T if given."""
+    o = np.tensordot(np.asarray(coeffs, np.float64), zbasis, axes=1)
+    if map_basis is not None and phase_map is not None:
+        o = o + map_basis @ np.asarray(phase_map, np.float64) @ map_basis.T
+    return o
+
+
+def pupil_field(transmission, opd, x, y, alpha, beta, lam):
+    """Unit-power pupil field A/sqrt(sum A^2) * exp(i 2 pi/lambda (OPD + x alpha + y beta)).
+
+    The source at angular offset (alpha, beta) tilts the incoming wavefront.
+    """
+    amp = transmission / np.sqrt(np.sum(transmission ** 2))
+    phase = (TWO_PI / lam) * (opd + x[None, :] * alpha + y[:, None] * beta)
+    return amp * np.exp(1j * phase)
+
+
+def bin_detector(I, Q, K=None):
+    """B[p, q] = sum_{a,b<Q} K[a, b] I[Qp+a, Qq+b] (K = 1 if None)."""
+    n = I.shape[-1] // Q
+    if K is not None:
+        I = I * np.tile(K, (n, n))
+    return I.reshape(n, Q, n, Q).sum(axis=(1, 3))
+
+
+def expand_detector(G, Q, K=None):
+    """Adjoint of ``bin_detector``: G[k, l] = K[k%Q, l%Q] * g[k//Q, l//Q]."""
+    out = np.kron(G, np.ones((Q, Q)))
+    if K is not None:
+        out = out * np.tile(K, G.shape)
+    return out
+
+
+def _grids(prob: OracleProblem):
+    x = pixel_grid(prob.n_pupil, prob.dx)
+    u = pixel_grid(prob.n_focal, prob.focal_pixel)
+    return x, u
+
+
+def _psf_field(prob, opd, x, u, alpha, beta, lam):
+    P = pupil_field(prob.transmission, opd, x, x, alpha, beta, lam)
+    c = prob.dx * prob.focal_pixel / lam
+    return P, focal_field(P, x, x, u, u, lam, c), c
+
+
+def forward(prob: OracleProblem, coeffs, phase_map, sources, flat):
+    """Binned image B [F, Nd, Nd] and model m = flat * B (Section 3).
+
+    ``sources`` is [F, S, 3]: per frame and star the angular position
+    (alpha, beta) in radians -- dither included -- and the photon count.
+    I_f = sum_s sum_lambda w_lambda * phi_s * |E|^2, then Q x Q binning with
+    the intra-pixel kernel, then the pixel response.
+    """
+    sources = np.asarray(sources, np.float64)
+    flat = np.asarray(flat, np.float64)
+    x, u = _grids(prob)
+    opd = opd_map(prob.zbasis, coeffs, prob.map_basis, phase_map)
+    F, S = sources.shape[:2]
+    No = prob.n_focal
+    binned = np.zeros((F, prob.n_det, prob.n_det))
+    for f in range(F):
+        I = np.zeros((No, No))
+        for s in range(S):
+            a, b, phi = sources[f, s]
+            for lam, w in zip(prob.wavelengths, prob.weights):
+                _, E, _ = _psf_field(prob, opd, x, u, a, b, lam)
+                I += w * phi * np.abs(E) ** 2
+        binned[f] = bin_detector(I, prob.oversample, prob.intrapixel)
+    return binned, flat[None] * binned
+
+
+def loss_grad(model, binned, data, flat, kind="poisson", prior_mu=1.0, prior_sigma=0.1):
+    """Loss, residual r = dL/dm and flat-field gradient (Section 4).
+
+    Poisson: l = m - d ln m (the ln d! constant dropped).
+    chi2:    l = (m - d)^2 / (2 max(d, 1)).
+    Prior:   sum_p (F_p - mu)^2 / (2 sigma^2).
+    dL/dF_p = sum_f r_fp B_fp + (F_p - mu) / sigma^2.
+    Returns (L, r, dL/dF, domain_flag); m <= 0 is clamped to 1e-30 and flagged.
+    """
+    m = np.asarray(model, np.float64)
+    d = np.asarray(data, np.float64)
+    Fl = np.asarray(flat, np.float64)
+    bad = bool(np.any(m <= 0.0))
+    m = np.maximum(m, 1e-30)
+    if kind == "poisson":
+        ell = m - d * np.log(m)
+        r = 1.0 - d / m
+    elif kind == "chi2":
+        wgt = np.maximum(d, 1.0)
+        ell = 0.5 * (m - d) ** 2 / wgt
+        r = (m - d) / wgt
+    else:
+        raise ValueError(kind)
+    L = float(np.sum(ell) + np.sum((Fl - prior_mu) ** 2) / (2.0 * prior_sigma ** 2))
+    gF = np.sum(r * np.asarray(binned, np.float64), axis=0) + (Fl - prior_mu) / prior_sigma ** 2
+    return L, r, gF, bad
+
+
+def backward(prob: OracleProblem, coeffs, phase_map, sources, flat, r):
+    """Gradients of L through the optics given r = dL/dm [F, Nd, Nd].
+
+    Per (frame, star, wavelength), recomputing E:
+      G = K * expand(F * r)        (dL/dI)
+      Y = w phi G E                (dL/dE*)
+      W = adjoint MFT of Y
+      g = 2 Im(conj(P) W)          (dL/dphase)
+    and dL/dc_j = sum (2 pi/lambda) Z_j g; dL/dalpha = sum (2 pi/lambda) x g;
+    dL/dbeta likewise with y; dL/dphi = sum_lambda w sum G |E|^2.
+    Returns (grad_coeffs [Nz], grad_map [n_map, n_map] or None, grad_sources [F, S, 3]).
+    """
+    sources = np.asarray(sources, np.float64)
+    flat = np.asarray(flat, np.float64)
+    r = np.asarray(r, np.float64)
+    x, u = _grids(prob)
+    opd = opd_map(prob.zbasis, coeffs, prob.map_basis, phase_map)
+    F, S = sources.shape[:2]
+    g_opd = np.zeros((prob.n_pupil, prob.n_pupil))
+    g_src = np.zeros((F, S, 3))
+    for f in range(F):
+        G = expand_detector(flat * r[f], prob.oversample, prob.intrapixel)
+        for s in range(S):
+            a, b, phi = sources[f, s]
+            for lam, w in zip(prob.wavelengths, prob.weights):
+                P, E, c = _psf_field(prob, opd, x, u, a, b, lam)
+                Y = w * phi * G * E
+                W = focal_field_adjoint(Y, x, x, u, u, lam, c)
+                g = 2.0 * np.imag(np.conj(P) * W) * (TWO_PI / lam)
+                g_opd += g
+                g_src[f, s, 0] += np.sum(g * x[None, :])
+                g_src[f, s, 1] += np.sum(g * x[:, None])
+                g_src[f, s, 2] += w * np.sum(G * np.abs(E) ** 2)
+    g_c = np.tensordot(prob.zbasis, g_opd, axes=([1, 2], [0, 1]))
+    g_map = None
+    if prob.map_basis is not None and phase_map is not None:
+        g_map = prob.map_basis.T @ g_opd @ prob.map_basis
+    return g_c, g_map, g_src
+
+
+def value_and_grad(prob, coeffs, phase_map, sources, flat, data, kind="poisson", prior_mu=1.0, prior_sigma=0.1):
+    """Forward, loss and all gradients in one call (a convenience for tests and the baseline)."""
+    B, m = forward(prob, coeffs, phase_map, sources, flat)
+    L, r, gF, bad = loss_grad(m, B, data, flat, kind, prior_mu, prior_sigma)
+    g_c, g_map, g_src = backward(prob, coeffs, phase_map, sources, flat, r)
+    return dict(binned=B, model=m, loss=L, r=r, grad_flat=gF, grad_coeffs=g_c, grad_map=g_map,
+                grad_sources=g_src, domain=bad)
+
+
+def binned_pixels(prob: OracleProblem, coeffs, phase_map, sources, frame, pixels):
+    """B_f at selected detector pixels [(p, q), ...], evaluating E only on their Q x Q samples.
+
+    The same definition as ``forward`` with the DFT taken at the needed
+    output coordinates only, for spot checks at sizes where the full oracle
+    is too slow.
+    """
+    sources = np.asarray(sources, np.float64)
+    x, u = _grids(prob)
+    opd = opd_map(prob.zbasis, coeffs, prob.map_basis, phase_map)
+    Q = prob.oversample
+    K = prob.intrapixel if prob.intrapixel is not None else np.ones((Q, Q))
+    out = np.zeros(len(pixels))
+    for i, (p, q) in enumerate(pixels):
+        rows = u[Q * p:Q * p + Q]
+        cols = u[Q * q:Q * q + Q]
+        acc = 0.0
+        for s in range(sources.shape[1]):
+            a, b, phi = sources[frame, s]
+            for lam, w in zip(prob.wavelengths, prob.weights):
+                P = pupil_field(prob.transmission, opd, x, x, a, b, lam)
+                E = focal_field(P, x, x, cols, rows, lam, prob.dx * prob.focal_pixel / lam)
+                acc += w * phi * np.sum(K * np.abs(E) ** 2)
+        out[i] = acc
+    return out

@@ -1,0 +1,11 @@
+"""Seeded synthetic inputs for the differentiable PSF path.
+
+This package builds the *inputs* of the forward model and nothing else:
+pupil grids, aperture transmission, the Zernike basis, the bicubic
+map-to-pupil interpolation matrix, random parameter draws, dithers and the
+workload shapes. It contains none of the propagation, binning, flat-field,
+loss or gradient arithmetic; those live, independently, in the HIP library
+and in the FP64 oracle. Both sides read their inputs from here.
+"""
+from .geometry import pixel_centres, aperture, noll_to_nm, zernike_basis, keys_bicubic_matrix  # noqa: F401
+from .configs import Problem, Workload, make_problem, make_workload, CONFIG_NAMES, DEFAULT_DIAMETER  # noqa: F401
