@@ -1,0 +1,208 @@
+"""Forward + gradient throughput of the differentiable PSF path on one MI355X.
+
+One step = dlx_psf_forward -> dlx_loss_grad -> dlx_psf_backward over the whole
+workload (every wavelength, star and frame), inputs resident in HBM. Prints
+one JSON line: PSF evals/s, MFT TFLOP/s, the roofline of the dominant MFT
+stage (timed with HIP events on its stream), the relative error against the
+FP64 oracle on the same inputs, and the oracle's own throughput on the host.
+
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--config c2]
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+FP32_MFMA_PEAK_TFLOPS = 157.3
+HBM_PEAK_GBS = 8000.0
+METRIC = "fwd+grad PSF evals/s & MFT TFLOP/s (% MFMA peak) at rel err ≤1e-5 vs FP64"
+
+WORKLOADS = {
+    "c1": "64x64 pupil -> 64x64 focal (Q=2, 32x32 det), 1 wavelength, 1 star, 1 frame, 10 Zernikes",
+    "c2": "256x256 obstructed pupil -> 512x512 focal (Q=4, 128x128 det), 20 wavelengths 500-700 nm, "
+          "1 star, 1 frame, 64 Zernikes, 16384 flat-field pixels",
+    "c3": "512x512 pupil -> 768x768 focal (Q=3, 256x256 det), 32 wavelengths, binary star, 64 dithered "
+          "frames, 128 Zernikes, intra-pixel kernel",
+    "c5": "1024x1024 pupil -> 2048x2048 focal (Q=2, 1024x1024 det), 16 wavelengths, 1 star, 16 dithered "
+          "frames, 256 Zernikes + 64x64 bicubic map",
+}
+
+
+def stage_flops(P, stage):
+    ni, no = P.n_pupil, P.n_focal
+    return {"F1": 8.0 * no * ni * ni, "F2": 8.0 * no * no * ni, "B2": 8.0 * no * no * ni,
+            "B3": 8.0 * ni * no * no, "B4": 8.0 * ni * ni * no}.get(stage)
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--config", default="c2", choices=sorted(WORKLOADS))
+    ap.add_argument("--precision", default="fp32", choices=["fp32"])
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-parity", action="store_true")
+    ap.add_argument("--cpu-seconds", type=float, default=12.0, help="target host time of the oracle sample")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU; --gpus {args.gpus} is not supported (the path shards by frame "
+              "with one all-reduce of the flat-field gradient, which this build does not run).", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    from synth import make_workload, standin_image
+    from paper_2406_08703_amd import Geometry, PsfPlan
+    from paper_2406_08703_amd import dlx as C
+
+    log = lambda *a: print(*a, file=sys.stderr, flush=True)
+    w = make_workload(args.config)
+    P = w.problem
+    small = args.config in ("c1", "c2")
+    oracle_prob = None
+    if small:
+        import oracle as O
+        oracle_prob = O.OracleProblem.from_arrays(P.n_pupil, P.n_focal, P.oversample, P.diameter, P.focal_pixel,
+                                                  P.wavelengths, P.weights, w.transmission, w.zbasis, w.map_basis,
+                                                  w.intrapixel)
+        _, m_true = O.forward(oracle_prob, w.coeffs_true, w.map_true, w.sources_true, w.flat_true)
+        w = w.with_data(m_true)
+        data_kind = "Poisson draw of the FP64 oracle model at the truth"
+    else:
+        w = w.with_data(standin_image(w))
+        data_kind = "Poisson draw of a smooth stand-in image"
+    log(f"workload {args.config}: {WORKLOADS[args.config]}; data: {data_kind}")
+
+    dev = lambda a: None if a is None else torch.from_numpy(np.ascontiguousarray(a, np.float32)).cuda()
+    geom = Geometry(P.n_pupil, P.n_focal, P.oversample, tuple(P.wavelengths), tuple(P.weights), P.n_sources,
+                    P.n_frames, P.n_zernike, P.n_map, P.diameter, P.focal_pixel)
+    plan = PsfPlan(geom, dev(w.transmission), dev(w.zbasis), dev(w.map_basis), dev(w.intrapixel),
+                   precision=args.precision)
+    ep = w.eval_params()
+    c, pm, s, fl, d = dev(ep["coeffs"]), dev(ep["phase_map"]), dev(ep["sources"]), dev(ep["flat"]), dev(w.data)
+    shp = (P.n_frames, P.n_det, P.n_det)
+    B = torch.empty(shp, device="cuda")
+    m = torch.empty(shp, device="cuda")
+    loss = torch.empty(1, dtype=torch.float64, device="cuda")
+    r = torch.empty(shp, device="cuda")
+    gF = torch.empty((P.n_det, P.n_det), dtype=torch.float64, device="cuda")
+    gz = torch.empty(max(P.n_zernike, 1), dtype=torch.float64, device="cuda")
+    gm = torch.empty((P.n_map, P.n_map), dtype=torch.float64, device="cuda") if P.n_map else None
+    gs = torch.empty((P.n_frames, P.n_sources, 3), dtype=torch.float64, device="cuda")
+
+    def step():
+        plan.forward(c, pm, s, fl, binned=B, model=m)
+        plan.loss_grad(m, B, d, fl, "poisson", w.prior_mu, w.prior_sigma, out=(loss, r, gF))
+        plan.backward(c, pm, s, fl, r, out=(gz, gm, gs))
+
+    for i in range(args.warmup):
+        step()
+        log(f"warmup step {i + 1}/{args.warmup} done")
+    torch.cuda.synchronize()
+    assert plan.sync() == 0
+    C.dlx_plan_profile(plan.plan, True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for i in range(args.steps):
+        step()
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    stages = C.dlx_plan_stage_times(plan.plan)
+    C.dlx_plan_profile(plan.plan, False)
+    log(f"timed {args.steps} steps in {t1 - t0:.4f} s")
+    ms_step = (t1 - t0) * 1e3 / args.steps
+    n_psf = P.n_psf
+    evals = n_psf * args.steps / (t1 - t0)
+    F_mft = P.mft_flops()
+    tf_alg = 2 * F_mft * n_psf / (ms_step * 1e-3) / 1e12
+    tf_exec = 3 * F_mft * n_psf / (ms_step * 1e-3) / 1e12
+
+    table = {}
+    for name, (tot, la, ps) in stages.items():
+        if la:
+            table[name] = dict(ms_per_step=tot / args.steps, launches=la, psfs=ps, avg_launch_ms=tot / la)
+    for k, v in table.items():
+        log(f"  {k:5s} {v['ms_per_step']:9.4f} ms/step  {v['launches']:5d} launches  avg {v['avg_launch_ms']:.4f} ms")
+    gemm = {k: v for k, v in table.items() if stage_flops(P, k)}
+    dom = max(gemm, key=lambda k: gemm[k]["ms_per_step"])
+    dv = gemm[dom]
+    flops_per_launch = stage_flops(P, dom) * dv["psfs"] / dv["launches"]
+    achieved = flops_per_launch / (dv["avg_launch_ms"] * 1e-3) / 1e12
+    roofline = {"bound": "mfma", "kernel": f"cgemm_kernel<{dom}>", "achieved": round(achieved, 3),
+                "peak": FP32_MFMA_PEAK_TFLOPS, "unit": "TFLOP/s", "frac": round(achieved / FP32_MFMA_PEAK_TFLOPS, 4),
+                "traffic": None, "flops_per_launch": flops_per_launch, "avg_launch_ms": round(dv["avg_launch_ms"], 5)}
+    gemm_ms = sum(v["ms_per_step"] for v in gemm.values())
+    all_ms = sum(v["ms_per_step"] for v in table.values())
+
+    parity = None
+    if small and not args.no_parity:
+        import oracle as O
+        ref = O.value_and_grad(oracle_prob, ep["coeffs"], ep["phase_map"], ep["sources"], ep["flat"], w.data,
+                               "poisson", w.prior_mu, w.prior_sigma)
+        rel = lambda a, b: float(np.linalg.norm(np.ravel(a) - np.ravel(b)) / max(np.linalg.norm(np.ravel(b)), 1e-300))
+        parity = {"model": rel(m.cpu().numpy(), ref["model"]),
+                  "loss": abs(float(loss.cpu()[0]) - ref["loss"]) / abs(ref["loss"]),
+                  "grad_flat": rel(gF.cpu().numpy(), ref["grad_flat"]),
+                  "grad_zernike": rel(gz.cpu().numpy()[:P.n_zernike], ref["grad_coeffs"]),
+                  "grad_position": rel(gs.cpu().numpy()[..., :2], ref["grad_sources"][..., :2]),
+                  "grad_flux": rel(gs.cpu().numpy()[..., 2], ref["grad_sources"][..., 2])}
+        parity = {k: float(f"{v:.3e}") for k, v in parity.items()}
+        log(f"parity vs FP64 oracle: {parity}")
+
+    cpu = None
+    if not args.no_cpu_baseline:
+        import oracle as O
+        from threadpoolctl import threadpool_info
+        if oracle_prob is None:
+            oracle_prob = O.OracleProblem.from_arrays(P.n_pupil, P.n_focal, P.oversample, P.diameter, P.focal_pixel,
+                                                      P.wavelengths, P.weights, w.transmission, w.zbasis, w.map_basis,
+                                                      w.intrapixel)
+        # sample: frame 0 and the first wavelengths, grown until the run lasts ~cpu-seconds
+        nl = 1
+        src0 = ep["sources"][:1]
+        sample_desc = None
+        while True:
+            sub = O.OracleProblem(**{**oracle_prob.__dict__, "wavelengths": oracle_prob.wavelengths[:nl],
+                                     "weights": oracle_prob.weights[:nl]})
+            t = time.perf_counter()
+            O.value_and_grad(sub, ep["coeffs"], ep["phase_map"], src0, ep["flat"], w.data[:1], "poisson",
+                             w.prior_mu, w.prior_sigma)
+            dt = time.perf_counter() - t
+            sample_desc = f"frame 0, {P.n_sources} star(s), first {nl} of {P.n_wavelengths} wavelengths"
+            npsf_s = P.n_sources * nl
+            if dt >= args.cpu_seconds or nl >= P.n_wavelengths:
+                break
+            nl = min(P.n_wavelengths, max(nl + 1, int(nl * args.cpu_seconds / max(dt, 1e-3) * 0.9)))
+        threads = max([i.get("num_threads", 1) for i in threadpool_info()] + [1])
+        cpu = {"value": round(npsf_s / dt, 4), "unit": "PSF evals/s", "cores": threads, "kind": "oracle",
+               "sample": f"FP64 NumPy oracle forward+loss+gradient on {sample_desc} "
+                         f"({npsf_s} PSFs, {dt:.2f} s)", "host_cpus": os.cpu_count()}
+        log(f"cpu baseline: {cpu}")
+
+    out = {"metric": METRIC, "value": round(evals, 3), "unit": "PSF evals/s", "n_gpus": 1, "steps": args.steps,
+           "warmup": args.warmup, "ms_per_step": round(ms_step, 4), "higher_is_better": True, "scaling": "weak",
+           "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+           "config": {"workload": f"{args.config}: {WORKLOADS[args.config]}", "psf_per_step": n_psf,
+                      "n_pupil": P.n_pupil, "n_focal": P.n_focal, "oversample": P.oversample,
+                      "wavelengths": P.n_wavelengths, "sources": P.n_sources, "frames": P.n_frames,
+                      "zernikes": P.n_zernike, "flat_pixels": P.n_det ** 2, "precision": args.precision},
+           "mft_tflops": {"algorithmic": round(tf_alg, 3), "executed": round(tf_exec, 3),
+                          "frac_fp32_mfma_peak_algorithmic": round(tf_alg / FP32_MFMA_PEAK_TFLOPS, 4),
+                          "frac_fp32_mfma_peak_executed": round(tf_exec / FP32_MFMA_PEAK_TFLOPS, 4)},
+           "stage_ms_per_step": {k: round(v["ms_per_step"], 5) for k, v in table.items()},
+           "gemm_share_of_step": round(gemm_ms / all_ms, 4) if all_ms else None,
+           "roofline": roofline, "rel_err_vs_fp64": parity, "cpu_baseline": cpu}
+    plan.close()
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

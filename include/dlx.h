@@ -1,0 +1,184 @@
+/*
+ * dlx.h -- C ABI of the MI355X differentiable PSF library (libdlx.so).
+ *
+ * The library evaluates the forward model of Desdoigts et al., "Differentiable
+ * optics with dLux I" (arXiv 2406.08703), and its gradient:
+ *
+ *   Section 3 (aperture listing): pupil OPD = sum_j c_j Z_j (+ an optional
+ *     bicubic pixel-phase map B C B^T), on a grey transmission normalised to
+ *     unit power;
+ *   Section 3 (propagation paragraph): Fraunhofer propagation to an
+ *     oversampled focal grid by a two-sided matrix Fourier transform, |E|^2
+ *     summed over wavelengths and stars, binned to detector pixels, times the
+ *     per-pixel response (flat field);
+ *   Section 4: per-pixel Poisson log-likelihood plus a chi-squared prior on
+ *     the pixel response, differentiated with respect to star positions,
+ *     fluxes, Zernike coefficients and every pixel-response value.
+ *
+ * Conventions used throughout:
+ *   - Every array argument is a DEVICE pointer owned by the caller, contiguous
+ *     and row-major, unless marked "host".
+ *   - Pupil arrays are [n_pupil][n_pupil] indexed [y][x]; detector arrays are
+ *     [n_det][n_det] with n_det = n_focal / oversample; frames are outermost.
+ *   - Grids are pixel-centred: sample i of an n-point grid of pitch p sits at
+ *     (i - (n-1)/2) p. The pupil pitch is diameter / n_pupil; the focal pitch
+ *     is focal_pixel_rad; a detector pixel is oversample focal pixels.
+ *   - The MFT kernel is exp(-2 pi i x u / lambda); a star at angular offset
+ *     (alpha, beta) tilts the pupil by exp(+2 pi i (x alpha + y beta)/lambda),
+ *     placing its image at +alpha, +beta. The focal field carries the factor
+ *     dx du / lambda, so that a full-period focal grid holds unit power.
+ *   - Calls are asynchronous on the HIP stream passed in (NULL = default
+ *     stream). A plan must not be used from two streams at once.
+ *   - Argument and shape errors are returned synchronously before any launch.
+ *     Conditions detected on the device (non-finite values; model <= 0 where
+ *     the data are positive, which is clamped) set a status word in the plan,
+ *     returned by dlx_plan_sync. The library never aborts the process.
+ *   - forward, loss_grad and backward allocate nothing; the plan owns all
+ *     workspaces, allocated once by dlx_plan_create.
+ */
+#ifndef DLX_H
+#define DLX_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  DLX_OK = 0,
+  DLX_ERR_INVALID_ARG = 1, /* null pointer, non-positive size, bad enum value */
+  DLX_ERR_SHAPE = 2,       /* inconsistent sizes (n_focal % oversample != 0, ...) */
+  DLX_ERR_OOM = 3,         /* workspace does not fit the device or the given limit */
+  DLX_ERR_HIP = 4,         /* a HIP runtime call failed (no device, launch failure) */
+  DLX_ERR_NONFINITE = 5,   /* device saw a NaN or Inf in the model or data */
+  DLX_ERR_DOMAIN = 6,      /* model <= 0 where the Poisson loss needs m > 0 (clamped to 1e-30) */
+  DLX_ERR_UNSUPPORTED = 7  /* valid request this build does not implement */
+} dlx_status;
+
+/* Arithmetic of the matrix Fourier transforms. DLX_FP32: FP32 MFMA with FP32
+ * accumulation. DLX_BF16X3: each FP32 operand split as hi = bf16(x),
+ * lo = bf16(x - hi); products hi*hi + hi*lo + lo*hi on BF16 MFMA, FP32
+ * accumulation. DFT-matrix phases and tilt phases are always generated in
+ * FP64; the loss and the flat-field gradient are always reduced in FP64. */
+typedef enum { DLX_FP32 = 0, DLX_BF16X3 = 1 } dlx_precision;
+
+/* Data term of the loss (Section 4). POISSON: m - d ln m (ln d! dropped).
+ * CHI2: (m - d)^2 / (2 max(d, 1)). Both add the prior
+ * sum_p (F_p - mu)^2 / (2 sigma^2) on the pixel response F. */
+typedef enum { DLX_LOSS_POISSON = 0, DLX_LOSS_CHI2 = 1 } dlx_loss_kind;
+
+/* One forward+gradient problem (the sizes of Section 3's optical system). */
+typedef struct {
+  int32_t n_pupil;       /* N_i: pupil samples per side, >= 2 */
+  int32_t n_focal;       /* N_o: focal samples per side, multiple of oversample */
+  int32_t oversample;    /* Q: focal samples per detector pixel per side, >= 1 */
+  int32_t n_wavelengths; /* >= 1 */
+  int32_t n_sources;     /* stars per frame, >= 1 */
+  int32_t n_frames;      /* images (dithers), >= 1 */
+  int32_t n_zernike;     /* basis terms, >= 0 */
+  int32_t n_map;         /* bicubic map nodes per side, 0 = no map */
+  double diameter_m;     /* D: pupil side length in metres, > 0 */
+  double focal_pixel_rad;/* focal-grid pitch in radians, > 0 */
+  const double* wavelengths_m;    /* host [n_wavelengths], each > 0 */
+  const double* spectral_weights; /* host [n_wavelengths] */
+} dlx_problem_desc;
+
+typedef struct dlx_plan dlx_plan;
+
+/* Check a problem description without touching the device.
+ * Returns DLX_OK, DLX_ERR_INVALID_ARG or DLX_ERR_SHAPE. */
+dlx_status dlx_validate(const dlx_problem_desc* probs, int32_t n_probs);
+
+/* Create a plan: validates, picks kernel tiles, allocates every workspace on
+ * the current device and builds the DFT matrices of each wavelength (FP64
+ * phase, FP32 storage). n_probs must be 1 in this build (others:
+ * DLX_ERR_UNSUPPORTED). flags: 0. workspace_limit_bytes: 0 = no limit;
+ * otherwise the frame-chunk size is reduced until the workspace fits, and
+ * DLX_ERR_OOM is returned if even one frame does not.
+ * On success *out owns the device memory until dlx_plan_destroy. */
+dlx_status dlx_plan_create(const dlx_problem_desc* probs, int32_t n_probs, dlx_precision precision,
+                           int32_t flags, size_t workspace_limit_bytes, dlx_plan** out);
+
+/* Free the plan and its device memory (synchronises the device first). NULL is a no-op. */
+dlx_status dlx_plan_destroy(dlx_plan* plan);
+
+/* Device bytes the plan holds. */
+size_t dlx_plan_workspace_bytes(const dlx_plan* plan);
+
+/* Synchronise `stream`, then return and clear the plan's device status word
+ * (DLX_OK, DLX_ERR_NONFINITE or DLX_ERR_DOMAIN). */
+dlx_status dlx_plan_sync(dlx_plan* plan, void* stream);
+
+/* Forward model (Section 3).
+ *   transmission [Ni][Ni]        grey pupil transmission A (>= 0)
+ *   zernike_basis [Nz][Ni][Ni]   Z_j in metres of OPD per unit coefficient
+ *   map_basis [Ni][n_map]        bicubic matrix B (NULL iff n_map == 0)
+ *   zernike_coeffs [Nz]          c (metres)
+ *   phase_map [n_map][n_map]     C (metres; NULL iff n_map == 0)
+ *   sources [F][S][3]            per frame and star: alpha, beta (radians,
+ *                                dither included), photons phi
+ *   flat [Nd][Nd]                pixel response F
+ *   intrapixel [Q][Q]            intra-pixel kernel K, NULL = all ones
+ * Outputs (may not alias inputs):
+ *   binned_out [F][Nd][Nd]       B_f = bin_Q(K * sum_s sum_l w_l phi_s |E|^2)
+ *   model_out  [F][Nd][Nd]       m_f = F * B_f */
+dlx_status dlx_psf_forward(dlx_plan* plan, const float* transmission, const float* zernike_basis,
+                           const float* map_basis, const float* zernike_coeffs, const float* phase_map,
+                           const float* sources, const float* flat, const float* intrapixel,
+                           float* binned_out, float* model_out, void* stream);
+
+/* Loss, residual and flat-field gradient (Section 4), all reductions FP64.
+ *   model, binned, data [F][Nd][Nd]; flat [Nd][Nd]; prior_sigma > 0.
+ * Outputs:
+ *   loss_out       device double[1]      L
+ *   dloss_dmodel   [F][Nd][Nd] float     r = dL/dm
+ *   grad_flat      [Nd][Nd] double       dL/dF_p = sum_f r_fp B_fp + (F_p - mu)/sigma^2 */
+dlx_status dlx_loss_grad(dlx_plan* plan, const float* model, const float* binned, const float* data,
+                         const float* flat, dlx_loss_kind kind, double prior_mu, double prior_sigma,
+                         double* loss_out, float* dloss_dmodel, double* grad_flat, void* stream);
+
+/* Gradient through the optics given r = dL/dm (Sections 3-4). The inputs are
+ * those of dlx_psf_forward; every focal field is recomputed, none is stored.
+ * Outputs (double, FP64-reduced):
+ *   grad_zernike [Nz]              dL/dc
+ *   grad_map [n_map][n_map]        dL/dC (NULL iff n_map == 0)
+ *   grad_sources [F][S][3]         dL/dalpha, dL/dbeta, dL/dphi per frame and star */
+dlx_status dlx_psf_backward(dlx_plan* plan, const float* transmission, const float* zernike_basis,
+                            const float* map_basis, const float* zernike_coeffs, const float* phase_map,
+                            const float* sources, const float* flat, const float* intrapixel,
+                            const float* dloss_dmodel, double* grad_zernike, double* grad_map,
+                            double* grad_sources, void* stream);
+
+/* Stages of one evaluation, for per-stage timing. PREP builds the OPD, the
+ * pupil field and the tilt vectors; F1/F2 are the two MFT products of the
+ * forward pass (F2 with the intensity/bin epilogue); BIN sums the binned
+ * partials and applies the flat; LOSS is dlx_loss_grad; B2 recomputes the
+ * focal field and forms the adjoint seed; B3/B4 are the two adjoint MFT
+ * products (B4 with the phase-gradient epilogue); GRAD reduces dL/dOPD and
+ * projects it onto the Zernike basis, the map, positions and fluxes. */
+typedef enum {
+  DLX_STAGE_PREP = 0, DLX_STAGE_F1, DLX_STAGE_F2, DLX_STAGE_BIN, DLX_STAGE_LOSS,
+  DLX_STAGE_B2, DLX_STAGE_B3, DLX_STAGE_B4, DLX_STAGE_GRAD, DLX_N_STAGES
+} dlx_stage;
+
+/* Diagnostics: while enabled (enable != 0), each stage launch is bracketed
+ * by HIP events recorded on the stream of the call, adding a few event
+ * records per stage. Disabling discards pending records. */
+dlx_status dlx_plan_profile(dlx_plan* plan, int32_t enable);
+
+/* Diagnostics: synchronise on the recorded events and return, per stage
+ * (arrays of DLX_N_STAGES, host memory), the summed device time in ms, the
+ * number of launches and the number of PSFs those launches processed since
+ * profiling was enabled or these counters were last read; then reset them. */
+dlx_status dlx_plan_stage_times(dlx_plan* plan, double* total_ms, int64_t* launches, int64_t* psfs);
+
+/* Static string naming a status code. */
+const char* dlx_status_string(dlx_status status);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* DLX_H */

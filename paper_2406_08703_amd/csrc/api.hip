@@ -1,0 +1,555 @@
+// C ABI of libdlx (include/dlx.h): validation, plan construction (tiles,
+// chunking, workspace, DFT matrices) and the forward / loss / backward
+// launch sequences. All device work is enqueued on the caller's stream.
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <new>
+
+#include "dlx_internal.h"
+
+namespace dlx {
+hipError_t launch_dft(dlx_plan* p, hipStream_t st);
+hipError_t launch_prep(dlx_plan* p, const float* A, const float* Z, const float* Bm, const float* c, const float* C,
+                       const float* sources, hipStream_t st);
+hipError_t launch_bin_reduce(dlx_plan* p, const float* flat, float* binned, float* model, hipStream_t st);
+hipError_t launch_loss(dlx_plan* p, const float* model, const float* binned, const float* data, const float* flat,
+                       int kind, double mu, double sigma, double* loss, float* r, double* gflat, hipStream_t st);
+hipError_t launch_grad_reduce(dlx_plan* p, const float* Z, const float* Bm, double* gz, double* gmap, double* gsrc,
+                              hipStream_t st);
+int loss_block_count(long long npix);
+}  // namespace dlx
+
+using namespace dlx;
+
+namespace {
+
+constexpr size_t kDefaultChunkBudget = size_t(8) << 30;  // bytes of per-chunk intermediates
+constexpr int kMaxSide = 16384;
+constexpr int kTargetWG = 1024;
+
+#define DLX_HIP(expr)                        \
+  do {                                       \
+    if ((expr) != hipSuccess) return DLX_ERR_HIP; \
+  } while (0)
+
+int ceil_div(long long a, long long b) { return (int)((a + b - 1) / b); }
+
+// Pick the output tile of a stage. A wave owns (16 w) x (16 w) outputs and
+// the workgroup (32 w) x (32 w); w = 4 (128 x 128) is used when it still
+// gives enough workgroups to fill the chip, otherwise the smallest valid w.
+// With q > 1 the wave tile edge must be divisible by q, so that each
+// detector pixel's q x q focal samples stay inside one wave's tile.
+TileShape choose_tile(int M, int N, long long items, int q) {
+  const int cand[3] = {4, 3, 2};
+  int smallest = 0;
+  for (int w : cand) {
+    if (q > 1 ? ((16 * w) % q != 0) : (w == 3)) continue;
+    const long long wg = (long long)ceil_div(M, 32 * w) * ceil_div(N, 32 * w) * items;
+    if (wg >= 2 * kTargetWG) return TileShape{w, w};
+    smallest = w;
+  }
+  return TileShape{smallest, smallest};
+}
+
+struct Pool {
+  char* base;
+  size_t off;
+  template <class T>
+  T* take(size_t count) {
+    off = (off + 255) & ~size_t(255);
+    T* p = reinterpret_cast<T*>(base + off);
+    off += sizeof(T) * count;
+    return p;
+  }
+};
+
+void layout(dlx_plan* p, Pool& pool) {
+  const size_t L = p->L, Ni = p->Ni, No = p->No, ldNi = p->ldNi, ldNo = p->ldNo, CP = p->chunk_psf;
+  p->d_wl = pool.take<WlInfo>(L);
+  p->d_MN = pool.take<float>(2 * L * No * ldNi);
+  p->d_MT = pool.take<float>(2 * L * Ni * ldNo);
+  p->d_x = pool.take<double>(Ni);
+  p->d_opd = pool.take<float>(Ni * Ni);
+  p->d_maptmp = pool.take<float>(std::max<size_t>(1, (size_t)p->Nmap * Ni));
+  p->d_norm = pool.take<double>(1);
+  p->d_P0T = pool.take<float>(2 * L * Ni * ldNi);
+  p->d_tx = pool.take<float>(2 * (size_t)p->n_psf * ldNi);
+  p->d_ty = pool.take<float>(2 * (size_t)p->n_psf * ldNi);
+  p->d_T = pool.take<float>(2 * CP * No * ldNi);
+  p->d_Y = pool.take<float>(2 * CP * No * ldNo);
+  p->d_UT = pool.take<float>(2 * CP * Ni * ldNo);
+  p->d_binpart = pool.take<float>((size_t)p->F * p->f2_groups * p->Nd * p->Nd);
+  p->d_gpart = pool.take<float>((size_t)p->b4_groups_max * Ni * Ni);
+  p->d_gopd = pool.take<double>(Ni * Ni);
+  p->d_flux = pool.take<double>((size_t)p->n_psf * p->tiles_b2);
+  p->d_pos = pool.take<double>((size_t)p->n_psf * p->tiles_b4 * 2);
+  p->d_lossblk = pool.take<double>(p->loss_blocks);
+  p->d_tmp2 = pool.take<double>(std::max<size_t>(1, Ni * (size_t)p->Nmap));
+  p->d_status = pool.take<int>(1);
+}
+
+size_t per_psf_bytes(const dlx_plan* p) {
+  return sizeof(float) * 2 *
+         ((size_t)p->No * p->ldNi + (size_t)p->No * p->ldNo + (size_t)p->Ni * p->ldNo);
+}
+
+bool ok_ptr(const void* q) { return q != nullptr; }
+
+GemmArgs base_args(const dlx_plan* p, int f0, int nframes) {
+  GemmArgs a;
+  std::memset(&a, 0, sizeof(a));
+  a.L = p->L;
+  a.S = p->S;
+  a.psf0 = f0 * p->S * p->L;
+  a.frame0 = f0;
+  a.n_chunk_psf = nframes * p->S * p->L;
+  a.tx = p->d_tx;
+  a.ty = p->d_ty;
+  a.tilt_plane = (long long)p->n_psf * p->ldNi;
+  a.ldt = p->ldNi;
+  a.p0t = p->d_P0T;
+  a.p0_plane = (long long)p->Ni * p->ldNi;
+  a.p0_by_wl = 2LL * p->Ni * p->ldNi;
+  a.ldp = p->ldNi;
+  a.wl = p->d_wl;
+  a.Q = p->Q;
+  a.n_det = p->Nd;
+  a.xcoord = p->d_x;
+  return a;
+}
+
+Operand op_MN(const dlx_plan* p) {
+  return Operand{p->d_MN, (long long)p->L * p->No * p->ldNi, (long long)p->No * p->ldNi, 0, p->ldNi};
+}
+Operand op_MT(const dlx_plan* p) {
+  return Operand{p->d_MT, (long long)p->L * p->Ni * p->ldNo, (long long)p->Ni * p->ldNo, 0, p->ldNo};
+}
+Operand op_T(const dlx_plan* p) {
+  return Operand{p->d_T, (long long)p->chunk_psf * p->No * p->ldNi, 0, (long long)p->No * p->ldNi, p->ldNi};
+}
+Operand op_Y(const dlx_plan* p) {
+  return Operand{p->d_Y, (long long)p->chunk_psf * p->No * p->ldNo, 0, (long long)p->No * p->ldNo, p->ldNo};
+}
+Operand op_UT(const dlx_plan* p) {
+  return Operand{p->d_UT, (long long)p->chunk_psf * p->Ni * p->ldNo, 0, (long long)p->Ni * p->ldNo, p->ldNo};
+}
+
+int wg_count(const GemmArgs& a) { return a.tiles_m * a.tiles_n * a.n_items; }
+
+// ---- stage timing (diagnostics): event pairs bracket each stage on the call's stream
+constexpr int kEventPool = 512;
+
+hipError_t flush_records(dlx_plan* p) {
+  for (const auto& r : p->recs) {
+    hipError_t e = hipEventSynchronize(p->ev_pool[r.e1]);
+    if (e != hipSuccess) return e;
+    float ms = 0.f;
+    e = hipEventElapsedTime(&ms, p->ev_pool[r.e0], p->ev_pool[r.e1]);
+    if (e != hipSuccess) return e;
+    p->stage_ms[r.stage] += ms;
+    p->stage_launches[r.stage] += 1;
+    p->stage_psfs[r.stage] += r.psfs;
+  }
+  p->recs.clear();
+  p->ev_used = 0;
+  return hipSuccess;
+}
+
+struct Stage {
+  dlx_plan* p;
+  hipStream_t st;
+  int stage;
+  long long psfs;
+  int e0 = -1;
+  Stage(dlx_plan* p_, hipStream_t st_, int stage_, long long psfs_) : p(p_), st(st_), stage(stage_), psfs(psfs_) {
+    if (!p->profiling) return;
+    if (p->ev_used + 2 > (int)p->ev_pool.size() && flush_records(p) != hipSuccess) return;
+    e0 = p->ev_used;
+    p->ev_used += 2;
+    if (hipEventRecord(p->ev_pool[e0], st) != hipSuccess) e0 = -1;
+  }
+  ~Stage() {
+    if (e0 < 0) return;
+    if (hipEventRecord(p->ev_pool[e0 + 1], st) == hipSuccess) p->recs.push_back({stage, e0, e0 + 1, psfs});
+  }
+};
+
+void set_tiles(GemmArgs& a, TileShape ts) {
+  a.tiles_m = ceil_div(a.M, ts.bm());
+  a.tiles_n = ceil_div(a.N, ts.bn());
+}
+
+// F1: T = M_l P for every PSF of frames [f0, f0 + nf)
+hipError_t run_f1(dlx_plan* p, int f0, int nf, hipStream_t st) {
+  GemmArgs a = base_args(p, f0, nf);
+  a.M = p->No;
+  a.N = p->Ni;
+  a.K = p->Ni;
+  a.n_items = a.n_chunk_psf;
+  a.A = op_MN(p);
+  a.B = Operand{p->d_P0T, (long long)p->Ni * p->ldNi, 2LL * p->Ni * p->ldNi, 0, p->ldNi};
+  a.out = p->d_T;
+  a.out_plane = op_T(p).plane;
+  a.out_by_psf = op_T(p).by_psf;
+  a.ldo = p->ldNi;
+  set_tiles(a, p->ts_f1);
+  return launch_gemm(KIND_F1, p->ts_f1, a, wg_count(a), st);
+}
+
+GemmArgs e_args(dlx_plan* p, int f0, int nf, TileShape ts) {
+  GemmArgs a = base_args(p, f0, nf);
+  a.M = p->No;
+  a.N = p->No;
+  a.K = p->Ni;
+  a.A = op_T(p);
+  a.B = op_MN(p);
+  set_tiles(a, ts);
+  return a;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* dlx_status_string(dlx_status s) {
+  switch (s) {
+    case DLX_OK: return "DLX_OK";
+    case DLX_ERR_INVALID_ARG: return "DLX_ERR_INVALID_ARG: null pointer, non-positive size or bad enum";
+    case DLX_ERR_SHAPE: return "DLX_ERR_SHAPE: inconsistent sizes";
+    case DLX_ERR_OOM: return "DLX_ERR_OOM: workspace does not fit";
+    case DLX_ERR_HIP: return "DLX_ERR_HIP: a HIP runtime call failed";
+    case DLX_ERR_NONFINITE: return "DLX_ERR_NONFINITE: non-finite model or data";
+    case DLX_ERR_DOMAIN: return "DLX_ERR_DOMAIN: model <= 0 under the Poisson loss (clamped)";
+    case DLX_ERR_UNSUPPORTED: return "DLX_ERR_UNSUPPORTED: not implemented in this build";
+  }
+  return "unknown dlx_status";
+}
+
+dlx_status dlx_validate(const dlx_problem_desc* probs, int32_t n_probs) {
+  if (!probs || n_probs < 1) return DLX_ERR_INVALID_ARG;
+  for (int i = 0; i < n_probs; ++i) {
+    const dlx_problem_desc& d = probs[i];
+    if (d.n_pupil < 2 || d.n_focal < 1 || d.oversample < 1 || d.n_wavelengths < 1 || d.n_sources < 1 ||
+        d.n_frames < 1 || d.n_zernike < 0 || d.n_map < 0)
+      return DLX_ERR_INVALID_ARG;
+    if (!(d.diameter_m > 0.0) || !(d.focal_pixel_rad > 0.0) || !std::isfinite(d.diameter_m) ||
+        !std::isfinite(d.focal_pixel_rad))
+      return DLX_ERR_INVALID_ARG;
+    if (!d.wavelengths_m || !d.spectral_weights) return DLX_ERR_INVALID_ARG;
+    for (int l = 0; l < d.n_wavelengths; ++l) {
+      if (!(d.wavelengths_m[l] > 0.0) || !std::isfinite(d.wavelengths_m[l])) return DLX_ERR_INVALID_ARG;
+      if (!std::isfinite(d.spectral_weights[l])) return DLX_ERR_INVALID_ARG;
+    }
+    if (d.n_focal % d.oversample != 0) return DLX_ERR_SHAPE;
+    if (d.n_pupil > kMaxSide || d.n_focal > kMaxSide) return DLX_ERR_SHAPE;
+    if ((long long)d.n_frames * d.n_sources * d.n_wavelengths > (1LL << 24)) return DLX_ERR_SHAPE;
+  }
+  return DLX_OK;
+}
+
+dlx_status dlx_plan_create(const dlx_problem_desc* probs, int32_t n_probs, dlx_precision precision, int32_t flags,
+                           size_t workspace_limit_bytes, dlx_plan** out) {
+  if (!out) return DLX_ERR_INVALID_ARG;
+  *out = nullptr;
+  dlx_status v = dlx_validate(probs, n_probs);
+  if (v != DLX_OK) return v;
+  if (precision != DLX_FP32 && precision != DLX_BF16X3) return DLX_ERR_INVALID_ARG;
+  if (flags != 0) return DLX_ERR_INVALID_ARG;
+  if (n_probs != 1) return DLX_ERR_UNSUPPORTED;
+  if (precision != DLX_FP32) return DLX_ERR_UNSUPPORTED;
+  const dlx_problem_desc& d = probs[0];
+
+  dlx_plan* p = new (std::nothrow) dlx_plan();
+  if (!p) return DLX_ERR_OOM;
+  p->Ni = d.n_pupil;
+  p->No = d.n_focal;
+  p->Q = d.oversample;
+  p->Nd = d.n_focal / d.oversample;
+  p->L = d.n_wavelengths;
+  p->S = d.n_sources;
+  p->F = d.n_frames;
+  p->Nz = d.n_zernike;
+  p->Nmap = d.n_map;
+  p->D = d.diameter_m;
+  p->du = d.focal_pixel_rad;
+  p->dx = d.diameter_m / d.n_pupil;
+  p->lam.assign(d.wavelengths_m, d.wavelengths_m + d.n_wavelengths);
+  p->wts.assign(d.spectral_weights, d.spectral_weights + d.n_wavelengths);
+  p->prec = precision;
+  p->ldNi = round_up(p->Ni, 16);
+  p->ldNo = round_up(p->No, 16);
+  p->n_psf = p->F * p->S * p->L;
+
+  // chunk of whole frames whose intermediates fit the budget
+  size_t budget = workspace_limit_bytes ? workspace_limit_bytes : kDefaultChunkBudget;
+  const size_t psf_bytes = per_psf_bytes(p);
+  const size_t frame_bytes = psf_bytes * p->S * p->L;
+  const size_t fixed = sizeof(float) * 2 * (size_t)p->L *
+                       ((size_t)p->No * p->ldNi + (size_t)p->Ni * p->ldNo + (size_t)p->Ni * p->ldNi);
+  if (workspace_limit_bytes) {
+    if (fixed + frame_bytes > budget) {
+      delete p;
+      return DLX_ERR_OOM;
+    }
+    budget -= fixed;
+  }
+  p->frames_per_chunk = (int)std::max<size_t>(1, std::min<size_t>(p->F, budget / frame_bytes));
+  p->n_chunks = ceil_div(p->F, p->frames_per_chunk);
+  p->chunk_psf = p->frames_per_chunk * p->S * p->L;
+
+  // tiles
+  const int Q = p->Q;
+  p->ts_f1 = choose_tile(p->No, p->Ni, p->chunk_psf, 1);
+  p->ts_b2 = choose_tile(p->No, p->No, p->chunk_psf, 1);
+  p->ts_b3 = choose_tile(p->Ni, p->No, p->chunk_psf, 1);
+  const int sl = p->S * p->L;
+  p->ts_f2 = choose_tile(p->No, p->No, (long long)p->frames_per_chunk * sl, Q);
+  if (p->ts_f2.wm == 0) {
+    delete p;
+    return DLX_ERR_UNSUPPORTED;
+  }
+  {
+    const int tiles = ceil_div(p->No, p->ts_f2.bm()) * ceil_div(p->No, p->ts_f2.bn());
+    int g = ceil_div(kTargetWG, (long long)p->frames_per_chunk * tiles);
+    g = std::max(1, std::min(g, sl));
+    p->f2_gsize = ceil_div(sl, g);
+    p->f2_groups = ceil_div(sl, p->f2_gsize);
+  }
+  {
+    const int t = ceil_div(p->Ni, 128) * ceil_div(p->Ni, 128);
+    const int g = std::max(1, std::min(ceil_div(kTargetWG, t), p->chunk_psf));
+    p->b4_gsize = ceil_div(p->chunk_psf, g);
+    p->b4_groups_max = ceil_div(p->chunk_psf, p->b4_gsize);
+    p->ts_b4 = choose_tile(p->Ni, p->Ni, p->b4_groups_max, 1);
+  }
+  p->tiles_b2 = ceil_div(p->No, p->ts_b2.bm()) * ceil_div(p->No, p->ts_b2.bn());
+  p->tiles_b4 = ceil_div(p->Ni, p->ts_b4.bm()) * ceil_div(p->Ni, p->ts_b4.bn());
+  p->loss_blocks = loss_block_count((long long)p->Nd * p->Nd);
+
+  Pool sizing{nullptr, 0};
+  layout(p, sizing);
+  p->pool_bytes = sizing.off + 256;
+  size_t free_b = 0, total_b = 0;
+  if (hipMemGetInfo(&free_b, &total_b) != hipSuccess) {
+    delete p;
+    return DLX_ERR_HIP;
+  }
+  if (p->pool_bytes > free_b) {
+    delete p;
+    return DLX_ERR_OOM;
+  }
+  if (hipMalloc(&p->pool, p->pool_bytes) != hipSuccess) {
+    delete p;
+    return DLX_ERR_OOM;
+  }
+  Pool pool{reinterpret_cast<char*>(p->pool), 0};
+  layout(p, pool);
+
+  std::vector<WlInfo> wl(p->L);
+  for (int l = 0; l < p->L; ++l) {
+    wl[l].lam = p->lam[l];
+    wl[l].w = (float)p->wts[l];
+    wl[l].scale = (float)(p->dx * p->du / p->lam[l]);
+    wl[l].kphase = (float)(kTwoPi / p->lam[l]);
+    wl[l].pad = 0.f;
+  }
+  hipError_t e = hipMemcpy(p->d_wl, wl.data(), sizeof(WlInfo) * p->L, hipMemcpyHostToDevice);
+  if (e == hipSuccess) e = hipMemset(p->d_status, 0, sizeof(int));
+  if (e == hipSuccess) e = launch_dft(p, nullptr);
+  if (e == hipSuccess) e = hipDeviceSynchronize();
+  if (e != hipSuccess) {
+    (void)hipFree(p->pool);
+    delete p;
+    return DLX_ERR_HIP;
+  }
+  *out = p;
+  return DLX_OK;
+}
+
+dlx_status dlx_plan_destroy(dlx_plan* p) {
+  if (!p) return DLX_OK;
+  const hipError_t e1 = hipDeviceSynchronize();
+  for (hipEvent_t ev : p->ev_pool) (void)hipEventDestroy(ev);
+  const hipError_t e2 = p->pool ? hipFree(p->pool) : hipSuccess;
+  delete p;
+  return (e1 == hipSuccess && e2 == hipSuccess) ? DLX_OK : DLX_ERR_HIP;
+}
+
+size_t dlx_plan_workspace_bytes(const dlx_plan* p) { return p ? p->pool_bytes : 0; }
+
+dlx_status dlx_plan_profile(dlx_plan* p, int32_t enable) {
+  if (!p) return DLX_ERR_INVALID_ARG;
+  if (enable && p->ev_pool.empty()) {
+    p->ev_pool.resize(kEventPool);
+    for (auto& ev : p->ev_pool) DLX_HIP(hipEventCreate(&ev));
+  }
+  if (!enable) {
+    p->recs.clear();
+    p->ev_used = 0;
+  }
+  p->profiling = enable != 0;
+  for (int i = 0; i < DLX_N_STAGES; ++i) {
+    p->stage_ms[i] = 0.0;
+    p->stage_launches[i] = 0;
+    p->stage_psfs[i] = 0;
+  }
+  return DLX_OK;
+}
+
+dlx_status dlx_plan_stage_times(dlx_plan* p, double* total_ms, int64_t* launches, int64_t* psfs) {
+  if (!p || !total_ms || !launches || !psfs) return DLX_ERR_INVALID_ARG;
+  DLX_HIP(flush_records(p));
+  for (int i = 0; i < DLX_N_STAGES; ++i) {
+    total_ms[i] = p->stage_ms[i];
+    launches[i] = p->stage_launches[i];
+    psfs[i] = p->stage_psfs[i];
+    p->stage_ms[i] = 0.0;
+    p->stage_launches[i] = 0;
+    p->stage_psfs[i] = 0;
+  }
+  return DLX_OK;
+}
+
+dlx_status dlx_plan_sync(dlx_plan* p, void* stream) {
+  if (!p) return DLX_ERR_INVALID_ARG;
+  hipStream_t st = reinterpret_cast<hipStream_t>(stream);
+  DLX_HIP(hipStreamSynchronize(st));
+  int h = 0;
+  DLX_HIP(hipMemcpy(&h, p->d_status, sizeof(int), hipMemcpyDeviceToHost));
+  DLX_HIP(hipMemset(p->d_status, 0, sizeof(int)));
+  if (h & 1) return DLX_ERR_NONFINITE;
+  if (h & 2) return DLX_ERR_DOMAIN;
+  return DLX_OK;
+}
+
+dlx_status dlx_psf_forward(dlx_plan* p, const float* transmission, const float* zernike_basis,
+                           const float* map_basis, const float* zernike_coeffs, const float* phase_map,
+                           const float* sources, const float* flat, const float* intrapixel, float* binned_out,
+                           float* model_out, void* stream) {
+  if (!p || !ok_ptr(transmission) || !ok_ptr(sources) || !ok_ptr(flat) || !ok_ptr(binned_out) || !ok_ptr(model_out))
+    return DLX_ERR_INVALID_ARG;
+  if (p->Nz > 0 && (!zernike_basis || !zernike_coeffs)) return DLX_ERR_INVALID_ARG;
+  if ((p->Nmap > 0) != (map_basis != nullptr) || (p->Nmap > 0) != (phase_map != nullptr)) return DLX_ERR_INVALID_ARG;
+  hipStream_t st = reinterpret_cast<hipStream_t>(stream);
+  {
+    Stage sg(p, st, DLX_STAGE_PREP, p->n_psf);
+    DLX_HIP(launch_prep(p, transmission, zernike_basis, map_basis, zernike_coeffs, phase_map, sources, st));
+  }
+  for (int c = 0; c < p->n_chunks; ++c) {
+    const int f0 = c * p->frames_per_chunk;
+    const int nf = std::min(p->frames_per_chunk, p->F - f0);
+    const int nc = nf * p->S * p->L;
+    {
+      Stage sg(p, st, DLX_STAGE_F1, nc);
+      DLX_HIP(run_f1(p, f0, nf, st));
+    }
+    Stage sg(p, st, DLX_STAGE_F2, nc);
+    GemmArgs a = e_args(p, f0, nf, p->ts_f2);
+    a.groups = p->f2_groups;
+    a.group_size = p->f2_gsize;
+    a.n_items = nf * p->f2_groups;
+    a.sources = sources;
+    a.part = p->d_binpart;
+    a.intrapixel = intrapixel;
+    DLX_HIP(launch_gemm(KIND_F2, p->ts_f2, a, wg_count(a), st));
+  }
+  Stage sg(p, st, DLX_STAGE_BIN, p->n_psf);
+  DLX_HIP(launch_bin_reduce(p, flat, binned_out, model_out, st));
+  return DLX_OK;
+}
+
+dlx_status dlx_loss_grad(dlx_plan* p, const float* model, const float* binned, const float* data, const float* flat,
+                         dlx_loss_kind kind, double prior_mu, double prior_sigma, double* loss_out,
+                         float* dloss_dmodel, double* grad_flat, void* stream) {
+  if (!p || !model || !binned || !data || !flat || !loss_out || !dloss_dmodel || !grad_flat)
+    return DLX_ERR_INVALID_ARG;
+  if (kind != DLX_LOSS_POISSON && kind != DLX_LOSS_CHI2) return DLX_ERR_INVALID_ARG;
+  if (!(prior_sigma > 0.0) || !std::isfinite(prior_sigma) || !std::isfinite(prior_mu)) return DLX_ERR_INVALID_ARG;
+  hipStream_t st = reinterpret_cast<hipStream_t>(stream);
+  Stage sg(p, st, DLX_STAGE_LOSS, p->n_psf);
+  DLX_HIP(launch_loss(p, model, binned, data, flat, (int)kind, prior_mu, prior_sigma, loss_out, dloss_dmodel,
+                      grad_flat, st));
+  return DLX_OK;
+}
+
+dlx_status dlx_psf_backward(dlx_plan* p, const float* transmission, const float* zernike_basis,
+                            const float* map_basis, const float* zernike_coeffs, const float* phase_map,
+                            const float* sources, const float* flat, const float* intrapixel,
+                            const float* dloss_dmodel, double* grad_zernike, double* grad_map, double* grad_sources,
+                            void* stream) {
+  if (!p || !transmission || !sources || !flat || !dloss_dmodel || !grad_sources) return DLX_ERR_INVALID_ARG;
+  if (p->Nz > 0 && (!zernike_basis || !zernike_coeffs || !grad_zernike)) return DLX_ERR_INVALID_ARG;
+  if ((p->Nmap > 0) != (map_basis != nullptr) || (p->Nmap > 0) != (phase_map != nullptr) ||
+      (p->Nmap > 0) != (grad_map != nullptr))
+    return DLX_ERR_INVALID_ARG;
+  hipStream_t st = reinterpret_cast<hipStream_t>(stream);
+  {
+    Stage sg(p, st, DLX_STAGE_PREP, p->n_psf);
+    DLX_HIP(launch_prep(p, transmission, zernike_basis, map_basis, zernike_coeffs, phase_map, sources, st));
+  }
+  for (int c = 0; c < p->n_chunks; ++c) {
+    const int f0 = c * p->frames_per_chunk;
+    const int nf = std::min(p->frames_per_chunk, p->F - f0);
+    const int nc = nf * p->S * p->L;
+    {
+      Stage sg(p, st, DLX_STAGE_F1, nc);
+      DLX_HIP(run_f1(p, f0, nf, st));
+    }
+    {  // B2: recompute E, seed Y = w phi G E
+      Stage sg(p, st, DLX_STAGE_B2, nc);
+      GemmArgs a = e_args(p, f0, nf, p->ts_b2);
+      a.n_items = nc;
+      a.sources = sources;
+      a.out = p->d_Y;
+      a.out_plane = op_Y(p).plane;
+      a.out_by_psf = op_Y(p).by_psf;
+      a.ldo = p->ldNo;
+      a.red = p->d_flux;
+      a.flat = flat;
+      a.resid = dloss_dmodel;
+      a.intrapixel = intrapixel;
+      DLX_HIP(launch_gemm(KIND_B2, p->ts_b2, a, wg_count(a), st));
+    }
+    {  // B3: U^T = conj(M)^T Y^T
+      Stage sg(p, st, DLX_STAGE_B3, nc);
+      GemmArgs a = base_args(p, f0, nf);
+      a.M = p->Ni;
+      a.N = p->No;
+      a.K = p->No;
+      a.n_items = nc;
+      a.A = op_MT(p);
+      a.conj_a = 1;
+      a.B = op_Y(p);
+      a.out = p->d_UT;
+      a.out_plane = op_UT(p).plane;
+      a.out_by_psf = op_UT(p).by_psf;
+      a.ldo = p->ldNo;
+      set_tiles(a, p->ts_b3);
+      DLX_HIP(launch_gemm(KIND_B3, p->ts_b3, a, wg_count(a), st));
+    }
+    {  // B4: W = c M^H U, phase gradient and position sums
+      Stage sg(p, st, DLX_STAGE_B4, nc);
+      GemmArgs a = base_args(p, f0, nf);
+      a.M = p->Ni;
+      a.N = p->Ni;
+      a.K = p->No;
+      a.A = op_MT(p);
+      a.conj_a = 1;
+      a.B = op_UT(p);
+      a.group_size = p->b4_gsize;
+      a.groups = ceil_div(nc, p->b4_gsize);
+      a.n_items = a.groups;
+      a.part = p->d_gpart;
+      a.accumulate = c > 0;
+      a.red = p->d_pos;
+      set_tiles(a, p->ts_b4);
+      DLX_HIP(launch_gemm(KIND_B4, p->ts_b4, a, wg_count(a), st));
+    }
+  }
+  Stage sg(p, st, DLX_STAGE_GRAD, p->n_psf);
+  DLX_HIP(launch_grad_reduce(p, zernike_basis, map_basis, grad_zernike, grad_map, grad_sources, st));
+  return DLX_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,153 @@
+// Internal declarations of libdlx: plan layout, kernel argument blocks and
+// launcher prototypes. Not part of the public ABI (see include/dlx.h).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstddef>
+#include <cstdint>
+#include <vector>
+
+#include "dlx.h"
+
+namespace dlx {
+
+constexpr double kTwoPi = 6.283185307179586476925286766559;
+
+inline int round_up(int v, int m) { return (v + m - 1) / m * m; }
+
+// Per-wavelength constants, read by the kernels.
+struct WlInfo {
+  double lam;     // metres
+  float w;        // spectral weight
+  float scale;    // dx * du / lambda, the focal-field factor
+  float kphase;   // 2 pi / lambda
+  float pad;
+};
+
+// A planar complex operand: re plane at base, im plane at base + plane.
+// The item's matrix starts at base + (psf % L) * by_wl + local_psf * by_psf.
+// Rows are `ld` floats apart (ld a multiple of 16, padded columns are never
+// read: the loaders mask k >= K).
+struct Operand {
+  const float* base;
+  long long plane;
+  long long by_wl;
+  long long by_psf;
+  int ld;
+};
+
+// The five matrix-Fourier stages of one forward+gradient evaluation.
+//   F1  T = M_l P              (pupil field generated in the operand loader)
+//   F2  E = c T M_l^T          epilogue: w phi |E|^2 summed over a PSF group, K-weighted, binned
+//   B2  E = c T M_l^T          epilogue: Y = w phi G E stored, flux partial sum G |E|^2
+//   B3  U^T = conj(M_l)^T Y^T  stored
+//   B4  W = c M_l^H U          epilogue: g = 2 Im(conj(P) W) (2 pi / l) summed over a group; position partials
+enum GemmKind { KIND_F1 = 0, KIND_F2 = 1, KIND_B2 = 2, KIND_B3 = 3, KIND_B4 = 4 };
+
+struct GemmArgs {
+  int M, N, K;          // C[M][N] = sum_k A[i][k] B[j][k] per PSF
+  int tiles_m, tiles_n;
+  int n_items;          // PSFs (F1, B2, B3) or PSF groups (F2, B4)
+  int L, S;             // wavelengths, sources
+  int psf0;             // global index of the chunk's first PSF
+  int frame0;           // first frame of the chunk
+  int group_size;       // PSFs per group item
+  int groups;           // F2: groups per frame; B4: groups in the chunk
+  int n_chunk_psf;
+  int conj_a, conj_b;
+  Operand A, B;
+  // pupil field pieces: P[m][n] = P0T[n][m] * ty[m] * tx[n] (F1 loader, B4 epilogue)
+  const float* tx;
+  const float* ty;
+  long long tilt_plane;
+  int ldt;
+  const float* p0t;
+  long long p0_plane;
+  long long p0_by_wl;
+  int ldp;
+  const WlInfo* wl;
+  const float* sources;   // [F][S][3]
+  // dense outputs (F1: T, B2: Y, B3: U^T), indexed by local PSF
+  float* out;
+  long long out_plane;
+  long long out_by_psf;
+  int ldo;
+  // group partials: F2 binned [F][groups][Nd*Nd]; B4 dL/dOPD [groups][Ni*Ni]
+  float* part;
+  int accumulate;
+  // per-(PSF, tile) FP64 partials: B2 flux [n_psf][tiles]; B4 positions [n_psf][tiles][2]
+  double* red;
+  // detector
+  int Q, n_det;
+  const float* intrapixel;
+  const float* flat;
+  const float* resid;
+  const double* xcoord;   // pupil sample coordinates (metres), [Ni]
+};
+
+// Tile shape of one GEMM launch: 4 waves (2 x 2), each WM x WN blocks of 16 x 16.
+struct TileShape {
+  int wm, wn;
+  int bm() const { return 32 * wm; }
+  int bn() const { return 32 * wn; }
+};
+
+hipError_t launch_gemm(int kind, TileShape ts, const GemmArgs& a, int n_wg, hipStream_t st);
+bool tile_supported(int kind, TileShape ts);
+
+}  // namespace dlx
+
+struct dlx_plan {
+  // problem
+  int Ni, No, Q, Nd, L, S, F, Nz, Nmap;
+  double D, du, dx;
+  std::vector<double> lam, wts;
+  dlx_precision prec;
+  // padded leading dimensions
+  int ldNi, ldNo;
+  // chunking
+  int frames_per_chunk;
+  int n_chunks;
+  int chunk_psf;        // PSFs in a full chunk
+  int n_psf;
+  // tiles
+  dlx::TileShape ts_f1, ts_f2, ts_b2, ts_b3, ts_b4;
+  int f2_groups, f2_gsize;   // per frame
+  int b4_gsize, b4_groups_max;
+  // device memory
+  void* pool = nullptr;
+  size_t pool_bytes = 0;
+  dlx::WlInfo* d_wl = nullptr;
+  float* d_MN = nullptr;   // [L][No][ldNi] planar
+  float* d_MT = nullptr;   // [L][Ni][ldNo] planar
+  double* d_x = nullptr;   // [Ni]
+  float* d_opd = nullptr;  // [Ni*Ni]
+  float* d_maptmp = nullptr;  // [Nmap][Ni]
+  double* d_norm = nullptr;   // 1/sqrt(sum A^2)
+  float* d_P0T = nullptr;  // [L][Ni][ldNi] planar
+  float* d_tx = nullptr;   // [n_psf][ldNi] planar
+  float* d_ty = nullptr;
+  float* d_T = nullptr;    // [chunk_psf][No][ldNi] planar
+  float* d_Y = nullptr;    // [chunk_psf][No][ldNo] planar
+  float* d_UT = nullptr;   // [chunk_psf][Ni][ldNo] planar
+  float* d_binpart = nullptr;  // [F][f2_groups][Nd*Nd]
+  float* d_gpart = nullptr;    // [b4_groups_max][Ni*Ni]
+  double* d_gopd = nullptr;    // [Ni*Ni]
+  double* d_flux = nullptr;    // [n_psf][tiles_b2]
+  double* d_pos = nullptr;     // [n_psf][tiles_b4][2]
+  double* d_lossblk = nullptr; // [loss blocks]
+  double* d_tmp2 = nullptr;    // [Ni][Nmap] for the map gradient
+  int* d_status = nullptr;
+  int loss_blocks = 0;
+  // stage timing (diagnostics)
+  bool profiling = false;
+  std::vector<hipEvent_t> ev_pool;
+  int ev_used = 0;
+  struct Rec { int stage; int e0, e1; long long psfs; };
+  std::vector<Rec> recs;
+  double stage_ms[DLX_N_STAGES] = {};
+  long long stage_launches[DLX_N_STAGES] = {};
+  long long stage_psfs[DLX_N_STAGES] = {};
+  int tiles_b2 = 0, tiles_b4 = 0;
+};

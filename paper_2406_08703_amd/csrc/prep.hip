@@ -1,0 +1,202 @@
+// Operand preparation for the two-sided MFT (Section 3).
+//
+//   DFT matrices   M_l[k][n] = exp(-2 pi i x_n u_k / lambda_l), stored once per plan as
+//                  M (rows = focal index) and M^T (rows = pupil index), planar FP32.
+//                  x_n u_k / lambda = (2n - Ni + 1)(2k - No + 1) * dx du / (4 lambda):
+//                  the integer product is exact, the scale is FP64 and the result is
+//                  reduced modulo one cycle before sincospi, so the phase error does
+//                  not grow with the grid size.
+//   OPD            sum_j c_j Z_j (+ B C B^T), FP64 accumulation (basis optic, Section 3).
+//   Pupil field    P0_l = A / sqrt(sum A^2) * exp(i 2 pi OPD / lambda_l), stored transposed.
+//   Tilts          tx[n] = exp(+2 pi i x_n alpha / lambda), ty[m] likewise with beta,
+//                  one pair of vectors per PSF, phases in FP64 reduced modulo one cycle.
+// All of these are HBM- or launch-bound; none is on the MFMA path.
+#include "dlx_internal.h"
+
+namespace dlx {
+namespace {
+
+__global__ void dft_matrix_kernel(float* MN, float* MT, int Ni, int No, int ldNi, int ldNo, double s4,
+                                  const WlInfo* wl, long long mn_plane, long long mn_wl, long long mt_plane,
+                                  long long mt_wl) {
+  const int l = blockIdx.z;
+  const double s = s4 / wl[l].lam;  // dx du / (4 lambda)
+  const int n = blockIdx.x * blockDim.x + threadIdx.x;  // pupil index (padded)
+  const int k = blockIdx.y * blockDim.y + threadIdx.y;  // focal index (padded)
+  if (n >= ldNi && n >= Ni) return;
+  float re = 0.f, im = 0.f;
+  if (n < Ni && k < No) {
+    const long long p = (long long)(2 * n - Ni + 1) * (long long)(2 * k - No + 1);
+    const double t = (double)p * s;           // cycles
+    const double fr = t - rint(t);
+    double sn, cs;
+    sincospi(2.0 * fr, &sn, &cs);
+    re = (float)cs;
+    im = (float)(-sn);
+  }
+  if (k < No && n < ldNi) {
+    MN[l * mn_wl + (long long)k * ldNi + n] = re;
+    MN[l * mn_wl + mn_plane + (long long)k * ldNi + n] = im;
+  }
+  if (n < Ni && k < ldNo) {
+    MT[l * mt_wl + (long long)n * ldNo + k] = re;
+    MT[l * mt_wl + mt_plane + (long long)n * ldNo + k] = im;
+  }
+}
+
+// Coordinates of the pupil samples (x and y grids are identical).
+__global__ void coords_kernel(double* x, int Ni, double dx) {
+  const int n = blockIdx.x * blockDim.x + threadIdx.x;
+  if (n < Ni) x[n] = ((double)n - 0.5 * (double)(Ni - 1)) * dx;
+}
+
+// 1 / sqrt(sum A^2) in one 1024-thread block, FP64, fixed reduction order.
+__global__ void norm_kernel(const float* A, long long n, double* out) {
+  __shared__ double sh[1024];
+  double acc = 0.0;
+  for (long long i = threadIdx.x; i < n; i += blockDim.x) {
+    const double v = A[i];
+    acc += v * v;
+  }
+  sh[threadIdx.x] = acc;
+  __syncthreads();
+  for (int o = blockDim.x / 2; o > 0; o >>= 1) {
+    if ((int)threadIdx.x < o) sh[threadIdx.x] += sh[threadIdx.x + o];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) out[0] = sh[0] > 0.0 ? 1.0 / sqrt(sh[0]) : 0.0;
+}
+
+// tmp[j][n] = sum_k C[j][k] B[n][k]   (first half of B C B^T)
+__global__ void map_tmp_kernel(const float* C, const float* Bm, float* tmp, int Nmap, int Ni) {
+  const int n = blockIdx.x * blockDim.x + threadIdx.x;
+  const int j = blockIdx.y;
+  if (n >= Ni) return;
+  double acc = 0.0;
+  for (int k = 0; k < Nmap; ++k) acc += (double)C[j * Nmap + k] * (double)Bm[(long long)n * Nmap + k];
+  tmp[(long long)j * Ni + n] = (float)acc;
+}
+
+// OPD[m][n] = sum_j c_j Z_j[m][n] + sum_j B[m][j] tmp[j][n]
+__global__ void opd_kernel(const float* Z, const float* c, int Nz, long long npix, int Ni, const float* Bm,
+                           const float* tmp, int Nmap, float* opd) {
+  const long long p = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (p >= npix) return;
+  double acc = 0.0;
+  for (int j = 0; j < Nz; ++j) acc += (double)c[j] * (double)Z[(long long)j * npix + p];
+  if (Nmap > 0) {
+    const int m = (int)(p / Ni), n = (int)(p - (long long)m * Ni);
+    for (int j = 0; j < Nmap; ++j) acc += (double)Bm[(long long)m * Nmap + j] * (double)tmp[(long long)j * Ni + n];
+  }
+  opd[p] = (float)acc;
+}
+
+// P0T_l[n][m] = A[m][n] * norm * exp(i 2 pi OPD[m][n] / lambda_l), through a 32 x 32 LDS transpose.
+__global__ void pupil_kernel(const float* A, const float* opd, const double* norm, const WlInfo* wl, int L, int Ni,
+                             int ldp, float* P0T, long long plane, long long by_wl) {
+  __shared__ float tr[32][33], ti[32][33];
+  const int tx = threadIdx.x, ty = threadIdx.y;  // 32 x 8
+  const int m0 = blockIdx.y * 32, n0 = blockIdx.x * 32;
+  const double nrm = norm[0];
+  float a[4], o[4];
+  for (int q = 0; q < 4; ++q) {
+    const int m = m0 + ty + 8 * q, n = n0 + tx;
+    const bool in = (m < Ni && n < Ni);
+    a[q] = in ? A[(long long)m * Ni + n] : 0.f;
+    o[q] = in ? opd[(long long)m * Ni + n] : 0.f;
+  }
+  for (int l = 0; l < L; ++l) {
+    const double inv = 1.0 / wl[l].lam;
+    for (int q = 0; q < 4; ++q) {
+      const double t = (double)o[q] * inv;   // cycles
+      const double fr = t - rint(t);
+      double sn, cs;
+      sincospi(2.0 * fr, &sn, &cs);
+      const double amp = (double)a[q] * nrm;
+      tr[ty + 8 * q][tx] = (float)(amp * cs);
+      ti[ty + 8 * q][tx] = (float)(amp * sn);
+    }
+    __syncthreads();
+    for (int q = 0; q < 4; ++q) {
+      const int n = n0 + ty + 8 * q, m = m0 + tx;  // output row n, column m
+      if (n < Ni && m < ldp) {
+        const bool in = m < Ni;
+        P0T[l * by_wl + (long long)n * ldp + m] = in ? tr[tx][ty + 8 * q] : 0.f;
+        P0T[l * by_wl + plane + (long long)n * ldp + m] = in ? ti[tx][ty + 8 * q] : 0.f;
+      }
+    }
+    __syncthreads();
+  }
+}
+
+// Tilt vectors of all PSFs, psf = (f S + s) L + l, one thread per (psf, n).
+__global__ void tilt_kernel(const float* sources, const WlInfo* wl, const double* x, int S, int L, int Ni, int ldt,
+                            long long count, float* tx, float* ty, long long plane) {
+  const long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= count * ldt) return;
+  const int gb = (int)(t / ldt);
+  const int n = (int)(t - (long long)gb * ldt);
+  const int l = gb % L;
+  const int fs = gb / L;  // f * S + s
+  const double alpha = sources[fs * 3 + 0], beta = sources[fs * 3 + 1];
+  float xr = 0.f, xi = 0.f, yr = 0.f, yi = 0.f;
+  if (n < Ni) {
+    const double inv = 1.0 / wl[l].lam;
+    double sn, cs;
+    double t = x[n] * alpha * inv;
+    t -= rint(t);
+    sincospi(2.0 * t, &sn, &cs);
+    xr = (float)cs;
+    xi = (float)sn;
+    t = x[n] * beta * inv;
+    t -= rint(t);
+    sincospi(2.0 * t, &sn, &cs);
+    yr = (float)cs;
+    yi = (float)sn;
+  }
+  const long long o = (long long)gb * ldt + n;
+  tx[o] = xr;
+  tx[plane + o] = xi;
+  ty[o] = yr;
+  ty[plane + o] = yi;
+}
+
+}  // namespace
+
+hipError_t launch_dft(dlx_plan* p, hipStream_t st) {
+  const dim3 blk(64, 4);
+  const int nmax = p->ldNi > p->Ni ? p->ldNi : p->Ni;
+  const int kmax = p->ldNo > p->No ? p->ldNo : p->No;
+  const dim3 grid((nmax + 63) / 64, (kmax + 3) / 4, p->L);
+  const long long mn_plane = (long long)p->L * p->No * p->ldNi;
+  const long long mt_plane = (long long)p->L * p->Ni * p->ldNo;
+  const double s4 = p->dx * p->du / 4.0;
+  hipLaunchKernelGGL(dft_matrix_kernel, grid, blk, 0, st, p->d_MN, p->d_MT, p->Ni, p->No, p->ldNi, p->ldNo, s4,
+                     p->d_wl, mn_plane, (long long)p->No * p->ldNi, mt_plane, (long long)p->Ni * p->ldNo);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(coords_kernel, dim3((p->Ni + 255) / 256), dim3(256), 0, st, p->d_x, p->Ni, p->dx);
+  return hipGetLastError();
+}
+
+hipError_t launch_prep(dlx_plan* p, const float* A, const float* Z, const float* Bm, const float* c, const float* C,
+                       const float* sources, hipStream_t st) {
+  const long long npix = (long long)p->Ni * p->Ni;
+  hipLaunchKernelGGL(norm_kernel, dim3(1), dim3(1024), 0, st, A, npix, p->d_norm);
+  if (p->Nmap > 0) {
+    hipLaunchKernelGGL(map_tmp_kernel, dim3((p->Ni + 255) / 256, p->Nmap), dim3(256), 0, st, C, Bm, p->d_maptmp,
+                       p->Nmap, p->Ni);
+  }
+  hipLaunchKernelGGL(opd_kernel, dim3((unsigned)((npix + 255) / 256)), dim3(256), 0, st, Z, c, p->Nz, npix, p->Ni,
+                     Bm, p->d_maptmp, p->Nmap, p->d_opd);
+  const long long p0_by_wl = 2LL * p->Ni * p->ldNi;
+  hipLaunchKernelGGL(pupil_kernel, dim3((p->ldNi + 31) / 32, (p->Ni + 31) / 32), dim3(32, 8), 0, st, A, p->d_opd,
+                     p->d_norm, p->d_wl, p->L, p->Ni, p->ldNi, p->d_P0T, (long long)p->Ni * p->ldNi, p0_by_wl);
+  const long long tplane = (long long)p->n_psf * p->ldNi;
+  const long long nt = (long long)p->n_psf * p->ldNi;
+  hipLaunchKernelGGL(tilt_kernel, dim3((unsigned)((nt + 255) / 256)), dim3(256), 0, st, sources, p->d_wl, p->d_x,
+                     p->S, p->L, p->Ni, p->ldNi, (long long)p->n_psf, p->d_tx, p->d_ty, tplane);
+  return hipGetLastError();
+}
+
+}  // namespace dlx

@@ -1,0 +1,188 @@
+"""Torch-facing wrapper of libdlx: device buffers, streams and autograd.
+
+PyTorch supplies device memory and the current HIP stream; every step of
+the model, loss and gradient runs in the library's kernels. The wrapper
+only checks tensor dtypes/shapes and passes pointers (argument marshalling).
+"""
+from __future__ import annotations
+
+from dataclasses import dataclass
+
+import torch
+
+from . import dlx as _c
+
+
+@dataclass
+class Geometry:
+    """Sizes and optics of one problem (the fields of dlx_problem_desc)."""
+    n_pupil: int
+    n_focal: int
+    oversample: int
+    wavelengths: tuple
+    weights: tuple
+    n_sources: int
+    n_frames: int
+    n_zernike: int
+    n_map: int
+    diameter: float
+    focal_pixel: float
+
+    @property
+    def n_det(self) -> int:
+        return self.n_focal // self.oversample
+
+
+def _f32(t: torch.Tensor, shape, name: str) -> torch.Tensor:
+    if not isinstance(t, torch.Tensor):
+        raise TypeError(f"{name} must be a torch tensor")
+    if t.dtype != torch.float32 or not t.is_cuda:
+        raise TypeError(f"{name} must be a float32 CUDA tensor")
+    if tuple(t.shape) != tuple(shape):
+        raise ValueError(f"{name} has shape {tuple(t.shape)}, expected {tuple(shape)}")
+    return t.contiguous()
+
+
+def _ptr(t):
+    return 0 if t is None else t.data_ptr()
+
+
+def _stream(device) -> int:
+    return torch.cuda.current_stream(device).cuda_stream
+
+
+class PsfPlan:
+    """A libdlx plan plus the static inputs of one problem.
+
+    Static inputs (transmission, Zernike basis, bicubic matrix, intra-pixel
+    kernel) are bound once; parameters are passed per call.
+    """
+
+    def __init__(self, geom: Geometry, transmission, zbasis, map_basis=None, intrapixel=None,
+                 precision: str = "fp32", workspace_limit: int = 0, device="cuda"):
+        if not torch.cuda.is_available():
+            raise RuntimeError("libdlx needs a ROCm GPU")
+        self.geom = geom
+        self.device = torch.device(device)
+        g = geom
+        self.transmission = _f32(transmission, (g.n_pupil, g.n_pupil), "transmission")
+        self.zbasis = _f32(zbasis, (g.n_zernike, g.n_pupil, g.n_pupil), "zernike_basis") if g.n_zernike else None
+        self.map_basis = _f32(map_basis, (g.n_pupil, g.n_map), "map_basis") if g.n_map else None
+        Q = g.oversample
+        self.intrapixel = None if intrapixel is None else _f32(intrapixel, (Q, Q), "intrapixel")
+        desc, self._keep = _c.make_desc(g.n_pupil, g.n_focal, g.oversample, g.wavelengths, g.weights, g.n_sources,
+                                        g.n_frames, g.n_zernike, g.n_map, g.diameter, g.focal_pixel)
+        prec = {"fp32": _c.DLX_FP32, "bf16x3": _c.DLX_BF16X3}[precision]
+        with torch.cuda.device(self.device):
+            self.plan = _c.dlx_plan_create(desc, 1, prec, 0, int(workspace_limit))
+        self.precision = precision
+
+    # ------------------------------------------------------------------ lifetime
+    def close(self):
+        if getattr(self, "plan", None):
+            _c.dlx_plan_destroy(self.plan)
+            self.plan = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    @property
+    def workspace_bytes(self) -> int:
+        return _c.dlx_plan_workspace_bytes(self.plan)
+
+    def sync(self) -> int:
+        return _c.dlx_plan_sync(self.plan, _stream(self.device))
+
+    # ------------------------------------------------------------------ calls
+    def _params(self, coeffs, phase_map, sources, flat):
+        g = self.geom
+        c = _f32(coeffs, (g.n_zernike,), "zernike_coeffs") if g.n_zernike else None
+        pm = _f32(phase_map, (g.n_map, g.n_map), "phase_map") if g.n_map else None
+        s = _f32(sources, (g.n_frames, g.n_sources, 3), "sources")
+        fl = _f32(flat, (g.n_det, g.n_det), "flat")
+        return c, pm, s, fl
+
+    def forward(self, coeffs, phase_map, sources, flat, binned=None, model=None):
+        """dlx_psf_forward: returns (binned B_f, model m_f), each [F, Nd, Nd] float32."""
+        g = self.geom
+        c, pm, s, fl = self._params(coeffs, phase_map, sources, flat)
+        shp = (g.n_frames, g.n_det, g.n_det)
+        binned = torch.empty(shp, dtype=torch.float32, device=self.device) if binned is None else _f32(binned, shp, "binned")
+        model = torch.empty(shp, dtype=torch.float32, device=self.device) if model is None else _f32(model, shp, "model")
+        _c.dlx_psf_forward(self.plan, _ptr(self.transmission), _ptr(self.zbasis), _ptr(self.map_basis), _ptr(c),
+                           _ptr(pm), _ptr(s), _ptr(fl), _ptr(self.intrapixel), _ptr(binned), _ptr(model),
+                           _stream(self.device))
+        return binned, model
+
+    def loss_grad(self, model, binned, data, flat, kind: str = "poisson", prior_mu: float = 1.0,
+                  prior_sigma: float = 0.1, out=None):
+        """dlx_loss_grad: returns (loss double[1], r float32 [F,Nd,Nd], grad_flat double [Nd,Nd])."""
+        g = self.geom
+        shp = (g.n_frames, g.n_det, g.n_det)
+        m = _f32(model, shp, "model")
+        b = _f32(binned, shp, "binned")
+        d = _f32(data, shp, "data")
+        fl = _f32(flat, (g.n_det, g.n_det), "flat")
+        if out is None:
+            loss = torch.empty(1, dtype=torch.float64, device=self.device)
+            r = torch.empty(shp, dtype=torch.float32, device=self.device)
+            gF = torch.empty((g.n_det, g.n_det), dtype=torch.float64, device=self.device)
+        else:
+            loss, r, gF = out
+        k = {"poisson": _c.DLX_LOSS_POISSON, "chi2": _c.DLX_LOSS_CHI2}[kind]
+        _c.dlx_loss_grad(self.plan, _ptr(m), _ptr(b), _ptr(d), _ptr(fl), k, prior_mu, prior_sigma, _ptr(loss),
+                         _ptr(r), _ptr(gF), _stream(self.device))
+        return loss, r, gF
+
+    def backward(self, coeffs, phase_map, sources, flat, r, out=None):
+        """dlx_psf_backward: returns (grad_zernike [Nz], grad_map [n_map,n_map] or None, grad_sources [F,S,3]), double."""
+        g = self.geom
+        c, pm, s, fl = self._params(coeffs, phase_map, sources, flat)
+        rr = _f32(r, (g.n_frames, g.n_det, g.n_det), "dloss_dmodel")
+        if out is None:
+            gz = torch.empty(max(g.n_zernike, 1), dtype=torch.float64, device=self.device)
+            gm = torch.empty((g.n_map, g.n_map), dtype=torch.float64, device=self.device) if g.n_map else None
+            gs = torch.empty((g.n_frames, g.n_sources, 3), dtype=torch.float64, device=self.device)
+        else:
+            gz, gm, gs = out
+        _c.dlx_psf_backward(self.plan, _ptr(self.transmission), _ptr(self.zbasis), _ptr(self.map_basis), _ptr(c),
+                            _ptr(pm), _ptr(s), _ptr(fl), _ptr(self.intrapixel), _ptr(rr),
+                            _ptr(gz) if g.n_zernike else 0, _ptr(gm), _ptr(gs), _stream(self.device))
+        return (gz[:g.n_zernike], gm, gs)
+
+
+class PsfLoss(torch.autograd.Function):
+    """L(coeffs, phase_map, sources, flat) with the hand-written adjoint of the whole chain.
+
+    Forward: dlx_psf_forward then dlx_loss_grad (which also yields r and
+    dL/dF). Backward: dlx_psf_backward with r; focal fields are recomputed
+    in the library, not stored.
+    """
+
+    @staticmethod
+    def forward(ctx, plan: PsfPlan, data, kind, prior_mu, prior_sigma, coeffs, phase_map, sources, flat):
+        B, m = plan.forward(coeffs, phase_map, sources, flat)
+        loss, r, gF = plan.loss_grad(m, B, data, flat, kind, prior_mu, prior_sigma)
+        ctx.plan = plan
+        ctx.has_map = phase_map is not None
+        ctx.save_for_backward(coeffs, phase_map if phase_map is not None else torch.empty(0, device=coeffs.device),
+                              sources, flat, r, gF)
+        return loss[0]
+
+    @staticmethod
+    def backward(ctx, grad_out):
+        coeffs, pm, sources, flat, r, gF = ctx.saved_tensors
+        plan = ctx.plan
+        gz, gm, gs = plan.backward(coeffs, pm if ctx.has_map else None, sources, flat, r)
+        go = grad_out.to(torch.float64)
+        to = lambda g, like: None if g is None else (g * go).to(like.dtype)
+        return (None, None, None, None, None, to(gz, coeffs), to(gm, pm) if ctx.has_map else None,
+                to(gs, sources), to(gF, flat))
+
+
+def psf_loss(plan: PsfPlan, data, coeffs, phase_map, sources, flat, kind="poisson", prior_mu=1.0, prior_sigma=0.1):
+    """Differentiable loss of the forward model (torch autograd entry point)."""
+    return PsfLoss.apply(plan, data, kind, prior_mu, prior_sigma, coeffs, phase_map, sources, flat)

@@ -1,0 +1,97 @@
+"""C-ABI checks that need no GPU: the library loads, exports every declared
+symbol, and rejects bad arguments before touching the device."""
+import os
+import re
+
+import pytest
+
+from paper_2406_08703_amd import dlx
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def header_functions():
+    src = open(os.path.join(ROOT, "include", "dlx.h")).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(dlx_[a-z_]+)\s*\(", src)))
+
+
+def test_header_declares_exactly_the_bound_functions():
+    assert header_functions() == sorted(dlx.EXPORTS)
+
+
+def test_library_loads_and_exports_every_declared_symbol():
+    lib = dlx.lib()
+    for name in header_functions():
+        assert hasattr(lib, name), name
+
+
+def _desc(**kw):
+    base = dict(n_pupil=64, n_focal=64, oversample=2, wavelengths=[600e-9], weights=[1.0], n_sources=1,
+                n_frames=1, n_zernike=10, n_map=0, diameter=0.5, focal_pixel=3e-7)
+    base.update(kw)
+    return dlx.make_desc(base["n_pupil"], base["n_focal"], base["oversample"], base["wavelengths"],
+                         base["weights"], base["n_sources"], base["n_frames"], base["n_zernike"], base["n_map"],
+                         base["diameter"], base["focal_pixel"])
+
+
+def test_status_strings():
+    for s in range(8):
+        assert dlx.dlx_status_string(s).startswith("DLX_")
+    assert "unknown" in dlx.dlx_status_string(99)
+
+
+def test_validate_accepts_a_good_problem():
+    d, keep = _desc()
+    assert dlx.dlx_validate(d) == dlx.DLX_OK
+
+
+@pytest.mark.parametrize("kw,code", [
+    (dict(n_pupil=1), dlx.DLX_ERR_INVALID_ARG),
+    (dict(n_focal=0), dlx.DLX_ERR_INVALID_ARG),
+    (dict(oversample=0), dlx.DLX_ERR_INVALID_ARG),
+    (dict(n_sources=0), dlx.DLX_ERR_INVALID_ARG),
+    (dict(n_frames=0), dlx.DLX_ERR_INVALID_ARG),
+    (dict(n_zernike=-1), dlx.DLX_ERR_INVALID_ARG),
+    (dict(diameter=0.0), dlx.DLX_ERR_INVALID_ARG),
+    (dict(focal_pixel=-1.0), dlx.DLX_ERR_INVALID_ARG),
+    (dict(wavelengths=[-5e-7], weights=[1.0]), dlx.DLX_ERR_INVALID_ARG),
+    (dict(wavelengths=[float("nan")], weights=[1.0]), dlx.DLX_ERR_INVALID_ARG),
+    (dict(n_focal=63, oversample=2), dlx.DLX_ERR_SHAPE),
+    (dict(n_pupil=20000), dlx.DLX_ERR_SHAPE),
+])
+def test_validate_rejects(kw, code):
+    d, keep = _desc(**kw)
+    assert dlx.dlx_validate(d) == code
+    # plan creation fails the same way, synchronously, before any device call
+    with pytest.raises(dlx.DlxError) as e:
+        dlx.dlx_plan_create(d)
+    assert e.value.status == code
+
+
+def test_validate_null_and_count():
+    assert dlx.lib().dlx_validate(None, 1) == dlx.DLX_ERR_INVALID_ARG
+    d, keep = _desc()
+    assert dlx.dlx_validate(d, 0) == dlx.DLX_ERR_INVALID_ARG
+
+
+def test_plan_create_rejects_bad_precision_and_flags():
+    d, keep = _desc()
+    with pytest.raises(dlx.DlxError) as e:
+        dlx.dlx_plan_create(d, precision=7)
+    assert e.value.status == dlx.DLX_ERR_INVALID_ARG
+    with pytest.raises(dlx.DlxError) as e:
+        dlx.dlx_plan_create(d, flags=3)
+    assert e.value.status == dlx.DLX_ERR_INVALID_ARG
+
+
+def test_calls_on_null_plan_are_rejected():
+    assert dlx.lib().dlx_plan_destroy(None) == dlx.DLX_OK
+    assert dlx.dlx_plan_workspace_bytes(0) == 0
+    assert dlx.dlx_plan_sync(0) == dlx.DLX_ERR_INVALID_ARG
+    with pytest.raises(dlx.DlxError):
+        dlx.dlx_psf_forward(0, 1, 1, 0, 1, 0, 1, 1, 0, 1, 1)
+    with pytest.raises(dlx.DlxError):
+        dlx.dlx_loss_grad(0, 1, 1, 1, 1, 0, 1.0, 0.1, 1, 1, 1)
+    with pytest.raises(dlx.DlxError):
+        dlx.dlx_psf_backward(0, 1, 1, 0, 1, 0, 1, 1, 0, 1, 1, 0, 1)
