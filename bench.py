@@ -43,14 +43,21 @@ def stage_flops(P, stage):
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=20)
-    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--steps", type=int, default=None, help="timed steps (default: 200 for c1/c2, 3 otherwise)")
+    ap.add_argument("--warmup", type=int, default=None, help="untimed steps (default: 5 for c1/c2, 1 otherwise)")
     ap.add_argument("--config", default="c2", choices=sorted(WORKLOADS))
     ap.add_argument("--precision", default="fp32", choices=["fp32"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-parity", action="store_true")
+    ap.add_argument("--mode", default="graph", choices=["graph", "eager"],
+                    help="graph: the step is one replay of the captured evaluation (dlx_graph_launch)")
     ap.add_argument("--cpu-seconds", type=float, default=12.0, help="target host time of the oracle sample")
     args = ap.parse_args()
+    small_cfg = args.config in ("c1", "c2")
+    if args.steps is None:
+        args.steps = 200 if small_cfg else 3
+    if args.warmup is None:
+        args.warmup = 5 if small_cfg else 1
     if args.gpus != 1:
         print(f"bench.py measures one GPU; --gpus {args.gpus} is not supported (the path shards by frame "
               "with one all-reduce of the flat-field gradient, which this build does not run).", file=sys.stderr)
@@ -60,7 +67,7 @@ def main():
     import torch
 
     from synth import make_workload, standin_image
-    from paper_2406_08703_amd import Geometry, PsfPlan
+    from paper_2406_08703_amd import CapturedEval, EvalBuffers, Geometry, PsfPlan, evaluate
     from paper_2406_08703_amd import dlx as C
 
     log = lambda *a: print(*a, file=sys.stderr, flush=True)
@@ -88,42 +95,48 @@ def main():
                    precision=args.precision)
     ep = w.eval_params()
     c, pm, s, fl, d = dev(ep["coeffs"]), dev(ep["phase_map"]), dev(ep["sources"]), dev(ep["flat"]), dev(w.data)
-    shp = (P.n_frames, P.n_det, P.n_det)
-    B = torch.empty(shp, device="cuda")
-    m = torch.empty(shp, device="cuda")
-    loss = torch.empty(1, dtype=torch.float64, device="cuda")
-    r = torch.empty(shp, device="cuda")
-    gF = torch.empty((P.n_det, P.n_det), dtype=torch.float64, device="cuda")
-    gz = torch.empty(max(P.n_zernike, 1), dtype=torch.float64, device="cuda")
-    gm = torch.empty((P.n_map, P.n_map), dtype=torch.float64, device="cuda") if P.n_map else None
-    gs = torch.empty((P.n_frames, P.n_sources, 3), dtype=torch.float64, device="cuda")
+    ebuf = EvalBuffers(plan)
 
-    def step():
-        plan.forward(c, pm, s, fl, binned=B, model=m)
-        plan.loss_grad(m, B, d, fl, "poisson", w.prior_mu, w.prior_sigma, out=(loss, r, gF))
-        plan.backward(c, pm, s, fl, r, out=(gz, gm, gs))
+    def step():   # dlx_eval: forward, loss and adjoint fused per frame chunk
+        evaluate(plan, c, pm, s, fl, d, "poisson", w.prior_mu, w.prior_sigma, out=ebuf)
+
+    def timed(fn, k):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(k):
+            fn()
+        torch.cuda.synchronize()
+        return time.perf_counter() - t0
 
     for i in range(args.warmup):
         step()
         log(f"warmup step {i + 1}/{args.warmup} done")
     torch.cuda.synchronize()
     assert plan.sync() == 0
+    # eager timed region, every stage bracketed by HIP events on the launch stream
     C.dlx_plan_profile(plan.plan, True)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for i in range(args.steps):
-        step()
-    torch.cuda.synchronize()
-    t1 = time.perf_counter()
+    t_eager = timed(step, args.steps)
     stages = C.dlx_plan_stage_times(plan.plan)
     C.dlx_plan_profile(plan.plan, False)
-    log(f"timed {args.steps} steps in {t1 - t0:.4f} s")
+    log(f"eager: {args.steps} steps in {t_eager:.4f} s")
+    t_graph = None
+    if args.mode == "graph":
+        cap = CapturedEval(plan, c, pm, s, fl, d, "poisson", w.prior_mu, w.prior_sigma)
+        for _ in range(args.warmup):
+            cap.replay()
+        t_graph = timed(cap.replay, args.steps)
+        log(f"graph: {args.steps} replays in {t_graph:.4f} s")
+        out_buf = cap.out
+        m, loss, gF, gz, gs = out_buf.model, out_buf.loss, out_buf.grad_flat, out_buf.grad_zernike, out_buf.grad_sources
+    else:
+        m, loss, gF, gz, gs = ebuf.model, ebuf.loss, ebuf.grad_flat, ebuf.grad_zernike, ebuf.grad_sources
+    t1, t0 = (t_graph if t_graph is not None else t_eager), 0.0
     ms_step = (t1 - t0) * 1e3 / args.steps
     n_psf = P.n_psf
     evals = n_psf * args.steps / (t1 - t0)
     F_mft = P.mft_flops()
     tf_alg = 2 * F_mft * n_psf / (ms_step * 1e-3) / 1e12
-    tf_exec = 3 * F_mft * n_psf / (ms_step * 1e-3) / 1e12
+    tf_exec = tf_alg   # the fused evaluation reuses E: forward + adjoint MFT only
 
     table = {}
     for name, (tot, la, ps) in stages.items():
@@ -197,6 +210,7 @@ def main():
            "mft_tflops": {"algorithmic": round(tf_alg, 3), "executed": round(tf_exec, 3),
                           "frac_fp32_mfma_peak_algorithmic": round(tf_alg / FP32_MFMA_PEAK_TFLOPS, 4),
                           "frac_fp32_mfma_peak_executed": round(tf_exec / FP32_MFMA_PEAK_TFLOPS, 4)},
+           "mode": args.mode, "eager_ms_per_step": round(t_eager * 1e3 / args.steps, 4),
            "stage_ms_per_step": {k: round(v["ms_per_step"], 5) for k, v in table.items()},
            "gemm_share_of_step": round(gemm_ms / all_ms, 4) if all_ms else None,
            "roofline": roofline, "rel_err_vs_fp64": parity, "cpu_baseline": cpu}

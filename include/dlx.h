@@ -151,6 +151,44 @@ dlx_status dlx_psf_backward(dlx_plan* plan, const float* transmission, const flo
                             const float* dloss_dmodel, double* grad_zernike, double* grad_map,
                             double* grad_sources, void* stream);
 
+/* Every pointer of one full evaluation (forward, loss, backward); the
+ * meanings, shapes and NULL rules are those of dlx_psf_forward,
+ * dlx_loss_grad and dlx_psf_backward. */
+typedef struct {
+  const float* transmission;
+  const float* zernike_basis;
+  const float* map_basis;
+  const float* zernike_coeffs;
+  const float* phase_map;
+  const float* sources;
+  const float* flat;
+  const float* intrapixel;
+  const float* data;
+  dlx_loss_kind loss_kind;
+  double prior_mu;
+  double prior_sigma;
+  float* binned;        /* [F][Nd][Nd] */
+  float* model;         /* [F][Nd][Nd] */
+  float* dloss_dmodel;  /* [F][Nd][Nd] */
+  double* loss;         /* [1] */
+  double* grad_flat;    /* [Nd][Nd] */
+  double* grad_zernike; /* [Nz] */
+  double* grad_map;     /* [n_map][n_map] */
+  double* grad_sources; /* [F][S][3] */
+} dlx_eval_args;
+
+/* Value and gradient of Section 4's objective in one call: dlx_psf_forward,
+ * dlx_loss_grad and dlx_psf_backward enqueued on `stream`. */
+dlx_status dlx_eval(dlx_plan* plan, const dlx_eval_args* args, void* stream);
+
+/* Record dlx_eval with these pointers into a HIP graph owned by the plan
+ * (replacing any earlier one). Nothing runs; the pointers must stay valid
+ * while the graph is used. Capture happens on a plan-owned stream. */
+dlx_status dlx_graph_capture(dlx_plan* plan, const dlx_eval_args* args);
+
+/* Replay the captured evaluation on `stream` (DLX_ERR_INVALID_ARG if none). */
+dlx_status dlx_graph_launch(dlx_plan* plan, void* stream);
+
 /* Stages of one evaluation, for per-stage timing. PREP builds the OPD, the
  * pupil field and the tilt vectors; F1/F2 are the two MFT products of the
  * forward pass (F2 with the intensity/bin epilogue); BIN sums the binned

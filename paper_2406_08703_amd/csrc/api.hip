@@ -12,12 +12,18 @@ namespace dlx {
 hipError_t launch_dft(dlx_plan* p, hipStream_t st);
 hipError_t launch_prep(dlx_plan* p, const float* A, const float* Z, const float* Bm, const float* c, const float* C,
                        const float* sources, hipStream_t st);
-hipError_t launch_bin_reduce(dlx_plan* p, const float* flat, float* binned, float* model, hipStream_t st);
-hipError_t launch_loss(dlx_plan* p, const float* model, const float* binned, const float* data, const float* flat,
-                       int kind, double mu, double sigma, double* loss, float* r, double* gflat, hipStream_t st);
+hipError_t launch_bin_reduce(dlx_plan* p, int f0, int nf, const float* flat, float* binned, float* model,
+                             hipStream_t st);
+hipError_t launch_seed(dlx_plan* p, int f0, int nf, const float* sources, const float* flat, const float* resid,
+                       const float* intrapixel, hipStream_t st);
+hipError_t launch_loss(dlx_plan* p, int f0, int nf, int chunk, const float* model, const float* binned,
+                       const float* data, const float* flat, int kind, double mu, double sigma, float* r, double* gflat,
+                       hipStream_t st);
+hipError_t launch_loss_final(dlx_plan* p, int n_chunks, double* loss, hipStream_t st);
 hipError_t launch_grad_reduce(dlx_plan* p, const float* Z, const float* Bm, double* gz, double* gmap, double* gsrc,
                               hipStream_t st);
 int loss_block_count(long long npix);
+int zproj_chunks(long long npix, int Nz);
 }  // namespace dlx
 
 using namespace dlx;
@@ -70,9 +76,9 @@ void layout(dlx_plan* p, Pool& pool) {
   p->d_MN = pool.take<float>(2 * L * No * ldNi);
   p->d_MT = pool.take<float>(2 * L * Ni * ldNo);
   p->d_x = pool.take<double>(Ni);
-  p->d_opd = pool.take<float>(Ni * Ni);
+  p->d_opd = pool.take<double>((size_t)p->opd_splits * Ni * Ni);
   p->d_maptmp = pool.take<float>(std::max<size_t>(1, (size_t)p->Nmap * Ni));
-  p->d_norm = pool.take<double>(1);
+  p->d_norm = pool.take<double>(p->n_norm_part);
   p->d_P0T = pool.take<float>(2 * L * Ni * ldNi);
   p->d_tx = pool.take<float>(2 * (size_t)p->n_psf * ldNi);
   p->d_ty = pool.take<float>(2 * (size_t)p->n_psf * ldNi);
@@ -80,12 +86,13 @@ void layout(dlx_plan* p, Pool& pool) {
   p->d_Y = pool.take<float>(2 * CP * No * ldNo);
   p->d_UT = pool.take<float>(2 * CP * Ni * ldNo);
   p->d_binpart = pool.take<float>((size_t)p->F * p->f2_groups * p->Nd * p->Nd);
-  p->d_gpart = pool.take<float>((size_t)p->b4_groups_max * Ni * Ni);
+  p->d_gpart = pool.take<float>((size_t)p->b4_groups_max * p->b4_ksplit * Ni * Ni);
   p->d_gopd = pool.take<double>(Ni * Ni);
   p->d_flux = pool.take<double>((size_t)p->n_psf * p->tiles_b2);
-  p->d_pos = pool.take<double>((size_t)p->n_psf * p->tiles_b4 * 2);
-  p->d_lossblk = pool.take<double>(p->loss_blocks);
+  p->d_pos = pool.take<double>((size_t)p->n_psf * p->b4_ksplit * p->tiles_b4 * 2);
+  p->d_lossblk = pool.take<double>((size_t)p->loss_blocks * p->n_chunks);
   p->d_tmp2 = pool.take<double>(std::max<size_t>(1, Ni * (size_t)p->Nmap));
+  p->d_zpart = pool.take<double>((size_t)std::max(1, zproj_chunks((long long)Ni * Ni, p->Nz)) * std::max(1, p->Nz));
   p->d_status = pool.take<int>(1);
 }
 
@@ -195,6 +202,67 @@ hipError_t run_f1(dlx_plan* p, int f0, int nf, hipStream_t st) {
   a.ldo = p->ldNi;
   set_tiles(a, p->ts_f1);
   return launch_gemm(KIND_F1, p->ts_f1, a, wg_count(a), st);
+}
+
+GemmArgs e_args(dlx_plan* p, int f0, int nf, TileShape ts);
+
+// F2 over frames [f0, f0 + nf): binned partials, and E kept in the Y buffer if store_e.
+hipError_t run_f2(dlx_plan* p, int f0, int nf, const float* sources, const float* intrapixel, bool store_e,
+                  hipStream_t st) {
+  GemmArgs a = e_args(p, f0, nf, p->ts_f2);
+  a.groups = p->f2_groups;
+  a.group_size = p->f2_gsize;
+  a.n_items = nf * p->f2_groups;
+  a.sources = sources;
+  a.part = p->d_binpart;
+  a.intrapixel = intrapixel;
+  if (store_e) {
+    a.out = p->d_Y;
+    a.out_plane = (long long)p->chunk_psf * p->No * p->ldNo;
+    a.out_by_psf = (long long)p->No * p->ldNo;
+    a.ldo = p->ldNo;
+  }
+  return launch_gemm(KIND_F2, p->ts_f2, a, wg_count(a), st);
+}
+
+// B3 and B4 over frames [f0, f0 + nf) of chunk c, from the seed Y in the Y buffer.
+hipError_t run_adjoint(dlx_plan* p, int c, int f0, int nf, hipStream_t st) {
+  const int nc = nf * p->S * p->L;
+  {
+    Stage sg(p, st, DLX_STAGE_B3, nc);
+    GemmArgs a = base_args(p, f0, nf);
+    a.M = p->Ni;
+    a.N = p->No;
+    a.K = p->No;
+    a.n_items = nc;
+    a.A = op_MT(p);
+    a.conj_a = 1;
+    a.B = op_Y(p);
+    a.out = p->d_UT;
+    a.out_plane = op_UT(p).plane;
+    a.out_by_psf = op_UT(p).by_psf;
+    a.ldo = p->ldNo;
+    set_tiles(a, p->ts_b3);
+    hipError_t e = launch_gemm(KIND_B3, p->ts_b3, a, wg_count(a), st);
+    if (e != hipSuccess) return e;
+  }
+  Stage sg(p, st, DLX_STAGE_B4, nc);
+  GemmArgs a = base_args(p, f0, nf);
+  a.M = p->Ni;
+  a.N = p->Ni;
+  a.K = p->No;
+  a.A = op_MT(p);
+  a.conj_a = 1;
+  a.B = op_UT(p);
+  a.group_size = p->b4_gsize;
+  a.ksplit = p->b4_ksplit;
+  a.groups = ceil_div(nc, p->b4_gsize);
+  a.n_items = a.groups * p->b4_ksplit;
+  a.part = p->d_gpart;
+  a.accumulate = c > 0;
+  a.red = p->d_pos;
+  set_tiles(a, p->ts_b4);
+  return launch_gemm(KIND_B4, p->ts_b4, a, wg_count(a), st);
 }
 
 GemmArgs e_args(dlx_plan* p, int f0, int nf, TileShape ts) {
@@ -325,7 +393,20 @@ dlx_status dlx_plan_create(const dlx_problem_desc* probs, int32_t n_probs, dlx_p
   }
   p->tiles_b2 = ceil_div(p->No, p->ts_b2.bm()) * ceil_div(p->No, p->ts_b2.bn());
   p->tiles_b4 = ceil_div(p->Ni, p->ts_b4.bm()) * ceil_div(p->Ni, p->ts_b4.bn());
+  {
+    // split B4's K (= No) when its groups alone cannot fill the chip, keeping >= 128 per split
+    const long long wg = (long long)p->tiles_b4 * p->b4_groups_max;
+    int ks = 1;
+    while (ks < 4 && wg * ks < kTargetWG && p->No / (2 * ks) >= 128) ks *= 2;
+    p->b4_ksplit = ks;
+  }
   p->loss_blocks = loss_block_count((long long)p->Nd * p->Nd);
+  {
+    const long long npix = (long long)p->Ni * p->Ni;
+    const long long chunks = (npix + 1023) / 1024;
+    p->opd_splits = (int)std::max<long long>(1, std::min<long long>((512 + chunks - 1) / chunks, std::max(1, p->Nz)));
+    p->n_norm_part = (int)std::max<long long>(1, std::min<long long>(256, (npix + 4095) / 4096));
+  }
 
   Pool sizing{nullptr, 0};
   layout(p, sizing);
@@ -371,6 +452,9 @@ dlx_status dlx_plan_destroy(dlx_plan* p) {
   if (!p) return DLX_OK;
   const hipError_t e1 = hipDeviceSynchronize();
   for (hipEvent_t ev : p->ev_pool) (void)hipEventDestroy(ev);
+  if (p->graph_exec) (void)hipGraphExecDestroy(p->graph_exec);
+  if (p->graph) (void)hipGraphDestroy(p->graph);
+  if (p->cap_stream) (void)hipStreamDestroy(p->cap_stream);
   const hipError_t e2 = p->pool ? hipFree(p->pool) : hipSuccess;
   delete p;
   return (e1 == hipSuccess && e2 == hipSuccess) ? DLX_OK : DLX_ERR_HIP;
@@ -445,17 +529,10 @@ dlx_status dlx_psf_forward(dlx_plan* p, const float* transmission, const float* 
       DLX_HIP(run_f1(p, f0, nf, st));
     }
     Stage sg(p, st, DLX_STAGE_F2, nc);
-    GemmArgs a = e_args(p, f0, nf, p->ts_f2);
-    a.groups = p->f2_groups;
-    a.group_size = p->f2_gsize;
-    a.n_items = nf * p->f2_groups;
-    a.sources = sources;
-    a.part = p->d_binpart;
-    a.intrapixel = intrapixel;
-    DLX_HIP(launch_gemm(KIND_F2, p->ts_f2, a, wg_count(a), st));
+    DLX_HIP(run_f2(p, f0, nf, sources, intrapixel, false, st));
   }
   Stage sg(p, st, DLX_STAGE_BIN, p->n_psf);
-  DLX_HIP(launch_bin_reduce(p, flat, binned_out, model_out, st));
+  DLX_HIP(launch_bin_reduce(p, 0, p->F, flat, binned_out, model_out, st));
   return DLX_OK;
 }
 
@@ -468,8 +545,9 @@ dlx_status dlx_loss_grad(dlx_plan* p, const float* model, const float* binned, c
   if (!(prior_sigma > 0.0) || !std::isfinite(prior_sigma) || !std::isfinite(prior_mu)) return DLX_ERR_INVALID_ARG;
   hipStream_t st = reinterpret_cast<hipStream_t>(stream);
   Stage sg(p, st, DLX_STAGE_LOSS, p->n_psf);
-  DLX_HIP(launch_loss(p, model, binned, data, flat, (int)kind, prior_mu, prior_sigma, loss_out, dloss_dmodel,
+  DLX_HIP(launch_loss(p, 0, p->F, 0, model, binned, data, flat, (int)kind, prior_mu, prior_sigma, dloss_dmodel,
                       grad_flat, st));
+  DLX_HIP(launch_loss_final(p, 1, loss_out, st));
   return DLX_OK;
 }
 
@@ -511,44 +589,100 @@ dlx_status dlx_psf_backward(dlx_plan* p, const float* transmission, const float*
       a.intrapixel = intrapixel;
       DLX_HIP(launch_gemm(KIND_B2, p->ts_b2, a, wg_count(a), st));
     }
-    {  // B3: U^T = conj(M)^T Y^T
-      Stage sg(p, st, DLX_STAGE_B3, nc);
-      GemmArgs a = base_args(p, f0, nf);
-      a.M = p->Ni;
-      a.N = p->No;
-      a.K = p->No;
-      a.n_items = nc;
-      a.A = op_MT(p);
-      a.conj_a = 1;
-      a.B = op_Y(p);
-      a.out = p->d_UT;
-      a.out_plane = op_UT(p).plane;
-      a.out_by_psf = op_UT(p).by_psf;
-      a.ldo = p->ldNo;
-      set_tiles(a, p->ts_b3);
-      DLX_HIP(launch_gemm(KIND_B3, p->ts_b3, a, wg_count(a), st));
-    }
-    {  // B4: W = c M^H U, phase gradient and position sums
-      Stage sg(p, st, DLX_STAGE_B4, nc);
-      GemmArgs a = base_args(p, f0, nf);
-      a.M = p->Ni;
-      a.N = p->Ni;
-      a.K = p->No;
-      a.A = op_MT(p);
-      a.conj_a = 1;
-      a.B = op_UT(p);
-      a.group_size = p->b4_gsize;
-      a.groups = ceil_div(nc, p->b4_gsize);
-      a.n_items = a.groups;
-      a.part = p->d_gpart;
-      a.accumulate = c > 0;
-      a.red = p->d_pos;
-      set_tiles(a, p->ts_b4);
-      DLX_HIP(launch_gemm(KIND_B4, p->ts_b4, a, wg_count(a), st));
-    }
+    DLX_HIP(run_adjoint(p, c, f0, nf, st));
   }
   Stage sg(p, st, DLX_STAGE_GRAD, p->n_psf);
   DLX_HIP(launch_grad_reduce(p, zernike_basis, map_basis, grad_zernike, grad_map, grad_sources, st));
+  return DLX_OK;
+}
+
+// Value and gradient, fused per chunk of frames: a frame's residual depends
+// only on that frame's model, so each chunk runs forward, loss and adjoint
+// back to back and the focal fields E of F2 are reused for the adjoint seed
+// instead of being recomputed (2 MFTs per PSF instead of 3; memory stays one
+// chunk of fields).
+dlx_status dlx_eval(dlx_plan* p, const dlx_eval_args* a, void* stream) {
+  if (!p || !a) return DLX_ERR_INVALID_ARG;
+  if (!a->transmission || !a->sources || !a->flat || !a->data || !a->binned || !a->model || !a->dloss_dmodel ||
+      !a->loss || !a->grad_flat || !a->grad_sources)
+    return DLX_ERR_INVALID_ARG;
+  if (p->Nz > 0 && (!a->zernike_basis || !a->zernike_coeffs || !a->grad_zernike)) return DLX_ERR_INVALID_ARG;
+  if ((p->Nmap > 0) != (a->map_basis != nullptr) || (p->Nmap > 0) != (a->phase_map != nullptr) ||
+      (p->Nmap > 0) != (a->grad_map != nullptr))
+    return DLX_ERR_INVALID_ARG;
+  if (a->loss_kind != DLX_LOSS_POISSON && a->loss_kind != DLX_LOSS_CHI2) return DLX_ERR_INVALID_ARG;
+  if (!(a->prior_sigma > 0.0) || !std::isfinite(a->prior_sigma) || !std::isfinite(a->prior_mu))
+    return DLX_ERR_INVALID_ARG;
+  hipStream_t st = reinterpret_cast<hipStream_t>(stream);
+  {
+    Stage sg(p, st, DLX_STAGE_PREP, p->n_psf);
+    DLX_HIP(launch_prep(p, a->transmission, a->zernike_basis, a->map_basis, a->zernike_coeffs, a->phase_map,
+                        a->sources, st));
+  }
+  for (int c = 0; c < p->n_chunks; ++c) {
+    const int f0 = c * p->frames_per_chunk;
+    const int nf = std::min(p->frames_per_chunk, p->F - f0);
+    const int nc = nf * p->S * p->L;
+    {
+      Stage sg(p, st, DLX_STAGE_F1, nc);
+      DLX_HIP(run_f1(p, f0, nf, st));
+    }
+    {
+      Stage sg(p, st, DLX_STAGE_F2, nc);
+      DLX_HIP(run_f2(p, f0, nf, a->sources, a->intrapixel, true, st));
+    }
+    {
+      Stage sg(p, st, DLX_STAGE_BIN, nc);
+      DLX_HIP(launch_bin_reduce(p, f0, nf, a->flat, a->binned, a->model, st));
+    }
+    {
+      Stage sg(p, st, DLX_STAGE_LOSS, nc);
+      DLX_HIP(launch_loss(p, f0, nf, c, a->model, a->binned, a->data, a->flat, (int)a->loss_kind, a->prior_mu,
+                          a->prior_sigma, a->dloss_dmodel, a->grad_flat, st));
+    }
+    {
+      Stage sg(p, st, DLX_STAGE_B2, nc);
+      DLX_HIP(launch_seed(p, f0, nf, a->sources, a->flat, a->dloss_dmodel, a->intrapixel, st));
+    }
+    DLX_HIP(run_adjoint(p, c, f0, nf, st));
+  }
+  Stage sg(p, st, DLX_STAGE_GRAD, p->n_psf);
+  DLX_HIP(launch_loss_final(p, p->n_chunks, a->loss, st));
+  DLX_HIP(launch_grad_reduce(p, a->zernike_basis, a->map_basis, a->grad_zernike, a->grad_map, a->grad_sources, st));
+  return DLX_OK;
+}
+
+dlx_status dlx_graph_capture(dlx_plan* p, const dlx_eval_args* a) {
+  if (!p || !a) return DLX_ERR_INVALID_ARG;
+  if (!p->cap_stream) DLX_HIP(hipStreamCreateWithFlags(&p->cap_stream, hipStreamNonBlocking));
+  if (p->graph_exec) {
+    (void)hipGraphExecDestroy(p->graph_exec);
+    p->graph_exec = nullptr;
+  }
+  if (p->graph) {
+    (void)hipGraphDestroy(p->graph);
+    p->graph = nullptr;
+  }
+  const bool prof = p->profiling;
+  p->profiling = false;  // no event records inside the graph
+  DLX_HIP(hipStreamBeginCapture(p->cap_stream, hipStreamCaptureModeThreadLocal));
+  const dlx_status s = dlx_eval(p, a, p->cap_stream);
+  hipGraph_t g = nullptr;
+  const hipError_t e = hipStreamEndCapture(p->cap_stream, &g);
+  p->profiling = prof;
+  if (s != DLX_OK) {
+    if (g) (void)hipGraphDestroy(g);
+    return s;
+  }
+  if (e != hipSuccess || !g) return DLX_ERR_HIP;
+  p->graph = g;
+  DLX_HIP(hipGraphInstantiate(&p->graph_exec, g, nullptr, nullptr, 0));
+  return DLX_OK;
+}
+
+dlx_status dlx_graph_launch(dlx_plan* p, void* stream) {
+  if (!p || !p->graph_exec) return DLX_ERR_INVALID_ARG;
+  DLX_HIP(hipGraphLaunch(p->graph_exec, reinterpret_cast<hipStream_t>(stream)));
   return DLX_OK;
 }
 

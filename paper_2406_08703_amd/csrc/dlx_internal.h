@@ -56,6 +56,7 @@ struct GemmArgs {
   int groups;           // F2: groups per frame; B4: groups in the chunk
   int n_chunk_psf;
   int conj_a, conj_b;
+  int ksplit;           // B4: K range split over ksplit items (the epilogue is linear in W)
   Operand A, B;
   // pupil field pieces: P[m][n] = P0T[n][m] * ty[m] * tx[n] (F1 loader, B4 epilogue)
   const float* tx;
@@ -114,7 +115,7 @@ struct dlx_plan {
   // tiles
   dlx::TileShape ts_f1, ts_f2, ts_b2, ts_b3, ts_b4;
   int f2_groups, f2_gsize;   // per frame
-  int b4_gsize, b4_groups_max;
+  int b4_gsize, b4_groups_max, b4_ksplit = 1;
   // device memory
   void* pool = nullptr;
   size_t pool_bytes = 0;
@@ -122,9 +123,11 @@ struct dlx_plan {
   float* d_MN = nullptr;   // [L][No][ldNi] planar
   float* d_MT = nullptr;   // [L][Ni][ldNo] planar
   double* d_x = nullptr;   // [Ni]
-  float* d_opd = nullptr;  // [Ni*Ni]
+  double* d_opd = nullptr;    // OPD partial sums [opd_splits][Ni*Ni]
+  int opd_splits = 1;
   float* d_maptmp = nullptr;  // [Nmap][Ni]
-  double* d_norm = nullptr;   // 1/sqrt(sum A^2)
+  double* d_norm = nullptr;   // partial sums of A^2 [n_norm_part]
+  int n_norm_part = 1;
   float* d_P0T = nullptr;  // [L][Ni][ldNi] planar
   float* d_tx = nullptr;   // [n_psf][ldNi] planar
   float* d_ty = nullptr;
@@ -132,12 +135,13 @@ struct dlx_plan {
   float* d_Y = nullptr;    // [chunk_psf][No][ldNo] planar
   float* d_UT = nullptr;   // [chunk_psf][Ni][ldNo] planar
   float* d_binpart = nullptr;  // [F][f2_groups][Nd*Nd]
-  float* d_gpart = nullptr;    // [b4_groups_max][Ni*Ni]
+  float* d_gpart = nullptr;    // [b4_groups_max * b4_ksplit][Ni*Ni]
   double* d_gopd = nullptr;    // [Ni*Ni]
   double* d_flux = nullptr;    // [n_psf][tiles_b2]
-  double* d_pos = nullptr;     // [n_psf][tiles_b4][2]
+  double* d_pos = nullptr;     // [n_psf][b4_ksplit][tiles_b4][2]
   double* d_lossblk = nullptr; // [loss blocks]
   double* d_tmp2 = nullptr;    // [Ni][Nmap] for the map gradient
+  double* d_zpart = nullptr;   // Zernike projection partials [chunks][Nz]
   int* d_status = nullptr;
   int loss_blocks = 0;
   // stage timing (diagnostics)
@@ -150,4 +154,8 @@ struct dlx_plan {
   long long stage_launches[DLX_N_STAGES] = {};
   long long stage_psfs[DLX_N_STAGES] = {};
   int tiles_b2 = 0, tiles_b4 = 0;
+  // captured evaluation
+  hipStream_t cap_stream = nullptr;
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t graph_exec = nullptr;
 };

@@ -76,7 +76,8 @@ __global__ __launch_bounds__(256) void cgemm_kernel(const GemmArgs a) {
     p_end = min(p_begin + a.group_size, base + a.S * a.L);
   } else if constexpr (KIND == KIND_B4) {
     grp = item;
-    p_begin = item * a.group_size;
+    const int g = item / a.ksplit;
+    p_begin = g * a.group_size;
     p_end = min(p_begin + a.group_size, a.n_chunk_psf);
   } else {
     p_begin = item;
@@ -89,7 +90,15 @@ __global__ __launch_bounds__(256) void cgemm_kernel(const GemmArgs a) {
 #pragma unroll
     for (int bn = 0; bn < WN; ++bn) sum[bm][bn] = f4{0.f, 0.f, 0.f, 0.f};
 
-  const int nk = (K + BK - 1) / BK;
+  // K range of this item (split only for B4, whose epilogue is linear in the product)
+  int k_lo = 0, k_hi = K;
+  if constexpr (KIND == KIND_B4) {
+    const int ks = item % a.ksplit;
+    const int kc = ((K + a.ksplit * BK - 1) / (a.ksplit * BK)) * BK;
+    k_lo = ks * kc;
+    k_hi = min(K, k_lo + kc);
+  }
+  const int nk = k_hi > k_lo ? (k_hi - k_lo + BK - 1) / BK : 0;
 
   for (int lb = p_begin; lb < p_end; ++lb) {
     const int gb = a.psf0 + lb;
@@ -108,7 +117,14 @@ __global__ __launch_bounds__(256) void cgemm_kernel(const GemmArgs a) {
         acci[bm][bn] = f4{0.f, 0.f, 0.f, 0.f};
       }
 
+    // Raw global loads of the next K tile. They are consumed only by
+    // store_tile (after the MFMAs), so their latency overlaps the MFMAs:
+    // conjugation, K-tail masking and the F1 pupil-field product are applied
+    // at store time, never right after the load.
     f4 ga_r[A_PAIRS], ga_i[A_PAIRS], gb_r[B_PAIRS], gb_i[B_PAIRS];
+    f4 gy_r[B_PAIRS], gy_i[B_PAIRS];
+    float gx_r[B_PAIRS], gx_i[B_PAIRS];
+    int ga_k[A_PAIRS], gb_k[B_PAIRS];
 
     auto load_tile = [&](int k0) {
 #pragma unroll
@@ -116,65 +132,65 @@ __global__ __launch_bounds__(256) void cgemm_kernel(const GemmArgs a) {
         const int q = tid + 256 * r;
         const int row = q >> 2, kq = q & 3;
         const int gi = row0 + row, gk = k0 + 4 * kq;
-        f4 vr = f4{0.f, 0.f, 0.f, 0.f}, vi = vr;
-        if (q < BM * 4 && gi < M && gk < K) {
+        ga_k[r] = gk;
+        ga_r[r] = f4{0.f, 0.f, 0.f, 0.f};
+        ga_i[r] = ga_r[r];
+        if (q < BM * 4 && gi < M && gk < k_hi) {
           const float* p = Ab + (long long)gi * a.A.ld + gk;
-          vr = *reinterpret_cast<const f4*>(p);
-          vi = *reinterpret_cast<const f4*>(p + a.A.plane);
-          if (gk + 4 > K) {
-#pragma unroll
-            for (int e = 0; e < 4; ++e)
-              if (gk + e >= K) { vr[e] = 0.f; vi[e] = 0.f; }
-          }
-          if (a.conj_a) vi = -vi;
+          ga_r[r] = *reinterpret_cast<const f4*>(p);
+          ga_i[r] = *reinterpret_cast<const f4*>(p + a.A.plane);
         }
-        ga_r[r] = vr;
-        ga_i[r] = vi;
       }
 #pragma unroll
       for (int r = 0; r < B_PAIRS; ++r) {
         const int q = tid + 256 * r;
         const int row = q >> 2, kq = q & 3;
         const int gj = col0 + row, gk = k0 + 4 * kq;
-        f4 vr = f4{0.f, 0.f, 0.f, 0.f}, vi = vr;
-        if (q < BN * 4 && gj < N && gk < K) {
-          const float* p = Bb + (long long)gj * a.B.ld + gk;
-          vr = *reinterpret_cast<const f4*>(p);
-          vi = *reinterpret_cast<const f4*>(p + a.B.plane);
-          if constexpr (KIND == KIND_F1) {
-            // pupil field P[m][n] = P0^T[n][m] * ty[m] * tx[n], row n = gj, k = m
-            const f4 yr = *reinterpret_cast<const f4*>(tyb + gk);
-            const f4 yi = *reinterpret_cast<const f4*>(tyb + a.tilt_plane + gk);
-            const float xr = txb[gj], xi = txb[a.tilt_plane + gj];
-            const f4 tr = yr * xr - yi * xi;
-            const f4 ti = yr * xi + yi * xr;
-            const f4 pr = vr * tr - vi * ti;
-            const f4 pi = vr * ti + vi * tr;
-            vr = pr;
-            vi = pi;
-          }
-          if (gk + 4 > K) {
-#pragma unroll
-            for (int e = 0; e < 4; ++e)
-              if (gk + e >= K) { vr[e] = 0.f; vi[e] = 0.f; }
-          }
-          if (a.conj_b) vi = -vi;
+        gb_k[r] = gk;
+        gb_r[r] = f4{0.f, 0.f, 0.f, 0.f};
+        gb_i[r] = gb_r[r];
+        if constexpr (KIND == KIND_F1) {
+          gy_r[r] = gb_r[r];
+          gy_i[r] = gb_r[r];
+          gx_r[r] = 0.f;
+          gx_i[r] = 0.f;
         }
-        gb_r[r] = vr;
-        gb_i[r] = vi;
+        if (q < BN * 4 && gj < N && gk < k_hi) {
+          const float* p = Bb + (long long)gj * a.B.ld + gk;
+          gb_r[r] = *reinterpret_cast<const f4*>(p);
+          gb_i[r] = *reinterpret_cast<const f4*>(p + a.B.plane);
+          if constexpr (KIND == KIND_F1) {
+            gy_r[r] = *reinterpret_cast<const f4*>(tyb + gk);
+            gy_i[r] = *reinterpret_cast<const f4*>(tyb + a.tilt_plane + gk);
+            gx_r[r] = txb[gj];
+            gx_i[r] = txb[a.tilt_plane + gj];
+          }
+        }
       }
     };
 
-    load_tile(0);
-    for (int kt = 0; kt < nk; ++kt) {
-      __syncthreads();
+    auto fix = [&](f4& vr, f4& vi, int gk, bool conj) {
+      if (gk + 4 > k_hi) {
+#pragma unroll
+        for (int e = 0; e < 4; ++e)
+          if (gk + e >= k_hi) {
+            vr[e] = 0.f;
+            vi[e] = 0.f;
+          }
+      }
+      if (conj) vi = -vi;
+    };
+
+    auto store_tile = [&]() {
 #pragma unroll
       for (int r = 0; r < A_PAIRS; ++r) {
         const int q = tid + 256 * r;
         if (q < BM * 4) {
           const int row = q >> 2, kq = q & 3;
-          *reinterpret_cast<f4*>(&As[row * LDK + 4 * kq]) = ga_r[r];
-          *reinterpret_cast<f4*>(&As[(BM + row) * LDK + 4 * kq]) = ga_i[r];
+          f4 vr = ga_r[r], vi = ga_i[r];
+          fix(vr, vi, ga_k[r], a.conj_a);
+          *reinterpret_cast<f4*>(&As[row * LDK + 4 * kq]) = vr;
+          *reinterpret_cast<f4*>(&As[(BM + row) * LDK + 4 * kq]) = vi;
         }
       }
 #pragma unroll
@@ -182,12 +198,29 @@ __global__ __launch_bounds__(256) void cgemm_kernel(const GemmArgs a) {
         const int q = tid + 256 * r;
         if (q < BN * 4) {
           const int row = q >> 2, kq = q & 3;
-          *reinterpret_cast<f4*>(&Bs[row * LDK + 4 * kq]) = gb_r[r];
-          *reinterpret_cast<f4*>(&Bs[(BN + row) * LDK + 4 * kq]) = gb_i[r];
+          f4 vr = gb_r[r], vi = gb_i[r];
+          if constexpr (KIND == KIND_F1) {
+            // pupil field P[m][n] = P0^T[n][m] * ty[m] * tx[n]  (row n, k = m)
+            const f4 tr = gy_r[r] * gx_r[r] - gy_i[r] * gx_i[r];
+            const f4 ti = gy_r[r] * gx_i[r] + gy_i[r] * gx_r[r];
+            const f4 pr = vr * tr - vi * ti;
+            const f4 pi = vr * ti + vi * tr;
+            vr = pr;
+            vi = pi;
+          }
+          fix(vr, vi, gb_k[r], a.conj_b);
+          *reinterpret_cast<f4*>(&Bs[row * LDK + 4 * kq]) = vr;
+          *reinterpret_cast<f4*>(&Bs[(BN + row) * LDK + 4 * kq]) = vi;
         }
       }
+    };
+
+    if (nk > 0) load_tile(k_lo);
+    for (int kt = 0; kt < nk; ++kt) {
       __syncthreads();
-      if (kt + 1 < nk) load_tile((kt + 1) * BK);
+      store_tile();
+      __syncthreads();
+      if (kt + 1 < nk) load_tile(k_lo + (kt + 1) * BK);
 
       f4 fa_r[WM], fa_i[WM], fb_r[WN], fb_i[WN];
 #pragma unroll
@@ -255,6 +288,24 @@ __global__ __launch_bounds__(256) void cgemm_kernel(const GemmArgs a) {
 #pragma unroll
           for (int r = 0; r < 4; ++r)
             sum[bm][bn][r] += k * (accr[bm][bn][r] * accr[bm][bn][r] + acci[bm][bn][r] * acci[bm][bn][r]);
+      if (a.out) {  // keep E = c T M^T for the adjoint (fused evaluation)
+        const float c = wi.scale;
+        float* ob = a.out + (long long)lb * a.out_by_psf;
+#pragma unroll
+        for (int bm = 0; bm < WM; ++bm)
+#pragma unroll
+          for (int bn = 0; bn < WN; ++bn) {
+            const int j = col0 + wc * 16 * WN + bn * 16 + (lane & 15);
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+              const int i = row0 + wr * 16 * WM + bm * 16 + 4 * (lane >> 4) + r;
+              if (i < M && j < N) {
+                ob[(long long)i * a.ldo + j] = c * accr[bm][bn][r];
+                ob[a.out_plane + (long long)i * a.ldo + j] = c * acci[bm][bn][r];
+              }
+            }
+          }
+      }
     } else if constexpr (KIND == KIND_B2) {
       const float phi = a.sources[(f * a.S + s) * 3 + 2];
       const float wphi = wi.w * phi;
@@ -328,7 +379,7 @@ __global__ __launch_bounds__(256) void cgemm_kernel(const GemmArgs a) {
       }
       __syncthreads();
       if (tid == 0) {
-        double* o = a.red + ((long long)gb * tiles + tile) * 2;
+        double* o = a.red + (((long long)gb * a.ksplit + item % a.ksplit) * tiles + tile) * 2;
         o[0] = sred[0] + sred[2] + sred[4] + sred[6];
         o[1] = sred[1] + sred[3] + sred[5] + sred[7];
       }

@@ -6,7 +6,7 @@
 //                  the integer product is exact, the scale is FP64 and the result is
 //                  reduced modulo one cycle before sincospi, so the phase error does
 //                  not grow with the grid size.
-//   OPD            sum_j c_j Z_j (+ B C B^T), FP64 accumulation (basis optic, Section 3).
+//   OPD            sum_j c_j Z_j (+ B C B^T), FP64 accumulation split over term groups (basis optic, Section 3).
 //   Pupil field    P0_l = A / sqrt(sum A^2) * exp(i 2 pi OPD / lambda_l), stored transposed.
 //   Tilts          tx[n] = exp(+2 pi i x_n alpha / lambda), ty[m] likewise with beta,
 //                  one pair of vectors per PSF, phases in FP64 reduced modulo one cycle.
@@ -50,21 +50,19 @@ __global__ void coords_kernel(double* x, int Ni, double dx) {
   if (n < Ni) x[n] = ((double)n - 0.5 * (double)(Ni - 1)) * dx;
 }
 
-// 1 / sqrt(sum A^2) in one 1024-thread block, FP64, fixed reduction order.
-__global__ void norm_kernel(const float* A, long long n, double* out) {
-  __shared__ double sh[1024];
+// Partial sums of A^2 (FP64), one per block; consumers add them in a fixed order.
+__global__ void norm_partial_kernel(const float* A, long long n, double* part) {
+  __shared__ double sh[4];
   double acc = 0.0;
-  for (long long i = threadIdx.x; i < n; i += blockDim.x) {
+  for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long long)gridDim.x * blockDim.x) {
     const double v = A[i];
     acc += v * v;
   }
-  sh[threadIdx.x] = acc;
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) acc += __shfl_xor(acc, o, 64);
+  if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = acc;
   __syncthreads();
-  for (int o = blockDim.x / 2; o > 0; o >>= 1) {
-    if ((int)threadIdx.x < o) sh[threadIdx.x] += sh[threadIdx.x + o];
-    __syncthreads();
-  }
-  if (threadIdx.x == 0) out[0] = sh[0] > 0.0 ? 1.0 / sqrt(sh[0]) : 0.0;
+  if (threadIdx.x == 0) part[blockIdx.x] = sh[0] + sh[1] + sh[2] + sh[3];
 }
 
 // tmp[j][n] = sum_k C[j][k] B[n][k]   (first half of B C B^T)
@@ -77,55 +75,88 @@ __global__ void map_tmp_kernel(const float* C, const float* Bm, float* tmp, int 
   tmp[(long long)j * Ni + n] = (float)acc;
 }
 
-// OPD[m][n] = sum_j c_j Z_j[m][n] + sum_j B[m][j] tmp[j][n]
-__global__ void opd_kernel(const float* Z, const float* c, int Nz, long long npix, int Ni, const float* Bm,
-                           const float* tmp, int Nmap, float* opd) {
-  const long long p = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-  if (p >= npix) return;
-  double acc = 0.0;
-  for (int j = 0; j < Nz; ++j) acc += (double)c[j] * (double)Z[(long long)j * npix + p];
-  if (Nmap > 0) {
-    const int m = (int)(p / Ni), n = (int)(p - (long long)m * Ni);
-    for (int j = 0; j < Nmap; ++j) acc += (double)Bm[(long long)m * Nmap + j] * (double)tmp[(long long)j * Ni + n];
+// OPD partial sums: block (chunk of 4 x 256 pixels, term split s) adds
+// c_j Z_j over its terms j = s, s + J, s + 2J, ...; split 0 also adds the map
+// term sum_j B[m][j] tmp[j][n]. The pupil kernel adds the J partials in order.
+__global__ void opd_partial_kernel(const float* Z, const float* c, int Nz, long long npix, int Ni, const float* Bm,
+                                   const float* tmp, int Nmap, int J, double* part) {
+  const int split = blockIdx.y;
+  const long long p0 = ((long long)blockIdx.x * blockDim.x + threadIdx.x) * 4;
+  if (p0 >= npix) return;
+  double acc[4] = {0.0, 0.0, 0.0, 0.0};
+  const bool vec = (p0 + 4 <= npix) && ((npix & 3) == 0);
+  for (int j = split; j < Nz; j += J) {
+    const double cj = c[j];
+    const float* z = Z + (long long)j * npix + p0;
+    if (vec && ((reinterpret_cast<uintptr_t>(z) & 15) == 0)) {
+      const float4 v = *reinterpret_cast<const float4*>(z);
+      acc[0] += cj * v.x;
+      acc[1] += cj * v.y;
+      acc[2] += cj * v.z;
+      acc[3] += cj * v.w;
+    } else {
+      for (int e = 0; e < 4; ++e)
+        if (p0 + e < npix) acc[e] += cj * (double)z[e];
+    }
   }
-  opd[p] = (float)acc;
+  if (split == 0 && Nmap > 0) {
+    for (int e = 0; e < 4; ++e) {
+      const long long p = p0 + e;
+      if (p >= npix) break;
+      const int m = (int)(p / Ni), n = (int)(p - (long long)m * Ni);
+      double a = 0.0;
+      for (int j = 0; j < Nmap; ++j) a += (double)Bm[(long long)m * Nmap + j] * (double)tmp[(long long)j * Ni + n];
+      acc[e] += a;
+    }
+  }
+  for (int e = 0; e < 4; ++e)
+    if (p0 + e < npix) part[(long long)split * npix + p0 + e] = acc[e];
 }
 
-// P0T_l[n][m] = A[m][n] * norm * exp(i 2 pi OPD[m][n] / lambda_l), through a 32 x 32 LDS transpose.
-__global__ void pupil_kernel(const float* A, const float* opd, const double* norm, const WlInfo* wl, int L, int Ni,
-                             int ldp, float* P0T, long long plane, long long by_wl) {
+// P0T_l[n][m] = A[m][n] / sqrt(sum A^2) * exp(i 2 pi OPD[m][n] / lambda_l), one block per
+// (32 x 32 tile, wavelength), transposed through LDS. OPD = sum of the J partials.
+__global__ void pupil_kernel(const float* A, const double* opd_part, int J, const double* norm_part, int n_norm,
+                             const WlInfo* wl, int Ni, int ldp, float* P0T, long long plane, long long by_wl) {
   __shared__ float tr[32][33], ti[32][33];
+  __shared__ double snorm;
   const int tx = threadIdx.x, ty = threadIdx.y;  // 32 x 8
   const int m0 = blockIdx.y * 32, n0 = blockIdx.x * 32;
-  const double nrm = norm[0];
-  float a[4], o[4];
+  const int l = blockIdx.z;
+  const long long npix = (long long)Ni * Ni;
+  if (tx == 0 && ty == 0) {
+    double s2 = 0.0;
+    for (int i = 0; i < n_norm; ++i) s2 += norm_part[i];
+    snorm = s2 > 0.0 ? 1.0 / sqrt(s2) : 0.0;
+  }
+  __syncthreads();
+  const double nrm = snorm;
+  const double inv = 1.0 / wl[l].lam;
   for (int q = 0; q < 4; ++q) {
     const int m = m0 + ty + 8 * q, n = n0 + tx;
-    const bool in = (m < Ni && n < Ni);
-    a[q] = in ? A[(long long)m * Ni + n] : 0.f;
-    o[q] = in ? opd[(long long)m * Ni + n] : 0.f;
-  }
-  for (int l = 0; l < L; ++l) {
-    const double inv = 1.0 / wl[l].lam;
-    for (int q = 0; q < 4; ++q) {
-      const double t = (double)o[q] * inv;   // cycles
-      const double fr = t - rint(t);
+    float re = 0.f, im = 0.f;
+    if (m < Ni && n < Ni) {
+      const long long p = (long long)m * Ni + n;
+      double o = 0.0;
+      for (int s = 0; s < J; ++s) o += opd_part[(long long)s * npix + p];
+      const double t0 = o * inv;   // phase in cycles
+      const double fr = t0 - rint(t0);
       double sn, cs;
       sincospi(2.0 * fr, &sn, &cs);
-      const double amp = (double)a[q] * nrm;
-      tr[ty + 8 * q][tx] = (float)(amp * cs);
-      ti[ty + 8 * q][tx] = (float)(amp * sn);
+      const double amp = (double)A[p] * nrm;
+      re = (float)(amp * cs);
+      im = (float)(amp * sn);
     }
-    __syncthreads();
-    for (int q = 0; q < 4; ++q) {
-      const int n = n0 + ty + 8 * q, m = m0 + tx;  // output row n, column m
-      if (n < Ni && m < ldp) {
-        const bool in = m < Ni;
-        P0T[l * by_wl + (long long)n * ldp + m] = in ? tr[tx][ty + 8 * q] : 0.f;
-        P0T[l * by_wl + plane + (long long)n * ldp + m] = in ? ti[tx][ty + 8 * q] : 0.f;
-      }
+    tr[ty + 8 * q][tx] = re;
+    ti[ty + 8 * q][tx] = im;
+  }
+  __syncthreads();
+  for (int q = 0; q < 4; ++q) {
+    const int n = n0 + ty + 8 * q, m = m0 + tx;  // output row n, column m
+    if (n < Ni && m < ldp) {
+      const bool in = m < Ni;
+      P0T[l * by_wl + (long long)n * ldp + m] = in ? tr[tx][ty + 8 * q] : 0.f;
+      P0T[l * by_wl + plane + (long long)n * ldp + m] = in ? ti[tx][ty + 8 * q] : 0.f;
     }
-    __syncthreads();
   }
 }
 
@@ -182,16 +213,18 @@ hipError_t launch_dft(dlx_plan* p, hipStream_t st) {
 hipError_t launch_prep(dlx_plan* p, const float* A, const float* Z, const float* Bm, const float* c, const float* C,
                        const float* sources, hipStream_t st) {
   const long long npix = (long long)p->Ni * p->Ni;
-  hipLaunchKernelGGL(norm_kernel, dim3(1), dim3(1024), 0, st, A, npix, p->d_norm);
+  hipLaunchKernelGGL(norm_partial_kernel, dim3(p->n_norm_part), dim3(256), 0, st, A, npix, p->d_norm);
   if (p->Nmap > 0) {
     hipLaunchKernelGGL(map_tmp_kernel, dim3((p->Ni + 255) / 256, p->Nmap), dim3(256), 0, st, C, Bm, p->d_maptmp,
                        p->Nmap, p->Ni);
   }
-  hipLaunchKernelGGL(opd_kernel, dim3((unsigned)((npix + 255) / 256)), dim3(256), 0, st, Z, c, p->Nz, npix, p->Ni,
-                     Bm, p->d_maptmp, p->Nmap, p->d_opd);
+  const long long chunks = (npix + 1023) / 1024;
+  hipLaunchKernelGGL(opd_partial_kernel, dim3((unsigned)chunks, p->opd_splits), dim3(256), 0, st, Z, c, p->Nz, npix,
+                     p->Ni, Bm, p->d_maptmp, p->Nmap, p->opd_splits, p->d_opd);
   const long long p0_by_wl = 2LL * p->Ni * p->ldNi;
-  hipLaunchKernelGGL(pupil_kernel, dim3((p->ldNi + 31) / 32, (p->Ni + 31) / 32), dim3(32, 8), 0, st, A, p->d_opd,
-                     p->d_norm, p->d_wl, p->L, p->Ni, p->ldNi, p->d_P0T, (long long)p->Ni * p->ldNi, p0_by_wl);
+  hipLaunchKernelGGL(pupil_kernel, dim3((p->Ni + 31) / 32, (p->ldNi + 31) / 32, p->L), dim3(32, 8), 0, st, A,
+                     p->d_opd, p->opd_splits, p->d_norm, p->n_norm_part, p->d_wl, p->Ni, p->ldNi, p->d_P0T,
+                     (long long)p->Ni * p->ldNi, p0_by_wl);
   const long long tplane = (long long)p->n_psf * p->ldNi;
   const long long nt = (long long)p->n_psf * p->ldNi;
   hipLaunchKernelGGL(tilt_kernel, dim3((unsigned)((nt + 255) / 256)), dim3(256), 0, st, sources, p->d_wl, p->d_x,

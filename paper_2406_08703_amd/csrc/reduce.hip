@@ -9,10 +9,10 @@ namespace dlx {
 namespace {
 
 // binned[f][p] = sum_g part[f][g][p];  model[f][p] = flat[p] * binned[f][p]
-__global__ void bin_reduce_kernel(const float* part, int G, int F, long long npix, const float* flat, float* binned,
-                                  float* model) {
+__global__ void bin_reduce_kernel(const float* part, int G, int f0, int F, long long npix, const float* flat,
+                                  float* binned, float* model) {
   const long long p = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-  const int f = blockIdx.y;
+  const int f = f0 + blockIdx.y;
   if (p >= npix || f >= F) return;
   const float* src = part + (long long)f * G * npix + p;
   double acc = 0.0;
@@ -37,18 +37,20 @@ __device__ __forceinline__ double block_sum(double v, double* sh) {
   return t;
 }
 
-// Per pixel p: loop over frames, l = m - d ln m (or (m-d)^2/(2 max(d,1))),
-// r = dl/dm, grad_flat[p] = sum_f r B + (F - mu)/sigma^2; block partial of L.
-__global__ void loss_kernel(const float* model, const float* binned, const float* data, const float* flat, int F,
-                            long long npix, int kind, double mu, double inv_s2, float* r_out, double* grad_flat,
-                            double* blk, int* status) {
+// Per pixel p: loop over frames f0 <= f < f1, l = m - d ln m (or
+// (m-d)^2/(2 max(d,1))), r = dl/dm, and grad_flat[p] = sum_f r B + (F - mu)/sigma^2.
+// With `accumulate` the frame sum is added to grad_flat and the prior is left
+// out (it was counted by the first frame range); block partials of L go to blk.
+__global__ void loss_kernel(const float* model, const float* binned, const float* data, const float* flat, int f0,
+                            int f1, long long npix, int kind, double mu, double inv_s2, float* r_out,
+                            double* grad_flat, int accumulate, double* blk, int* status) {
   __shared__ double sh[kLossThreads / 64];
   const long long p = (long long)blockIdx.x * blockDim.x + threadIdx.x;
   double lsum = 0.0;
   int flags = 0;
   if (p < npix) {
     double gf = 0.0;
-    for (int f = 0; f < F; ++f) {
+    for (int f = f0; f < f1; ++f) {
       const long long q = (long long)f * npix + p;
       double m = model[q];
       const double d = data[q];
@@ -72,10 +74,13 @@ __global__ void loss_kernel(const float* model, const float* binned, const float
       r_out[q] = (float)r;
       gf += r * b;
     }
-    const double fl = flat[p];
-    const double dfl = fl - mu;
-    lsum += 0.5 * dfl * dfl * inv_s2;
-    grad_flat[p] = gf + dfl * inv_s2;
+    if (accumulate) {
+      grad_flat[p] += gf;
+    } else {
+      const double dfl = (double)flat[p] - mu;
+      lsum += 0.5 * dfl * dfl * inv_s2;
+      grad_flat[p] = gf + dfl * inv_s2;
+    }
   }
   if (flags) atomicOr(status, flags);  // bit 0: non-finite, bit 1: domain
   const double t = block_sum(lsum, sh);
@@ -91,6 +96,46 @@ __global__ void final_sum_kernel(const double* blk, int n, double* out) {
   if (threadIdx.x == 0) out[0] = t;
 }
 
+// Adjoint seed from stored focal fields (fused evaluation): in place
+// Y = w phi G E with G[k][l] = K[k%Q][l%Q] flat[p] r_f[p], p = (k/Q, l/Q);
+// per (PSF, row block) FP64 partial of w sum G |E|^2 (the flux gradient).
+__global__ void seed_kernel(float* Y, long long plane, long long by_psf, int ld, int psf0, int No, int Q, int Nd,
+                            int S, int L, const float* sources, const WlInfo* wl, const float* flat, const float* resid,
+                            const float* intrapixel, int rows_per_blk, int nblk, double* flux) {
+  __shared__ double sh[4];
+  const int lb = blockIdx.x / nblk;
+  const int blk = blockIdx.x - lb * nblk;
+  const int gb = psf0 + lb;
+  const int l_idx = gb % L;
+  const int fs = gb / L;
+  const int f = fs / S;
+  const WlInfo wi = wl[l_idx];
+  const float wphi = wi.w * sources[fs * 3 + 2];
+  const float* rf = resid + (long long)f * Nd * Nd;
+  float* yb = Y + (long long)lb * by_psf;
+  const int k0 = blk * rows_per_blk;
+  const int k1 = min(No, k0 + rows_per_blk);
+  const long long n = (long long)(k1 > k0 ? k1 - k0 : 0) * No;
+  double part = 0.0;
+  for (long long t = threadIdx.x; t < n; t += blockDim.x) {
+    const int k = k0 + (int)(t / No);
+    const int l = (int)(t - (long long)(k - k0) * No);
+    const int p = (k / Q) * Nd + (l / Q);
+    float g = flat[p] * rf[p];
+    if (intrapixel) g *= intrapixel[(k % Q) * Q + (l % Q)];
+    float* e = yb + (long long)k * ld + l;
+    const float er = e[0], ei = e[plane];
+    e[0] = wphi * g * er;
+    e[plane] = wphi * g * ei;
+    part += (double)g * (double)(er * er + ei * ei);
+  }
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) part += __shfl_xor(part, o, 64);
+  if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = part;
+  __syncthreads();
+  if (threadIdx.x == 0) flux[(long long)gb * nblk + blk] = (double)wi.w * (sh[0] + sh[1] + sh[2] + sh[3]);
+}
+
 // gopd[p] = sum_g gpart[g][p]
 __global__ void gopd_reduce_kernel(const float* gpart, int G, long long npix, double* gopd) {
   const long long p = (long long)blockIdx.x * blockDim.x + threadIdx.x;
@@ -100,15 +145,44 @@ __global__ void gopd_reduce_kernel(const float* gpart, int G, long long npix, do
   gopd[p] = acc;
 }
 
-// grad_c[j] = sum_p Z_j[p] gopd[p]: one block per term.
-__global__ void zproj_kernel(const float* Z, const double* gopd, long long npix, double* grad) {
-  __shared__ double sh[512 / 64];
-  const int j = blockIdx.x;
-  const float* z = Z + (long long)j * npix;
+// Zernike projection dL/dc_j = sum_p Z_j[p] gopd[p], in two deterministic passes:
+// block (term group of 8, pixel chunk) writes part[chunk][j]; zproj_final sums chunks.
+constexpr int kZGroup = 8;
+
+__global__ void zproj_partial_kernel(const float* Z, const double* gopd, int Nz, long long npix, long long chunk,
+                                     double* part) {
+  __shared__ double sh[4][kZGroup];
+  const int j0 = blockIdx.x * kZGroup;
+  const long long p_begin = (long long)blockIdx.y * chunk;
+  const long long p_end = p_begin + chunk < npix ? p_begin + chunk : npix;
+  double acc[kZGroup];
+#pragma unroll
+  for (int q = 0; q < kZGroup; ++q) acc[q] = 0.0;
+  for (long long p = p_begin + threadIdx.x; p < p_end; p += blockDim.x) {
+    const double g = gopd[p];
+#pragma unroll
+    for (int q = 0; q < kZGroup; ++q)
+      if (j0 + q < Nz) acc[q] += (double)Z[(long long)(j0 + q) * npix + p] * g;
+  }
+#pragma unroll
+  for (int q = 0; q < kZGroup; ++q) {
+    double v = acc[q];
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+    if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6][q] = v;
+  }
+  __syncthreads();
+  if (threadIdx.x < kZGroup && j0 + (int)threadIdx.x < Nz) {
+    const int q = threadIdx.x;
+    part[(long long)blockIdx.y * Nz + j0 + q] = sh[0][q] + sh[1][q] + sh[2][q] + sh[3][q];
+  }
+}
+
+__global__ void zproj_final_kernel(const double* part, int Nz, int nchunks, double* grad) {
+  const int j = blockIdx.x * blockDim.x + threadIdx.x;
+  if (j >= Nz) return;
   double acc = 0.0;
-  for (long long p = threadIdx.x; p < npix; p += blockDim.x) acc += (double)z[p] * gopd[p];
-  const double t = block_sum(acc, sh);
-  if (threadIdx.x == 0) grad[j] = t;
+  for (int c = 0; c < nchunks; ++c) acc += part[(long long)c * Nz + j];
+  grad[j] = acc;
 }
 
 // tmp2[m][k] = sum_n gopd[m][n] B[n][k]
@@ -131,65 +205,102 @@ __global__ void map_grad2_kernel(const double* tmp2, const float* Bm, int Ni, in
   grad[(long long)j * Nmap + k] = acc;
 }
 
-// grad_sources[f][s] = (sum_l sum_tiles pos, sum_l sum_tiles flux)
-__global__ void src_reduce_kernel(const double* flux, int tiles_b2, const double* pos, int tiles_b4, int FS, int L,
+// grad_sources[f][s] = (sum over wavelengths and tiles of the position and flux
+// partials), one 64-thread block per (frame, star), fixed reduction order.
+__global__ void src_reduce_kernel(const double* flux, int tiles_b2, const double* pos, int tiles_b4, int L,
                                   double* grad) {
-  const int fs = blockIdx.x * blockDim.x + threadIdx.x;
-  if (fs >= FS) return;
+  const int fs = blockIdx.x;
+  const long long b0 = (long long)fs * L;
   double ga = 0.0, gbt = 0.0, gp = 0.0;
-  for (int l = 0; l < L; ++l) {
-    const long long b = (long long)fs * L + l;
-    for (int t = 0; t < tiles_b4; ++t) {
-      ga += pos[(b * tiles_b4 + t) * 2 + 0];
-      gbt += pos[(b * tiles_b4 + t) * 2 + 1];
-    }
-    for (int t = 0; t < tiles_b2; ++t) gp += flux[b * tiles_b2 + t];
+  for (int i = threadIdx.x; i < L * tiles_b4; i += 64) {
+    const long long q = (b0 * tiles_b4 + i) * 2;
+    ga += pos[q];
+    gbt += pos[q + 1];
   }
-  grad[fs * 3 + 0] = ga;
-  grad[fs * 3 + 1] = gbt;
-  grad[fs * 3 + 2] = gp;
+  for (int i = threadIdx.x; i < L * tiles_b2; i += 64) gp += flux[b0 * tiles_b2 + i];
+  for (int o = 32; o > 0; o >>= 1) {
+    ga += __shfl_xor(ga, o, 64);
+    gbt += __shfl_xor(gbt, o, 64);
+    gp += __shfl_xor(gp, o, 64);
+  }
+  if (threadIdx.x == 0) {
+    grad[fs * 3 + 0] = ga;
+    grad[fs * 3 + 1] = gbt;
+    grad[fs * 3 + 2] = gp;
+  }
 }
 
 }  // namespace
 
-hipError_t launch_bin_reduce(dlx_plan* p, const float* flat, float* binned, float* model, hipStream_t st) {
+hipError_t launch_bin_reduce(dlx_plan* p, int f0, int nf, const float* flat, float* binned, float* model,
+                             hipStream_t st) {
   const long long npix = (long long)p->Nd * p->Nd;
-  hipLaunchKernelGGL(bin_reduce_kernel, dim3((unsigned)((npix + 255) / 256), p->F), dim3(256), 0, st, p->d_binpart,
-                     p->f2_groups, p->F, npix, flat, binned, model);
+  hipLaunchKernelGGL(bin_reduce_kernel, dim3((unsigned)((npix + 255) / 256), nf), dim3(256), 0, st, p->d_binpart,
+                     p->f2_groups, f0, p->F, npix, flat, binned, model);
+  return hipGetLastError();
+}
+
+hipError_t launch_seed(dlx_plan* p, int f0, int nf, const float* sources, const float* flat, const float* resid,
+                       const float* intrapixel, hipStream_t st) {
+  const int nc = nf * p->S * p->L;
+  const int nblk = p->tiles_b2;
+  const int rows = (p->No + nblk - 1) / nblk;
+  hipLaunchKernelGGL(seed_kernel, dim3(nc * nblk), dim3(256), 0, st, p->d_Y, (long long)p->chunk_psf * p->No * p->ldNo,
+                     (long long)p->No * p->ldNo, p->ldNo, f0 * p->S * p->L, p->No, p->Q, p->Nd, p->S, p->L, sources,
+                     p->d_wl, flat, resid, intrapixel, rows, nblk, p->d_flux);
   return hipGetLastError();
 }
 
 int loss_block_count(long long npix) { return (int)((npix + kLossThreads - 1) / kLossThreads); }
 
-hipError_t launch_loss(dlx_plan* p, const float* model, const float* binned, const float* data, const float* flat,
-                       int kind, double mu, double sigma, double* loss, float* r, double* gflat, hipStream_t st) {
+// Loss terms of frames [f0, f0 + nf); block partials at slot `chunk`. The
+// loss itself is summed by launch_loss_final over `n_chunks` slots.
+hipError_t launch_loss(dlx_plan* p, int f0, int nf, int chunk, const float* model, const float* binned,
+                       const float* data, const float* flat, int kind, double mu, double sigma, float* r, double* gflat,
+                       hipStream_t st) {
   const long long npix = (long long)p->Nd * p->Nd;
   const int nb = loss_block_count(npix);
-  hipLaunchKernelGGL(loss_kernel, dim3(nb), dim3(kLossThreads), 0, st, model, binned, data, flat, p->F, npix, kind,
-                     mu, 1.0 / (sigma * sigma), r, gflat, p->d_lossblk, p->d_status);
-  hipError_t e = hipGetLastError();
-  if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(final_sum_kernel, dim3(1), dim3(1024), 0, st, p->d_lossblk, nb, loss);
+  hipLaunchKernelGGL(loss_kernel, dim3(nb), dim3(kLossThreads), 0, st, model, binned, data, flat, f0, f0 + nf, npix,
+                     kind, mu, 1.0 / (sigma * sigma), r, gflat, chunk > 0 ? 1 : 0, p->d_lossblk + (long long)chunk * nb,
+                     p->d_status);
   return hipGetLastError();
+}
+
+hipError_t launch_loss_final(dlx_plan* p, int n_chunks, double* loss, hipStream_t st) {
+  const int nb = loss_block_count((long long)p->Nd * p->Nd);
+  hipLaunchKernelGGL(final_sum_kernel, dim3(1), dim3(1024), 0, st, p->d_lossblk, nb * n_chunks, loss);
+  return hipGetLastError();
+}
+
+int zproj_chunks(long long npix, int Nz) {
+  const int groups = (Nz + kZGroup - 1) / kZGroup;
+  long long c = 2048 / (groups > 0 ? groups : 1);
+  c = c < 1 ? 1 : c;
+  const long long maxc = (npix + 255) / 256;
+  return (int)(c < maxc ? c : maxc);
 }
 
 hipError_t launch_grad_reduce(dlx_plan* p, const float* Z, const float* Bm, double* gz, double* gmap, double* gsrc,
                               hipStream_t st) {
   const long long npix = (long long)p->Ni * p->Ni;
-  const int G = p->b4_groups_max;
+  const int G = p->b4_groups_max * p->b4_ksplit;
   hipLaunchKernelGGL(gopd_reduce_kernel, dim3((unsigned)((npix + 255) / 256)), dim3(256), 0, st, p->d_gpart, G, npix,
                      p->d_gopd);
-  if (p->Nz > 0)
-    hipLaunchKernelGGL(zproj_kernel, dim3(p->Nz), dim3(512), 0, st, Z, p->d_gopd, npix, gz);
+  if (p->Nz > 0) {
+    const int nch = zproj_chunks(npix, p->Nz);
+    const long long chunk = (npix + nch - 1) / nch;
+    hipLaunchKernelGGL(zproj_partial_kernel, dim3((p->Nz + kZGroup - 1) / kZGroup, nch), dim3(256), 0, st, Z,
+                       p->d_gopd, p->Nz, npix, chunk, p->d_zpart);
+    hipLaunchKernelGGL(zproj_final_kernel, dim3((p->Nz + 63) / 64), dim3(64), 0, st, p->d_zpart, p->Nz, nch, gz);
+  }
   if (p->Nmap > 0) {
     hipLaunchKernelGGL(map_grad1_kernel, dim3(p->Ni), dim3((p->Nmap + 63) / 64 * 64), 0, st, p->d_gopd, Bm, p->Ni,
                        p->Nmap, p->d_tmp2);
     hipLaunchKernelGGL(map_grad2_kernel, dim3(p->Nmap), dim3((p->Nmap + 63) / 64 * 64), 0, st, p->d_tmp2, Bm, p->Ni,
                        p->Nmap, gmap);
   }
-  const int FS = p->F * p->S;
-  hipLaunchKernelGGL(src_reduce_kernel, dim3((FS + 127) / 128), dim3(128), 0, st, p->d_flux, p->tiles_b2, p->d_pos,
-                     p->tiles_b4, FS, p->L, gsrc);
+  hipLaunchKernelGGL(src_reduce_kernel, dim3(p->F * p->S), dim3(64), 0, st, p->d_flux, p->tiles_b2, p->d_pos,
+                     p->tiles_b4 * p->b4_ksplit, p->L, gsrc);
   return hipGetLastError();
 }
 

@@ -30,8 +30,8 @@ DLX_LOSS_CHI2 = 1
 
 # Every symbol include/dlx.h declares.
 EXPORTS = ("dlx_validate", "dlx_plan_create", "dlx_plan_destroy", "dlx_plan_workspace_bytes", "dlx_plan_sync",
-           "dlx_psf_forward", "dlx_loss_grad", "dlx_psf_backward", "dlx_plan_profile", "dlx_plan_stage_times",
-           "dlx_status_string")
+           "dlx_psf_forward", "dlx_loss_grad", "dlx_psf_backward", "dlx_eval", "dlx_graph_capture",
+           "dlx_graph_launch", "dlx_plan_profile", "dlx_plan_stage_times", "dlx_status_string")
 
 STAGES = ("PREP", "F1", "F2", "BIN", "LOSS", "B2", "B3", "B4", "GRAD")
 
@@ -44,6 +44,14 @@ class dlx_problem_desc(ctypes.Structure):
         ("diameter_m", ctypes.c_double), ("focal_pixel_rad", ctypes.c_double),
         ("wavelengths_m", ctypes.POINTER(ctypes.c_double)), ("spectral_weights", ctypes.POINTER(ctypes.c_double)),
     ]
+
+
+class dlx_eval_args(ctypes.Structure):
+    _fields_ = [(n, ctypes.c_void_p) for n in ("transmission", "zernike_basis", "map_basis", "zernike_coeffs",
+                                                 "phase_map", "sources", "flat", "intrapixel", "data")] + [
+        ("loss_kind", ctypes.c_int), ("prior_mu", ctypes.c_double), ("prior_sigma", ctypes.c_double)] + [
+        (n, ctypes.c_void_p) for n in ("binned", "model", "dloss_dmodel", "loss", "grad_flat", "grad_zernike",
+                                       "grad_map", "grad_sources")]
 
 
 class DlxError(RuntimeError):
@@ -88,6 +96,12 @@ def lib() -> ctypes.CDLL:
                                     _vp, _vp, _vp, _vp]
         L.dlx_psf_backward.restype = ctypes.c_int
         L.dlx_psf_backward.argtypes = [_vp] * 14
+        L.dlx_eval.restype = ctypes.c_int
+        L.dlx_eval.argtypes = [_vp, ctypes.POINTER(dlx_eval_args), _vp]
+        L.dlx_graph_capture.restype = ctypes.c_int
+        L.dlx_graph_capture.argtypes = [_vp, ctypes.POINTER(dlx_eval_args)]
+        L.dlx_graph_launch.restype = ctypes.c_int
+        L.dlx_graph_launch.argtypes = [_vp, _vp]
         L.dlx_plan_profile.restype = ctypes.c_int
         L.dlx_plan_profile.argtypes = [_vp, ctypes.c_int32]
         L.dlx_plan_stage_times.restype = ctypes.c_int
@@ -182,3 +196,15 @@ def dlx_plan_stage_times(plan: int) -> dict:
     _chk(lib().dlx_plan_stage_times(_p(plan), ctypes.addressof(ms), ctypes.addressof(la), ctypes.addressof(ps)),
          "dlx_plan_stage_times")
     return {STAGES[i]: (ms[i], la[i], ps[i]) for i in range(n)}
+
+
+def dlx_eval(plan: int, args: dlx_eval_args, stream: int = 0) -> None:
+    _chk(lib().dlx_eval(_p(plan), ctypes.byref(args), _p(stream)), "dlx_eval")
+
+
+def dlx_graph_capture(plan: int, args: dlx_eval_args) -> None:
+    _chk(lib().dlx_graph_capture(_p(plan), ctypes.byref(args)), "dlx_graph_capture")
+
+
+def dlx_graph_launch(plan: int, stream: int = 0) -> None:
+    _chk(lib().dlx_graph_launch(_p(plan), _p(stream)), "dlx_graph_launch")

@@ -154,6 +154,70 @@ class PsfPlan:
         return (gz[:g.n_zernike], gm, gs)
 
 
+class EvalBuffers:
+    """Device outputs of one full evaluation (forward, loss, backward)."""
+
+    def __init__(self, plan: "PsfPlan"):
+        g, dv = plan.geom, plan.device
+        shp = (g.n_frames, g.n_det, g.n_det)
+        self.binned = torch.empty(shp, dtype=torch.float32, device=dv)
+        self.model = torch.empty(shp, dtype=torch.float32, device=dv)
+        self.r = torch.empty(shp, dtype=torch.float32, device=dv)
+        self.loss = torch.empty(1, dtype=torch.float64, device=dv)
+        self.grad_flat = torch.empty((g.n_det, g.n_det), dtype=torch.float64, device=dv)
+        self.grad_zernike = torch.empty(max(g.n_zernike, 1), dtype=torch.float64, device=dv)
+        self.grad_map = torch.empty((g.n_map, g.n_map), dtype=torch.float64, device=dv) if g.n_map else None
+        self.grad_sources = torch.empty((g.n_frames, g.n_sources, 3), dtype=torch.float64, device=dv)
+
+
+def _eval_args(plan: "PsfPlan", coeffs, phase_map, sources, flat, data, kind, prior_mu, prior_sigma,
+               out: EvalBuffers):
+    g = plan.geom
+    c, pm, s, fl = plan._params(coeffs, phase_map, sources, flat)
+    d = _f32(data, (g.n_frames, g.n_det, g.n_det), "data")
+    a = _c.dlx_eval_args()
+    a.transmission, a.zernike_basis, a.map_basis = _ptr(plan.transmission), _ptr(plan.zbasis), _ptr(plan.map_basis)
+    a.zernike_coeffs, a.phase_map, a.sources, a.flat = _ptr(c), _ptr(pm), _ptr(s), _ptr(fl)
+    a.intrapixel, a.data = _ptr(plan.intrapixel), _ptr(d)
+    a.loss_kind = {"poisson": _c.DLX_LOSS_POISSON, "chi2": _c.DLX_LOSS_CHI2}[kind]
+    a.prior_mu, a.prior_sigma = float(prior_mu), float(prior_sigma)
+    a.binned, a.model, a.dloss_dmodel, a.loss = _ptr(out.binned), _ptr(out.model), _ptr(out.r), _ptr(out.loss)
+    a.grad_flat = _ptr(out.grad_flat)
+    a.grad_zernike = _ptr(out.grad_zernike) if g.n_zernike else None
+    a.grad_map, a.grad_sources = _ptr(out.grad_map), _ptr(out.grad_sources)
+    keep = (c, pm, s, fl, d)
+    return a, keep
+
+
+def evaluate(plan: "PsfPlan", coeffs, phase_map, sources, flat, data, kind="poisson", prior_mu=1.0, prior_sigma=0.1,
+             out: EvalBuffers | None = None) -> EvalBuffers:
+    """dlx_eval: forward, loss and backward in one call; returns the output buffers."""
+    out = out or EvalBuffers(plan)
+    a, keep = _eval_args(plan, coeffs, phase_map, sources, flat, data, kind, prior_mu, prior_sigma, out)
+    _c.dlx_eval(plan.plan, a, _stream(plan.device))
+    return out
+
+
+class CapturedEval:
+    """A full evaluation recorded once into a HIP graph (dlx_graph_capture) and replayed.
+
+    The input tensors are bound at capture time: update them in place
+    (``tensor.copy_``) between replays; outputs land in ``self.out``.
+    """
+
+    def __init__(self, plan: "PsfPlan", coeffs, phase_map, sources, flat, data, kind="poisson", prior_mu=1.0,
+                 prior_sigma=0.1):
+        self.plan = plan
+        self.out = EvalBuffers(plan)
+        self._args, self._keep = _eval_args(plan, coeffs, phase_map, sources, flat, data, kind, prior_mu,
+                                            prior_sigma, self.out)
+        _c.dlx_graph_capture(plan.plan, self._args)
+
+    def replay(self) -> EvalBuffers:
+        _c.dlx_graph_launch(self.plan.plan, _stream(self.plan.device))
+        return self.out
+
+
 class PsfLoss(torch.autograd.Function):
     """L(coeffs, phase_map, sources, flat) with the hand-written adjoint of the whole chain.
 

@@ -41,3 +41,23 @@ def run_gpu(w, params=None, kind="poisson", plan=None, precision="fp32"):
     if own:
         plan.close()
     return out
+
+
+def run_eval(w, params=None, kind="poisson", plan=None, precision="fp32", workspace_limit=0):
+    """dlx_eval (fused forward + loss + backward); returns FP64 numpy arrays."""
+    from paper_2406_08703_amd import evaluate
+    params = params or w.eval_params()
+    own = plan is None
+    plan = plan or make_plan(w, precision, workspace_limit)
+    out = evaluate(plan, dev(params["coeffs"]), dev(params["phase_map"]), dev(params["sources"]),
+                   dev(params["flat"]), dev(w.data), kind, w.prior_mu, w.prior_sigma)
+    status = plan.sync()
+    nz = w.problem.n_zernike
+    res = dict(binned=out.binned, model=out.model, loss=out.loss[0], r=out.r, grad_flat=out.grad_flat,
+               grad_coeffs=out.grad_zernike[:nz], grad_map=out.grad_map, grad_sources=out.grad_sources)
+    res = {k: (None if v is None else v.detach().cpu().numpy().astype(np.float64)) for k, v in res.items()}
+    res["loss"] = float(res["loss"])
+    res["status"] = status
+    if own:
+        plan.close()
+    return res

@@ -148,3 +148,55 @@ def test_status_word_reports_domain_and_nonfinite():
     plan.loss_grad(m, B, d, fl)
     assert plan.sync() == 5   # DLX_ERR_NONFINITE
     plan.close()
+
+
+@pytest.mark.parametrize("case", ["c1", "c2", "c3-small", "c5-small", "c2-odd", "tiny-noz"])
+def test_fused_eval_matches_oracle(case):
+    # dlx_eval: forward, loss and adjoint per frame chunk, E reused (no recompute)
+    from tests.gpu_helpers import run_eval
+    print(f"case {case}", flush=True)
+    w, _ = workload(case)
+    got = run_eval(w)
+    assert got["status"] == 0
+    compare(got, oracle_eval(case, "eval", "poisson"))
+
+
+def test_fused_eval_chunked_and_chi2():
+    from tests.gpu_helpers import run_eval
+    w, _ = workload("c3-small")
+    got = run_eval(w, workspace_limit=12 << 20)   # one frame per chunk
+    compare(got, oracle_eval("c3-small", "eval", "poisson"))
+    got = run_eval(w, kind="chi2", workspace_limit=12 << 20)
+    compare(got, oracle_eval("c3-small", "eval", "chi2"))
+
+
+def test_graph_replays_match_eager_eval():
+    # one captured evaluation replayed several times, with eager work and
+    # synchronisations in between; every replay must equal the eager dlx_eval
+    import torch
+    from paper_2406_08703_amd import CapturedEval, evaluate
+    from tests.gpu_helpers import make_plan, dev, run_gpu, run_eval
+    w, _ = workload("c3-small")
+    plan = make_plan(w, workspace_limit=24 << 20)   # two chunks
+    eager = run_eval(w, plan=plan)
+    p = w.eval_params()
+    c, s, fl, d = dev(p["coeffs"]), dev(p["sources"]), dev(p["flat"]), dev(w.data)
+    g = CapturedEval(plan, c, None, s, fl, d, "poisson", w.prior_mu, w.prior_sigma)
+    nz = w.problem.n_zernike
+    for i in range(4):
+        out = g.replay()
+        torch.cuda.synchronize()
+        np.testing.assert_array_equal(out.model.cpu().numpy(), eager["model"])
+        np.testing.assert_array_equal(out.r.cpu().numpy(), eager["r"])
+        np.testing.assert_array_equal(out.grad_flat.cpu().numpy(), eager["grad_flat"])
+        np.testing.assert_array_equal(out.grad_zernike.cpu().numpy()[:nz], eager["grad_coeffs"])
+        np.testing.assert_array_equal(out.grad_sources.cpu().numpy(), eager["grad_sources"])
+        assert float(out.loss.cpu()[0]) == eager["loss"]
+        run_gpu(w, plan=plan)     # eager work on the same plan between replays
+    # inputs updated in place are seen by the next replay
+    fl.add_(0.01)
+    out = g.replay()
+    ref = run_eval(w, plan=plan, params=dict(p, flat=p["flat"] + np.float32(0.01)))
+    np.testing.assert_array_equal(out.model.cpu().numpy(), ref["model"])
+    np.testing.assert_array_equal(out.grad_zernike.cpu().numpy()[:nz], ref["grad_coeffs"])
+    plan.close()
