@@ -12,8 +12,8 @@ namespace dlx {
 hipError_t launch_dft(dlx_plan* p, hipStream_t st);
 hipError_t launch_prep(dlx_plan* p, const float* A, const float* Z, const float* Bm, const float* c, const float* C,
                        const float* sources, hipStream_t st);
-hipError_t launch_bin_reduce(dlx_plan* p, int f0, int nf, const float* flat, float* binned, float* model,
-                             hipStream_t st);
+hipError_t launch_intensity(dlx_plan* p, int f0, int nf, const float* sources, const float* intrapixel,
+                            const float* flat, float* binned, float* model, hipStream_t st);
 hipError_t launch_seed(dlx_plan* p, int f0, int nf, const float* sources, const float* flat, const float* resid,
                        const float* intrapixel, hipStream_t st);
 hipError_t launch_loss(dlx_plan* p, int f0, int nf, int chunk, const float* model, const float* binned,
@@ -85,7 +85,7 @@ void layout(dlx_plan* p, Pool& pool) {
   p->d_T = pool.take<float>(2 * CP * No * ldNi);
   p->d_Y = pool.take<float>(2 * CP * No * ldNo);
   p->d_UT = pool.take<float>(2 * CP * Ni * ldNo);
-  p->d_binpart = pool.take<float>((size_t)p->F * p->f2_groups * p->Nd * p->Nd);
+  p->d_Ys = p->bf16() ? static_cast<void*>(pool.take<float>(2 * CP * No * ldNo)) : nullptr;
   p->d_gpart = pool.take<float>((size_t)p->b4_groups_max * p->b4_ksplit * Ni * Ni);
   p->d_gopd = pool.take<double>(Ni * Ni);
   p->d_flux = pool.take<double>((size_t)p->n_psf * p->tiles_b2);
@@ -98,7 +98,7 @@ void layout(dlx_plan* p, Pool& pool) {
 
 size_t per_psf_bytes(const dlx_plan* p) {
   return sizeof(float) * 2 *
-         ((size_t)p->No * p->ldNi + (size_t)p->No * p->ldNo + (size_t)p->Ni * p->ldNo);
+         ((size_t)p->No * p->ldNi + (size_t)(p->bf16() ? 2 : 1) * p->No * p->ldNo + (size_t)p->Ni * p->ldNo);
 }
 
 bool ok_ptr(const void* q) { return q != nullptr; }
@@ -135,8 +135,10 @@ Operand op_MT(const dlx_plan* p) {
 Operand op_T(const dlx_plan* p) {
   return Operand{p->d_T, (long long)p->chunk_psf * p->No * p->ldNi, 0, (long long)p->No * p->ldNi, p->ldNi};
 }
+// the adjoint seed: FP32 in place of E, or split BF16 in its own buffer
 Operand op_Y(const dlx_plan* p) {
-  return Operand{p->d_Y, (long long)p->chunk_psf * p->No * p->ldNo, 0, (long long)p->No * p->ldNo, p->ldNo};
+  return Operand{p->bf16() ? p->d_Ys : static_cast<const void*>(p->d_Y), (long long)p->chunk_psf * p->No * p->ldNo, 0,
+                 (long long)p->No * p->ldNo, p->ldNo};
 }
 Operand op_UT(const dlx_plan* p) {
   return Operand{p->d_UT, (long long)p->chunk_psf * p->Ni * p->ldNo, 0, (long long)p->Ni * p->ldNo, p->ldNo};
@@ -201,28 +203,20 @@ hipError_t run_f1(dlx_plan* p, int f0, int nf, hipStream_t st) {
   a.out_by_psf = op_T(p).by_psf;
   a.ldo = p->ldNi;
   set_tiles(a, p->ts_f1);
-  return launch_gemm(KIND_F1, p->ts_f1, a, wg_count(a), st);
+  return launch_gemm(KIND_F1, p->bf16(), p->ts_f1, a, wg_count(a), st);
 }
 
 GemmArgs e_args(dlx_plan* p, int f0, int nf, TileShape ts);
 
-// F2 over frames [f0, f0 + nf): binned partials, and E kept in the Y buffer if store_e.
-hipError_t run_f2(dlx_plan* p, int f0, int nf, const float* sources, const float* intrapixel, bool store_e,
-                  hipStream_t st) {
+// F2 over frames [f0, f0 + nf): E = c T M^T into the Y buffer.
+hipError_t run_f2(dlx_plan* p, int f0, int nf, hipStream_t st) {
   GemmArgs a = e_args(p, f0, nf, p->ts_f2);
-  a.groups = p->f2_groups;
-  a.group_size = p->f2_gsize;
-  a.n_items = nf * p->f2_groups;
-  a.sources = sources;
-  a.part = p->d_binpart;
-  a.intrapixel = intrapixel;
-  if (store_e) {
-    a.out = p->d_Y;
-    a.out_plane = (long long)p->chunk_psf * p->No * p->ldNo;
-    a.out_by_psf = (long long)p->No * p->ldNo;
-    a.ldo = p->ldNo;
-  }
-  return launch_gemm(KIND_F2, p->ts_f2, a, wg_count(a), st);
+  a.n_items = nf * p->S * p->L;
+  a.out = p->d_Y;
+  a.out_plane = (long long)p->chunk_psf * p->No * p->ldNo;
+  a.out_by_psf = (long long)p->No * p->ldNo;
+  a.ldo = p->ldNo;
+  return launch_gemm(KIND_F2, p->bf16(), p->ts_f2, a, wg_count(a), st);
 }
 
 // B3 and B4 over frames [f0, f0 + nf) of chunk c, from the seed Y in the Y buffer.
@@ -243,7 +237,7 @@ hipError_t run_adjoint(dlx_plan* p, int c, int f0, int nf, hipStream_t st) {
     a.out_by_psf = op_UT(p).by_psf;
     a.ldo = p->ldNo;
     set_tiles(a, p->ts_b3);
-    hipError_t e = launch_gemm(KIND_B3, p->ts_b3, a, wg_count(a), st);
+    hipError_t e = launch_gemm(KIND_B3, p->bf16(), p->ts_b3, a, wg_count(a), st);
     if (e != hipSuccess) return e;
   }
   Stage sg(p, st, DLX_STAGE_B4, nc);
@@ -262,7 +256,7 @@ hipError_t run_adjoint(dlx_plan* p, int c, int f0, int nf, hipStream_t st) {
   a.accumulate = c > 0;
   a.red = p->d_pos;
   set_tiles(a, p->ts_b4);
-  return launch_gemm(KIND_B4, p->ts_b4, a, wg_count(a), st);
+  return launch_gemm(KIND_B4, p->bf16(), p->ts_b4, a, wg_count(a), st);
 }
 
 GemmArgs e_args(dlx_plan* p, int f0, int nf, TileShape ts) {
@@ -325,7 +319,6 @@ dlx_status dlx_plan_create(const dlx_problem_desc* probs, int32_t n_probs, dlx_p
   if (precision != DLX_FP32 && precision != DLX_BF16X3) return DLX_ERR_INVALID_ARG;
   if (flags != 0) return DLX_ERR_INVALID_ARG;
   if (n_probs != 1) return DLX_ERR_UNSUPPORTED;
-  if (precision != DLX_FP32) return DLX_ERR_UNSUPPORTED;
   const dlx_problem_desc& d = probs[0];
 
   dlx_plan* p = new (std::nothrow) dlx_plan();
@@ -367,23 +360,11 @@ dlx_status dlx_plan_create(const dlx_problem_desc* probs, int32_t n_probs, dlx_p
   p->chunk_psf = p->frames_per_chunk * p->S * p->L;
 
   // tiles
-  const int Q = p->Q;
   p->ts_f1 = choose_tile(p->No, p->Ni, p->chunk_psf, 1);
   p->ts_b2 = choose_tile(p->No, p->No, p->chunk_psf, 1);
   p->ts_b3 = choose_tile(p->Ni, p->No, p->chunk_psf, 1);
   const int sl = p->S * p->L;
-  p->ts_f2 = choose_tile(p->No, p->No, (long long)p->frames_per_chunk * sl, Q);
-  if (p->ts_f2.wm == 0) {
-    delete p;
-    return DLX_ERR_UNSUPPORTED;
-  }
-  {
-    const int tiles = ceil_div(p->No, p->ts_f2.bm()) * ceil_div(p->No, p->ts_f2.bn());
-    int g = ceil_div(kTargetWG, (long long)p->frames_per_chunk * tiles);
-    g = std::max(1, std::min(g, sl));
-    p->f2_gsize = ceil_div(sl, g);
-    p->f2_groups = ceil_div(sl, p->f2_gsize);
-  }
+  p->ts_f2 = choose_tile(p->No, p->No, (long long)p->frames_per_chunk * sl, 1);
   {
     const int t = ceil_div(p->Ni, 128) * ceil_div(p->Ni, 128);
     const int g = std::max(1, std::min(ceil_div(kTargetWG, t), p->chunk_psf));
@@ -528,11 +509,13 @@ dlx_status dlx_psf_forward(dlx_plan* p, const float* transmission, const float* 
       Stage sg(p, st, DLX_STAGE_F1, nc);
       DLX_HIP(run_f1(p, f0, nf, st));
     }
-    Stage sg(p, st, DLX_STAGE_F2, nc);
-    DLX_HIP(run_f2(p, f0, nf, sources, intrapixel, false, st));
+    {
+      Stage sg(p, st, DLX_STAGE_F2, nc);
+      DLX_HIP(run_f2(p, f0, nf, st));
+    }
+    Stage sg(p, st, DLX_STAGE_BIN, nc);
+    DLX_HIP(launch_intensity(p, f0, nf, sources, intrapixel, flat, binned_out, model_out, st));
   }
-  Stage sg(p, st, DLX_STAGE_BIN, p->n_psf);
-  DLX_HIP(launch_bin_reduce(p, 0, p->F, flat, binned_out, model_out, st));
   return DLX_OK;
 }
 
@@ -579,7 +562,7 @@ dlx_status dlx_psf_backward(dlx_plan* p, const float* transmission, const float*
       GemmArgs a = e_args(p, f0, nf, p->ts_b2);
       a.n_items = nc;
       a.sources = sources;
-      a.out = p->d_Y;
+      a.out = const_cast<void*>(op_Y(p).base);
       a.out_plane = op_Y(p).plane;
       a.out_by_psf = op_Y(p).by_psf;
       a.ldo = p->ldNo;
@@ -587,7 +570,7 @@ dlx_status dlx_psf_backward(dlx_plan* p, const float* transmission, const float*
       a.flat = flat;
       a.resid = dloss_dmodel;
       a.intrapixel = intrapixel;
-      DLX_HIP(launch_gemm(KIND_B2, p->ts_b2, a, wg_count(a), st));
+      DLX_HIP(launch_gemm(KIND_B2, p->bf16(), p->ts_b2, a, wg_count(a), st));
     }
     DLX_HIP(run_adjoint(p, c, f0, nf, st));
   }
@@ -629,11 +612,11 @@ dlx_status dlx_eval(dlx_plan* p, const dlx_eval_args* a, void* stream) {
     }
     {
       Stage sg(p, st, DLX_STAGE_F2, nc);
-      DLX_HIP(run_f2(p, f0, nf, a->sources, a->intrapixel, true, st));
+      DLX_HIP(run_f2(p, f0, nf, st));
     }
     {
       Stage sg(p, st, DLX_STAGE_BIN, nc);
-      DLX_HIP(launch_bin_reduce(p, f0, nf, a->flat, a->binned, a->model, st));
+      DLX_HIP(launch_intensity(p, f0, nf, a->sources, a->intrapixel, a->flat, a->binned, a->model, st));
     }
     {
       Stage sg(p, st, DLX_STAGE_LOSS, nc);

@@ -25,21 +25,23 @@ struct WlInfo {
   float pad;
 };
 
-// A planar complex operand: re plane at base, im plane at base + plane.
-// The item's matrix starts at base + (psf % L) * by_wl + local_psf * by_psf.
-// Rows are `ld` floats apart (ld a multiple of 16, padded columns are never
-// read: the loaders mask k >= K).
+// A planar complex operand. FP32: re plane at base, im plane at base + plane
+// (floats). Split BF16: four planes re hi, re lo, im hi, im lo, `plane`
+// 16-bit elements apart. The item's matrix starts at
+// base + (psf % L) * by_wl + local_psf * by_psf; rows are `ld` elements
+// apart (ld a multiple of 16; padded columns are never read: the loaders
+// mask k >= K). All offsets are in elements of the operand's type.
 struct Operand {
-  const float* base;
+  const void* base;
   long long plane;
   long long by_wl;
   long long by_psf;
   int ld;
 };
 
-// The five matrix-Fourier stages of one forward+gradient evaluation.
+// The matrix-Fourier stages of one forward+gradient evaluation.
 //   F1  T = M_l P              (pupil field generated in the operand loader)
-//   F2  E = c T M_l^T          epilogue: w phi |E|^2 summed over a PSF group, K-weighted, binned
+//   F2  E = c T M_l^T          stored (intensity, binning and the adjoint seed read it)
 //   B2  E = c T M_l^T          epilogue: Y = w phi G E stored, flux partial sum G |E|^2
 //   B3  U^T = conj(M_l)^T Y^T  stored
 //   B4  W = c M_l^H U          epilogue: g = 2 Im(conj(P) W) (2 pi / l) summed over a group; position partials
@@ -53,7 +55,7 @@ struct GemmArgs {
   int psf0;             // global index of the chunk's first PSF
   int frame0;           // first frame of the chunk
   int group_size;       // PSFs per group item
-  int groups;           // F2: groups per frame; B4: groups in the chunk
+  int groups;           // B4: groups in the chunk
   int n_chunk_psf;
   int conj_a, conj_b;
   int ksplit;           // B4: K range split over ksplit items (the epilogue is linear in W)
@@ -69,12 +71,13 @@ struct GemmArgs {
   int ldp;
   const WlInfo* wl;
   const float* sources;   // [F][S][3]
-  // dense outputs (F1: T, B2: Y, B3: U^T), indexed by local PSF
-  float* out;
+  // dense outputs (F1: T, F2: E, B2: Y, B3: U^T), indexed by local PSF;
+  // E is FP32, the others are split BF16 under BF16X3
+  void* out;
   long long out_plane;
   long long out_by_psf;
   int ldo;
-  // group partials: F2 binned [F][groups][Nd*Nd]; B4 dL/dOPD [groups][Ni*Ni]
+  // group partials: B4 dL/dOPD [groups][Ni*Ni]
   float* part;
   int accumulate;
   // per-(PSF, tile) FP64 partials: B2 flux [n_psf][tiles]; B4 positions [n_psf][tiles][2]
@@ -94,7 +97,7 @@ struct TileShape {
   int bn() const { return 32 * wn; }
 };
 
-hipError_t launch_gemm(int kind, TileShape ts, const GemmArgs& a, int n_wg, hipStream_t st);
+hipError_t launch_gemm(int kind, int prec, TileShape ts, const GemmArgs& a, int n_wg, hipStream_t st);
 bool tile_supported(int kind, TileShape ts);
 
 }  // namespace dlx
@@ -105,6 +108,7 @@ struct dlx_plan {
   double D, du, dx;
   std::vector<double> lam, wts;
   dlx_precision prec;
+  int bf16() const { return prec == DLX_BF16X3 ? 1 : 0; }
   // padded leading dimensions
   int ldNi, ldNo;
   // chunking
@@ -114,7 +118,6 @@ struct dlx_plan {
   int n_psf;
   // tiles
   dlx::TileShape ts_f1, ts_f2, ts_b2, ts_b3, ts_b4;
-  int f2_groups, f2_gsize;   // per frame
   int b4_gsize, b4_groups_max, b4_ksplit = 1;
   // device memory
   void* pool = nullptr;
@@ -132,9 +135,9 @@ struct dlx_plan {
   float* d_tx = nullptr;   // [n_psf][ldNi] planar
   float* d_ty = nullptr;
   float* d_T = nullptr;    // [chunk_psf][No][ldNi] planar
-  float* d_Y = nullptr;    // [chunk_psf][No][ldNo] planar
+  float* d_Y = nullptr;    // [chunk_psf][No][ldNo] planar: E, then the seed Y in place
   float* d_UT = nullptr;   // [chunk_psf][Ni][ldNo] planar
-  float* d_binpart = nullptr;  // [F][f2_groups][Nd*Nd]
+  void* d_Ys = nullptr;    // BF16X3: split seed Y [chunk_psf][No][ldNo] (E stays FP32 in d_Y)
   float* d_gpart = nullptr;    // [b4_groups_max * b4_ksplit][Ni*Ni]
   double* d_gopd = nullptr;    // [Ni*Ni]
   double* d_flux = nullptr;    // [n_psf][tiles_b2]

@@ -1,30 +1,57 @@
 // Batched planar-complex GEMMs of the two-sided matrix Fourier transform
-// (Section 3: one product per side of the MFT) and of its adjoint, on FP32
-// MFMA (v_mfma_f32_16x16x4_f32) for gfx950.
+// (Section 3: one product per side of the MFT) and of its adjoint, for gfx950
+// on the matrix cores, in two arithmetics:
+//
+//   PREC 0 (DLX_FP32)   v_mfma_f32_16x16x4_f32, operands FP32, K step 16.
+//   PREC 1 (DLX_BF16X3) v_mfma_f32_16x16x32_bf16, each FP32 operand x held as
+//                       hi = bf16(x), lo = bf16(x - hi); a real product is
+//                       hi*hi + hi*lo + lo*hi (lo*lo dropped), FP32 accumulation,
+//                       K step 32. Operands arrive pre-split in HBM as four bf16
+//                       planes (re hi, re lo, im hi, im lo), the same bytes as
+//                       planar FP32; the F1 pupil field is split at LDS store.
 //
 // Every stage is a "TN" product C[i][j] = sum_k A[i][k] B[j][k] with both
-// operands K-contiguous, so one 128-bit LDS read feeds four MFMA k-steps.
-// A workgroup of 4 waves (2 x 2) owns a (32 WM) x (32 WN) complex output
-// tile; each wave holds WM x WN 16 x 16 blocks of real and imaginary
-// accumulators. K advances 16 at a time through one LDS stage, with the next
-// stage's global loads in flight during the MFMAs.
+// operands K-contiguous, so one 128-bit LDS read per operand block feeds the
+// MFMA (4 FP32 k-steps, or one 32-wide BF16 step). A workgroup of 4 waves
+// (2 x 2) owns a (32 WM) x (32 WN) complex output tile; each wave holds
+// WM x WN 16 x 16 blocks of real and imaginary FP32 accumulators, whose lane
+// layout is the same for both instructions, so the epilogues are shared.
 //
-// The complex product uses the four real products Re = ArBr - AiBi,
-// Im = ArBi + AiBr (no 3-multiply trick: it loses accuracy on operands of
-// very different size). Operand conjugation negates the imaginary part on
-// load. Stage-specific work is fused into the operand loader (the pupil
-// field of F1 is generated from P0^T, the row tilt and the column tilt) and
-// into the epilogues (intensity, intra-pixel weighting and binning for F2;
-// the adjoint seed for B2; the phase gradient and position sums for B4).
+// The next K stage's global loads are issued before the MFMAs and consumed
+// only when stored to LDS after them (conjugation, K-tail masking, the F1
+// pupil-field product and the BF16 split happen there), so their latency
+// overlaps the matrix work. The complex product uses the four real products
+// Re = ArBr - AiBi, Im = ArBi + AiBr (no 3-multiply trick: it loses accuracy
+// on operands of very different size).
+//
+// Stage-specific work is fused into the operand loader (F1: P0^T times the
+// row tilt) and into the epilogues (F1: the column tilt; F2: the focal-field
+// scale; B2: the adjoint seed; B4: the phase gradient and position sums).
+#include <type_traits>
+
 #include "dlx_internal.h"
 
 namespace dlx {
 namespace {
 
 typedef float f4 __attribute__((ext_vector_type(4)));
+typedef __bf16 bf8 __attribute__((ext_vector_type(8)));
+typedef unsigned int u4 __attribute__((ext_vector_type(4)));
 
-__device__ __forceinline__ f4 mfma4(float a, float b, f4 c) {
+__device__ __forceinline__ f4 mfma_f32(float a, float b, f4 c) {
   return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+}
+
+__device__ __forceinline__ f4 mfma_bf16(u4 a, u4 b, f4 c) {
+  return __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf8, a), __builtin_bit_cast(bf8, b), c, 0, 0, 0);
+}
+
+// RNE split of an FP32 value into bf16 hi + lo (as 16-bit patterns).
+__device__ __forceinline__ void split_bf16(float x, unsigned short& hi, unsigned short& lo) {
+  const __bf16 h = (__bf16)x;
+  const __bf16 l = (__bf16)(x - (float)h);
+  hi = __builtin_bit_cast(unsigned short, h);
+  lo = __builtin_bit_cast(unsigned short, l);
 }
 
 // Workgroups are dispatched round-robin over the 8 XCDs; renumber them so
@@ -42,19 +69,40 @@ __device__ __forceinline__ double wave_sum(double v) {
   return v;
 }
 
-template <int KIND, int WM, int WN>
+// Store one complex output element (FP32 planar, or four bf16 planes).
+template <int PREC>
+__device__ __forceinline__ void put(void* out, long long plane, long long idx, float re, float im) {
+  if constexpr (PREC == 0) {
+    float* o = static_cast<float*>(out);
+    o[idx] = re;
+    o[plane + idx] = im;
+  } else {
+    unsigned short* o = static_cast<unsigned short*>(out);
+    unsigned short h, l;
+    split_bf16(re, h, l);
+    o[idx] = h;
+    o[plane + idx] = l;
+    split_bf16(im, h, l);
+    o[2 * plane + idx] = h;
+    o[3 * plane + idx] = l;
+  }
+}
+
+template <int KIND, int WM, int WN, int PREC>
 __global__ __launch_bounds__(256) void cgemm_kernel(const GemmArgs a) {
-  constexpr int BM = 32 * WM, BN = 32 * WN, BK = 16, LDK = 20;
-  constexpr int A_FL = 2 * BM * LDK, B_FL = 2 * BN * LDK;
-  constexpr int OPS_FL = A_FL + B_FL;
-  constexpr int EPI_FL = (KIND == KIND_F2) ? BM * BN : 0;
-  constexpr int SM_FL = OPS_FL > EPI_FL ? OPS_FL : EPI_FL;
-  constexpr int A_PAIRS = (BM * 4 + 255) / 256;
-  constexpr int B_PAIRS = (BN * 4 + 255) / 256;
-  __shared__ __attribute__((aligned(16))) float smem[SM_FL];
+  constexpr int BM = 32 * WM, BN = 32 * WN;
+  constexpr int BK = PREC == 0 ? 16 : 32;
+  // LDS row pitch (elements): FP32 rows hold 16 k + 4 pad floats; BF16 rows 32 k + 8 pad halves.
+  constexpr int LDK = PREC == 0 ? 20 : 40;
+  constexpr int NPL = PREC == 0 ? 2 : 4;                 // planes per operand
+  constexpr int A_EL = NPL * BM * LDK, B_EL = NPL * BN * LDK;
+  constexpr int UNITS_A = BM * 4, UNITS_B = BN * 4;      // 16-byte k-chunks per plane row
+  constexpr int A_U = (UNITS_A + 255) / 256, B_U = (UNITS_B + 255) / 256;
+  using el_t = typename std::conditional<PREC == 0, float, unsigned short>::type;
+  __shared__ __attribute__((aligned(16))) el_t smem[A_EL + B_EL];
   __shared__ double sred[8];
-  float* As = smem;
-  float* Bs = smem + A_FL;
+  el_t* As = smem;
+  el_t* Bs = smem + A_EL;
 
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int wr = wave >> 1, wc = wave & 1;
@@ -67,14 +115,8 @@ __global__ __launch_bounds__(256) void cgemm_kernel(const GemmArgs a) {
   const int row0 = tm * BM, col0 = tn * BN;
   const int M = a.M, N = a.N, K = a.K;
 
-  int p_begin, p_end, grp = 0, fl = 0;
-  if constexpr (KIND == KIND_F2) {
-    fl = item / a.groups;
-    grp = item - fl * a.groups;
-    const int base = fl * a.S * a.L;
-    p_begin = base + grp * a.group_size;
-    p_end = min(p_begin + a.group_size, base + a.S * a.L);
-  } else if constexpr (KIND == KIND_B4) {
+  int p_begin, p_end, grp = 0;
+  if constexpr (KIND == KIND_B4) {
     grp = item;
     const int g = item / a.ksplit;
     p_begin = g * a.group_size;
@@ -103,10 +145,12 @@ __global__ __launch_bounds__(256) void cgemm_kernel(const GemmArgs a) {
   for (int lb = p_begin; lb < p_end; ++lb) {
     const int gb = a.psf0 + lb;
     const int wl = gb % a.L;
-    const float* Ab = a.A.base + (long long)wl * a.A.by_wl + (long long)lb * a.A.by_psf;
-    const float* Bb = a.B.base + (long long)wl * a.B.by_wl + (long long)lb * a.B.by_psf;
+    const el_t* Ab = static_cast<const el_t*>(a.A.base) + (long long)wl * a.A.by_wl + (long long)lb * a.A.by_psf;
     const float* txb = a.tx + (long long)gb * a.ldt;
     const float* tyb = a.ty + (long long)gb * a.ldt;
+    // F1's B operand is the FP32 field P0^T (row tilt applied at store); all others are el_t.
+    using bsrc_t = typename std::conditional<KIND == KIND_F1, float, el_t>::type;
+    const bsrc_t* Bb = static_cast<const bsrc_t*>(a.B.base) + (long long)wl * a.B.by_wl + (long long)lb * a.B.by_psf;
 
     f4 accr[WM][WN], acci[WM][WN];
 #pragma unroll
@@ -117,59 +161,62 @@ __global__ __launch_bounds__(256) void cgemm_kernel(const GemmArgs a) {
         acci[bm][bn] = f4{0.f, 0.f, 0.f, 0.f};
       }
 
-    // Raw global loads of the next K tile. They are consumed only by
-    // store_tile (after the MFMAs), so their latency overlaps the MFMAs:
-    // conjugation, K-tail masking and the F1 pupil-field product are applied
-    // at store time, never right after the load.
-    f4 ga_r[A_PAIRS], ga_i[A_PAIRS], gb_r[B_PAIRS], gb_i[B_PAIRS];
-    f4 gy_r[B_PAIRS], gy_i[B_PAIRS];
-    float gx_r[B_PAIRS], gx_i[B_PAIRS];
-    int ga_k[A_PAIRS], gb_k[B_PAIRS];
+    // ------------------------------------------------------------ staging registers
+    // A unit = one row, 16 bytes of k per plane: 4 FP32 k (PREC 0) or 8 bf16 k (PREC 1).
+    u4 ga[A_U][NPL];
+    int ga_k[A_U];
+    // B: el_t planes like A, except F1 which stages FP32 P0^T re/im and the row tilt
+    constexpr int BPL = (KIND == KIND_F1) ? (PREC == 0 ? 4 : 8) : NPL;
+    u4 gbv[B_U][BPL];
+    int gb_k[B_U];
 
     auto load_tile = [&](int k0) {
 #pragma unroll
-      for (int r = 0; r < A_PAIRS; ++r) {
+      for (int r = 0; r < A_U; ++r) {
         const int q = tid + 256 * r;
         const int row = q >> 2, kq = q & 3;
-        const int gi = row0 + row, gk = k0 + 4 * kq;
+        const int gi = row0 + row;
+        const int gk = k0 + (PREC == 0 ? 4 : 8) * kq;
         ga_k[r] = gk;
-        ga_r[r] = f4{0.f, 0.f, 0.f, 0.f};
-        ga_i[r] = ga_r[r];
-        if (q < BM * 4 && gi < M && gk < k_hi) {
-          const float* p = Ab + (long long)gi * a.A.ld + gk;
-          ga_r[r] = *reinterpret_cast<const f4*>(p);
-          ga_i[r] = *reinterpret_cast<const f4*>(p + a.A.plane);
+#pragma unroll
+        for (int pl = 0; pl < NPL; ++pl) ga[r][pl] = u4{0u, 0u, 0u, 0u};
+        if (q < UNITS_A && gi < M && gk < k_hi) {
+          const el_t* p = Ab + (long long)gi * a.A.ld + gk;
+#pragma unroll
+          for (int pl = 0; pl < NPL; ++pl) ga[r][pl] = *reinterpret_cast<const u4*>(p + pl * a.A.plane);
         }
       }
 #pragma unroll
-      for (int r = 0; r < B_PAIRS; ++r) {
+      for (int r = 0; r < B_U; ++r) {
         const int q = tid + 256 * r;
         const int row = q >> 2, kq = q & 3;
-        const int gj = col0 + row, gk = k0 + 4 * kq;
+        const int gj = col0 + row;
+        const int gk = k0 + (PREC == 0 ? 4 : 8) * kq;
         gb_k[r] = gk;
-        gb_r[r] = f4{0.f, 0.f, 0.f, 0.f};
-        gb_i[r] = gb_r[r];
-        if constexpr (KIND == KIND_F1) {
-          gy_r[r] = gb_r[r];
-          gy_i[r] = gb_r[r];
-          gx_r[r] = 0.f;
-          gx_i[r] = 0.f;
-        }
-        if (q < BN * 4 && gj < N && gk < k_hi) {
-          const float* p = Bb + (long long)gj * a.B.ld + gk;
-          gb_r[r] = *reinterpret_cast<const f4*>(p);
-          gb_i[r] = *reinterpret_cast<const f4*>(p + a.B.plane);
+#pragma unroll
+        for (int pl = 0; pl < BPL; ++pl) gbv[r][pl] = u4{0u, 0u, 0u, 0u};
+        if (q < UNITS_B && gj < N && gk < k_hi) {
+          const bsrc_t* p = Bb + (long long)gj * a.B.ld + gk;
           if constexpr (KIND == KIND_F1) {
-            gy_r[r] = *reinterpret_cast<const f4*>(tyb + gk);
-            gy_i[r] = *reinterpret_cast<const f4*>(tyb + a.tilt_plane + gk);
-            gx_r[r] = txb[gj];
-            gx_i[r] = txb[a.tilt_plane + gj];
+            // FP32 P0^T re, im and ty re, im for 4 (PREC 0) or 8 (PREC 1) consecutive k
+            constexpr int V = PREC == 0 ? 1 : 2;
+#pragma unroll
+            for (int v = 0; v < V; ++v) {
+              gbv[r][0 * V + v] = *reinterpret_cast<const u4*>(p + 4 * v);
+              gbv[r][1 * V + v] = *reinterpret_cast<const u4*>(p + a.B.plane + 4 * v);
+              gbv[r][2 * V + v] = *reinterpret_cast<const u4*>(tyb + gk + 4 * v);
+              gbv[r][3 * V + v] = *reinterpret_cast<const u4*>(tyb + a.tilt_plane + gk + 4 * v);
+            }
+          } else {
+#pragma unroll
+            for (int pl = 0; pl < NPL; ++pl) gbv[r][pl] = *reinterpret_cast<const u4*>(p + pl * a.B.plane);
           }
         }
       }
     };
 
-    auto fix = [&](f4& vr, f4& vi, int gk, bool conj) {
+    // zero k >= k_hi and conjugate, on FP32 values
+    auto fix32 = [&](f4& vr, f4& vi, int gk, bool conj) {
       if (gk + 4 > k_hi) {
 #pragma unroll
         for (int e = 0; e < 4; ++e)
@@ -180,37 +227,86 @@ __global__ __launch_bounds__(256) void cgemm_kernel(const GemmArgs a) {
       }
       if (conj) vi = -vi;
     };
+    // zero k >= k_hi and conjugate, on four bf16 planes of 8 k each
+    auto fix16 = [&](u4* pl, int gk, bool conj) {
+      if (gk + 8 > k_hi) {
+#pragma unroll
+        for (int e = 0; e < 8; ++e)
+          if (gk + e >= k_hi) {
+            const unsigned int mask = (e & 1) ? 0x0000ffffu : 0xffff0000u;
+#pragma unroll
+            for (int q = 0; q < 4; ++q) pl[q][e >> 1] &= mask;
+          }
+      }
+      if (conj) {
+        pl[2] ^= u4{0x80008000u, 0x80008000u, 0x80008000u, 0x80008000u};
+        pl[3] ^= u4{0x80008000u, 0x80008000u, 0x80008000u, 0x80008000u};
+      }
+    };
 
     auto store_tile = [&]() {
 #pragma unroll
-      for (int r = 0; r < A_PAIRS; ++r) {
+      for (int r = 0; r < A_U; ++r) {
         const int q = tid + 256 * r;
-        if (q < BM * 4) {
+        if (q < UNITS_A) {
           const int row = q >> 2, kq = q & 3;
-          f4 vr = ga_r[r], vi = ga_i[r];
-          fix(vr, vi, ga_k[r], a.conj_a);
-          *reinterpret_cast<f4*>(&As[row * LDK + 4 * kq]) = vr;
-          *reinterpret_cast<f4*>(&As[(BM + row) * LDK + 4 * kq]) = vi;
+          if constexpr (PREC == 0) {
+            f4 vr = __builtin_bit_cast(f4, ga[r][0]), vi = __builtin_bit_cast(f4, ga[r][1]);
+            fix32(vr, vi, ga_k[r], a.conj_a);
+            *reinterpret_cast<f4*>(&As[row * LDK + 4 * kq]) = vr;
+            *reinterpret_cast<f4*>(&As[(BM + row) * LDK + 4 * kq]) = vi;
+          } else {
+            fix16(ga[r], ga_k[r], a.conj_a);
+#pragma unroll
+            for (int pl = 0; pl < 4; ++pl) *reinterpret_cast<u4*>(&As[(pl * BM + row) * LDK + 8 * kq]) = ga[r][pl];
+          }
         }
       }
 #pragma unroll
-      for (int r = 0; r < B_PAIRS; ++r) {
+      for (int r = 0; r < B_U; ++r) {
         const int q = tid + 256 * r;
-        if (q < BN * 4) {
+        if (q < UNITS_B) {
           const int row = q >> 2, kq = q & 3;
-          f4 vr = gb_r[r], vi = gb_i[r];
           if constexpr (KIND == KIND_F1) {
-            // pupil field P[m][n] = P0^T[n][m] * ty[m] * tx[n]  (row n, k = m)
-            const f4 tr = gy_r[r] * gx_r[r] - gy_i[r] * gx_i[r];
-            const f4 ti = gy_r[r] * gx_i[r] + gy_i[r] * gx_r[r];
-            const f4 pr = vr * tr - vi * ti;
-            const f4 pi = vr * ti + vi * tr;
-            vr = pr;
-            vi = pi;
+            // P[m][n] / tx[n] = P0^T[n][m] * ty[m]  (row n, k = m); tx is applied in the epilogue
+            constexpr int V = PREC == 0 ? 1 : 2;
+            f4 pr[V], pi[V];
+#pragma unroll
+            for (int v = 0; v < V; ++v) {
+              const f4 xr = __builtin_bit_cast(f4, gbv[r][0 * V + v]), xi = __builtin_bit_cast(f4, gbv[r][1 * V + v]);
+              const f4 yr = __builtin_bit_cast(f4, gbv[r][2 * V + v]), yi = __builtin_bit_cast(f4, gbv[r][3 * V + v]);
+              pr[v] = xr * yr - xi * yi;
+              pi[v] = xr * yi + xi * yr;
+              fix32(pr[v], pi[v], gb_k[r] + 4 * v, false);
+            }
+            if constexpr (PREC == 0) {
+              *reinterpret_cast<f4*>(&Bs[row * LDK + 4 * kq]) = pr[0];
+              *reinterpret_cast<f4*>(&Bs[(BN + row) * LDK + 4 * kq]) = pi[0];
+            } else {
+              unsigned short h[4][8];
+#pragma unroll
+              for (int e = 0; e < 8; ++e) {
+                split_bf16(pr[e >> 2][e & 3], h[0][e], h[1][e]);
+                split_bf16(pi[e >> 2][e & 3], h[2][e], h[3][e]);
+              }
+#pragma unroll
+              for (int pl = 0; pl < 4; ++pl) {
+                u4 w;
+#pragma unroll
+                for (int e = 0; e < 4; ++e) w[e] = (unsigned int)h[pl][2 * e] | ((unsigned int)h[pl][2 * e + 1] << 16);
+                *reinterpret_cast<u4*>(&Bs[(pl * BN + row) * LDK + 8 * kq]) = w;
+              }
+            }
+          } else if constexpr (PREC == 0) {
+            f4 vr = __builtin_bit_cast(f4, gbv[r][0]), vi = __builtin_bit_cast(f4, gbv[r][1]);
+            fix32(vr, vi, gb_k[r], a.conj_b);
+            *reinterpret_cast<f4*>(&Bs[row * LDK + 4 * kq]) = vr;
+            *reinterpret_cast<f4*>(&Bs[(BN + row) * LDK + 4 * kq]) = vi;
+          } else {
+            fix16(gbv[r], gb_k[r], a.conj_b);
+#pragma unroll
+            for (int pl = 0; pl < 4; ++pl) *reinterpret_cast<u4*>(&Bs[(pl * BN + row) * LDK + 8 * kq]) = gbv[r][pl];
           }
-          fix(vr, vi, gb_k[r], a.conj_b);
-          *reinterpret_cast<f4*>(&Bs[row * LDK + 4 * kq]) = vr;
-          *reinterpret_cast<f4*>(&Bs[(BN + row) * LDK + 4 * kq]) = vi;
         }
       }
     };
@@ -222,39 +318,77 @@ __global__ __launch_bounds__(256) void cgemm_kernel(const GemmArgs a) {
       __syncthreads();
       if (kt + 1 < nk) load_tile(k_lo + (kt + 1) * BK);
 
-      f4 fa_r[WM], fa_i[WM], fb_r[WN], fb_i[WN];
-#pragma unroll
-      for (int bm = 0; bm < WM; ++bm) {
-        const int r = wr * 16 * WM + bm * 16 + (lane & 15);
-        fa_r[bm] = *reinterpret_cast<const f4*>(&As[r * LDK + 4 * (lane >> 4)]);
-        fa_i[bm] = *reinterpret_cast<const f4*>(&As[(BM + r) * LDK + 4 * (lane >> 4)]);
-      }
-#pragma unroll
-      for (int bn = 0; bn < WN; ++bn) {
-        const int c = wc * 16 * WN + bn * 16 + (lane & 15);
-        fb_r[bn] = *reinterpret_cast<const f4*>(&Bs[c * LDK + 4 * (lane >> 4)]);
-        fb_i[bn] = *reinterpret_cast<const f4*>(&Bs[(BN + c) * LDK + 4 * (lane >> 4)]);
-      }
-#pragma unroll
-      for (int s = 0; s < 4; ++s) {
-#pragma unroll
-        for (int bm = 0; bm < WM; ++bm)
-#pragma unroll
-          for (int bn = 0; bn < WN; ++bn) accr[bm][bn] = mfma4(fa_r[bm][s], fb_r[bn][s], accr[bm][bn]);
-#pragma unroll
-        for (int bm = 0; bm < WM; ++bm)
-#pragma unroll
-          for (int bn = 0; bn < WN; ++bn) acci[bm][bn] = mfma4(fa_r[bm][s], fb_i[bn][s], acci[bm][bn]);
+      if constexpr (PREC == 0) {
+        f4 fa_r[WM], fa_i[WM], fb_r[WN], fb_i[WN];
 #pragma unroll
         for (int bm = 0; bm < WM; ++bm) {
-          const float na = -fa_i[bm][s];
-#pragma unroll
-          for (int bn = 0; bn < WN; ++bn) accr[bm][bn] = mfma4(na, fb_i[bn][s], accr[bm][bn]);
+          const int r = wr * 16 * WM + bm * 16 + (lane & 15);
+          fa_r[bm] = *reinterpret_cast<const f4*>(&As[r * LDK + 4 * (lane >> 4)]);
+          fa_i[bm] = *reinterpret_cast<const f4*>(&As[(BM + r) * LDK + 4 * (lane >> 4)]);
         }
 #pragma unroll
-        for (int bm = 0; bm < WM; ++bm)
+        for (int bn = 0; bn < WN; ++bn) {
+          const int c = wc * 16 * WN + bn * 16 + (lane & 15);
+          fb_r[bn] = *reinterpret_cast<const f4*>(&Bs[c * LDK + 4 * (lane >> 4)]);
+          fb_i[bn] = *reinterpret_cast<const f4*>(&Bs[(BN + c) * LDK + 4 * (lane >> 4)]);
+        }
 #pragma unroll
-          for (int bn = 0; bn < WN; ++bn) acci[bm][bn] = mfma4(fa_i[bm][s], fb_r[bn][s], acci[bm][bn]);
+        for (int s = 0; s < 4; ++s) {
+#pragma unroll
+          for (int bm = 0; bm < WM; ++bm)
+#pragma unroll
+            for (int bn = 0; bn < WN; ++bn) accr[bm][bn] = mfma_f32(fa_r[bm][s], fb_r[bn][s], accr[bm][bn]);
+#pragma unroll
+          for (int bm = 0; bm < WM; ++bm)
+#pragma unroll
+            for (int bn = 0; bn < WN; ++bn) acci[bm][bn] = mfma_f32(fa_r[bm][s], fb_i[bn][s], acci[bm][bn]);
+#pragma unroll
+          for (int bm = 0; bm < WM; ++bm) {
+            const float na = -fa_i[bm][s];
+#pragma unroll
+            for (int bn = 0; bn < WN; ++bn) accr[bm][bn] = mfma_f32(na, fb_i[bn][s], accr[bm][bn]);
+          }
+#pragma unroll
+          for (int bm = 0; bm < WM; ++bm)
+#pragma unroll
+            for (int bn = 0; bn < WN; ++bn) acci[bm][bn] = mfma_f32(fa_i[bm][s], fb_r[bn][s], acci[bm][bn]);
+        }
+      } else {
+        // B fragments for all blocks, A fragments one block row at a time
+        u4 fb[WN][4];
+#pragma unroll
+        for (int bn = 0; bn < WN; ++bn) {
+          const int c = wc * 16 * WN + bn * 16 + (lane & 15);
+#pragma unroll
+          for (int pl = 0; pl < 4; ++pl)
+            fb[bn][pl] = *reinterpret_cast<const u4*>(&Bs[(pl * BN + c) * LDK + 8 * (lane >> 4)]);
+        }
+#pragma unroll
+        for (int bm = 0; bm < WM; ++bm) {
+          const int r = wr * 16 * WM + bm * 16 + (lane & 15);
+          u4 fa[4];
+#pragma unroll
+          for (int pl = 0; pl < 4; ++pl)
+            fa[pl] = *reinterpret_cast<const u4*>(&As[(pl * BM + r) * LDK + 8 * (lane >> 4)]);
+          const u4 sgn = u4{0x80008000u, 0x80008000u, 0x80008000u, 0x80008000u};
+          const u4 nih = fa[2] ^ sgn, nil = fa[3] ^ sgn;   // -Ai (hi, lo)
+#pragma unroll
+          for (int bn = 0; bn < WN; ++bn) {
+            // Re += Ar Br - Ai Bi ; Im += Ar Bi + Ai Br ; each as hi*hi + hi*lo + lo*hi
+            accr[bm][bn] = mfma_bf16(fa[0], fb[bn][0], accr[bm][bn]);
+            acci[bm][bn] = mfma_bf16(fa[0], fb[bn][2], acci[bm][bn]);
+            accr[bm][bn] = mfma_bf16(fa[0], fb[bn][1], accr[bm][bn]);
+            acci[bm][bn] = mfma_bf16(fa[0], fb[bn][3], acci[bm][bn]);
+            accr[bm][bn] = mfma_bf16(fa[1], fb[bn][0], accr[bm][bn]);
+            acci[bm][bn] = mfma_bf16(fa[1], fb[bn][2], acci[bm][bn]);
+            accr[bm][bn] = mfma_bf16(nih, fb[bn][2], accr[bm][bn]);
+            acci[bm][bn] = mfma_bf16(fa[2], fb[bn][0], acci[bm][bn]);
+            accr[bm][bn] = mfma_bf16(nih, fb[bn][3], accr[bm][bn]);
+            acci[bm][bn] = mfma_bf16(fa[2], fb[bn][1], acci[bm][bn]);
+            accr[bm][bn] = mfma_bf16(nil, fb[bn][2], accr[bm][bn]);
+            acci[bm][bn] = mfma_bf16(fa[3], fb[bn][0], acci[bm][bn]);
+          }
+        }
       }
     }
 
@@ -262,57 +396,50 @@ __global__ __launch_bounds__(256) void cgemm_kernel(const GemmArgs a) {
     const int f = gb / (a.S * a.L);
     const int s = (gb / a.L) % a.S;
     const WlInfo wi = a.wl[wl];
-    if constexpr (KIND == KIND_F1 || KIND == KIND_B3) {
-      float* ob = a.out + (long long)lb * a.out_by_psf;
+    if constexpr (KIND == KIND_F1 || KIND == KIND_F2 || KIND == KIND_B3) {
+      // F1: T = acc * tx[n] (column tilt); F2: E = c acc, always FP32; B3: U^T = acc
+      constexpr int OP = (KIND == KIND_F2) ? 0 : PREC;
+      void* ob = (OP == 0) ? static_cast<void*>(static_cast<float*>(a.out) + (long long)lb * a.out_by_psf)
+                           : static_cast<void*>(static_cast<unsigned short*>(a.out) + (long long)lb * a.out_by_psf);
 #pragma unroll
       for (int bm = 0; bm < WM; ++bm)
 #pragma unroll
         for (int bn = 0; bn < WN; ++bn) {
           const int j = col0 + wc * 16 * WN + bn * 16 + (lane & 15);
+          float cr = 1.f, ci = 0.f;
+          if constexpr (KIND == KIND_F1) {
+            if (j < N) {
+              cr = txb[j];
+              ci = txb[a.tilt_plane + j];
+            }
+          } else if constexpr (KIND == KIND_F2) {
+            cr = wi.scale;
+          }
 #pragma unroll
           for (int r = 0; r < 4; ++r) {
             const int i = row0 + wr * 16 * WM + bm * 16 + 4 * (lane >> 4) + r;
             if (i < M && j < N) {
-              ob[(long long)i * a.ldo + j] = accr[bm][bn][r];
-              ob[a.out_plane + (long long)i * a.ldo + j] = acci[bm][bn][r];
+              const float xr = accr[bm][bn][r], xi = acci[bm][bn][r];
+              float re, im;
+              if constexpr (KIND == KIND_F1) {
+                re = xr * cr - xi * ci;
+                im = xr * ci + xi * cr;
+              } else {
+                re = cr * xr;
+                im = cr * xi;
+              }
+              put<OP>(ob, a.out_plane, (long long)i * a.ldo + j, re, im);
             }
           }
         }
-    } else if constexpr (KIND == KIND_F2) {
-      const float phi = a.sources[(f * a.S + s) * 3 + 2];
-      const float k = wi.w * phi * wi.scale * wi.scale;
-#pragma unroll
-      for (int bm = 0; bm < WM; ++bm)
-#pragma unroll
-        for (int bn = 0; bn < WN; ++bn)
-#pragma unroll
-          for (int r = 0; r < 4; ++r)
-            sum[bm][bn][r] += k * (accr[bm][bn][r] * accr[bm][bn][r] + acci[bm][bn][r] * acci[bm][bn][r]);
-      if (a.out) {  // keep E = c T M^T for the adjoint (fused evaluation)
-        const float c = wi.scale;
-        float* ob = a.out + (long long)lb * a.out_by_psf;
-#pragma unroll
-        for (int bm = 0; bm < WM; ++bm)
-#pragma unroll
-          for (int bn = 0; bn < WN; ++bn) {
-            const int j = col0 + wc * 16 * WN + bn * 16 + (lane & 15);
-#pragma unroll
-            for (int r = 0; r < 4; ++r) {
-              const int i = row0 + wr * 16 * WM + bm * 16 + 4 * (lane >> 4) + r;
-              if (i < M && j < N) {
-                ob[(long long)i * a.ldo + j] = c * accr[bm][bn][r];
-                ob[a.out_plane + (long long)i * a.ldo + j] = c * acci[bm][bn][r];
-              }
-            }
-          }
-      }
     } else if constexpr (KIND == KIND_B2) {
       const float phi = a.sources[(f * a.S + s) * 3 + 2];
       const float wphi = wi.w * phi;
       const float c = wi.scale;
       const int Nd = a.n_det, Q = a.Q;
       const float* rf = a.resid + (long long)f * Nd * Nd;
-      float* ob = a.out + (long long)lb * a.out_by_psf;
+      void* ob = (PREC == 0) ? static_cast<void*>(static_cast<float*>(a.out) + (long long)lb * a.out_by_psf)
+                             : static_cast<void*>(static_cast<unsigned short*>(a.out) + (long long)lb * a.out_by_psf);
       double part = 0.0;
 #pragma unroll
       for (int bm = 0; bm < WM; ++bm)
@@ -327,8 +454,7 @@ __global__ __launch_bounds__(256) void cgemm_kernel(const GemmArgs a) {
               float g = a.flat[p] * rf[p];
               if (a.intrapixel) g *= a.intrapixel[(i % Q) * Q + (j % Q)];
               const float er = c * accr[bm][bn][r], ei = c * acci[bm][bn][r];
-              ob[(long long)i * a.ldo + j] = wphi * g * er;
-              ob[a.out_plane + (long long)i * a.ldo + j] = wphi * g * ei;
+              put<PREC>(ob, a.out_plane, (long long)i * a.ldo + j, wphi * g * er, wphi * g * ei);
               part += (double)g * (double)(er * er + ei * ei);
             }
           }
@@ -386,37 +512,8 @@ __global__ __launch_bounds__(256) void cgemm_kernel(const GemmArgs a) {
     }
   }
 
-  // ------------------------------------------------------------------ group epilogues
-  if constexpr (KIND == KIND_F2) {
-    const int Q = a.Q, Nd = a.n_det;
-    __syncthreads();  // operand LDS is reused for the intensity tile
-#pragma unroll
-    for (int bm = 0; bm < WM; ++bm)
-#pragma unroll
-      for (int bn = 0; bn < WN; ++bn) {
-        const int jj = wc * 16 * WN + bn * 16 + (lane & 15);
-#pragma unroll
-        for (int r = 0; r < 4; ++r) {
-          const int ii = wr * 16 * WM + bm * 16 + 4 * (lane >> 4) + r;
-          float v = sum[bm][bn][r];
-          if (a.intrapixel) v *= a.intrapixel[(ii % Q) * Q + (jj % Q)];
-          smem[ii * BN + jj] = v;
-        }
-      }
-    __syncthreads();
-    const int nbr = BM / Q, nbc = BN / Q;
-    float* dst = a.part + ((long long)(a.frame0 + fl) * a.groups + grp) * Nd * Nd;
-    for (int q = tid; q < nbr * nbc; q += 256) {
-      const int bp = q / nbc, bq = q - bp * nbc;
-      const int pr = row0 / Q + bp, pc = col0 / Q + bq;
-      if (pr < Nd && pc < Nd) {
-        float acc = 0.f;
-        for (int u = 0; u < Q; ++u)
-          for (int v = 0; v < Q; ++v) acc += smem[(bp * Q + u) * BN + bq * Q + v];
-        dst[pr * Nd + pc] = acc;
-      }
-    }
-  } else if constexpr (KIND == KIND_B4) {
+  // ------------------------------------------------------------------ group epilogue
+  if constexpr (KIND == KIND_B4) {
     float* dst = a.part + (long long)grp * M * N;
 #pragma unroll
     for (int bm = 0; bm < WM; ++bm)
@@ -435,19 +532,31 @@ __global__ __launch_bounds__(256) void cgemm_kernel(const GemmArgs a) {
   }
 }
 
-template <int KIND>
+template <int KIND, int PREC>
 hipError_t launch_kind(TileShape ts, const GemmArgs& a, int n_wg, hipStream_t st) {
   const dim3 grid(n_wg), block(256);
   if (ts.wm == 4 && ts.wn == 4) {
-    hipLaunchKernelGGL((cgemm_kernel<KIND, 4, 4>), grid, block, 0, st, a);
+    hipLaunchKernelGGL((cgemm_kernel<KIND, 4, 4, PREC>), grid, block, 0, st, a);
   } else if (ts.wm == 3 && ts.wn == 3) {
-    hipLaunchKernelGGL((cgemm_kernel<KIND, 3, 3>), grid, block, 0, st, a);
+    hipLaunchKernelGGL((cgemm_kernel<KIND, 3, 3, PREC>), grid, block, 0, st, a);
   } else if (ts.wm == 2 && ts.wn == 2) {
-    hipLaunchKernelGGL((cgemm_kernel<KIND, 2, 2>), grid, block, 0, st, a);
+    hipLaunchKernelGGL((cgemm_kernel<KIND, 2, 2, PREC>), grid, block, 0, st, a);
   } else {
     return hipErrorInvalidValue;
   }
   return hipGetLastError();
+}
+
+template <int PREC>
+hipError_t launch_prec(int kind, TileShape ts, const GemmArgs& a, int n_wg, hipStream_t st) {
+  switch (kind) {
+    case KIND_F1: return launch_kind<KIND_F1, PREC>(ts, a, n_wg, st);
+    case KIND_F2: return launch_kind<KIND_F2, PREC>(ts, a, n_wg, st);
+    case KIND_B2: return launch_kind<KIND_B2, PREC>(ts, a, n_wg, st);
+    case KIND_B3: return launch_kind<KIND_B3, PREC>(ts, a, n_wg, st);
+    case KIND_B4: return launch_kind<KIND_B4, PREC>(ts, a, n_wg, st);
+    default: return hipErrorInvalidValue;
+  }
 }
 
 }  // namespace
@@ -456,16 +565,9 @@ bool tile_supported(int, TileShape ts) {
   return (ts.wm == ts.wn) && (ts.wm == 4 || ts.wm == 3 || ts.wm == 2);
 }
 
-hipError_t launch_gemm(int kind, TileShape ts, const GemmArgs& a, int n_wg, hipStream_t st) {
+hipError_t launch_gemm(int kind, int prec, TileShape ts, const GemmArgs& a, int n_wg, hipStream_t st) {
   if (n_wg <= 0) return hipSuccess;
-  switch (kind) {
-    case KIND_F1: return launch_kind<KIND_F1>(ts, a, n_wg, st);
-    case KIND_F2: return launch_kind<KIND_F2>(ts, a, n_wg, st);
-    case KIND_B2: return launch_kind<KIND_B2>(ts, a, n_wg, st);
-    case KIND_B3: return launch_kind<KIND_B3>(ts, a, n_wg, st);
-    case KIND_B4: return launch_kind<KIND_B4>(ts, a, n_wg, st);
-    default: return hipErrorInvalidValue;
-  }
+  return prec == 0 ? launch_prec<0>(kind, ts, a, n_wg, st) : launch_prec<1>(kind, ts, a, n_wg, st);
 }
 
 }  // namespace dlx

@@ -1,7 +1,8 @@
 // Operand preparation for the two-sided MFT (Section 3).
 //
 //   DFT matrices   M_l[k][n] = exp(-2 pi i x_n u_k / lambda_l), stored once per plan as
-//                  M (rows = focal index) and M^T (rows = pupil index), planar FP32.
+//                  M (rows = focal index) and M^T (rows = pupil index), planar FP32, or
+//                  split into bf16 hi/lo planes from the FP64 value (BF16X3 plans).
 //                  x_n u_k / lambda = (2n - Ni + 1)(2k - No + 1) * dx du / (4 lambda):
 //                  the integer product is exact, the scale is FP64 and the result is
 //                  reduced modulo one cycle before sincospi, so the phase error does
@@ -16,7 +17,34 @@
 namespace dlx {
 namespace {
 
-__global__ void dft_matrix_kernel(float* MN, float* MT, int Ni, int No, int ldNi, int ldNo, double s4,
+// Split of an FP64 value into bf16 hi (RNE of the FP32 rounding) and lo (RNE of the rest).
+__device__ __forceinline__ void split64(double x, unsigned short& hi, unsigned short& lo) {
+  const __bf16 h = (__bf16)(float)x;
+  const __bf16 l = (__bf16)(float)(x - (double)(float)h);
+  hi = __builtin_bit_cast(unsigned short, h);
+  lo = __builtin_bit_cast(unsigned short, l);
+}
+
+template <int SPLIT>
+__device__ __forceinline__ void put_m(void* base, long long plane, long long idx, double re, double im) {
+  if constexpr (SPLIT == 0) {
+    float* o = static_cast<float*>(base);
+    o[idx] = (float)re;
+    o[plane + idx] = (float)im;
+  } else {
+    unsigned short* o = static_cast<unsigned short*>(base);
+    unsigned short h, l;
+    split64(re, h, l);
+    o[idx] = h;
+    o[plane + idx] = l;
+    split64(im, h, l);
+    o[2 * plane + idx] = h;
+    o[3 * plane + idx] = l;
+  }
+}
+
+template <int SPLIT>
+__global__ void dft_matrix_kernel(void* MN, void* MT, int Ni, int No, int ldNi, int ldNo, double s4,
                                   const WlInfo* wl, long long mn_plane, long long mn_wl, long long mt_plane,
                                   long long mt_wl) {
   const int l = blockIdx.z;
@@ -24,24 +52,18 @@ __global__ void dft_matrix_kernel(float* MN, float* MT, int Ni, int No, int ldNi
   const int n = blockIdx.x * blockDim.x + threadIdx.x;  // pupil index (padded)
   const int k = blockIdx.y * blockDim.y + threadIdx.y;  // focal index (padded)
   if (n >= ldNi && n >= Ni) return;
-  float re = 0.f, im = 0.f;
+  double re = 0.0, im = 0.0;
   if (n < Ni && k < No) {
     const long long p = (long long)(2 * n - Ni + 1) * (long long)(2 * k - No + 1);
     const double t = (double)p * s;           // cycles
     const double fr = t - rint(t);
     double sn, cs;
     sincospi(2.0 * fr, &sn, &cs);
-    re = (float)cs;
-    im = (float)(-sn);
+    re = cs;
+    im = -sn;
   }
-  if (k < No && n < ldNi) {
-    MN[l * mn_wl + (long long)k * ldNi + n] = re;
-    MN[l * mn_wl + mn_plane + (long long)k * ldNi + n] = im;
-  }
-  if (n < Ni && k < ldNo) {
-    MT[l * mt_wl + (long long)n * ldNo + k] = re;
-    MT[l * mt_wl + mt_plane + (long long)n * ldNo + k] = im;
-  }
+  if (k < No && n < ldNi) put_m<SPLIT>(MN, mn_plane, l * mn_wl + (long long)k * ldNi + n, re, im);
+  if (n < Ni && k < ldNo) put_m<SPLIT>(MT, mt_plane, l * mt_wl + (long long)n * ldNo + k, re, im);
 }
 
 // Coordinates of the pupil samples (x and y grids are identical).
@@ -202,8 +224,12 @@ hipError_t launch_dft(dlx_plan* p, hipStream_t st) {
   const long long mn_plane = (long long)p->L * p->No * p->ldNi;
   const long long mt_plane = (long long)p->L * p->Ni * p->ldNo;
   const double s4 = p->dx * p->du / 4.0;
-  hipLaunchKernelGGL(dft_matrix_kernel, grid, blk, 0, st, p->d_MN, p->d_MT, p->Ni, p->No, p->ldNi, p->ldNo, s4,
-                     p->d_wl, mn_plane, (long long)p->No * p->ldNi, mt_plane, (long long)p->Ni * p->ldNo);
+  if (p->bf16())
+    hipLaunchKernelGGL(dft_matrix_kernel<1>, grid, blk, 0, st, p->d_MN, p->d_MT, p->Ni, p->No, p->ldNi, p->ldNo, s4,
+                       p->d_wl, mn_plane, (long long)p->No * p->ldNi, mt_plane, (long long)p->Ni * p->ldNo);
+  else
+    hipLaunchKernelGGL(dft_matrix_kernel<0>, grid, blk, 0, st, p->d_MN, p->d_MT, p->Ni, p->No, p->ldNi, p->ldNo, s4,
+                       p->d_wl, mn_plane, (long long)p->No * p->ldNi, mt_plane, (long long)p->Ni * p->ldNo);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL(coords_kernel, dim3((p->Ni + 255) / 256), dim3(256), 0, st, p->d_x, p->Ni, p->dx);

@@ -8,18 +8,41 @@
 namespace dlx {
 namespace {
 
-// binned[f][p] = sum_g part[f][g][p];  model[f][p] = flat[p] * binned[f][p]
-__global__ void bin_reduce_kernel(const float* part, int G, int f0, int F, long long npix, const float* flat,
-                                  float* binned, float* model) {
+// Intensity, intra-pixel weighting, binning and pixel response (Section 3)
+// from the stored focal fields E of frames [f0, f0 + nf):
+//   binned[f][p] = sum_s sum_l w_l phi_s sum_{a,b<Q} K[a][b] |E[Qp_r + a][Qp_c + b]|^2,
+//   model[f][p] = flat[p] * binned[f][p].
+// One thread per detector pixel; star, wavelength and sub-pixel sums in a fixed order.
+__global__ void intensity_kernel(const float* E, long long plane, long long by_psf, int ld, int f0, int F, int S, int L,
+                                 int Q, int Nd, const float* sources, const WlInfo* wl, const float* intrapixel,
+                                 const float* flat, float* binned, float* model) {
+  const long long npix = (long long)Nd * Nd;
   const long long p = (long long)blockIdx.x * blockDim.x + threadIdx.x;
   const int f = f0 + blockIdx.y;
   if (p >= npix || f >= F) return;
-  const float* src = part + (long long)f * G * npix + p;
+  const int pr = (int)(p / Nd), pc = (int)(p - (long long)pr * Nd);
   double acc = 0.0;
-  for (int g = 0; g < G; ++g) acc += (double)src[(long long)g * npix];
-  const float b = (float)acc;
-  binned[(long long)f * npix + p] = b;
-  model[(long long)f * npix + p] = flat[p] * b;
+  for (int s = 0; s < S; ++s) {
+    const float phi = sources[(f * S + s) * 3 + 2];
+    for (int l = 0; l < L; ++l) {
+      const long long lb = (long long)((f - f0) * S + s) * L + l;
+      const float* e = E + lb * by_psf + (long long)(Q * pr) * ld + Q * pc;
+      float part = 0.f;
+      for (int a = 0; a < Q; ++a) {
+#pragma unroll 4
+        for (int b = 0; b < Q; ++b) {
+          const float er = e[(long long)a * ld + b], ei = e[plane + (long long)a * ld + b];
+          float v = er * er + ei * ei;
+          if (intrapixel) v *= intrapixel[a * Q + b];
+          part += v;
+        }
+      }
+      acc += (double)(wl[l].w * phi) * (double)part;
+    }
+  }
+  const float bv = (float)acc;
+  binned[(long long)f * npix + p] = bv;
+  model[(long long)f * npix + p] = flat[p] * bv;
 }
 
 constexpr int kLossThreads = 256;
@@ -99,9 +122,12 @@ __global__ void final_sum_kernel(const double* blk, int n, double* out) {
 // Adjoint seed from stored focal fields (fused evaluation): in place
 // Y = w phi G E with G[k][l] = K[k%Q][l%Q] flat[p] r_f[p], p = (k/Q, l/Q);
 // per (PSF, row block) FP64 partial of w sum G |E|^2 (the flux gradient).
+// With a split output (BF16X3) the seed is written as bf16 hi/lo planes to Ys
+// and E is left in place.
+template <int SPLIT>
 __global__ void seed_kernel(float* Y, long long plane, long long by_psf, int ld, int psf0, int No, int Q, int Nd,
                             int S, int L, const float* sources, const WlInfo* wl, const float* flat, const float* resid,
-                            const float* intrapixel, int rows_per_blk, int nblk, double* flux) {
+                            const float* intrapixel, int rows_per_blk, int nblk, double* flux, unsigned short* Ys) {
   __shared__ double sh[4];
   const int lb = blockIdx.x / nblk;
   const int blk = blockIdx.x - lb * nblk;
@@ -123,10 +149,21 @@ __global__ void seed_kernel(float* Y, long long plane, long long by_psf, int ld,
     const int p = (k / Q) * Nd + (l / Q);
     float g = flat[p] * rf[p];
     if (intrapixel) g *= intrapixel[(k % Q) * Q + (l % Q)];
-    float* e = yb + (long long)k * ld + l;
+    const long long off = (long long)k * ld + l;
+    float* e = yb + off;
     const float er = e[0], ei = e[plane];
-    e[0] = wphi * g * er;
-    e[plane] = wphi * g * ei;
+    const float yr = wphi * g * er, yi = wphi * g * ei;
+    if constexpr (SPLIT == 0) {
+      e[0] = yr;
+      e[plane] = yi;
+    } else {
+      unsigned short* o = Ys + (long long)lb * by_psf + off;
+      const __bf16 hr = (__bf16)yr, hi = (__bf16)yi;
+      o[0] = __builtin_bit_cast(unsigned short, hr);
+      o[plane] = __builtin_bit_cast(unsigned short, (__bf16)(yr - (float)hr));
+      o[2 * plane] = __builtin_bit_cast(unsigned short, hi);
+      o[3 * plane] = __builtin_bit_cast(unsigned short, (__bf16)(yi - (float)hi));
+    }
     part += (double)g * (double)(er * er + ei * ei);
   }
 #pragma unroll
@@ -141,6 +178,7 @@ __global__ void gopd_reduce_kernel(const float* gpart, int G, long long npix, do
   const long long p = (long long)blockIdx.x * blockDim.x + threadIdx.x;
   if (p >= npix) return;
   double acc = 0.0;
+#pragma unroll 8
   for (int g = 0; g < G; ++g) acc += (double)gpart[(long long)g * npix + p];
   gopd[p] = acc;
 }
@@ -177,12 +215,14 @@ __global__ void zproj_partial_kernel(const float* Z, const double* gopd, int Nz,
   }
 }
 
+// one 64-thread wave per term: strided partial sums, then a fixed butterfly
 __global__ void zproj_final_kernel(const double* part, int Nz, int nchunks, double* grad) {
-  const int j = blockIdx.x * blockDim.x + threadIdx.x;
-  if (j >= Nz) return;
+  const int j = blockIdx.x;
   double acc = 0.0;
-  for (int c = 0; c < nchunks; ++c) acc += part[(long long)c * Nz + j];
-  grad[j] = acc;
+  for (int c = threadIdx.x; c < nchunks; c += 64) acc += part[(long long)c * Nz + j];
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) acc += __shfl_xor(acc, o, 64);
+  if (threadIdx.x == 0) grad[j] = acc;
 }
 
 // tmp2[m][k] = sum_n gopd[m][n] B[n][k]
@@ -232,11 +272,12 @@ __global__ void src_reduce_kernel(const double* flux, int tiles_b2, const double
 
 }  // namespace
 
-hipError_t launch_bin_reduce(dlx_plan* p, int f0, int nf, const float* flat, float* binned, float* model,
-                             hipStream_t st) {
+hipError_t launch_intensity(dlx_plan* p, int f0, int nf, const float* sources, const float* intrapixel,
+                            const float* flat, float* binned, float* model, hipStream_t st) {
   const long long npix = (long long)p->Nd * p->Nd;
-  hipLaunchKernelGGL(bin_reduce_kernel, dim3((unsigned)((npix + 255) / 256), nf), dim3(256), 0, st, p->d_binpart,
-                     p->f2_groups, f0, p->F, npix, flat, binned, model);
+  hipLaunchKernelGGL(intensity_kernel, dim3((unsigned)((npix + 255) / 256), nf), dim3(256), 0, st, p->d_Y,
+                     (long long)p->chunk_psf * p->No * p->ldNo, (long long)p->No * p->ldNo, p->ldNo, f0, p->F, p->S,
+                     p->L, p->Q, p->Nd, sources, p->d_wl, intrapixel, flat, binned, model);
   return hipGetLastError();
 }
 
@@ -245,9 +286,15 @@ hipError_t launch_seed(dlx_plan* p, int f0, int nf, const float* sources, const 
   const int nc = nf * p->S * p->L;
   const int nblk = p->tiles_b2;
   const int rows = (p->No + nblk - 1) / nblk;
-  hipLaunchKernelGGL(seed_kernel, dim3(nc * nblk), dim3(256), 0, st, p->d_Y, (long long)p->chunk_psf * p->No * p->ldNo,
-                     (long long)p->No * p->ldNo, p->ldNo, f0 * p->S * p->L, p->No, p->Q, p->Nd, p->S, p->L, sources,
-                     p->d_wl, flat, resid, intrapixel, rows, nblk, p->d_flux);
+  const long long plane = (long long)p->chunk_psf * p->No * p->ldNo, by = (long long)p->No * p->ldNo;
+  if (p->bf16())
+    hipLaunchKernelGGL(seed_kernel<1>, dim3(nc * nblk), dim3(256), 0, st, p->d_Y, plane, by, p->ldNo,
+                       f0 * p->S * p->L, p->No, p->Q, p->Nd, p->S, p->L, sources, p->d_wl, flat, resid, intrapixel,
+                       rows, nblk, p->d_flux, static_cast<unsigned short*>(p->d_Ys));
+  else
+    hipLaunchKernelGGL(seed_kernel<0>, dim3(nc * nblk), dim3(256), 0, st, p->d_Y, plane, by, p->ldNo,
+                       f0 * p->S * p->L, p->No, p->Q, p->Nd, p->S, p->L, sources, p->d_wl, flat, resid, intrapixel,
+                       rows, nblk, p->d_flux, nullptr);
   return hipGetLastError();
 }
 
@@ -291,7 +338,7 @@ hipError_t launch_grad_reduce(dlx_plan* p, const float* Z, const float* Bm, doub
     const long long chunk = (npix + nch - 1) / nch;
     hipLaunchKernelGGL(zproj_partial_kernel, dim3((p->Nz + kZGroup - 1) / kZGroup, nch), dim3(256), 0, st, Z,
                        p->d_gopd, p->Nz, npix, chunk, p->d_zpart);
-    hipLaunchKernelGGL(zproj_final_kernel, dim3((p->Nz + 63) / 64), dim3(64), 0, st, p->d_zpart, p->Nz, nch, gz);
+    hipLaunchKernelGGL(zproj_final_kernel, dim3(p->Nz), dim3(64), 0, st, p->d_zpart, p->Nz, nch, gz);
   }
   if (p->Nmap > 0) {
     hipLaunchKernelGGL(map_grad1_kernel, dim3(p->Ni), dim3((p->Nmap + 63) / 64 * 64), 0, st, p->d_gopd, Bm, p->Ni,
