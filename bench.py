@@ -35,6 +35,33 @@ WORKLOADS = {
 }
 
 
+def measured_traffic(config, precision, stage):
+    """HBM bytes per launch of `stage` from the committed rocprofv3 counter summary.
+
+    FETCH_SIZE and WRITE_SIZE (KiB per dispatch) are scaled by what the same
+    counters read for a plain copy kernel of known size. Returns None when no
+    summary exists or when the GEMM source changed since it was taken.
+    """
+    import hashlib
+    path = os.path.join(ROOT, "profiles", f"traffic_{config}_{precision}.txt")
+    src = os.path.join(ROOT, "paper_2406_08703_amd", "csrc", "mft_gemm.hip")
+    if not os.path.exists(path):
+        return None
+    fields, stages = {}, {}
+    for line in open(path):
+        parts = line.split()
+        if len(parts) == 2 and parts[0] in ("fetch_scale", "write_scale", "kernel_source_sha256"):
+            fields[parts[0]] = parts[1]
+        elif len(parts) == 6 and parts[0] == "stage":
+            stages[parts[1]] = (float(parts[4]), float(parts[5]))
+    if fields.get("kernel_source_sha256") != hashlib.sha256(open(src, "rb").read()).hexdigest():
+        return None
+    if stage not in stages:
+        return None
+    f, w = stages[stage]
+    return round(1024.0 * (f * float(fields["fetch_scale"]) + w * float(fields["write_scale"])))
+
+
 def stage_flops(P, stage):
     ni, no = P.n_pupil, P.n_focal
     return {"F1": 8.0 * no * ni * ni, "F2": 8.0 * no * no * ni, "B2": 8.0 * no * no * ni,
@@ -176,6 +203,7 @@ def main():
                     "traffic": None, "flops_per_launch": 3.0 * flops_per_launch,
                     "avg_launch_ms": round(dv["avg_launch_ms"], 5), "fp32_equivalent_tflops": round(achieved, 3),
                     "frac_of_fp32_mfma_peak": round(achieved / FP32_MFMA_PEAK_TFLOPS, 4)}
+    roofline["traffic"] = measured_traffic(args.config, args.precision, dom)
     gemm_ms = sum(v["ms_per_step"] for v in gemm.values())
     all_ms = sum(v["ms_per_step"] for v in table.values())
 

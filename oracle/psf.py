@@ -258,15 +258,13 @@ def binned_pixels(prob: OracleProblem, coeffs, phase_map, sources, frame, pixels
     Q = prob.oversample
     K = prob.intrapixel if prob.intrapixel is not None else np.ones((Q, Q))
     out = np.zeros(len(pixels))
-    for i, (p, q) in enumerate(pixels):
-        rows = u[Q * p:Q * p + Q]
-        cols = u[Q * q:Q * q + Q]
-        acc = 0.0
-        for s in range(sources.shape[1]):
-            a, b, phi = sources[frame, s]
-            for lam, w in zip(prob.wavelengths, prob.weights):
-                P = pupil_field(prob.transmission, opd, x, x, a, b, lam)
+    for s in range(sources.shape[1]):
+        a, b, phi = sources[frame, s]
+        for lam, w in zip(prob.wavelengths, prob.weights):
+            P = pupil_field(prob.transmission, opd, x, x, a, b, lam)
+            for i, (p, q) in enumerate(pixels):
+                rows = u[Q * p:Q * p + Q]
+                cols = u[Q * q:Q * q + Q]
                 E = focal_field(P, x, x, cols, rows, lam, prob.dx * prob.focal_pixel / lam)
-                acc += w * phi * np.sum(K * np.abs(E) ** 2)
-        out[i] = acc
+                out[i] += w * phi * np.sum(K * np.abs(E) ** 2)
     return out
