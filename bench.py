@@ -133,7 +133,7 @@ def main():
                     P.n_frames, P.n_zernike, P.n_map, P.diameter, P.focal_pixel)
     plan = PsfPlan(geom, dev(w.transmission), dev(w.zbasis), dev(w.map_basis), dev(w.intrapixel),
                    precision=args.precision)
-    log(f"precision {args.precision}, plan workspace {plan.workspace_bytes / 2**30:.2f} GiB")
+    log(f"precision {args.precision}, plan workspace {plan.workspace_bytes / 2**30:.2f} GiB, tiles {plan.tiles}")
     ep = w.eval_params()
     c, pm, s, fl, d = dev(ep["coeffs"]), dev(ep["phase_map"]), dev(ep["sources"]), dev(ep["flat"]), dev(w.data)
     ebuf = EvalBuffers(plan)
@@ -263,6 +263,7 @@ def main():
                           "frac_fp32_mfma_peak_algorithmic": round(tf_alg / FP32_MFMA_PEAK_TFLOPS, 4),
                           "frac_fp32_mfma_peak_executed": round(tf_exec / FP32_MFMA_PEAK_TFLOPS, 4)},
            "mode": args.mode, "eager_ms_per_step": round(t_eager * 1e3 / args.steps, 4),
+           "tiles": {k: f"{v[0]}x{v[1]}" for k, v in plan.tiles.items()},
            "stage_ms_per_step": {k: round(v["ms_per_step"], 5) for k, v in table.items()},
            "gemm_share_of_step": round(gemm_ms / all_ms, 4) if all_ms else None,
            "roofline": roofline, "rel_err_vs_fp64": parity, "cpu_baseline": cpu}

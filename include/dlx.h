@@ -91,10 +91,19 @@ typedef struct dlx_plan dlx_plan;
  * Returns DLX_OK, DLX_ERR_INVALID_ARG or DLX_ERR_SHAPE. */
 dlx_status dlx_validate(const dlx_problem_desc* probs, int32_t n_probs);
 
+/* Plan flags. By default dlx_plan_create autotunes: for each MFT stage it
+ * times every compiled output-tile shape on the plan's own (zeroed)
+ * workspace for the first frame chunk and keeps the fastest.
+ * DLX_FLAG_NO_AUTOTUNE keeps the built-in size heuristic instead. */
+enum { DLX_FLAG_NO_AUTOTUNE = 1 };
+
 /* Create a plan: validates, picks kernel tiles, allocates every workspace on
  * the current device and builds the DFT matrices of each wavelength (FP64
- * phase, FP32 storage). n_probs must be 1 in this build (others:
- * DLX_ERR_UNSUPPORTED). flags: 0. workspace_limit_bytes: 0 = no limit;
+ * phase; FP32, or bf16 hi/lo planes for DLX_BF16X3). n_probs must be 1 in
+ * this build (others: DLX_ERR_UNSUPPORTED). flags: 0 or DLX_FLAG_NO_AUTOTUNE
+ * (others: DLX_ERR_INVALID_ARG). Results do not depend on the tiles chosen
+ * except for the order of FP32/FP64 partial sums in the gradient
+ * reductions. workspace_limit_bytes: 0 = no limit;
  * otherwise the frame-chunk size is reduced until the workspace fits, and
  * DLX_ERR_OOM is returned if even one frame does not.
  * On success *out owns the device memory until dlx_plan_destroy. */
@@ -106,6 +115,11 @@ dlx_status dlx_plan_destroy(dlx_plan* plan);
 
 /* Device bytes the plan holds. */
 size_t dlx_plan_workspace_bytes(const dlx_plan* plan);
+
+/* Output-tile shape of each MFT stage (autotuned or heuristic): tiles[2k],
+ * tiles[2k+1] = rows/32 and columns/32 of a workgroup's tile for stage
+ * k = F1, F2, B2, B3, B4 (host int32_t[10]). */
+dlx_status dlx_plan_tiles(const dlx_plan* plan, int32_t* tiles);
 
 /* Synchronise `stream`, then return and clear the plan's device status word
  * (DLX_OK, DLX_ERR_NONFINITE or DLX_ERR_DOMAIN). */

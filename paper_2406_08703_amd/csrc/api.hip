@@ -86,14 +86,16 @@ void layout(dlx_plan* p, Pool& pool) {
   p->d_Y = pool.take<float>(2 * CP * No * ldNo);
   p->d_UT = pool.take<float>(2 * CP * Ni * ldNo);
   p->d_Ys = p->bf16() ? static_cast<void*>(pool.take<float>(2 * CP * No * ldNo)) : nullptr;
-  p->d_gpart = pool.take<float>((size_t)p->b4_groups_max * p->b4_ksplit * Ni * Ni);
+  p->d_gpart = pool.take<float>((size_t)p->b4_groups_max * p->ksplit_cap * Ni * Ni);
   p->d_gopd = pool.take<double>(Ni * Ni);
-  p->d_flux = pool.take<double>((size_t)p->n_psf * p->tiles_b2);
-  p->d_pos = pool.take<double>((size_t)p->n_psf * p->b4_ksplit * p->tiles_b4 * 2);
+  p->d_flux = pool.take<double>((size_t)p->n_psf * p->tiles_b2_cap);
+  p->d_pos = pool.take<double>((size_t)p->n_psf * p->ksplit_cap * p->tiles_b4_cap * 2);
   p->d_lossblk = pool.take<double>((size_t)p->loss_blocks * p->n_chunks);
   p->d_tmp2 = pool.take<double>(std::max<size_t>(1, Ni * (size_t)p->Nmap));
   p->d_zpart = pool.take<double>((size_t)std::max(1, zproj_chunks((long long)Ni * Ni, p->Nz)) * std::max(1, p->Nz));
   p->d_status = pool.take<int>(1);
+  // autotuning stand-ins for caller arrays read by B2: flat [Nd^2], residual [frames_per_chunk][Nd^2], sources
+  p->d_tune = pool.take<float>((size_t)(p->frames_per_chunk + 1) * p->Nd * p->Nd + (size_t)p->F * p->S * 3);
 }
 
 size_t per_psf_bytes(const dlx_plan* p) {
@@ -219,28 +221,27 @@ hipError_t run_f2(dlx_plan* p, int f0, int nf, hipStream_t st) {
   return launch_gemm(KIND_F2, p->bf16(), p->ts_f2, a, wg_count(a), st);
 }
 
-// B3 and B4 over frames [f0, f0 + nf) of chunk c, from the seed Y in the Y buffer.
-hipError_t run_adjoint(dlx_plan* p, int c, int f0, int nf, hipStream_t st) {
+// B3 over frames [f0, f0 + nf): U^T = conj(M)^T Y^T from the seed Y.
+hipError_t run_b3(dlx_plan* p, int f0, int nf, hipStream_t st) {
+  GemmArgs a = base_args(p, f0, nf);
+  a.M = p->Ni;
+  a.N = p->No;
+  a.K = p->No;
+  a.n_items = nf * p->S * p->L;
+  a.A = op_MT(p);
+  a.conj_a = 1;
+  a.B = op_Y(p);
+  a.out = p->d_UT;
+  a.out_plane = op_UT(p).plane;
+  a.out_by_psf = op_UT(p).by_psf;
+  a.ldo = p->ldNo;
+  set_tiles(a, p->ts_b3);
+  return launch_gemm(KIND_B3, p->bf16(), p->ts_b3, a, wg_count(a), st);
+}
+
+// B4 over frames [f0, f0 + nf) of chunk c: W = c M^H U, phase gradient and position sums.
+hipError_t run_b4(dlx_plan* p, int c, int f0, int nf, hipStream_t st) {
   const int nc = nf * p->S * p->L;
-  {
-    Stage sg(p, st, DLX_STAGE_B3, nc);
-    GemmArgs a = base_args(p, f0, nf);
-    a.M = p->Ni;
-    a.N = p->No;
-    a.K = p->No;
-    a.n_items = nc;
-    a.A = op_MT(p);
-    a.conj_a = 1;
-    a.B = op_Y(p);
-    a.out = p->d_UT;
-    a.out_plane = op_UT(p).plane;
-    a.out_by_psf = op_UT(p).by_psf;
-    a.ldo = p->ldNo;
-    set_tiles(a, p->ts_b3);
-    hipError_t e = launch_gemm(KIND_B3, p->bf16(), p->ts_b3, a, wg_count(a), st);
-    if (e != hipSuccess) return e;
-  }
-  Stage sg(p, st, DLX_STAGE_B4, nc);
   GemmArgs a = base_args(p, f0, nf);
   a.M = p->Ni;
   a.N = p->Ni;
@@ -257,6 +258,115 @@ hipError_t run_adjoint(dlx_plan* p, int c, int f0, int nf, hipStream_t st) {
   a.red = p->d_pos;
   set_tiles(a, p->ts_b4);
   return launch_gemm(KIND_B4, p->bf16(), p->ts_b4, a, wg_count(a), st);
+}
+
+// B3 and B4 of chunk c.
+hipError_t run_adjoint(dlx_plan* p, int c, int f0, int nf, hipStream_t st) {
+  const int nc = nf * p->S * p->L;
+  {
+    Stage sg(p, st, DLX_STAGE_B3, nc);
+    hipError_t e = run_b3(p, f0, nf, st);
+    if (e != hipSuccess) return e;
+  }
+  Stage sg(p, st, DLX_STAGE_B4, nc);
+  return run_b4(p, c, f0, nf, st);
+}
+
+GemmArgs e_args(dlx_plan* p, int f0, int nf, TileShape ts);
+
+// B2 over frames [f0, f0 + nf): recompute E, seed Y = w phi G E, flux partials.
+hipError_t run_b2(dlx_plan* p, int f0, int nf, const float* sources, const float* flat, const float* resid,
+                  const float* intrapixel, hipStream_t st) {
+  GemmArgs a = e_args(p, f0, nf, p->ts_b2);
+  a.n_items = nf * p->S * p->L;
+  a.sources = sources;
+  a.out = const_cast<void*>(op_Y(p).base);
+  a.out_plane = op_Y(p).plane;
+  a.out_by_psf = op_Y(p).by_psf;
+  a.ldo = p->ldNo;
+  a.red = p->d_flux;
+  a.flat = flat;
+  a.resid = resid;
+  a.intrapixel = intrapixel;
+  return launch_gemm(KIND_B2, p->bf16(), p->ts_b2, a, wg_count(a), st);
+}
+
+// Tile-dependent derived sizes: partial-sum tile counts and B4's split of K.
+void derive_tiles(dlx_plan* p) {
+  p->tiles_b2 = ceil_div(p->No, p->ts_b2.bm()) * ceil_div(p->No, p->ts_b2.bn());
+  p->tiles_b4 = ceil_div(p->Ni, p->ts_b4.bm()) * ceil_div(p->Ni, p->ts_b4.bn());
+  // split B4's K (= No) when its groups alone cannot fill the chip, keeping >= 128 per split
+  const long long wg = (long long)p->tiles_b4 * p->b4_groups_max;
+  int ks = 1;
+  while (ks < 4 && wg * ks < kTargetWG && p->No / (2 * ks) >= 128) ks *= 2;
+  p->b4_ksplit = ks;
+}
+
+// ---- autotuner: time every compiled tile shape per MFT stage on chunk 0
+hipError_t run_stage_for_tuning(dlx_plan* p, int kind, hipStream_t st) {
+  const int nf = std::min(p->frames_per_chunk, p->F);
+  const size_t nd2 = (size_t)p->Nd * p->Nd;
+  const float* flat = p->d_tune;
+  const float* resid = p->d_tune + nd2;
+  const float* src = p->d_tune + nd2 * (p->frames_per_chunk + 1);
+  switch (kind) {
+    case KIND_F1: return run_f1(p, 0, nf, st);
+    case KIND_F2: return run_f2(p, 0, nf, st);
+    case KIND_B2: return run_b2(p, 0, nf, src, flat, resid, nullptr, st);
+    case KIND_B3: return run_b3(p, 0, nf, st);
+    default: return run_b4(p, 0, 0, nf, st);
+  }
+}
+
+TileShape* stage_tile(dlx_plan* p, int kind) {
+  switch (kind) {
+    case KIND_F1: return &p->ts_f1;
+    case KIND_F2: return &p->ts_f2;
+    case KIND_B2: return &p->ts_b2;
+    case KIND_B3: return &p->ts_b3;
+    default: return &p->ts_b4;
+  }
+}
+
+// Runs on the zeroed workspace with the DFT matrices built, so every operand is finite.
+hipError_t autotune(dlx_plan* p) {
+  hipError_t e;
+  hipEvent_t t0, t1;
+  if ((e = hipEventCreate(&t0)) != hipSuccess) return e;
+  if ((e = hipEventCreate(&t1)) != hipSuccess) {
+    (void)hipEventDestroy(t0);
+    return e;
+  }
+  const int kinds[5] = {KIND_F1, KIND_F2, KIND_B2, KIND_B3, KIND_B4};
+  for (int kind : kinds) {
+    TileShape* ts = stage_tile(p, kind);
+    TileShape best = *ts;
+    float best_ms = 1e30f;
+    for (const TileShape& cand : kTileShapes) {
+      *ts = cand;
+      derive_tiles(p);
+      if ((e = run_stage_for_tuning(p, kind, nullptr)) != hipSuccess) break;   // warm-up
+      if ((e = hipEventRecord(t0, nullptr)) != hipSuccess) break;
+      for (int r = 0; r < 2 && e == hipSuccess; ++r) e = run_stage_for_tuning(p, kind, nullptr);
+      if (e != hipSuccess) break;
+      if ((e = hipEventRecord(t1, nullptr)) != hipSuccess) break;
+      if ((e = hipEventSynchronize(t1)) != hipSuccess) break;
+      float ms = 0.f;
+      if ((e = hipEventElapsedTime(&ms, t0, t1)) != hipSuccess) break;
+      if (ms < best_ms) {
+        best_ms = ms;
+        best = cand;
+      }
+    }
+    *ts = best;
+    derive_tiles(p);
+    if (e != hipSuccess) break;
+  }
+  (void)hipEventDestroy(t0);
+  (void)hipEventDestroy(t1);
+  if (e == hipSuccess) e = hipDeviceSynchronize();
+  p->tuned = e == hipSuccess;
+  return e;
 }
 
 GemmArgs e_args(dlx_plan* p, int f0, int nf, TileShape ts) {
@@ -317,7 +427,7 @@ dlx_status dlx_plan_create(const dlx_problem_desc* probs, int32_t n_probs, dlx_p
   dlx_status v = dlx_validate(probs, n_probs);
   if (v != DLX_OK) return v;
   if (precision != DLX_FP32 && precision != DLX_BF16X3) return DLX_ERR_INVALID_ARG;
-  if (flags != 0) return DLX_ERR_INVALID_ARG;
+  if ((flags & ~DLX_FLAG_NO_AUTOTUNE) != 0) return DLX_ERR_INVALID_ARG;
   if (n_probs != 1) return DLX_ERR_UNSUPPORTED;
   const dlx_problem_desc& d = probs[0];
 
@@ -372,15 +482,11 @@ dlx_status dlx_plan_create(const dlx_problem_desc* probs, int32_t n_probs, dlx_p
     p->b4_groups_max = ceil_div(p->chunk_psf, p->b4_gsize);
     p->ts_b4 = choose_tile(p->Ni, p->Ni, p->b4_groups_max, 1);
   }
-  p->tiles_b2 = ceil_div(p->No, p->ts_b2.bm()) * ceil_div(p->No, p->ts_b2.bn());
-  p->tiles_b4 = ceil_div(p->Ni, p->ts_b4.bm()) * ceil_div(p->Ni, p->ts_b4.bn());
-  {
-    // split B4's K (= No) when its groups alone cannot fill the chip, keeping >= 128 per split
-    const long long wg = (long long)p->tiles_b4 * p->b4_groups_max;
-    int ks = 1;
-    while (ks < 4 && wg * ks < kTargetWG && p->No / (2 * ks) >= 128) ks *= 2;
-    p->b4_ksplit = ks;
-  }
+  derive_tiles(p);
+  // partial-sum buffers are sized for the smallest candidate tile (32 x 32) and the largest split
+  p->tiles_b2_cap = ceil_div(p->No, 32) * ceil_div(p->No, 32);
+  p->tiles_b4_cap = ceil_div(p->Ni, 32) * ceil_div(p->Ni, 32);
+  p->ksplit_cap = 4;
   p->loss_blocks = loss_block_count((long long)p->Nd * p->Nd);
   {
     const long long npix = (long long)p->Ni * p->Ni;
@@ -416,9 +522,11 @@ dlx_status dlx_plan_create(const dlx_problem_desc* probs, int32_t n_probs, dlx_p
     wl[l].kphase = (float)(kTwoPi / p->lam[l]);
     wl[l].pad = 0.f;
   }
-  hipError_t e = hipMemcpy(p->d_wl, wl.data(), sizeof(WlInfo) * p->L, hipMemcpyHostToDevice);
-  if (e == hipSuccess) e = hipMemset(p->d_status, 0, sizeof(int));
+  hipError_t e = hipMemset(p->pool, 0, p->pool_bytes);
+  if (e == hipSuccess) e = hipMemcpy(p->d_wl, wl.data(), sizeof(WlInfo) * p->L, hipMemcpyHostToDevice);
   if (e == hipSuccess) e = launch_dft(p, nullptr);
+  if (e == hipSuccess && !(flags & DLX_FLAG_NO_AUTOTUNE)) e = autotune(p);
+  if (e == hipSuccess) e = hipMemset(p->d_status, 0, sizeof(int));
   if (e == hipSuccess) e = hipDeviceSynchronize();
   if (e != hipSuccess) {
     (void)hipFree(p->pool);
@@ -442,6 +550,16 @@ dlx_status dlx_plan_destroy(dlx_plan* p) {
 }
 
 size_t dlx_plan_workspace_bytes(const dlx_plan* p) { return p ? p->pool_bytes : 0; }
+
+dlx_status dlx_plan_tiles(const dlx_plan* p, int32_t* tiles) {
+  if (!p || !tiles) return DLX_ERR_INVALID_ARG;
+  const TileShape t[5] = {p->ts_f1, p->ts_f2, p->ts_b2, p->ts_b3, p->ts_b4};
+  for (int k = 0; k < 5; ++k) {
+    tiles[2 * k] = t[k].wm;
+    tiles[2 * k + 1] = t[k].wn;
+  }
+  return DLX_OK;
+}
 
 dlx_status dlx_plan_profile(dlx_plan* p, int32_t enable) {
   if (!p) return DLX_ERR_INVALID_ARG;
@@ -559,18 +677,7 @@ dlx_status dlx_psf_backward(dlx_plan* p, const float* transmission, const float*
     }
     {  // B2: recompute E, seed Y = w phi G E
       Stage sg(p, st, DLX_STAGE_B2, nc);
-      GemmArgs a = e_args(p, f0, nf, p->ts_b2);
-      a.n_items = nc;
-      a.sources = sources;
-      a.out = const_cast<void*>(op_Y(p).base);
-      a.out_plane = op_Y(p).plane;
-      a.out_by_psf = op_Y(p).by_psf;
-      a.ldo = p->ldNo;
-      a.red = p->d_flux;
-      a.flat = flat;
-      a.resid = dloss_dmodel;
-      a.intrapixel = intrapixel;
-      DLX_HIP(launch_gemm(KIND_B2, p->bf16(), p->ts_b2, a, wg_count(a), st));
+      DLX_HIP(run_b2(p, f0, nf, sources, flat, dloss_dmodel, intrapixel, st));
     }
     DLX_HIP(run_adjoint(p, c, f0, nf, st));
   }

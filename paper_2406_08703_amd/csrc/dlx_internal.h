@@ -97,6 +97,9 @@ struct TileShape {
   int bn() const { return 32 * wn; }
 };
 
+// Tile shapes compiled for every stage and precision (the autotuner's candidates).
+constexpr TileShape kTileShapes[] = {{4, 4}, {3, 3}, {2, 2}, {4, 2}, {2, 4}, {2, 1}, {1, 2}};
+
 hipError_t launch_gemm(int kind, int prec, TileShape ts, const GemmArgs& a, int n_wg, hipStream_t st);
 bool tile_supported(int kind, TileShape ts);
 
@@ -157,6 +160,9 @@ struct dlx_plan {
   long long stage_launches[DLX_N_STAGES] = {};
   long long stage_psfs[DLX_N_STAGES] = {};
   int tiles_b2 = 0, tiles_b4 = 0;
+  int tiles_b2_cap = 0, tiles_b4_cap = 0, ksplit_cap = 1;   // sizes the partial-sum buffers
+  float* d_tune = nullptr;
+  bool tuned = false;
   // captured evaluation
   hipStream_t cap_stream = nullptr;
   hipGraph_t graph = nullptr;

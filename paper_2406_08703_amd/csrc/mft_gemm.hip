@@ -535,16 +535,20 @@ __global__ __launch_bounds__(256) void cgemm_kernel(const GemmArgs a) {
 template <int KIND, int PREC>
 hipError_t launch_kind(TileShape ts, const GemmArgs& a, int n_wg, hipStream_t st) {
   const dim3 grid(n_wg), block(256);
-  if (ts.wm == 4 && ts.wn == 4) {
-    hipLaunchKernelGGL((cgemm_kernel<KIND, 4, 4, PREC>), grid, block, 0, st, a);
-  } else if (ts.wm == 3 && ts.wn == 3) {
-    hipLaunchKernelGGL((cgemm_kernel<KIND, 3, 3, PREC>), grid, block, 0, st, a);
-  } else if (ts.wm == 2 && ts.wn == 2) {
-    hipLaunchKernelGGL((cgemm_kernel<KIND, 2, 2, PREC>), grid, block, 0, st, a);
-  } else {
-    return hipErrorInvalidValue;
+#define DLX_TILE(WM_, WN_)                                                                     \
+  if (ts.wm == WM_ && ts.wn == WN_) {                                                          \
+    hipLaunchKernelGGL((cgemm_kernel<KIND, WM_, WN_, PREC>), grid, block, 0, st, a);          \
+    return hipGetLastError();                                                                  \
   }
-  return hipGetLastError();
+  DLX_TILE(4, 4)
+  DLX_TILE(3, 3)
+  DLX_TILE(2, 2)
+  DLX_TILE(4, 2)
+  DLX_TILE(2, 4)
+  DLX_TILE(2, 1)
+  DLX_TILE(1, 2)
+#undef DLX_TILE
+  return hipErrorInvalidValue;
 }
 
 template <int PREC>
@@ -562,7 +566,9 @@ hipError_t launch_prec(int kind, TileShape ts, const GemmArgs& a, int n_wg, hipS
 }  // namespace
 
 bool tile_supported(int, TileShape ts) {
-  return (ts.wm == ts.wn) && (ts.wm == 4 || ts.wm == 3 || ts.wm == 2);
+  for (const TileShape& t : kTileShapes)
+    if (t.wm == ts.wm && t.wn == ts.wn) return true;
+  return false;
 }
 
 hipError_t launch_gemm(int kind, int prec, TileShape ts, const GemmArgs& a, int n_wg, hipStream_t st) {

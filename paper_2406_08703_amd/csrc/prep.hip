@@ -135,6 +135,15 @@ __global__ void opd_partial_kernel(const float* Z, const float* c, int Nz, long 
     if (p0 + e < npix) part[(long long)split * npix + p0 + e] = acc[e];
 }
 
+// OPD[p] = sum of the J partials (fixed order), once for all wavelengths.
+__global__ void opd_sum_kernel(double* part, int J, long long npix) {
+  const long long p = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (p >= npix || J <= 1) return;
+  double o = part[p];
+  for (int s = 1; s < J; ++s) o += part[(long long)s * npix + p];
+  part[p] = o;
+}
+
 // P0T_l[n][m] = A[m][n] / sqrt(sum A^2) * exp(i 2 pi OPD[m][n] / lambda_l), one block per
 // (32 x 32 tile, wavelength), transposed through LDS. OPD = sum of the J partials.
 __global__ void pupil_kernel(const float* A, const double* opd_part, int J, const double* norm_part, int n_norm,
@@ -144,7 +153,6 @@ __global__ void pupil_kernel(const float* A, const double* opd_part, int J, cons
   const int tx = threadIdx.x, ty = threadIdx.y;  // 32 x 8
   const int m0 = blockIdx.y * 32, n0 = blockIdx.x * 32;
   const int l = blockIdx.z;
-  const long long npix = (long long)Ni * Ni;
   if (tx == 0 && ty == 0) {
     double s2 = 0.0;
     for (int i = 0; i < n_norm; ++i) s2 += norm_part[i];
@@ -158,9 +166,7 @@ __global__ void pupil_kernel(const float* A, const double* opd_part, int J, cons
     float re = 0.f, im = 0.f;
     if (m < Ni && n < Ni) {
       const long long p = (long long)m * Ni + n;
-      double o = 0.0;
-      for (int s = 0; s < J; ++s) o += opd_part[(long long)s * npix + p];
-      const double t0 = o * inv;   // phase in cycles
+      const double t0 = opd_part[p] * inv;   // phase in cycles (partials already summed into slot 0)
       const double fr = t0 - rint(t0);
       double sn, cs;
       sincospi(2.0 * fr, &sn, &cs);
@@ -247,6 +253,9 @@ hipError_t launch_prep(dlx_plan* p, const float* A, const float* Z, const float*
   const long long chunks = (npix + 1023) / 1024;
   hipLaunchKernelGGL(opd_partial_kernel, dim3((unsigned)chunks, p->opd_splits), dim3(256), 0, st, Z, c, p->Nz, npix,
                      p->Ni, Bm, p->d_maptmp, p->Nmap, p->opd_splits, p->d_opd);
+  if (p->opd_splits > 1)
+    hipLaunchKernelGGL(opd_sum_kernel, dim3((unsigned)((npix + 255) / 256)), dim3(256), 0, st, p->d_opd, p->opd_splits,
+                       npix);
   const long long p0_by_wl = 2LL * p->Ni * p->ldNi;
   hipLaunchKernelGGL(pupil_kernel, dim3((p->Ni + 31) / 32, (p->ldNi + 31) / 32, p->L), dim3(32, 8), 0, st, A,
                      p->d_opd, p->opd_splits, p->d_norm, p->n_norm_part, p->d_wl, p->Ni, p->ldNi, p->d_P0T,

@@ -12,37 +12,60 @@ namespace {
 // from the stored focal fields E of frames [f0, f0 + nf):
 //   binned[f][p] = sum_s sum_l w_l phi_s sum_{a,b<Q} K[a][b] |E[Qp_r + a][Qp_c + b]|^2,
 //   model[f][p] = flat[p] * binned[f][p].
-// One thread per detector pixel; star, wavelength and sub-pixel sums in a fixed order.
+// Block (64, 4): 64 detector pixels x 4 PSF lanes; lane y sums PSFs
+// y, y + 4, ... and the lanes are added in a fixed order (deterministic).
+// QT > 0 fixes Q at compile time (vector loads along the pixel's rows).
+template <int QT>
 __global__ void intensity_kernel(const float* E, long long plane, long long by_psf, int ld, int f0, int F, int S, int L,
-                                 int Q, int Nd, const float* sources, const WlInfo* wl, const float* intrapixel,
+                                 int Qr, int Nd, const float* sources, const WlInfo* wl, const float* intrapixel,
                                  const float* flat, float* binned, float* model) {
+  __shared__ double sh[4][64];
+  const int Q = QT > 0 ? QT : Qr;
   const long long npix = (long long)Nd * Nd;
-  const long long p = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  const long long p = (long long)blockIdx.x * 64 + threadIdx.x;
   const int f = f0 + blockIdx.y;
-  if (p >= npix || f >= F) return;
-  const int pr = (int)(p / Nd), pc = (int)(p - (long long)pr * Nd);
+  const int y = threadIdx.y;
   double acc = 0.0;
-  for (int s = 0; s < S; ++s) {
-    const float phi = sources[(f * S + s) * 3 + 2];
-    for (int l = 0; l < L; ++l) {
-      const long long lb = (long long)((f - f0) * S + s) * L + l;
+  if (p < npix && f < F) {
+    const int pr = (int)(p / Nd), pc = (int)(p - (long long)pr * Nd);
+    const int SL = S * L;
+    for (int q = y; q < SL; q += 4) {
+      const int s = q / L, l = q - s * L;
+      const long long lb = (long long)(f - f0) * SL + q;
       const float* e = E + lb * by_psf + (long long)(Q * pr) * ld + Q * pc;
       float part = 0.f;
-      for (int a = 0; a < Q; ++a) {
-#pragma unroll 4
-        for (int b = 0; b < Q; ++b) {
-          const float er = e[(long long)a * ld + b], ei = e[plane + (long long)a * ld + b];
-          float v = er * er + ei * ei;
-          if (intrapixel) v *= intrapixel[a * Q + b];
-          part += v;
+      if constexpr (QT == 4 || QT == 2) {
+        typedef float vq __attribute__((ext_vector_type(QT)));
+#pragma unroll
+        for (int a = 0; a < QT; ++a) {
+          const vq vr = *reinterpret_cast<const vq*>(e + (long long)a * ld);
+          const vq vi = *reinterpret_cast<const vq*>(e + plane + (long long)a * ld);
+#pragma unroll
+          for (int b = 0; b < QT; ++b) {
+            float v = vr[b] * vr[b] + vi[b] * vi[b];
+            if (intrapixel) v *= intrapixel[a * QT + b];
+            part += v;
+          }
         }
+      } else {
+        for (int a = 0; a < Q; ++a)
+          for (int b = 0; b < Q; ++b) {
+            const float er = e[(long long)a * ld + b], ei = e[plane + (long long)a * ld + b];
+            float v = er * er + ei * ei;
+            if (intrapixel) v *= intrapixel[a * Q + b];
+            part += v;
+          }
       }
-      acc += (double)(wl[l].w * phi) * (double)part;
+      acc += (double)(wl[l].w * sources[((long long)f * S + s) * 3 + 2]) * (double)part;
     }
   }
-  const float bv = (float)acc;
-  binned[(long long)f * npix + p] = bv;
-  model[(long long)f * npix + p] = flat[p] * bv;
+  sh[y][threadIdx.x] = acc;
+  __syncthreads();
+  if (y == 0 && p < npix && f < F) {
+    const float bv = (float)(sh[0][threadIdx.x] + sh[1][threadIdx.x] + sh[2][threadIdx.x] + sh[3][threadIdx.x]);
+    binned[(long long)f * npix + p] = bv;
+    model[(long long)f * npix + p] = flat[p] * bv;
+  }
 }
 
 constexpr int kLossThreads = 256;
@@ -128,6 +151,7 @@ template <int SPLIT>
 __global__ void seed_kernel(float* Y, long long plane, long long by_psf, int ld, int psf0, int No, int Q, int Nd,
                             int S, int L, const float* sources, const WlInfo* wl, const float* flat, const float* resid,
                             const float* intrapixel, int rows_per_blk, int nblk, double* flux, unsigned short* Ys) {
+  typedef float f4 __attribute__((ext_vector_type(4)));
   __shared__ double sh[4];
   const int lb = blockIdx.x / nblk;
   const int blk = blockIdx.x - lb * nblk;
@@ -141,30 +165,52 @@ __global__ void seed_kernel(float* Y, long long plane, long long by_psf, int ld,
   float* yb = Y + (long long)lb * by_psf;
   const int k0 = blk * rows_per_blk;
   const int k1 = min(No, k0 + rows_per_blk);
-  const long long n = (long long)(k1 > k0 ? k1 - k0 : 0) * No;
+  const int nq = (No + 3) / 4;                       // groups of 4 columns per row (ld is a multiple of 16)
+  const long long n = (long long)(k1 > k0 ? k1 - k0 : 0) * nq;
   double part = 0.0;
   for (long long t = threadIdx.x; t < n; t += blockDim.x) {
-    const int k = k0 + (int)(t / No);
-    const int l = (int)(t - (long long)(k - k0) * No);
-    const int p = (k / Q) * Nd + (l / Q);
-    float g = flat[p] * rf[p];
-    if (intrapixel) g *= intrapixel[(k % Q) * Q + (l % Q)];
-    const long long off = (long long)k * ld + l;
-    float* e = yb + off;
-    const float er = e[0], ei = e[plane];
-    const float yr = wphi * g * er, yi = wphi * g * ei;
-    if constexpr (SPLIT == 0) {
-      e[0] = yr;
-      e[plane] = yi;
-    } else {
-      unsigned short* o = Ys + (long long)lb * by_psf + off;
-      const __bf16 hr = (__bf16)yr, hi = (__bf16)yi;
-      o[0] = __builtin_bit_cast(unsigned short, hr);
-      o[plane] = __builtin_bit_cast(unsigned short, (__bf16)(yr - (float)hr));
-      o[2 * plane] = __builtin_bit_cast(unsigned short, hi);
-      o[3 * plane] = __builtin_bit_cast(unsigned short, (__bf16)(yi - (float)hi));
+    const int k = k0 + (int)(t / nq);
+    const int l0 = 4 * (int)(t - (long long)(k - k0) * nq);
+    const long long off = (long long)k * ld + l0;
+    f4 er = *reinterpret_cast<const f4*>(yb + off);
+    f4 ei = *reinterpret_cast<const f4*>(yb + plane + off);
+    f4 yr, yi;
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+      const int l = l0 + e;
+      float g = 0.f;
+      if (l < No) {
+        const int p = (k / Q) * Nd + (l / Q);
+        g = flat[p] * rf[p];
+        if (intrapixel) g *= intrapixel[(k % Q) * Q + (l % Q)];
+      } else {
+        er[e] = 0.f;
+        ei[e] = 0.f;
+      }
+      yr[e] = wphi * g * er[e];
+      yi[e] = wphi * g * ei[e];
+      part += (double)g * (double)(er[e] * er[e] + ei[e] * ei[e]);
     }
-    part += (double)g * (double)(er * er + ei * ei);
+    if constexpr (SPLIT == 0) {
+      *reinterpret_cast<f4*>(yb + off) = yr;
+      *reinterpret_cast<f4*>(yb + plane + off) = yi;
+    } else {
+      typedef unsigned short us4 __attribute__((ext_vector_type(4)));
+      us4 hr, lr, hi, li;
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        const __bf16 a = (__bf16)yr[e], b = (__bf16)yi[e];
+        hr[e] = __builtin_bit_cast(unsigned short, a);
+        lr[e] = __builtin_bit_cast(unsigned short, (__bf16)(yr[e] - (float)a));
+        hi[e] = __builtin_bit_cast(unsigned short, b);
+        li[e] = __builtin_bit_cast(unsigned short, (__bf16)(yi[e] - (float)b));
+      }
+      unsigned short* o = Ys + (long long)lb * by_psf + off;
+      *reinterpret_cast<us4*>(o) = hr;
+      *reinterpret_cast<us4*>(o + plane) = lr;
+      *reinterpret_cast<us4*>(o + 2 * plane) = hi;
+      *reinterpret_cast<us4*>(o + 3 * plane) = li;
+    }
   }
 #pragma unroll
   for (int o = 32; o > 0; o >>= 1) part += __shfl_xor(part, o, 64);
@@ -196,11 +242,24 @@ __global__ void zproj_partial_kernel(const float* Z, const double* gopd, int Nz,
   double acc[kZGroup];
 #pragma unroll
   for (int q = 0; q < kZGroup; ++q) acc[q] = 0.0;
-  for (long long p = p_begin + threadIdx.x; p < p_end; p += blockDim.x) {
-    const double g = gopd[p];
+  // four consecutive pixels per thread and step (chunk is a multiple of 1024)
+  for (long long p = p_begin + 4 * threadIdx.x; p < p_end; p += 4 * blockDim.x) {
+    const bool full = p + 4 <= p_end && (npix & 3) == 0;
+    double g[4];
 #pragma unroll
-    for (int q = 0; q < kZGroup; ++q)
-      if (j0 + q < Nz) acc[q] += (double)Z[(long long)(j0 + q) * npix + p] * g;
+    for (int e = 0; e < 4; ++e) g[e] = (p + e < p_end) ? gopd[p + e] : 0.0;
+#pragma unroll
+    for (int q = 0; q < kZGroup; ++q) {
+      if (j0 + q >= Nz) break;
+      const float* z = Z + (long long)(j0 + q) * npix + p;
+      if (full) {
+        const float4 v = *reinterpret_cast<const float4*>(z);
+        acc[q] += (double)v.x * g[0] + (double)v.y * g[1] + (double)v.z * g[2] + (double)v.w * g[3];
+      } else {
+        for (int e = 0; e < 4; ++e)
+          if (p + e < p_end) acc[q] += (double)z[e] * g[e];
+      }
+    }
   }
 #pragma unroll
   for (int q = 0; q < kZGroup; ++q) {
@@ -249,25 +308,29 @@ __global__ void map_grad2_kernel(const double* tmp2, const float* Bm, int Ni, in
 // partials), one 64-thread block per (frame, star), fixed reduction order.
 __global__ void src_reduce_kernel(const double* flux, int tiles_b2, const double* pos, int tiles_b4, int L,
                                   double* grad) {
+  __shared__ double sh[3][4];
   const int fs = blockIdx.x;
   const long long b0 = (long long)fs * L;
   double ga = 0.0, gbt = 0.0, gp = 0.0;
-  for (int i = threadIdx.x; i < L * tiles_b4; i += 64) {
+  for (int i = threadIdx.x; i < L * tiles_b4; i += 256) {
     const long long q = (b0 * tiles_b4 + i) * 2;
     ga += pos[q];
     gbt += pos[q + 1];
   }
-  for (int i = threadIdx.x; i < L * tiles_b2; i += 64) gp += flux[b0 * tiles_b2 + i];
+  for (int i = threadIdx.x; i < L * tiles_b2; i += 256) gp += flux[b0 * tiles_b2 + i];
   for (int o = 32; o > 0; o >>= 1) {
     ga += __shfl_xor(ga, o, 64);
     gbt += __shfl_xor(gbt, o, 64);
     gp += __shfl_xor(gp, o, 64);
   }
-  if (threadIdx.x == 0) {
-    grad[fs * 3 + 0] = ga;
-    grad[fs * 3 + 1] = gbt;
-    grad[fs * 3 + 2] = gp;
+  const int w = threadIdx.x >> 6;
+  if ((threadIdx.x & 63) == 0) {
+    sh[0][w] = ga;
+    sh[1][w] = gbt;
+    sh[2][w] = gp;
   }
+  __syncthreads();
+  if (threadIdx.x < 3) grad[fs * 3 + threadIdx.x] = sh[threadIdx.x][0] + sh[threadIdx.x][1] + sh[threadIdx.x][2] + sh[threadIdx.x][3];
 }
 
 }  // namespace
@@ -275,9 +338,17 @@ __global__ void src_reduce_kernel(const double* flux, int tiles_b2, const double
 hipError_t launch_intensity(dlx_plan* p, int f0, int nf, const float* sources, const float* intrapixel,
                             const float* flat, float* binned, float* model, hipStream_t st) {
   const long long npix = (long long)p->Nd * p->Nd;
-  hipLaunchKernelGGL(intensity_kernel, dim3((unsigned)((npix + 255) / 256), nf), dim3(256), 0, st, p->d_Y,
-                     (long long)p->chunk_psf * p->No * p->ldNo, (long long)p->No * p->ldNo, p->ldNo, f0, p->F, p->S,
-                     p->L, p->Q, p->Nd, sources, p->d_wl, intrapixel, flat, binned, model);
+  const dim3 grid((unsigned)((npix + 63) / 64), nf), blk(64, 4);
+  const long long plane = (long long)p->chunk_psf * p->No * p->ldNo, by = (long long)p->No * p->ldNo;
+#define DLX_INTENSITY(QT)                                                                                         \
+  hipLaunchKernelGGL(intensity_kernel<QT>, grid, blk, 0, st, p->d_Y, plane, by, p->ldNo, f0, p->F, p->S, p->L, \
+                     p->Q, p->Nd, sources, p->d_wl, intrapixel, flat, binned, model)
+  switch (p->Q) {
+    case 2: DLX_INTENSITY(2); break;
+    case 4: DLX_INTENSITY(4); break;
+    default: DLX_INTENSITY(0); break;
+  }
+#undef DLX_INTENSITY
   return hipGetLastError();
 }
 
@@ -319,11 +390,14 @@ hipError_t launch_loss_final(dlx_plan* p, int n_chunks, double* loss, hipStream_
   return hipGetLastError();
 }
 
+// pixel chunks of the Zernike projection: about 2048 blocks in all, each
+// thread covering at least 8 pixels (latency of the scattered loads hides
+// behind each thread's own loop)
 int zproj_chunks(long long npix, int Nz) {
   const int groups = (Nz + kZGroup - 1) / kZGroup;
   long long c = 2048 / (groups > 0 ? groups : 1);
   c = c < 1 ? 1 : c;
-  const long long maxc = (npix + 255) / 256;
+  const long long maxc = (npix + 1023) / 1024;
   return (int)(c < maxc ? c : maxc);
 }
 
@@ -335,7 +409,7 @@ hipError_t launch_grad_reduce(dlx_plan* p, const float* Z, const float* Bm, doub
                      p->d_gopd);
   if (p->Nz > 0) {
     const int nch = zproj_chunks(npix, p->Nz);
-    const long long chunk = (npix + nch - 1) / nch;
+    const long long chunk = ((npix + nch - 1) / nch + 1023) / 1024 * 1024;
     hipLaunchKernelGGL(zproj_partial_kernel, dim3((p->Nz + kZGroup - 1) / kZGroup, nch), dim3(256), 0, st, Z,
                        p->d_gopd, p->Nz, npix, chunk, p->d_zpart);
     hipLaunchKernelGGL(zproj_final_kernel, dim3(p->Nz), dim3(64), 0, st, p->d_zpart, p->Nz, nch, gz);
@@ -346,7 +420,7 @@ hipError_t launch_grad_reduce(dlx_plan* p, const float* Z, const float* Bm, doub
     hipLaunchKernelGGL(map_grad2_kernel, dim3(p->Nmap), dim3((p->Nmap + 63) / 64 * 64), 0, st, p->d_tmp2, Bm, p->Ni,
                        p->Nmap, gmap);
   }
-  hipLaunchKernelGGL(src_reduce_kernel, dim3(p->F * p->S), dim3(64), 0, st, p->d_flux, p->tiles_b2, p->d_pos,
+  hipLaunchKernelGGL(src_reduce_kernel, dim3(p->F * p->S), dim3(256), 0, st, p->d_flux, p->tiles_b2, p->d_pos,
                      p->tiles_b4 * p->b4_ksplit, p->L, gsrc);
   return hipGetLastError();
 }

@@ -29,7 +29,10 @@ DLX_LOSS_POISSON = 0
 DLX_LOSS_CHI2 = 1
 
 # Every symbol include/dlx.h declares.
-EXPORTS = ("dlx_validate", "dlx_plan_create", "dlx_plan_destroy", "dlx_plan_workspace_bytes", "dlx_plan_sync",
+DLX_FLAG_NO_AUTOTUNE = 1
+
+EXPORTS = ("dlx_validate", "dlx_plan_create", "dlx_plan_destroy", "dlx_plan_workspace_bytes", "dlx_plan_tiles",
+           "dlx_plan_sync",
            "dlx_psf_forward", "dlx_loss_grad", "dlx_psf_backward", "dlx_eval", "dlx_graph_capture",
            "dlx_graph_launch", "dlx_plan_profile", "dlx_plan_stage_times", "dlx_status_string")
 
@@ -87,6 +90,8 @@ def lib() -> ctypes.CDLL:
         L.dlx_plan_destroy.argtypes = [_vp]
         L.dlx_plan_workspace_bytes.restype = ctypes.c_size_t
         L.dlx_plan_workspace_bytes.argtypes = [_vp]
+        L.dlx_plan_tiles.restype = ctypes.c_int
+        L.dlx_plan_tiles.argtypes = [_vp, _vp]
         L.dlx_plan_sync.restype = ctypes.c_int
         L.dlx_plan_sync.argtypes = [_vp, _vp]
         L.dlx_psf_forward.restype = ctypes.c_int
@@ -155,6 +160,13 @@ def dlx_plan_destroy(plan: int) -> None:
 
 def dlx_plan_workspace_bytes(plan: int) -> int:
     return int(lib().dlx_plan_workspace_bytes(_p(plan)))
+
+
+def dlx_plan_tiles(plan: int) -> dict:
+    """{stage: (rows, cols)} of each MFT stage's workgroup output tile."""
+    t = (ctypes.c_int32 * 10)()
+    _chk(lib().dlx_plan_tiles(_p(plan), ctypes.addressof(t)), "dlx_plan_tiles")
+    return {k: (32 * t[2 * i], 32 * t[2 * i + 1]) for i, k in enumerate(("F1", "F2", "B2", "B3", "B4"))}
 
 
 def dlx_plan_sync(plan: int, stream: int = 0) -> int:

@@ -59,7 +59,7 @@ class PsfPlan:
     """
 
     def __init__(self, geom: Geometry, transmission, zbasis, map_basis=None, intrapixel=None,
-                 precision: str = "fp32", workspace_limit: int = 0, device="cuda"):
+                 precision: str = "fp32", workspace_limit: int = 0, device="cuda", autotune: bool = True):
         if not torch.cuda.is_available():
             raise RuntimeError("libdlx needs a ROCm GPU")
         self.geom = geom
@@ -74,7 +74,8 @@ class PsfPlan:
                                         g.n_frames, g.n_zernike, g.n_map, g.diameter, g.focal_pixel)
         prec = {"fp32": _c.DLX_FP32, "bf16x3": _c.DLX_BF16X3}[precision]
         with torch.cuda.device(self.device):
-            self.plan = _c.dlx_plan_create(desc, 1, prec, 0, int(workspace_limit))
+            flags = 0 if autotune else _c.DLX_FLAG_NO_AUTOTUNE
+            self.plan = _c.dlx_plan_create(desc, 1, prec, flags, int(workspace_limit))
         self.precision = precision
 
     # ------------------------------------------------------------------ lifetime
@@ -88,6 +89,10 @@ class PsfPlan:
             self.close()
         except Exception:
             pass
+
+    @property
+    def tiles(self) -> dict:
+        return _c.dlx_plan_tiles(self.plan)
 
     @property
     def workspace_bytes(self) -> int:

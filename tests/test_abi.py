@@ -81,7 +81,7 @@ def test_plan_create_rejects_bad_precision_and_flags():
         dlx.dlx_plan_create(d, precision=7)
     assert e.value.status == dlx.DLX_ERR_INVALID_ARG
     with pytest.raises(dlx.DlxError) as e:
-        dlx.dlx_plan_create(d, flags=3)
+        dlx.dlx_plan_create(d, flags=6)
     assert e.value.status == dlx.DLX_ERR_INVALID_ARG
 
 
