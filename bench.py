@@ -32,6 +32,8 @@ WORKLOADS = {
           "frames, 128 Zernikes, intra-pixel kernel",
     "c5": "1024x1024 pupil -> 2048x2048 focal (Q=2, 1024x1024 det), 16 wavelengths, 1 star, 16 dithered "
           "frames, 256 Zernikes + 64x64 bicubic map",
+    "c4": "128 independent uneven problems in one plan: pupils 128-512, focal 63-256 (Q 2-4), 8-64 "
+          "wavelengths 450-800 nm, 16-128 Zernikes, 1-3 stars, 1 frame each",
 }
 
 
@@ -95,13 +97,16 @@ def main():
         return
     small_cfg = args.config in ("c1", "c2")
     if args.steps is None:
-        args.steps = 200 if small_cfg else 3
+        args.steps = 200 if small_cfg else (10 if args.config == "c4" else 3)
     if args.warmup is None:
         args.warmup = 5 if small_cfg else 1
     if args.gpus != 1:
         print(f"bench.py measures one GPU; --gpus {args.gpus} is not supported (the path shards by frame "
               "with one all-reduce of the flat-field gradient, which this build does not run).", file=sys.stderr)
         sys.exit(2)
+
+    if args.config == "c4":
+        return bench_batch(args)
 
     import numpy as np
     import torch
@@ -269,6 +274,148 @@ def main():
            "roofline": roofline, "rel_err_vs_fp64": parity, "cpu_baseline": cpu}
     plan.close()
     print(json.dumps(out), flush=True)
+
+
+def bench_batch(args):
+    """The batched configuration: 128 uneven problems, three forms of the same evaluation.
+
+    plain:   one plan per problem, dlx_eval problem after problem on one stream, no graph;
+    batched: one multi-problem plan, problems spread over concurrent streams, replayed from one HIP graph;
+    the precision flag selects FP32 or BF16x3 for the batched form (plain is always FP32).
+    """
+    import numpy as np
+    import torch
+
+    from synth import make_c4_workloads, standin_image
+    from paper_2406_08703_amd import BatchPlan, EvalBuffers, Geometry, PsfPlan, evaluate
+    from paper_2406_08703_amd import dlx as C
+
+    log = lambda *a: print(*a, file=sys.stderr, flush=True)
+    t0 = time.perf_counter()
+    ws = [w.with_data(standin_image(w)) for w in make_c4_workloads()]
+    log(f"workload c4: {WORKLOADS['c4']}; {len(ws)} problems drawn in {time.perf_counter() - t0:.1f} s")
+    geoms = [Geometry(w.problem.n_pupil, w.problem.n_focal, w.problem.oversample, tuple(w.problem.wavelengths),
+                      tuple(w.problem.weights), w.problem.n_sources, w.problem.n_frames, w.problem.n_zernike,
+                      w.problem.n_map, w.problem.diameter, w.problem.focal_pixel) for w in ws]
+    n_psf = sum(w.problem.n_psf for w in ws)
+    F_alg = sum(2.0 * w.problem.mft_flops() * w.problem.n_psf for w in ws)
+    t = lambda a: torch.from_numpy(np.ascontiguousarray(a, np.float32))
+    dev = lambda a: t(a).cuda()
+    eps = [w.eval_params() for w in ws]
+    mu, sigma = ws[0].prior_mu, ws[0].prior_sigma
+
+    def timed(fn, k):
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        for _ in range(k):
+            fn()
+        torch.cuda.synchronize()
+        return time.perf_counter() - t1
+
+    # plain FP32: problem after problem on the current stream
+    t1 = time.perf_counter()
+    plans = [PsfPlan(g, dev(w.transmission), dev(w.zbasis)) for g, w in zip(geoms, ws)]
+    log(f"plain: 128 plans created in {time.perf_counter() - t1:.1f} s")
+    pin = [(dev(e["coeffs"]), dev(e["sources"]), dev(e["flat"]), dev(w.data)) for e, w in zip(eps, ws)]
+    pbuf = [EvalBuffers(p) for p in plans]
+
+    def plain_step():
+        for p, (c, s_, fl, d), b in zip(plans, pin, pbuf):
+            evaluate(p, c, None, s_, fl, d, "poisson", mu, sigma, out=b)
+
+    for _ in range(args.warmup):
+        plain_step()
+    torch.cuda.synchronize()
+    for p in plans:
+        C.dlx_plan_profile(p.plan, True)
+    t_plain = timed(plain_step, args.steps)
+    stage_tot = {}
+    for p, w in zip(plans, ws):
+        for name, (tot, la, ps) in C.dlx_plan_stage_times(p.plan).items():
+            fl_ = stage_flops(w.problem, name)
+            acc = stage_tot.setdefault(name, [0.0, 0, 0, 0.0])
+            acc[0] += tot
+            acc[1] += la
+            acc[2] += ps
+            acc[3] += (fl_ or 0.0) * ps
+    assert all(p.sync() == 0 for p in plans)
+    plain_loss = [float(b.loss[0]) for b in pbuf]
+    for p in plans:
+        p.close()
+    del plans, pbuf, pin
+    torch.cuda.empty_cache()
+    log(f"plain: {args.steps} steps in {t_plain:.4f} s")
+
+    # batched: one plan, one graph
+    t1 = time.perf_counter()
+    bp = BatchPlan(geoms, [t(w.transmission) for w in ws], [t(w.zbasis) for w in ws], precision=args.precision)
+    log(f"batched {args.precision}: plan created in {time.perf_counter() - t1:.1f} s, "
+        f"workspace {bp.workspace_bytes / 2**30:.2f} GiB")
+    c = bp.pack("zernike_coeffs", [t(e["coeffs"]) for e in eps])
+    s_ = bp.pack("sources", [t(e["sources"]) for e in eps])
+    fl = bp.pack("flat", [t(e["flat"]) for e in eps])
+    d = bp.pack("images", [t(w.data) for w in ws])
+    out = bp.buffers()
+    a = bp.eval_args(c, None, s_, fl, d, out, "poisson", mu, sigma)
+    bp.capture(a)
+    for _ in range(args.warmup):
+        bp.replay()
+    t_batch = timed(bp.replay, args.steps)
+    assert bp.sync() == 0
+    batch_loss = [float(v[0]) for v in bp.unpack("loss", out["loss"].cpu())]
+    bp.close()
+    log(f"batched: {args.steps} replays in {t_batch:.4f} s")
+    loss_dev = max(abs(x - y) / abs(y) for x, y in zip(batch_loss, plain_loss))
+
+    ms_step = t_batch * 1e3 / args.steps
+    evals = n_psf * args.steps / t_batch
+    tf_alg = F_alg / (ms_step * 1e-3) / 1e12
+    table = {k: dict(ms_per_step=v[0] / args.steps, launches=v[1], psfs=v[2], flops=v[3])
+             for k, v in stage_tot.items() if v[1]}
+    gemm = {k: v for k, v in table.items() if v["flops"] > 0}
+    dom = max(gemm, key=lambda k: gemm[k]["ms_per_step"])
+    dv = gemm[dom]
+    avg_ms = dv["ms_per_step"] * args.steps / dv["launches"]
+    achieved = dv["flops"] / (dv["ms_per_step"] * args.steps * 1e-3) / 1e12
+    roofline = {"bound": "mfma", "kernel": f"cgemm_kernel<{dom}> (plain FP32 run, launches do not overlap)",
+                "achieved": round(achieved, 3), "peak": FP32_MFMA_PEAK_TFLOPS, "unit": "TFLOP/s",
+                "frac": round(achieved / FP32_MFMA_PEAK_TFLOPS, 4), "traffic": None,
+                "flops_per_launch": dv["flops"] / dv["launches"], "avg_launch_ms": round(avg_ms, 5)}
+
+    cpu = None
+    if not args.no_cpu_baseline:
+        import oracle as O
+        from threadpoolctl import threadpool_info
+        done, dt, k = 0, 0.0, 0
+        while dt < args.cpu_seconds and k < len(ws):
+            w, e = ws[k], eps[k]
+            P = w.problem
+            prob = O.OracleProblem.from_arrays(P.n_pupil, P.n_focal, P.oversample, P.diameter, P.focal_pixel,
+                                               P.wavelengths, P.weights, w.transmission, w.zbasis, None, None)
+            t1 = time.perf_counter()
+            O.value_and_grad(prob, e["coeffs"], None, e["sources"], e["flat"], w.data, "poisson", mu, sigma)
+            dt += time.perf_counter() - t1
+            done += P.n_psf
+            k += 1
+        threads = max([i.get("num_threads", 1) for i in threadpool_info()] + [1])
+        cpu = {"value": round(done / dt, 4), "unit": "PSF evals/s", "cores": threads, "kind": "oracle",
+               "sample": f"FP64 NumPy oracle forward+loss+gradient of the first {k} of 128 problems "
+                         f"({done} PSFs, {dt:.2f} s)", "host_cpus": os.cpu_count()}
+        log(f"cpu baseline: {cpu}")
+
+    res = {"metric": METRIC, "value": round(evals, 3), "unit": "PSF evals/s", "n_gpus": 1, "steps": args.steps,
+           "warmup": args.warmup, "ms_per_step": round(ms_step, 4), "higher_is_better": True, "scaling": "weak",
+           "vs_baseline": None, "dtype": "f32" if args.precision == "fp32" else "bf16x3", "data": "synthetic",
+           "config": {"workload": f"c4: {WORKLOADS['c4']}", "problems": len(ws), "psf_per_step": n_psf,
+                      "precision": args.precision},
+           "mft_tflops": {"algorithmic": round(tf_alg, 3),
+                          "frac_fp32_mfma_peak_algorithmic": round(tf_alg / FP32_MFMA_PEAK_TFLOPS, 4)},
+           "mode": "graph", "plain_fp32_ms_per_step": round(t_plain * 1e3 / args.steps, 4),
+           "speedup_vs_plain_fp32": round(t_plain / t_batch, 3),
+           "max_rel_loss_diff_vs_plain": float(f"{loss_dev:.3e}"),
+           "stage_ms_per_step_plain": {k: round(v["ms_per_step"], 5) for k, v in table.items()},
+           "roofline": roofline, "rel_err_vs_fp64": None, "cpu_baseline": cpu}
+    print(json.dumps(res), flush=True)
 
 
 if __name__ == "__main__":

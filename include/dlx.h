@@ -99,8 +99,12 @@ enum { DLX_FLAG_NO_AUTOTUNE = 1 };
 
 /* Create a plan: validates, picks kernel tiles, allocates every workspace on
  * the current device and builds the DFT matrices of each wavelength (FP64
- * phase; FP32, or bf16 hi/lo planes for DLX_BF16X3). n_probs must be 1 in
- * this build (others: DLX_ERR_UNSUPPORTED). flags: 0 or DLX_FLAG_NO_AUTOTUNE
+ * phase; FP32, or bf16 hi/lo planes for DLX_BF16X3).
+ * n_probs > 1 makes one plan for several independent problems (fits of
+ * uneven size): every per-call array of dlx_psf_forward / dlx_loss_grad /
+ * dlx_psf_backward / dlx_eval then packs the problems' arrays one after the
+ * other, problem k starting at the element offsets dlx_plan_offsets reports
+ * (loss_out holds one loss per problem). flags: 0 or DLX_FLAG_NO_AUTOTUNE
  * (others: DLX_ERR_INVALID_ARG). Results do not depend on the tiles chosen
  * except for the order of FP32/FP64 partial sums in the gradient
  * reductions. workspace_limit_bytes: 0 = no limit;
@@ -115,6 +119,21 @@ dlx_status dlx_plan_destroy(dlx_plan* plan);
 
 /* Device bytes the plan holds. */
 size_t dlx_plan_workspace_bytes(const dlx_plan* plan);
+
+/* Element offsets of problem k's arrays in the packed arrays of a plan made
+ * for several problems (all zero for k = 0). Sizes per problem:
+ * transmission Ni^2, zernike_basis Nz Ni^2, map_basis Ni n_map,
+ * zernike_coeffs / grad_zernike Nz, phase_map / grad_map n_map^2,
+ * sources / grad_sources 3 F S, flat / grad_flat Nd^2, intrapixel Q^2,
+ * images (data, binned, model, dloss_dmodel) F Nd^2, loss 1. */
+typedef struct {
+  int64_t transmission, zernike_basis, map_basis, zernike_coeffs, phase_map, sources, flat, intrapixel, images,
+      loss;
+} dlx_offsets;
+dlx_status dlx_plan_offsets(const dlx_plan* plan, int32_t problem, dlx_offsets* out);
+
+/* Number of problems of the plan. */
+int32_t dlx_plan_problems(const dlx_plan* plan);
 
 /* Output-tile shape of each MFT stage (autotuned or heuristic): tiles[2k],
  * tiles[2k+1] = rows/32 and columns/32 of a workgroup's tile for stage

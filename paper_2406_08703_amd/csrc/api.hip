@@ -2,7 +2,10 @@
 // chunking, workspace, DFT matrices) and the forward / loss / backward
 // launch sequences. All device work is enqueued on the caller's stream.
 #include <algorithm>
+#include <array>
 #include <cmath>
+#include <map>
+#include <mutex>
 #include <cstring>
 #include <new>
 
@@ -369,6 +372,42 @@ hipError_t autotune(dlx_plan* p) {
   return e;
 }
 
+// Tuned tiles per problem shape and device, shared by every plan of the
+// process, so plans of a shape already seen skip the timing runs.
+using TuneKey = std::array<long long, 11>;
+std::mutex g_tune_mu;
+std::map<TuneKey, std::array<TileShape, 5>> g_tune;
+
+TuneKey tune_key(const dlx_plan* p) {
+  int dev = 0;
+  (void)hipGetDevice(&dev);
+  return {dev, (long long)p->prec, p->Ni, p->No, p->Q, p->L, p->S, p->F, p->frames_per_chunk, p->Nz, p->Nmap};
+}
+
+hipError_t autotune_cached(dlx_plan* p) {
+  const TuneKey key = tune_key(p);
+  {
+    std::lock_guard<std::mutex> lock(g_tune_mu);
+    auto it = g_tune.find(key);
+    if (it != g_tune.end()) {
+      p->ts_f1 = it->second[0];
+      p->ts_f2 = it->second[1];
+      p->ts_b2 = it->second[2];
+      p->ts_b3 = it->second[3];
+      p->ts_b4 = it->second[4];
+      derive_tiles(p);
+      p->tuned = true;
+      return hipSuccess;
+    }
+  }
+  const hipError_t e = autotune(p);
+  if (e == hipSuccess) {
+    std::lock_guard<std::mutex> lock(g_tune_mu);
+    g_tune[key] = {p->ts_f1, p->ts_f2, p->ts_b2, p->ts_b3, p->ts_b4};
+  }
+  return e;
+}
+
 GemmArgs e_args(dlx_plan* p, int f0, int nf, TileShape ts) {
   GemmArgs a = base_args(p, f0, nf);
   a.M = p->No;
@@ -378,6 +417,83 @@ GemmArgs e_args(dlx_plan* p, int f0, int nf, TileShape ts) {
   a.B = op_MN(p);
   set_tiles(a, ts);
   return a;
+}
+
+}  // namespace
+
+extern "C" dlx_status dlx_plan_destroy(dlx_plan* p);
+extern "C" dlx_status dlx_plan_create(const dlx_problem_desc* probs, int32_t n_probs, dlx_precision precision,
+                                      int32_t flags, size_t workspace_limit_bytes, dlx_plan** out);
+
+namespace {
+
+constexpr int kSideStreams = 4;
+
+// One plan per problem; problem k's arrays sit at offs[k] in every packed array.
+dlx_status create_multi(const dlx_problem_desc* probs, int32_t n, dlx_precision prec, int32_t flags, size_t limit,
+                        dlx_plan** out) {
+  dlx_plan* p = new (std::nothrow) dlx_plan();
+  if (!p) return DLX_ERR_OOM;
+  p->prec = prec;
+  dlx_offsets o{};
+  for (int k = 0; k < n; ++k) {
+    dlx_plan* sub = nullptr;
+    const dlx_status s = dlx_plan_create(&probs[k], 1, prec, flags, limit, &sub);
+    if (s != DLX_OK) {
+      dlx_plan_destroy(p);
+      return s;
+    }
+    p->subs.push_back(sub);
+    p->offs.push_back(o);
+    p->pool_bytes += sub->pool_bytes;
+    const dlx_problem_desc& d = probs[k];
+    const long long ni2 = (long long)d.n_pupil * d.n_pupil, nd = d.n_focal / d.oversample;
+    o.transmission += ni2;
+    o.zernike_basis += (long long)d.n_zernike * ni2;
+    o.map_basis += (long long)d.n_pupil * d.n_map;
+    o.zernike_coeffs += d.n_zernike;
+    o.phase_map += (long long)d.n_map * d.n_map;
+    o.sources += 3LL * d.n_frames * d.n_sources;
+    o.flat += nd * nd;
+    o.intrapixel += (long long)d.oversample * d.oversample;
+    o.images += (long long)d.n_frames * nd * nd;
+    o.loss += 1;
+  }
+  p->side.resize(kSideStreams, nullptr);
+  p->joins.resize(kSideStreams, nullptr);
+  bool ok = hipEventCreateWithFlags(&p->fork, hipEventDisableTiming) == hipSuccess;
+  for (int i = 0; ok && i < kSideStreams; ++i) {
+    ok = hipStreamCreateWithFlags(&p->side[i], hipStreamNonBlocking) == hipSuccess &&
+         hipEventCreateWithFlags(&p->joins[i], hipEventDisableTiming) == hipSuccess;
+  }
+  if (!ok) {
+    dlx_plan_destroy(p);
+    return DLX_ERR_HIP;
+  }
+  *out = p;
+  return DLX_OK;
+}
+
+// Run fn(k, sub, stream) for every problem, spread over the side streams,
+// ordered after prior work on `st` and joined back into `st` (also under
+// stream capture, where it records parallel branches).
+template <class Fn>
+dlx_status run_multi(dlx_plan* p, hipStream_t st, Fn fn) {
+  DLX_HIP(hipEventRecord(p->fork, st));
+  for (hipStream_t s : p->side) DLX_HIP(hipStreamWaitEvent(s, p->fork, 0));
+  dlx_status status = DLX_OK;
+  for (size_t k = 0; k < p->subs.size() && status == DLX_OK; ++k)
+    status = fn((int)k, p->subs[k], p->side[k % p->side.size()]);
+  for (size_t i = 0; i < p->side.size(); ++i) {
+    DLX_HIP(hipEventRecord(p->joins[i], p->side[i]));
+    DLX_HIP(hipStreamWaitEvent(st, p->joins[i], 0));
+  }
+  return status;
+}
+
+template <class T>
+T* at(T* base, long long off) {
+  return base ? base + off : nullptr;
 }
 
 }  // namespace
@@ -428,7 +544,7 @@ dlx_status dlx_plan_create(const dlx_problem_desc* probs, int32_t n_probs, dlx_p
   if (v != DLX_OK) return v;
   if (precision != DLX_FP32 && precision != DLX_BF16X3) return DLX_ERR_INVALID_ARG;
   if ((flags & ~DLX_FLAG_NO_AUTOTUNE) != 0) return DLX_ERR_INVALID_ARG;
-  if (n_probs != 1) return DLX_ERR_UNSUPPORTED;
+  if (n_probs > 1) return create_multi(probs, n_probs, precision, flags, workspace_limit_bytes, out);
   const dlx_problem_desc& d = probs[0];
 
   dlx_plan* p = new (std::nothrow) dlx_plan();
@@ -525,7 +641,7 @@ dlx_status dlx_plan_create(const dlx_problem_desc* probs, int32_t n_probs, dlx_p
   hipError_t e = hipMemset(p->pool, 0, p->pool_bytes);
   if (e == hipSuccess) e = hipMemcpy(p->d_wl, wl.data(), sizeof(WlInfo) * p->L, hipMemcpyHostToDevice);
   if (e == hipSuccess) e = launch_dft(p, nullptr);
-  if (e == hipSuccess && !(flags & DLX_FLAG_NO_AUTOTUNE)) e = autotune(p);
+  if (e == hipSuccess && !(flags & DLX_FLAG_NO_AUTOTUNE)) e = autotune_cached(p);
   if (e == hipSuccess) e = hipMemset(p->d_status, 0, sizeof(int));
   if (e == hipSuccess) e = hipDeviceSynchronize();
   if (e != hipSuccess) {
@@ -539,6 +655,21 @@ dlx_status dlx_plan_create(const dlx_problem_desc* probs, int32_t n_probs, dlx_p
 
 dlx_status dlx_plan_destroy(dlx_plan* p) {
   if (!p) return DLX_OK;
+  if (p->multi() || !p->side.empty()) {
+    dlx_status s = DLX_OK;
+    for (dlx_plan* sub : p->subs)
+      if (dlx_plan_destroy(sub) != DLX_OK) s = DLX_ERR_HIP;
+    for (hipStream_t st : p->side)
+      if (st) (void)hipStreamDestroy(st);
+    for (hipEvent_t ev : p->joins)
+      if (ev) (void)hipEventDestroy(ev);
+    if (p->fork) (void)hipEventDestroy(p->fork);
+    if (p->graph_exec) (void)hipGraphExecDestroy(p->graph_exec);
+    if (p->graph) (void)hipGraphDestroy(p->graph);
+    if (p->cap_stream) (void)hipStreamDestroy(p->cap_stream);
+    delete p;
+    return s;
+  }
   const hipError_t e1 = hipDeviceSynchronize();
   for (hipEvent_t ev : p->ev_pool) (void)hipEventDestroy(ev);
   if (p->graph_exec) (void)hipGraphExecDestroy(p->graph_exec);
@@ -551,8 +682,23 @@ dlx_status dlx_plan_destroy(dlx_plan* p) {
 
 size_t dlx_plan_workspace_bytes(const dlx_plan* p) { return p ? p->pool_bytes : 0; }
 
+dlx_status dlx_plan_offsets(const dlx_plan* p, int32_t k, dlx_offsets* out) {
+  if (!p || !out) return DLX_ERR_INVALID_ARG;
+  if (!p->multi()) {
+    if (k != 0) return DLX_ERR_INVALID_ARG;
+    *out = dlx_offsets{};
+    return DLX_OK;
+  }
+  if (k < 0 || k >= (int32_t)p->subs.size()) return DLX_ERR_INVALID_ARG;
+  *out = p->offs[k];
+  return DLX_OK;
+}
+
+int32_t dlx_plan_problems(const dlx_plan* p) { return p ? (p->multi() ? (int32_t)p->subs.size() : 1) : 0; }
+
 dlx_status dlx_plan_tiles(const dlx_plan* p, int32_t* tiles) {
   if (!p || !tiles) return DLX_ERR_INVALID_ARG;
+  if (p->multi()) return dlx_plan_tiles(p->subs[0], tiles);
   const TileShape t[5] = {p->ts_f1, p->ts_f2, p->ts_b2, p->ts_b3, p->ts_b4};
   for (int k = 0; k < 5; ++k) {
     tiles[2 * k] = t[k].wm;
@@ -563,6 +709,13 @@ dlx_status dlx_plan_tiles(const dlx_plan* p, int32_t* tiles) {
 
 dlx_status dlx_plan_profile(dlx_plan* p, int32_t enable) {
   if (!p) return DLX_ERR_INVALID_ARG;
+  if (p->multi()) {
+    for (dlx_plan* sub : p->subs) {
+      const dlx_status s = dlx_plan_profile(sub, enable);
+      if (s != DLX_OK) return s;
+    }
+    return DLX_OK;
+  }
   if (enable && p->ev_pool.empty()) {
     p->ev_pool.resize(kEventPool);
     for (auto& ev : p->ev_pool) DLX_HIP(hipEventCreate(&ev));
@@ -582,6 +735,24 @@ dlx_status dlx_plan_profile(dlx_plan* p, int32_t enable) {
 
 dlx_status dlx_plan_stage_times(dlx_plan* p, double* total_ms, int64_t* launches, int64_t* psfs) {
   if (!p || !total_ms || !launches || !psfs) return DLX_ERR_INVALID_ARG;
+  if (p->multi()) {  // summed over problems (they run concurrently on side streams)
+    for (int i = 0; i < DLX_N_STAGES; ++i) {
+      total_ms[i] = 0.0;
+      launches[i] = psfs[i] = 0;
+    }
+    for (dlx_plan* sub : p->subs) {
+      double ms[DLX_N_STAGES];
+      int64_t la[DLX_N_STAGES], ps[DLX_N_STAGES];
+      const dlx_status s = dlx_plan_stage_times(sub, ms, la, ps);
+      if (s != DLX_OK) return s;
+      for (int i = 0; i < DLX_N_STAGES; ++i) {
+        total_ms[i] += ms[i];
+        launches[i] += la[i];
+        psfs[i] += ps[i];
+      }
+    }
+    return DLX_OK;
+  }
   DLX_HIP(flush_records(p));
   for (int i = 0; i < DLX_N_STAGES; ++i) {
     total_ms[i] = p->stage_ms[i];
@@ -597,6 +768,16 @@ dlx_status dlx_plan_stage_times(dlx_plan* p, double* total_ms, int64_t* launches
 dlx_status dlx_plan_sync(dlx_plan* p, void* stream) {
   if (!p) return DLX_ERR_INVALID_ARG;
   hipStream_t st = reinterpret_cast<hipStream_t>(stream);
+  if (p->multi()) {
+    DLX_HIP(hipStreamSynchronize(st));
+    dlx_status worst = DLX_OK;
+    for (dlx_plan* sub : p->subs) {
+      const dlx_status s = dlx_plan_sync(sub, stream);
+      if (s == DLX_ERR_HIP) return s;
+      if (s == DLX_ERR_NONFINITE || (s == DLX_ERR_DOMAIN && worst == DLX_OK)) worst = s;
+    }
+    return worst;
+  }
   DLX_HIP(hipStreamSynchronize(st));
   int h = 0;
   DLX_HIP(hipMemcpy(&h, p->d_status, sizeof(int), hipMemcpyDeviceToHost));
@@ -612,6 +793,16 @@ dlx_status dlx_psf_forward(dlx_plan* p, const float* transmission, const float* 
                            float* model_out, void* stream) {
   if (!p || !ok_ptr(transmission) || !ok_ptr(sources) || !ok_ptr(flat) || !ok_ptr(binned_out) || !ok_ptr(model_out))
     return DLX_ERR_INVALID_ARG;
+  if (p->multi()) {
+    return run_multi(p, reinterpret_cast<hipStream_t>(stream), [&](int k, dlx_plan* q, hipStream_t s) {
+      const dlx_offsets& o = p->offs[k];
+      return dlx_psf_forward(q, at(transmission, o.transmission), q->Nz ? at(zernike_basis, o.zernike_basis) : nullptr,
+                             q->Nmap ? at(map_basis, o.map_basis) : nullptr,
+                             q->Nz ? at(zernike_coeffs, o.zernike_coeffs) : nullptr,
+                             q->Nmap ? at(phase_map, o.phase_map) : nullptr, at(sources, o.sources), at(flat, o.flat),
+                             at(intrapixel, o.intrapixel), at(binned_out, o.images), at(model_out, o.images), s);
+    });
+  }
   if (p->Nz > 0 && (!zernike_basis || !zernike_coeffs)) return DLX_ERR_INVALID_ARG;
   if ((p->Nmap > 0) != (map_basis != nullptr) || (p->Nmap > 0) != (phase_map != nullptr)) return DLX_ERR_INVALID_ARG;
   hipStream_t st = reinterpret_cast<hipStream_t>(stream);
@@ -642,6 +833,13 @@ dlx_status dlx_loss_grad(dlx_plan* p, const float* model, const float* binned, c
                          float* dloss_dmodel, double* grad_flat, void* stream) {
   if (!p || !model || !binned || !data || !flat || !loss_out || !dloss_dmodel || !grad_flat)
     return DLX_ERR_INVALID_ARG;
+  if (p->multi()) {
+    return run_multi(p, reinterpret_cast<hipStream_t>(stream), [&](int k, dlx_plan* q, hipStream_t s) {
+      const dlx_offsets& o = p->offs[k];
+      return dlx_loss_grad(q, at(model, o.images), at(binned, o.images), at(data, o.images), at(flat, o.flat), kind, prior_mu,
+                           prior_sigma, at(loss_out, o.loss), at(dloss_dmodel, o.images), at(grad_flat, o.flat), s);
+    });
+  }
   if (kind != DLX_LOSS_POISSON && kind != DLX_LOSS_CHI2) return DLX_ERR_INVALID_ARG;
   if (!(prior_sigma > 0.0) || !std::isfinite(prior_sigma) || !std::isfinite(prior_mu)) return DLX_ERR_INVALID_ARG;
   hipStream_t st = reinterpret_cast<hipStream_t>(stream);
@@ -658,6 +856,18 @@ dlx_status dlx_psf_backward(dlx_plan* p, const float* transmission, const float*
                             const float* dloss_dmodel, double* grad_zernike, double* grad_map, double* grad_sources,
                             void* stream) {
   if (!p || !transmission || !sources || !flat || !dloss_dmodel || !grad_sources) return DLX_ERR_INVALID_ARG;
+  if (p->multi()) {
+    return run_multi(p, reinterpret_cast<hipStream_t>(stream), [&](int k, dlx_plan* q, hipStream_t s) {
+      const dlx_offsets& o = p->offs[k];
+      return dlx_psf_backward(q, at(transmission, o.transmission), q->Nz ? at(zernike_basis, o.zernike_basis) : nullptr,
+                              q->Nmap ? at(map_basis, o.map_basis) : nullptr,
+                              q->Nz ? at(zernike_coeffs, o.zernike_coeffs) : nullptr,
+                              q->Nmap ? at(phase_map, o.phase_map) : nullptr, at(sources, o.sources), at(flat, o.flat),
+                              at(intrapixel, o.intrapixel), at(dloss_dmodel, o.images),
+                              q->Nz ? at(grad_zernike, o.zernike_coeffs) : nullptr,
+                              q->Nmap ? at(grad_map, o.phase_map) : nullptr, at(grad_sources, o.sources), s);
+    });
+  }
   if (p->Nz > 0 && (!zernike_basis || !zernike_coeffs || !grad_zernike)) return DLX_ERR_INVALID_ARG;
   if ((p->Nmap > 0) != (map_basis != nullptr) || (p->Nmap > 0) != (phase_map != nullptr) ||
       (p->Nmap > 0) != (grad_map != nullptr))
@@ -693,6 +903,33 @@ dlx_status dlx_psf_backward(dlx_plan* p, const float* transmission, const float*
 // chunk of fields).
 dlx_status dlx_eval(dlx_plan* p, const dlx_eval_args* a, void* stream) {
   if (!p || !a) return DLX_ERR_INVALID_ARG;
+  if (p->multi()) {
+    if (!a->transmission || !a->sources || !a->flat || !a->data || !a->binned || !a->model || !a->dloss_dmodel ||
+        !a->loss || !a->grad_flat || !a->grad_sources)
+      return DLX_ERR_INVALID_ARG;
+    return run_multi(p, reinterpret_cast<hipStream_t>(stream), [&](int k, dlx_plan* q, hipStream_t s) {
+      const dlx_offsets& o = p->offs[k];
+      dlx_eval_args b = *a;
+      b.transmission = at(a->transmission, o.transmission);
+      b.zernike_basis = q->Nz ? at(a->zernike_basis, o.zernike_basis) : nullptr;
+      b.map_basis = q->Nmap ? at(a->map_basis, o.map_basis) : nullptr;
+      b.zernike_coeffs = q->Nz ? at(a->zernike_coeffs, o.zernike_coeffs) : nullptr;
+      b.phase_map = q->Nmap ? at(a->phase_map, o.phase_map) : nullptr;
+      b.sources = at(a->sources, o.sources);
+      b.flat = at(a->flat, o.flat);
+      b.intrapixel = at(a->intrapixel, o.intrapixel);
+      b.data = at(a->data, o.images);
+      b.binned = at(a->binned, o.images);
+      b.model = at(a->model, o.images);
+      b.dloss_dmodel = at(a->dloss_dmodel, o.images);
+      b.loss = at(a->loss, o.loss);
+      b.grad_flat = at(a->grad_flat, o.flat);
+      b.grad_zernike = q->Nz ? at(a->grad_zernike, o.zernike_coeffs) : nullptr;
+      b.grad_map = q->Nmap ? at(a->grad_map, o.phase_map) : nullptr;
+      b.grad_sources = at(a->grad_sources, o.sources);
+      return dlx_eval(q, &b, s);
+    });
+  }
   if (!a->transmission || !a->sources || !a->flat || !a->data || !a->binned || !a->model || !a->dloss_dmodel ||
       !a->loss || !a->grad_flat || !a->grad_sources)
     return DLX_ERR_INVALID_ARG;
@@ -753,13 +990,19 @@ dlx_status dlx_graph_capture(dlx_plan* p, const dlx_eval_args* a) {
     (void)hipGraphDestroy(p->graph);
     p->graph = nullptr;
   }
-  const bool prof = p->profiling;
-  p->profiling = false;  // no event records inside the graph
+  // No timing-event records inside the graph.
+  std::vector<bool> prof{p->profiling};
+  p->profiling = false;
+  for (dlx_plan* sub : p->subs) {
+    prof.push_back(sub->profiling);
+    sub->profiling = false;
+  }
   DLX_HIP(hipStreamBeginCapture(p->cap_stream, hipStreamCaptureModeThreadLocal));
   const dlx_status s = dlx_eval(p, a, p->cap_stream);
   hipGraph_t g = nullptr;
   const hipError_t e = hipStreamEndCapture(p->cap_stream, &g);
-  p->profiling = prof;
+  p->profiling = prof[0];
+  for (size_t k = 0; k < p->subs.size(); ++k) p->subs[k]->profiling = prof[k + 1];
   if (s != DLX_OK) {
     if (g) (void)hipGraphDestroy(g);
     return s;

@@ -106,6 +106,13 @@ bool tile_supported(int kind, TileShape ts);
 }  // namespace dlx
 
 struct dlx_plan {
+  // several independent problems: one sub-plan each, run on side streams
+  std::vector<dlx_plan*> subs;
+  std::vector<dlx_offsets> offs;
+  std::vector<hipStream_t> side;
+  hipEvent_t fork = nullptr;
+  std::vector<hipEvent_t> joins;
+  bool multi() const { return !subs.empty(); }
   // problem
   int Ni, No, Q, Nd, L, S, F, Nz, Nmap;
   double D, du, dx;

@@ -244,7 +244,7 @@ __global__ void zproj_partial_kernel(const float* Z, const double* gopd, int Nz,
   for (int q = 0; q < kZGroup; ++q) acc[q] = 0.0;
   // four consecutive pixels per thread and step (chunk is a multiple of 1024)
   for (long long p = p_begin + 4 * threadIdx.x; p < p_end; p += 4 * blockDim.x) {
-    const bool full = p + 4 <= p_end && (npix & 3) == 0;
+    const bool full = p + 4 <= p_end && (npix & 3) == 0 && (reinterpret_cast<uintptr_t>(Z) & 15) == 0;
     double g[4];
 #pragma unroll
     for (int e = 0; e < 4; ++e) g[e] = (p + e < p_end) ? gopd[p + e] : 0.0;

@@ -34,7 +34,11 @@ DLX_FLAG_NO_AUTOTUNE = 1
 EXPORTS = ("dlx_validate", "dlx_plan_create", "dlx_plan_destroy", "dlx_plan_workspace_bytes", "dlx_plan_tiles",
            "dlx_plan_sync",
            "dlx_psf_forward", "dlx_loss_grad", "dlx_psf_backward", "dlx_eval", "dlx_graph_capture",
-           "dlx_graph_launch", "dlx_plan_profile", "dlx_plan_stage_times", "dlx_status_string")
+           "dlx_graph_launch", "dlx_plan_profile", "dlx_plan_stage_times", "dlx_status_string",
+           "dlx_plan_offsets", "dlx_plan_problems")
+
+OFFSET_FIELDS = ("transmission", "zernike_basis", "map_basis", "zernike_coeffs", "phase_map", "sources", "flat",
+                 "intrapixel", "images", "loss")
 
 STAGES = ("PREP", "F1", "F2", "BIN", "LOSS", "B2", "B3", "B4", "GRAD")
 
@@ -55,6 +59,10 @@ class dlx_eval_args(ctypes.Structure):
         ("loss_kind", ctypes.c_int), ("prior_mu", ctypes.c_double), ("prior_sigma", ctypes.c_double)] + [
         (n, ctypes.c_void_p) for n in ("binned", "model", "dloss_dmodel", "loss", "grad_flat", "grad_zernike",
                                        "grad_map", "grad_sources")]
+
+
+class dlx_offsets(ctypes.Structure):
+    _fields_ = [(n, ctypes.c_int64) for n in OFFSET_FIELDS]
 
 
 class DlxError(RuntimeError):
@@ -111,6 +119,10 @@ def lib() -> ctypes.CDLL:
         L.dlx_plan_profile.argtypes = [_vp, ctypes.c_int32]
         L.dlx_plan_stage_times.restype = ctypes.c_int
         L.dlx_plan_stage_times.argtypes = [_vp, _vp, _vp, _vp]
+        L.dlx_plan_offsets.restype = ctypes.c_int
+        L.dlx_plan_offsets.argtypes = [_vp, ctypes.c_int32, ctypes.POINTER(dlx_offsets)]
+        L.dlx_plan_problems.restype = ctypes.c_int32
+        L.dlx_plan_problems.argtypes = [_vp]
         _LIB = L
     return _LIB
 
@@ -148,10 +160,23 @@ def dlx_validate(desc: dlx_problem_desc, n_probs: int = 1) -> int:
 
 def dlx_plan_create(desc: dlx_problem_desc, n_probs: int = 1, precision: int = DLX_FP32, flags: int = 0,
                     workspace_limit_bytes: int = 0) -> int:
+    """`desc` is one dlx_problem_desc, or a ctypes array of n_probs of them."""
     out = _vp()
-    _chk(lib().dlx_plan_create(ctypes.byref(desc), n_probs, precision, flags, workspace_limit_bytes,
-                               ctypes.byref(out)), "dlx_plan_create")
+    ref = desc if isinstance(desc, ctypes.Array) else ctypes.byref(desc)
+    _chk(lib().dlx_plan_create(ref, n_probs, precision, flags, workspace_limit_bytes, ctypes.byref(out)),
+         "dlx_plan_create")
     return out.value
+
+
+def dlx_plan_problems(plan: int) -> int:
+    return int(lib().dlx_plan_problems(_p(plan)))
+
+
+def dlx_plan_offsets(plan: int, problem: int) -> dict:
+    """{array: element offset} of problem `problem` inside the packed arrays of a multi-problem plan."""
+    o = dlx_offsets()
+    _chk(lib().dlx_plan_offsets(_p(plan), int(problem), ctypes.byref(o)), "dlx_plan_offsets")
+    return {n: int(getattr(o, n)) for n in OFFSET_FIELDS}
 
 
 def dlx_plan_destroy(plan: int) -> None:

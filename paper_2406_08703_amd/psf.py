@@ -255,3 +255,151 @@ class PsfLoss(torch.autograd.Function):
 def psf_loss(plan: PsfPlan, data, coeffs, phase_map, sources, flat, kind="poisson", prior_mu=1.0, prior_sigma=0.1):
     """Differentiable loss of the forward model (torch autograd entry point)."""
     return PsfLoss.apply(plan, data, kind, prior_mu, prior_sigma, coeffs, phase_map, sources, flat)
+
+
+class BatchPlan:
+    """Many independent problems in one libdlx plan (dlx_plan_create with n_probs > 1).
+
+    Every array crosses the boundary as one flat tensor holding the problems'
+    arrays back to back, problem k at the element offsets the plan reports
+    (dlx_plan_offsets). ``pack`` builds such a tensor from per-problem
+    tensors and ``unpack`` returns per-problem views of one. One call
+    evaluates every problem; the library spreads them over concurrent
+    streams joined back into the caller's stream.
+    """
+
+    _FIELDS = ("transmission", "zernike_basis", "map_basis", "zernike_coeffs", "phase_map", "sources", "flat",
+               "intrapixel", "images", "loss")
+
+    def __init__(self, geoms, transmissions, zbases, map_bases=None, intrapixels=None, precision: str = "fp32",
+                 workspace_limit: int = 0, device="cuda", autotune: bool = True):
+        if not torch.cuda.is_available():
+            raise RuntimeError("libdlx needs a ROCm GPU")
+        self.geoms = list(geoms)
+        n = len(self.geoms)
+        if n < 1:
+            raise ValueError("need at least one problem")
+        self.device = torch.device(device)
+        descs = (_c.dlx_problem_desc * n)()
+        self._keep = []
+        for k, g in enumerate(self.geoms):
+            d, keep = _c.make_desc(g.n_pupil, g.n_focal, g.oversample, g.wavelengths, g.weights, g.n_sources,
+                                   g.n_frames, g.n_zernike, g.n_map, g.diameter, g.focal_pixel)
+            descs[k] = d
+            self._keep.append(keep)
+        prec = {"fp32": _c.DLX_FP32, "bf16x3": _c.DLX_BF16X3}[precision]
+        with torch.cuda.device(self.device):
+            flags = 0 if autotune else _c.DLX_FLAG_NO_AUTOTUNE
+            self.plan = _c.dlx_plan_create(descs, n, prec, flags, int(workspace_limit))
+        self.precision = precision
+        self.offsets = [_c.dlx_plan_offsets(self.plan, k) for k in range(_c.dlx_plan_problems(self.plan))]
+        self.transmission = self.pack("transmission", transmissions)
+        self.zbasis = self.pack("zernike_basis", zbases) if self.total("zernike_basis") else None
+        self.map_basis = self.pack("map_basis", map_bases) if self.total("map_basis") else None
+        if intrapixels is not None and any(k is None for k in intrapixels):
+            raise ValueError("give an intra-pixel kernel for every problem or for none")
+        self.intrapixel = None if intrapixels is None else self.pack("intrapixel", intrapixels)
+
+    def shape(self, field: str, k: int) -> tuple:
+        g = self.geoms[k]
+        return {"transmission": (g.n_pupil, g.n_pupil), "zernike_basis": (g.n_zernike, g.n_pupil, g.n_pupil),
+                "map_basis": (g.n_pupil, g.n_map), "zernike_coeffs": (g.n_zernike,),
+                "phase_map": (g.n_map, g.n_map), "sources": (g.n_frames, g.n_sources, 3),
+                "flat": (g.n_det, g.n_det), "intrapixel": (g.oversample, g.oversample),
+                "images": (g.n_frames, g.n_det, g.n_det), "loss": (1,)}[field]
+
+    def total(self, field: str) -> int:
+        k = len(self.geoms) - 1
+        n = 1
+        for s in self.shape(field, k):
+            n *= s
+        return self.offsets[k][field] + n
+
+    def pack(self, field: str, tensors, dtype=torch.float32) -> torch.Tensor:
+        """One flat device tensor holding tensors[k] at problem k's offset."""
+        out = torch.zeros(self.total(field), dtype=dtype, device=self.device)
+        for k, t in enumerate(tensors):
+            shp = self.shape(field, k)
+            n = 1
+            for s in shp:
+                n *= s
+            if n == 0:
+                continue
+            t = torch.as_tensor(t)
+            if tuple(t.shape) != shp:
+                raise ValueError(f"{field}[{k}] has shape {tuple(t.shape)}, expected {shp}")
+            o = self.offsets[k][field]
+            out[o:o + n] = t.reshape(-1).to(device=self.device, dtype=dtype)
+        return out
+
+    def unpack(self, field: str, flat: torch.Tensor) -> list:
+        """Per-problem views of a packed tensor."""
+        out = []
+        for k in range(len(self.geoms)):
+            shp = self.shape(field, k)
+            n = 1
+            for s in shp:
+                n *= s
+            o = self.offsets[k][field]
+            out.append(flat[o:o + n].view(shp))
+        return out
+
+    def buffers(self) -> dict:
+        """Packed device outputs of one evaluation."""
+        dv, f32, f64 = self.device, torch.float32, torch.float64
+        e = lambda field, dt: torch.empty(max(self.total(field), 1), dtype=dt, device=dv)
+        return dict(binned=e("images", f32), model=e("images", f32), r=e("images", f32), loss=e("loss", f64),
+                    grad_flat=e("flat", f64), grad_zernike=e("zernike_coeffs", f64),
+                    grad_map=e("phase_map", f64) if self.map_basis is not None else None,
+                    grad_sources=e("sources", f64))
+
+    def eval_args(self, coeffs, phase_map, sources, flat, data, out: dict, kind="poisson", prior_mu=1.0,
+                  prior_sigma=0.1) -> _c.dlx_eval_args:
+        """dlx_eval_args over packed parameter tensors (see ``pack``)."""
+        for name, t, field in (("coeffs", coeffs, "zernike_coeffs"), ("sources", sources, "sources"),
+                               ("flat", flat, "flat"), ("data", data, "images"), ("phase_map", phase_map,
+                                                                                  "phase_map")):
+            if t is None:
+                continue
+            if t.dtype != torch.float32 or not t.is_cuda or not t.is_contiguous() or t.numel() < self.total(field):
+                raise ValueError(f"{name} must be a packed contiguous float32 CUDA tensor of {self.total(field)}")
+        a = _c.dlx_eval_args()
+        a.transmission, a.zernike_basis, a.map_basis = _ptr(self.transmission), _ptr(self.zbasis), _ptr(self.map_basis)
+        a.zernike_coeffs, a.phase_map, a.sources, a.flat = _ptr(coeffs), _ptr(phase_map), _ptr(sources), _ptr(flat)
+        a.intrapixel, a.data = _ptr(self.intrapixel), _ptr(data)
+        a.loss_kind = {"poisson": _c.DLX_LOSS_POISSON, "chi2": _c.DLX_LOSS_CHI2}[kind]
+        a.prior_mu, a.prior_sigma = float(prior_mu), float(prior_sigma)
+        a.binned, a.model, a.dloss_dmodel, a.loss = _ptr(out["binned"]), _ptr(out["model"]), _ptr(out["r"]), \
+            _ptr(out["loss"])
+        a.grad_flat, a.grad_zernike = _ptr(out["grad_flat"]), _ptr(out["grad_zernike"])
+        a.grad_map, a.grad_sources = _ptr(out["grad_map"]), _ptr(out["grad_sources"])
+        return a
+
+    def evaluate(self, args: _c.dlx_eval_args) -> None:
+        """dlx_eval over every problem, on the current stream."""
+        _c.dlx_eval(self.plan, args, _stream(self.device))
+
+    def capture(self, args: _c.dlx_eval_args) -> None:
+        """Record dlx_eval over every problem into the plan's HIP graph."""
+        _c.dlx_graph_capture(self.plan, args)
+
+    def replay(self) -> None:
+        _c.dlx_graph_launch(self.plan, _stream(self.device))
+
+    def sync(self) -> int:
+        return _c.dlx_plan_sync(self.plan, _stream(self.device))
+
+    @property
+    def workspace_bytes(self) -> int:
+        return _c.dlx_plan_workspace_bytes(self.plan)
+
+    def close(self):
+        if getattr(self, "plan", None):
+            _c.dlx_plan_destroy(self.plan)
+            self.plan = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -18,6 +18,7 @@ in FP64 on the host is too slow.
 from __future__ import annotations
 
 import dataclasses
+import functools
 from dataclasses import dataclass, field
 
 import numpy as np
@@ -241,3 +242,72 @@ def standin_image(w: Workload) -> np.ndarray:
             img = np.outer(gy, gx)
             out[f] += phi * img / img.sum()
     return out * w.flat_true[None].astype(np.float64) + 1.0
+
+
+def make_c4_workloads(n_problems: int = 128, scale: float = 1.0) -> list:
+    """Independent uneven fits of the batched configuration, drawn from seed child 7.
+
+    Per problem: pupil N_i from {128, 192, 256, 384, 512}, focal N_o from
+    {64, 128, 256} at oversampling Q ~ U{2, 3, 4} with N_det = floor(N_o / Q)
+    and N_o := Q N_det (so 63, 126 and 255 occur), 8-64 wavelengths in
+    450-800 nm, 16-128 Zernikes ~N(0, 25 nm), 1-3 stars with positions
+    U(-N_det/4, N_det/4) px and fluxes log-uniform in [1e6, 1e8], one frame,
+    the 30%-obstructed aperture with spiders, flat ~N(1, 0.05), detector pixel
+    Nyquist at 625 nm. ``scale`` < 1 shrinks the sizes (pupil, focal grid,
+    wavelengths, Zernikes) for tests that compare every problem with the oracle.
+    """
+    ss = np.random.SeedSequence([2406, 8703, _SEED_INDEX["c4"]])
+    size_rng = np.random.default_rng(ss.spawn(8)[7])
+    out = []
+    for k in range(n_problems):
+        ni = int(size_rng.choice([128, 192, 256, 384, 512]))
+        no = int(size_rng.choice([64, 128, 256]))
+        q = int(size_rng.integers(2, 5))
+        nl = int(size_rng.integers(8, 65))
+        nz = int(size_rng.integers(16, 129))
+        ns = int(size_rng.integers(1, 4))
+        if scale != 1.0:
+            ni = max(16, int(round(ni * scale / 8)) * 8)
+            no = max(2 * q, int(no * scale))
+            nl = max(1, int(round(nl * scale)))
+            nz = max(2, int(round(nz * scale)))
+        nd = no // q
+        no = q * nd
+        out.append(_c4_problem(k, ni, no, q, nl, nz, ns))
+    return out
+
+
+@functools.lru_cache(maxsize=None)
+def _c4_static(ni: int):
+    """Aperture and the Noll 2..129 basis of one pupil size (shared by every problem of that size)."""
+    D = DEFAULT_DIAMETER
+    return (np.ascontiguousarray(aperture(ni, D, 0.3, 2.0), dtype=np.float32),
+            np.ascontiguousarray(zernike_basis(list(range(2, 130)), ni, D), dtype=np.float32))
+
+
+def _c4_problem(k, ni, no, q, nl, nz, ns) -> Workload:
+    ss = np.random.SeedSequence([2406, 8703, _SEED_INDEX["c4"], k])
+    rz, rf, rs, rpois, rinit = (np.random.default_rng(c) for c in ss.spawn(5))
+    D, lam_c = DEFAULT_DIAMETER, 625e-9
+    det_pix = lam_c / (2.0 * D)
+    lam = np.linspace(450e-9, 800e-9, nl) if nl > 1 else np.array([lam_c])
+    noll = tuple(range(2, nz + 2))
+    P = Problem(n_pupil=ni, n_focal=no, oversample=q, wavelengths=lam, weights=np.full(nl, 1.0 / nl), n_sources=ns,
+                n_frames=1, n_zernike=nz, diameter=D, focal_pixel=det_pix / q, obstruction=0.3, spider_px=2.0,
+                noll=noll)
+    nd = P.n_det
+    f32 = lambda a: np.ascontiguousarray(a, dtype=np.float32)
+    pos = rs.uniform(-nd / 4, nd / 4, size=(ns, 2)) * det_pix
+    flux = 10 ** rs.uniform(6, 8, size=ns)
+    src_true = np.zeros((1, ns, 3))
+    src_true[0, :, :2] = pos
+    src_true[0, :, 2] = flux
+    src_eval = src_true.copy()
+    src_eval[0, :, :2] += rinit.normal(0.0, 1.0, size=(ns, 2)) * det_pix
+    src_eval[0, :, 2] *= rinit.normal(1.0, 0.1, size=ns)
+    trans, basis = _c4_static(ni)
+    return Workload(problem=P, transmission=trans, zbasis=np.ascontiguousarray(basis[:nz]),
+                    map_basis=None, intrapixel=None, coeffs_true=f32(rz.normal(0.0, 25e-9, nz)), map_true=None,
+                    flat_true=f32(1.0 + 0.05 * rf.normal(size=(nd, nd))), sources_true=f32(src_true),
+                    coeffs=np.zeros(nz, np.float32), phase_map=None, flat=np.ones((nd, nd), np.float32),
+                    sources=f32(src_eval), prior_mu=1.0, prior_sigma=0.05, _data_seed=ss.spawn(6)[5])

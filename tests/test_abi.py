@@ -95,3 +95,20 @@ def test_calls_on_null_plan_are_rejected():
         dlx.dlx_loss_grad(0, 1, 1, 1, 1, 0, 1.0, 0.1, 1, 1, 1)
     with pytest.raises(dlx.DlxError):
         dlx.dlx_psf_backward(0, 1, 1, 0, 1, 0, 1, 1, 0, 1, 1, 0, 1)
+
+
+def test_multi_problem_validation_and_null_plan():
+    import ctypes
+    good, k1 = _desc()
+    bad, k2 = _desc(n_focal=63, oversample=2)
+    arr = (dlx.dlx_problem_desc * 3)(good, good, bad)
+    assert dlx.lib().dlx_validate(arr, 2) == dlx.DLX_OK
+    assert dlx.lib().dlx_validate(arr, 3) == dlx.DLX_ERR_SHAPE
+    # one bad problem fails the whole plan, before any device call
+    with pytest.raises(dlx.DlxError) as e:
+        dlx.dlx_plan_create(arr, 3)
+    assert e.value.status == dlx.DLX_ERR_SHAPE
+    assert dlx.dlx_plan_problems(0) == 0
+    with pytest.raises(dlx.DlxError):
+        dlx.dlx_plan_offsets(0, 0)
+    assert dlx.lib().dlx_plan_offsets(None, 0, ctypes.byref(dlx.dlx_offsets())) == dlx.DLX_ERR_INVALID_ARG

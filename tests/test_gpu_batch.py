@@ -1,0 +1,108 @@
+"""Many uneven problems in one plan: every problem against the FP64 oracle.
+
+Six problems of the batched configuration at a quarter of its sizes
+(pupils 32-128, ragged focal grids such as 63 = 3 x 21, 2-16 wavelengths,
+1-3 stars), evaluated in one dlx_eval call over packed arrays, eagerly and
+from a captured HIP graph.
+"""
+import functools
+
+import numpy as np
+import pytest
+
+import oracle as O
+from synth import make_c4_workloads
+from tests.helpers import oracle_problem
+from tests.test_gpu_parity import TOL, TOL_BF16X3, compare
+
+pytestmark = pytest.mark.gpu
+
+N_PROBLEMS = 6
+
+
+@functools.lru_cache(maxsize=None)
+def batch():
+    items = []
+    for w in make_c4_workloads(N_PROBLEMS, scale=0.25):
+        prob = oracle_problem(w)
+        _, m = O.forward(prob, w.coeffs_true, w.map_true, w.sources_true, w.flat_true)
+        w = w.with_data(m)
+        p = w.eval_params()
+        ref = O.value_and_grad(prob, p["coeffs"], p["phase_map"], p["sources"], p["flat"], w.data, "poisson",
+                               w.prior_mu, w.prior_sigma)
+        items.append((w, ref))
+    return items
+
+
+def run_batch(precision, graph=False, replays=1):
+    import torch
+    from paper_2406_08703_amd import BatchPlan
+    from tests.gpu_helpers import geometry
+    ws = [w for w, _ in batch()]
+    t = lambda a: torch.from_numpy(np.ascontiguousarray(a, dtype=np.float32))
+    bp = BatchPlan([geometry(w) for w in ws], [t(w.transmission) for w in ws], [t(w.zbasis) for w in ws],
+                   precision=precision)
+    assert len(bp.offsets) == len(ws)
+    eps = [w.eval_params() for w in ws]
+    c = bp.pack("zernike_coeffs", [t(e["coeffs"]) for e in eps])
+    s = bp.pack("sources", [t(e["sources"]) for e in eps])
+    fl = bp.pack("flat", [t(e["flat"]) for e in eps])
+    d = bp.pack("images", [t(w.data) for w in ws])
+    out = bp.buffers()
+    a = bp.eval_args(c, None, s, fl, d, out, "poisson", ws[0].prior_mu, ws[0].prior_sigma)
+    runs = []
+    if graph:
+        bp.capture(a)
+        for _ in range(replays):
+            bp.replay()
+            torch.cuda.synchronize()
+            runs.append({k: (None if v is None else v.clone()) for k, v in out.items()})
+    else:
+        bp.evaluate(a)
+        runs.append(out)
+    assert bp.sync() == 0
+    res = []
+    for run in runs:
+        per = []
+        views = {n: bp.unpack(f, run[k]) for n, k, f in (
+            ("binned", "binned", "images"), ("model", "model", "images"), ("r", "r", "images"),
+            ("loss", "loss", "loss"), ("grad_flat", "grad_flat", "flat"),
+            ("grad_coeffs", "grad_zernike", "zernike_coeffs"), ("grad_sources", "grad_sources", "sources"))}
+        for k in range(len(ws)):
+            g = {n: v[k].cpu().numpy().astype(np.float64) for n, v in views.items()}
+            g["loss"] = float(g["loss"][0])
+            g["grad_map"] = None
+            per.append(g)
+        res.append(per)
+    bp.close()
+    return res
+
+
+def test_batch_eval_matches_oracle_per_problem():
+    print("batch fp32 eager", flush=True)
+    got = run_batch("fp32")[0]
+    for k, (w, ref) in enumerate(batch()):
+        P = w.problem
+        print(f"problem {k}: Ni={P.n_pupil} No={P.n_focal} Q={P.oversample} nl={len(P.wavelengths)} "
+              f"nz={P.n_zernike} ns={P.n_sources}", flush=True)
+        compare(got[k], ref, tol_grad=TOL)
+
+
+def test_batch_graph_replays_match_eager_bitwise():
+    print("batch fp32 graph", flush=True)
+    eager = run_batch("fp32")[0]
+    reps = run_batch("fp32", graph=True, replays=3)
+    for rep in reps:
+        for k in range(N_PROBLEMS):
+            for n, v in eager[k].items():
+                if v is None:
+                    continue
+                assert np.array_equal(np.asarray(rep[k][n]), np.asarray(v)), (k, n)
+
+
+def test_batch_bf16x3_matches_oracle_per_problem():
+    print("batch bf16x3 graph", flush=True)
+    got = run_batch("bf16x3", graph=True)[0]
+    for k, (w, ref) in enumerate(batch()):
+        compare(got[k], ref, tol_grad=TOL_BF16X3, tol_resid=TOL_BF16X3, tol_img=TOL_BF16X3,
+                sources=w.eval_params()["sources"])
