@@ -37,12 +37,13 @@ WORKLOADS = {
 }
 
 
-def measured_traffic(config, precision, stage):
-    """HBM bytes per launch of `stage` from the committed rocprofv3 counter summary.
+def measured_traffic(config, precision, stage, tile):
+    """HBM bytes per launch of `stage`'s kernel at `tile` (WM, WN) from the committed rocprofv3 summary.
 
     FETCH_SIZE and WRITE_SIZE (KiB per dispatch) are scaled by what the same
     counters read for a plain copy kernel of known size. Returns None when no
-    summary exists or when the GEMM source changed since it was taken.
+    summary exists, when it lacks this kernel, or when the GEMM source
+    changed since it was taken.
     """
     import hashlib
     path = os.path.join(ROOT, "profiles", f"traffic_{config}_{precision}.txt")
@@ -55,12 +56,14 @@ def measured_traffic(config, precision, stage):
         if len(parts) == 2 and parts[0] in ("fetch_scale", "write_scale", "kernel_source_sha256"):
             fields[parts[0]] = parts[1]
         elif len(parts) == 6 and parts[0] == "stage":
-            stages[parts[1]] = (float(parts[4]), float(parts[5]))
+            stages[parts[2]] = (float(parts[4]), float(parts[5]))
     if fields.get("kernel_source_sha256") != hashlib.sha256(open(src, "rb").read()).hexdigest():
         return None
-    if stage not in stages:
+    kind = {"F1": 0, "F2": 1, "B2": 2, "B3": 3, "B4": 4}[stage]
+    name = f"cgemm_kernel<{kind},{tile[0]},{tile[1]},{0 if precision == 'fp32' else 1}>"
+    if name not in stages:
         return None
-    f, w = stages[stage]
+    f, w = stages[name]
     return round(1024.0 * (f * float(fields["fetch_scale"]) + w * float(fields["write_scale"])))
 
 
@@ -195,20 +198,23 @@ def main():
     dv = gemm[dom]
     flops_per_launch = stage_flops(P, dom) * dv["psfs"] / dv["launches"]
     achieved = flops_per_launch / (dv["avg_launch_ms"] * 1e-3) / 1e12
+    tile = plan.tiles[dom]
+    kname = (f"cgemm_kernel<{['F1', 'F2', 'B2', 'B3', 'B4'].index(dom)}, {tile[0] // 32}, {tile[1] // 32}, "
+             f"{0 if args.precision == 'fp32' else 1}> ({dom})")
     if args.precision == "fp32":
-        roofline = {"bound": "mfma", "kernel": f"cgemm_kernel<{dom}>", "achieved": round(achieved, 3),
+        roofline = {"bound": "mfma", "kernel": kname, "achieved": round(achieved, 3),
                     "peak": FP32_MFMA_PEAK_TFLOPS, "unit": "TFLOP/s", "frac": round(achieved / FP32_MFMA_PEAK_TFLOPS, 4),
                     "traffic": None, "flops_per_launch": flops_per_launch,
                     "avg_launch_ms": round(dv["avg_launch_ms"], 5)}
     else:
         # each real product runs as three BF16 MFMA products (hi*hi + hi*lo + lo*hi)
         bf = 3.0 * achieved
-        roofline = {"bound": "mfma", "kernel": f"cgemm_kernel<{dom}> bf16x3", "achieved": round(bf, 3),
+        roofline = {"bound": "mfma", "kernel": kname + " bf16x3", "achieved": round(bf, 3),
                     "peak": BF16_MFMA_PEAK_TFLOPS, "unit": "TFLOP/s", "frac": round(bf / BF16_MFMA_PEAK_TFLOPS, 4),
                     "traffic": None, "flops_per_launch": 3.0 * flops_per_launch,
                     "avg_launch_ms": round(dv["avg_launch_ms"], 5), "fp32_equivalent_tflops": round(achieved, 3),
                     "frac_of_fp32_mfma_peak": round(achieved / FP32_MFMA_PEAK_TFLOPS, 4)}
-    roofline["traffic"] = measured_traffic(args.config, args.precision, dom)
+    roofline["traffic"] = measured_traffic(args.config, args.precision, dom, (tile[0] // 32, tile[1] // 32))
     gemm_ms = sum(v["ms_per_step"] for v in gemm.values())
     all_ms = sum(v["ms_per_step"] for v in table.values())
 

@@ -63,6 +63,12 @@ __device__ __forceinline__ int xcd_remap(int w, int n) {
   return (xcd < r ? xcd * (q + 1) : r * (q + 1) + (xcd - r) * q) + k;
 }
 
+// XOR swizzle of the four 16-byte k-chunks of LDS row r: a bijection on the
+// chunk index for each row, and on the rows {b, b+4, b+8, b+12} and on the
+// rows of one parity within 8, so that 16 consecutive rows at one chunk, or
+// 4 consecutive rows at all chunks, never share a bank (32 or 64 banks).
+__device__ __forceinline__ int lds_swz(int r) { return (((r >> 2) & 1) << 1) | (((r >> 1) ^ (r >> 3)) & 1); }
+
 __device__ __forceinline__ double wave_sum(double v) {
 #pragma unroll
   for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
@@ -92,8 +98,11 @@ template <int KIND, int WM, int WN, int PREC>
 __global__ __launch_bounds__(256) void cgemm_kernel(const GemmArgs a) {
   constexpr int BM = 32 * WM, BN = 32 * WN;
   constexpr int BK = PREC == 0 ? 16 : 32;
-  // LDS row pitch (elements): FP32 rows hold 16 k + 4 pad floats; BF16 rows 32 k + 8 pad halves.
-  constexpr int LDK = PREC == 0 ? 20 : 40;
+  // LDS rows hold BK k values as four 16-byte chunks (4 FP32 or 8 bf16), unpadded; chunk kq of
+  // row r sits at slot kq ^ swz(r) (see lds_swz), so the loader's stores (4 rows x 4 chunks per
+  // 16 lanes) and the fragment reads (16 rows, one chunk) both spread over all LDS banks.
+  constexpr int CH = PREC == 0 ? 4 : 8;
+  constexpr int LDK = 4 * CH;
   constexpr int NPL = PREC == 0 ? 2 : 4;                 // planes per operand
   constexpr int A_EL = NPL * BM * LDK, B_EL = NPL * BN * LDK;
   constexpr int UNITS_A = BM * 4, UNITS_B = BN * 4;      // 16-byte k-chunks per plane row
@@ -253,12 +262,12 @@ __global__ __launch_bounds__(256) void cgemm_kernel(const GemmArgs a) {
           if constexpr (PREC == 0) {
             f4 vr = __builtin_bit_cast(f4, ga[r][0]), vi = __builtin_bit_cast(f4, ga[r][1]);
             fix32(vr, vi, ga_k[r], a.conj_a);
-            *reinterpret_cast<f4*>(&As[row * LDK + 4 * kq]) = vr;
-            *reinterpret_cast<f4*>(&As[(BM + row) * LDK + 4 * kq]) = vi;
+            *reinterpret_cast<f4*>(&As[row * LDK + 4 * (kq ^ lds_swz(row))]) = vr;
+            *reinterpret_cast<f4*>(&As[(BM + row) * LDK + 4 * (kq ^ lds_swz(row))]) = vi;
           } else {
             fix16(ga[r], ga_k[r], a.conj_a);
 #pragma unroll
-            for (int pl = 0; pl < 4; ++pl) *reinterpret_cast<u4*>(&As[(pl * BM + row) * LDK + 8 * kq]) = ga[r][pl];
+            for (int pl = 0; pl < 4; ++pl) *reinterpret_cast<u4*>(&As[(pl * BM + row) * LDK + 8 * (kq ^ lds_swz(row))]) = ga[r][pl];
           }
         }
       }
@@ -280,8 +289,8 @@ __global__ __launch_bounds__(256) void cgemm_kernel(const GemmArgs a) {
               fix32(pr[v], pi[v], gb_k[r] + 4 * v, false);
             }
             if constexpr (PREC == 0) {
-              *reinterpret_cast<f4*>(&Bs[row * LDK + 4 * kq]) = pr[0];
-              *reinterpret_cast<f4*>(&Bs[(BN + row) * LDK + 4 * kq]) = pi[0];
+              *reinterpret_cast<f4*>(&Bs[row * LDK + 4 * (kq ^ lds_swz(row))]) = pr[0];
+              *reinterpret_cast<f4*>(&Bs[(BN + row) * LDK + 4 * (kq ^ lds_swz(row))]) = pi[0];
             } else {
               unsigned short h[4][8];
 #pragma unroll
@@ -294,18 +303,18 @@ __global__ __launch_bounds__(256) void cgemm_kernel(const GemmArgs a) {
                 u4 w;
 #pragma unroll
                 for (int e = 0; e < 4; ++e) w[e] = (unsigned int)h[pl][2 * e] | ((unsigned int)h[pl][2 * e + 1] << 16);
-                *reinterpret_cast<u4*>(&Bs[(pl * BN + row) * LDK + 8 * kq]) = w;
+                *reinterpret_cast<u4*>(&Bs[(pl * BN + row) * LDK + 8 * (kq ^ lds_swz(row))]) = w;
               }
             }
           } else if constexpr (PREC == 0) {
             f4 vr = __builtin_bit_cast(f4, gbv[r][0]), vi = __builtin_bit_cast(f4, gbv[r][1]);
             fix32(vr, vi, gb_k[r], a.conj_b);
-            *reinterpret_cast<f4*>(&Bs[row * LDK + 4 * kq]) = vr;
-            *reinterpret_cast<f4*>(&Bs[(BN + row) * LDK + 4 * kq]) = vi;
+            *reinterpret_cast<f4*>(&Bs[row * LDK + 4 * (kq ^ lds_swz(row))]) = vr;
+            *reinterpret_cast<f4*>(&Bs[(BN + row) * LDK + 4 * (kq ^ lds_swz(row))]) = vi;
           } else {
             fix16(gbv[r], gb_k[r], a.conj_b);
 #pragma unroll
-            for (int pl = 0; pl < 4; ++pl) *reinterpret_cast<u4*>(&Bs[(pl * BN + row) * LDK + 8 * kq]) = gbv[r][pl];
+            for (int pl = 0; pl < 4; ++pl) *reinterpret_cast<u4*>(&Bs[(pl * BN + row) * LDK + 8 * (kq ^ lds_swz(row))]) = gbv[r][pl];
           }
         }
       }
@@ -323,14 +332,14 @@ __global__ __launch_bounds__(256) void cgemm_kernel(const GemmArgs a) {
 #pragma unroll
         for (int bm = 0; bm < WM; ++bm) {
           const int r = wr * 16 * WM + bm * 16 + (lane & 15);
-          fa_r[bm] = *reinterpret_cast<const f4*>(&As[r * LDK + 4 * (lane >> 4)]);
-          fa_i[bm] = *reinterpret_cast<const f4*>(&As[(BM + r) * LDK + 4 * (lane >> 4)]);
+          fa_r[bm] = *reinterpret_cast<const f4*>(&As[r * LDK + 4 * ((lane >> 4) ^ lds_swz(r))]);
+          fa_i[bm] = *reinterpret_cast<const f4*>(&As[(BM + r) * LDK + 4 * ((lane >> 4) ^ lds_swz(r))]);
         }
 #pragma unroll
         for (int bn = 0; bn < WN; ++bn) {
           const int c = wc * 16 * WN + bn * 16 + (lane & 15);
-          fb_r[bn] = *reinterpret_cast<const f4*>(&Bs[c * LDK + 4 * (lane >> 4)]);
-          fb_i[bn] = *reinterpret_cast<const f4*>(&Bs[(BN + c) * LDK + 4 * (lane >> 4)]);
+          fb_r[bn] = *reinterpret_cast<const f4*>(&Bs[c * LDK + 4 * ((lane >> 4) ^ lds_swz(c))]);
+          fb_i[bn] = *reinterpret_cast<const f4*>(&Bs[(BN + c) * LDK + 4 * ((lane >> 4) ^ lds_swz(c))]);
         }
 #pragma unroll
         for (int s = 0; s < 4; ++s) {
@@ -361,7 +370,7 @@ __global__ __launch_bounds__(256) void cgemm_kernel(const GemmArgs a) {
           const int c = wc * 16 * WN + bn * 16 + (lane & 15);
 #pragma unroll
           for (int pl = 0; pl < 4; ++pl)
-            fb[bn][pl] = *reinterpret_cast<const u4*>(&Bs[(pl * BN + c) * LDK + 8 * (lane >> 4)]);
+            fb[bn][pl] = *reinterpret_cast<const u4*>(&Bs[(pl * BN + c) * LDK + 8 * ((lane >> 4) ^ lds_swz(c))]);
         }
 #pragma unroll
         for (int bm = 0; bm < WM; ++bm) {
@@ -369,7 +378,7 @@ __global__ __launch_bounds__(256) void cgemm_kernel(const GemmArgs a) {
           u4 fa[4];
 #pragma unroll
           for (int pl = 0; pl < 4; ++pl)
-            fa[pl] = *reinterpret_cast<const u4*>(&As[(pl * BM + r) * LDK + 8 * (lane >> 4)]);
+            fa[pl] = *reinterpret_cast<const u4*>(&As[(pl * BM + r) * LDK + 8 * ((lane >> 4) ^ lds_swz(r))]);
           const u4 sgn = u4{0x80008000u, 0x80008000u, 0x80008000u, 0x80008000u};
           const u4 nih = fa[2] ^ sgn, nil = fa[3] ^ sgn;   // -Ai (hi, lo)
 #pragma unroll
