@@ -59,7 +59,7 @@ def measured_traffic(config, precision, stage, tile):
             stages[parts[2]] = (float(parts[4]), float(parts[5]))
     if fields.get("kernel_source_sha256") != hashlib.sha256(open(src, "rb").read()).hexdigest():
         return None
-    kind = {"F1": 0, "F2": 1, "B2": 2, "B3": 3, "B4": 4}[stage]
+    kind = {"F1": 0, "F2": 1, "B3": 3, "B4": 4}[stage]
     name = f"cgemm_kernel<{kind},{tile[0]},{tile[1]},{0 if precision == 'fp32' else 1}>"
     if name not in stages:
         return None
@@ -69,7 +69,7 @@ def measured_traffic(config, precision, stage, tile):
 
 def stage_flops(P, stage):
     ni, no = P.n_pupil, P.n_focal
-    return {"F1": 8.0 * no * ni * ni, "F2": 8.0 * no * no * ni, "B2": 8.0 * no * no * ni,
+    return {"F1": 8.0 * no * ni * ni, "F2": 8.0 * no * no * ni,
             "B3": 8.0 * ni * no * no, "B4": 8.0 * ni * ni * no}.get(stage)
 
 
@@ -199,7 +199,7 @@ def main():
     flops_per_launch = stage_flops(P, dom) * dv["psfs"] / dv["launches"]
     achieved = flops_per_launch / (dv["avg_launch_ms"] * 1e-3) / 1e12
     tile = plan.tiles[dom]
-    kname = (f"cgemm_kernel<{['F1', 'F2', 'B2', 'B3', 'B4'].index(dom)}, {tile[0] // 32}, {tile[1] // 32}, "
+    kname = (f"cgemm_kernel<{dict(F1=0, F2=1, B3=3, B4=4)[dom]}, {tile[0] // 32}, {tile[1] // 32}, "
              f"{0 if args.precision == 'fp32' else 1}> ({dom})")
     if args.precision == "fp32":
         roofline = {"bound": "mfma", "kernel": kname, "achieved": round(achieved, 3),

@@ -94,8 +94,12 @@ dlx_status dlx_validate(const dlx_problem_desc* probs, int32_t n_probs);
 /* Plan flags. By default dlx_plan_create autotunes: for each MFT stage it
  * times every compiled output-tile shape on the plan's own (zeroed)
  * workspace for the first frame chunk and keeps the fastest.
- * DLX_FLAG_NO_AUTOTUNE keeps the built-in size heuristic instead. */
-enum { DLX_FLAG_NO_AUTOTUNE = 1 };
+ * DLX_FLAG_NO_AUTOTUNE keeps the built-in size heuristic instead.
+ * The adjoint seed w phi G E is formed inside the first adjoint product's
+ * operand loader unless a frame's seed weights G exceed 4 MiB, in which case
+ * a separate elementwise pass forms it first; DLX_FLAG_SEED_PASS forces the
+ * separate pass (same results, bit for bit). */
+enum { DLX_FLAG_NO_AUTOTUNE = 1, DLX_FLAG_SEED_PASS = 2 };
 
 /* Create a plan: validates, picks kernel tiles, allocates every workspace on
  * the current device and builds the DFT matrices of each wavelength (FP64
@@ -104,8 +108,8 @@ enum { DLX_FLAG_NO_AUTOTUNE = 1 };
  * uneven size): every per-call array of dlx_psf_forward / dlx_loss_grad /
  * dlx_psf_backward / dlx_eval then packs the problems' arrays one after the
  * other, problem k starting at the element offsets dlx_plan_offsets reports
- * (loss_out holds one loss per problem). flags: 0 or DLX_FLAG_NO_AUTOTUNE
- * (others: DLX_ERR_INVALID_ARG). Results do not depend on the tiles chosen
+ * (loss_out holds one loss per problem). flags: an OR of DLX_FLAG_NO_AUTOTUNE
+ * and DLX_FLAG_SEED_PASS (other bits: DLX_ERR_INVALID_ARG). Results do not depend on the tiles chosen
  * except for the order of FP32/FP64 partial sums in the gradient
  * reductions. workspace_limit_bytes: 0 = no limit;
  * otherwise the frame-chunk size is reduced until the workspace fits, and
@@ -137,7 +141,7 @@ int32_t dlx_plan_problems(const dlx_plan* plan);
 
 /* Output-tile shape of each MFT stage (autotuned or heuristic): tiles[2k],
  * tiles[2k+1] = rows/32 and columns/32 of a workgroup's tile for stage
- * k = F1, F2, B2, B3, B4 (host int32_t[10]). */
+ * k = F1, F2, B3, B4 (host int32_t[8]). */
 dlx_status dlx_plan_tiles(const dlx_plan* plan, int32_t* tiles);
 
 /* Synchronise `stream`, then return and clear the plan's device status word
@@ -173,7 +177,9 @@ dlx_status dlx_loss_grad(dlx_plan* plan, const float* model, const float* binned
                          double* loss_out, float* dloss_dmodel, double* grad_flat, void* stream);
 
 /* Gradient through the optics given r = dL/dm (Sections 3-4). The inputs are
- * those of dlx_psf_forward; every focal field is recomputed, none is stored.
+ * those of dlx_psf_forward; the focal fields are recomputed (one chunk of
+ * frames at a time in the plan's workspace), nothing from the forward call
+ * is kept.
  * Outputs (double, FP64-reduced):
  *   grad_zernike [Nz]              dL/dc
  *   grad_map [n_map][n_map]        dL/dC (NULL iff n_map == 0)
@@ -224,14 +230,16 @@ dlx_status dlx_graph_launch(dlx_plan* plan, void* stream);
 
 /* Stages of one evaluation, for per-stage timing. PREP builds the OPD, the
  * pupil field and the tilt vectors; F1/F2 are the two MFT products of the
- * forward pass (F2 with the intensity/bin epilogue); BIN sums the binned
- * partials and applies the flat; LOSS is dlx_loss_grad; B2 recomputes the
- * focal field and forms the adjoint seed; B3/B4 are the two adjoint MFT
- * products (B4 with the phase-gradient epilogue); GRAD reduces dL/dOPD and
- * projects it onto the Zernike basis, the map, positions and fluxes. */
+ * forward pass (F2 stores the focal fields E); BIN forms the intensity, the
+ * intra-pixel weighting and the binning (per source, and the model with the
+ * flat); LOSS is the loss and residual; SEED expands the adjoint seed
+ * weights G = K flat r and the flux-gradient partials; B3/B4 are the two
+ * adjoint MFT products (B3 forms w phi G E in its loader, B4 has the
+ * phase-gradient epilogue); GRAD reduces dL/dOPD and projects it onto the
+ * Zernike basis, the map, positions and fluxes. */
 typedef enum {
   DLX_STAGE_PREP = 0, DLX_STAGE_F1, DLX_STAGE_F2, DLX_STAGE_BIN, DLX_STAGE_LOSS,
-  DLX_STAGE_B2, DLX_STAGE_B3, DLX_STAGE_B4, DLX_STAGE_GRAD, DLX_N_STAGES
+  DLX_STAGE_SEED, DLX_STAGE_B3, DLX_STAGE_B4, DLX_STAGE_GRAD, DLX_N_STAGES
 } dlx_stage;
 
 /* Diagnostics: while enabled (enable != 0), each stage launch is bracketed

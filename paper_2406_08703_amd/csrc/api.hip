@@ -6,6 +6,8 @@
 #include <cmath>
 #include <map>
 #include <mutex>
+#include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <new>
 
@@ -17,8 +19,9 @@ hipError_t launch_prep(dlx_plan* p, const float* A, const float* Z, const float*
                        const float* sources, hipStream_t st);
 hipError_t launch_intensity(dlx_plan* p, int f0, int nf, const float* sources, const float* intrapixel,
                             const float* flat, float* binned, float* model, hipStream_t st);
-hipError_t launch_seed(dlx_plan* p, int f0, int nf, const float* sources, const float* flat, const float* resid,
-                       const float* intrapixel, hipStream_t st);
+hipError_t launch_seed(dlx_plan* p, int f0, int nf, const float* flat, const float* resid, const float* intrapixel,
+                       hipStream_t st);
+hipError_t launch_seed_apply(dlx_plan* p, int f0, int nf, const float* sources, hipStream_t st);
 hipError_t launch_loss(dlx_plan* p, int f0, int nf, int chunk, const float* model, const float* binned,
                        const float* data, const float* flat, int kind, double mu, double sigma, float* r, double* gflat,
                        hipStream_t st);
@@ -26,6 +29,7 @@ hipError_t launch_loss_final(dlx_plan* p, int n_chunks, double* loss, hipStream_
 hipError_t launch_grad_reduce(dlx_plan* p, const float* Z, const float* Bm, double* gz, double* gmap, double* gsrc,
                               hipStream_t st);
 int loss_block_count(long long npix);
+int seed_block_count(long long npix);
 int zproj_chunks(long long npix, int Nz);
 }  // namespace dlx
 
@@ -36,6 +40,9 @@ namespace {
 constexpr size_t kDefaultChunkBudget = size_t(8) << 30;  // bytes of per-chunk intermediates
 constexpr int kMaxSide = 16384;
 constexpr int kTargetWG = 1024;
+// A frame's seed weights larger than this (bytes) are applied in a separate
+// pass rather than streamed by every B3 workgroup (about one XCD's L2).
+constexpr size_t kSeedFuseMaxBytes = size_t(4) << 20;
 
 #define DLX_HIP(expr)                        \
   do {                                       \
@@ -88,22 +95,28 @@ void layout(dlx_plan* p, Pool& pool) {
   p->d_T = pool.take<float>(2 * CP * No * ldNi);
   p->d_Y = pool.take<float>(2 * CP * No * ldNo);
   p->d_UT = pool.take<float>(2 * CP * Ni * ldNo);
-  p->d_Ys = p->bf16() ? static_cast<void*>(pool.take<float>(2 * CP * No * ldNo)) : nullptr;
+  p->d_G = pool.take<float>((size_t)p->frames_per_chunk * No * ldNo);
+  p->d_bs = pool.take<float>((size_t)p->frames_per_chunk * p->S * p->Nd * p->Nd);
   p->d_gpart = pool.take<float>((size_t)p->b4_groups_max * p->ksplit_cap * Ni * Ni);
   p->d_gopd = pool.take<double>(Ni * Ni);
-  p->d_flux = pool.take<double>((size_t)p->n_psf * p->tiles_b2_cap);
+  p->d_flux = pool.take<double>((size_t)p->F * p->S * p->seed_blocks);
   p->d_pos = pool.take<double>((size_t)p->n_psf * p->ksplit_cap * p->tiles_b4_cap * 2);
   p->d_lossblk = pool.take<double>((size_t)p->loss_blocks * p->n_chunks);
   p->d_tmp2 = pool.take<double>(std::max<size_t>(1, Ni * (size_t)p->Nmap));
   p->d_zpart = pool.take<double>((size_t)std::max(1, zproj_chunks((long long)Ni * Ni, p->Nz)) * std::max(1, p->Nz));
   p->d_status = pool.take<int>(1);
-  // autotuning stand-ins for caller arrays read by B2: flat [Nd^2], residual [frames_per_chunk][Nd^2], sources
-  p->d_tune = pool.take<float>((size_t)(p->frames_per_chunk + 1) * p->Nd * p->Nd + (size_t)p->F * p->S * 3);
+  // autotuning stand-in for the caller's sources, read by B3 [F][S][3]
+  p->d_tune = pool.take<float>((size_t)p->F * p->S * 3);
 }
 
+// T, E and U^T of one PSF
 size_t per_psf_bytes(const dlx_plan* p) {
-  return sizeof(float) * 2 *
-         ((size_t)p->No * p->ldNi + (size_t)(p->bf16() ? 2 : 1) * p->No * p->ldNo + (size_t)p->Ni * p->ldNo);
+  return sizeof(float) * 2 * ((size_t)p->No * p->ldNi + (size_t)p->No * p->ldNo + (size_t)p->Ni * p->ldNo);
+}
+
+// seed weights and per-source binned images of one frame
+size_t per_frame_bytes(const dlx_plan* p) {
+  return sizeof(float) * ((size_t)p->No * p->ldNo + (size_t)p->S * p->Nd * p->Nd);
 }
 
 bool ok_ptr(const void* q) { return q != nullptr; }
@@ -125,8 +138,6 @@ GemmArgs base_args(const dlx_plan* p, int f0, int nframes) {
   a.p0_by_wl = 2LL * p->Ni * p->ldNi;
   a.ldp = p->ldNi;
   a.wl = p->d_wl;
-  a.Q = p->Q;
-  a.n_det = p->Nd;
   a.xcoord = p->d_x;
   return a;
 }
@@ -140,10 +151,9 @@ Operand op_MT(const dlx_plan* p) {
 Operand op_T(const dlx_plan* p) {
   return Operand{p->d_T, (long long)p->chunk_psf * p->No * p->ldNi, 0, (long long)p->No * p->ldNi, p->ldNi};
 }
-// the adjoint seed: FP32 in place of E, or split BF16 in its own buffer
-Operand op_Y(const dlx_plan* p) {
-  return Operand{p->bf16() ? p->d_Ys : static_cast<const void*>(p->d_Y), (long long)p->chunk_psf * p->No * p->ldNo, 0,
-                 (long long)p->No * p->ldNo, p->ldNo};
+// the stored focal fields E (FP32 in both arithmetics)
+Operand op_E(const dlx_plan* p) {
+  return Operand{p->d_Y, (long long)p->chunk_psf * p->No * p->ldNo, 0, (long long)p->No * p->ldNo, p->ldNo};
 }
 Operand op_UT(const dlx_plan* p) {
   return Operand{p->d_UT, (long long)p->chunk_psf * p->Ni * p->ldNo, 0, (long long)p->Ni * p->ldNo, p->ldNo};
@@ -224,8 +234,9 @@ hipError_t run_f2(dlx_plan* p, int f0, int nf, hipStream_t st) {
   return launch_gemm(KIND_F2, p->bf16(), p->ts_f2, a, wg_count(a), st);
 }
 
-// B3 over frames [f0, f0 + nf): U^T = conj(M)^T Y^T from the seed Y.
-hipError_t run_b3(dlx_plan* p, int f0, int nf, hipStream_t st) {
+// B3 over frames [f0, f0 + nf): U^T = conj(M)^T Y^T with the seed Y = w phi G E
+// formed in the loader from E and the seed weights G.
+hipError_t run_b3(dlx_plan* p, int f0, int nf, const float* sources, hipStream_t st) {
   GemmArgs a = base_args(p, f0, nf);
   a.M = p->Ni;
   a.N = p->No;
@@ -233,7 +244,10 @@ hipError_t run_b3(dlx_plan* p, int f0, int nf, hipStream_t st) {
   a.n_items = nf * p->S * p->L;
   a.A = op_MT(p);
   a.conj_a = 1;
-  a.B = op_Y(p);
+  a.B = op_E(p);
+  a.sources = sources;
+  a.seedw = p->seed_pass ? nullptr : p->d_G;
+  a.seedw_by_frame = (long long)p->No * p->ldNo;
   a.out = p->d_UT;
   a.out_plane = op_UT(p).plane;
   a.out_by_psf = op_UT(p).by_psf;
@@ -264,39 +278,19 @@ hipError_t run_b4(dlx_plan* p, int c, int f0, int nf, hipStream_t st) {
 }
 
 // B3 and B4 of chunk c.
-hipError_t run_adjoint(dlx_plan* p, int c, int f0, int nf, hipStream_t st) {
+hipError_t run_adjoint(dlx_plan* p, int c, int f0, int nf, const float* sources, hipStream_t st) {
   const int nc = nf * p->S * p->L;
   {
     Stage sg(p, st, DLX_STAGE_B3, nc);
-    hipError_t e = run_b3(p, f0, nf, st);
+    hipError_t e = run_b3(p, f0, nf, sources, st);
     if (e != hipSuccess) return e;
   }
   Stage sg(p, st, DLX_STAGE_B4, nc);
   return run_b4(p, c, f0, nf, st);
 }
 
-GemmArgs e_args(dlx_plan* p, int f0, int nf, TileShape ts);
-
-// B2 over frames [f0, f0 + nf): recompute E, seed Y = w phi G E, flux partials.
-hipError_t run_b2(dlx_plan* p, int f0, int nf, const float* sources, const float* flat, const float* resid,
-                  const float* intrapixel, hipStream_t st) {
-  GemmArgs a = e_args(p, f0, nf, p->ts_b2);
-  a.n_items = nf * p->S * p->L;
-  a.sources = sources;
-  a.out = const_cast<void*>(op_Y(p).base);
-  a.out_plane = op_Y(p).plane;
-  a.out_by_psf = op_Y(p).by_psf;
-  a.ldo = p->ldNo;
-  a.red = p->d_flux;
-  a.flat = flat;
-  a.resid = resid;
-  a.intrapixel = intrapixel;
-  return launch_gemm(KIND_B2, p->bf16(), p->ts_b2, a, wg_count(a), st);
-}
-
 // Tile-dependent derived sizes: partial-sum tile counts and B4's split of K.
 void derive_tiles(dlx_plan* p) {
-  p->tiles_b2 = ceil_div(p->No, p->ts_b2.bm()) * ceil_div(p->No, p->ts_b2.bn());
   p->tiles_b4 = ceil_div(p->Ni, p->ts_b4.bm()) * ceil_div(p->Ni, p->ts_b4.bn());
   // split B4's K (= No) when its groups alone cannot fill the chip, keeping >= 128 per split
   const long long wg = (long long)p->tiles_b4 * p->b4_groups_max;
@@ -308,15 +302,10 @@ void derive_tiles(dlx_plan* p) {
 // ---- autotuner: time every compiled tile shape per MFT stage on chunk 0
 hipError_t run_stage_for_tuning(dlx_plan* p, int kind, hipStream_t st) {
   const int nf = std::min(p->frames_per_chunk, p->F);
-  const size_t nd2 = (size_t)p->Nd * p->Nd;
-  const float* flat = p->d_tune;
-  const float* resid = p->d_tune + nd2;
-  const float* src = p->d_tune + nd2 * (p->frames_per_chunk + 1);
   switch (kind) {
     case KIND_F1: return run_f1(p, 0, nf, st);
     case KIND_F2: return run_f2(p, 0, nf, st);
-    case KIND_B2: return run_b2(p, 0, nf, src, flat, resid, nullptr, st);
-    case KIND_B3: return run_b3(p, 0, nf, st);
+    case KIND_B3: return run_b3(p, 0, nf, p->d_tune, st);
     default: return run_b4(p, 0, 0, nf, st);
   }
 }
@@ -325,7 +314,6 @@ TileShape* stage_tile(dlx_plan* p, int kind) {
   switch (kind) {
     case KIND_F1: return &p->ts_f1;
     case KIND_F2: return &p->ts_f2;
-    case KIND_B2: return &p->ts_b2;
     case KIND_B3: return &p->ts_b3;
     default: return &p->ts_b4;
   }
@@ -340,7 +328,9 @@ hipError_t autotune(dlx_plan* p) {
     (void)hipEventDestroy(t0);
     return e;
   }
-  const int kinds[5] = {KIND_F1, KIND_F2, KIND_B2, KIND_B3, KIND_B4};
+  const int kinds[4] = {KIND_F1, KIND_F2, KIND_B3, KIND_B4};
+  const char* env = std::getenv("DLX_TUNE_LOG");   // diagnostics: print every candidate's time
+  const bool log = env && env[0] == '1';
   for (int kind : kinds) {
     TileShape* ts = stage_tile(p, kind);
     TileShape best = *ts;
@@ -356,6 +346,8 @@ hipError_t autotune(dlx_plan* p) {
       if ((e = hipEventSynchronize(t1)) != hipSuccess) break;
       float ms = 0.f;
       if ((e = hipEventElapsedTime(&ms, t0, t1)) != hipSuccess) break;
+      if (log)
+        std::fprintf(stderr, "dlx tune: stage %d tile %dx%d: %.4f ms per launch\n", kind, cand.bm(), cand.bn(), ms / 2);
       if (ms < best_ms) {
         best_ms = ms;
         best = cand;
@@ -374,14 +366,15 @@ hipError_t autotune(dlx_plan* p) {
 
 // Tuned tiles per problem shape and device, shared by every plan of the
 // process, so plans of a shape already seen skip the timing runs.
-using TuneKey = std::array<long long, 11>;
+using TuneKey = std::array<long long, 12>;
 std::mutex g_tune_mu;
-std::map<TuneKey, std::array<TileShape, 5>> g_tune;
+std::map<TuneKey, std::array<TileShape, 4>> g_tune;
 
 TuneKey tune_key(const dlx_plan* p) {
   int dev = 0;
   (void)hipGetDevice(&dev);
-  return {dev, (long long)p->prec, p->Ni, p->No, p->Q, p->L, p->S, p->F, p->frames_per_chunk, p->Nz, p->Nmap};
+  return {dev, (long long)p->prec, p->Ni, p->No, p->Q, p->L, p->S, p->F, p->frames_per_chunk, p->Nz, p->Nmap,
+          p->seed_pass ? 1 : 0};
 }
 
 hipError_t autotune_cached(dlx_plan* p) {
@@ -392,9 +385,8 @@ hipError_t autotune_cached(dlx_plan* p) {
     if (it != g_tune.end()) {
       p->ts_f1 = it->second[0];
       p->ts_f2 = it->second[1];
-      p->ts_b2 = it->second[2];
-      p->ts_b3 = it->second[3];
-      p->ts_b4 = it->second[4];
+      p->ts_b3 = it->second[2];
+      p->ts_b4 = it->second[3];
       derive_tiles(p);
       p->tuned = true;
       return hipSuccess;
@@ -403,7 +395,7 @@ hipError_t autotune_cached(dlx_plan* p) {
   const hipError_t e = autotune(p);
   if (e == hipSuccess) {
     std::lock_guard<std::mutex> lock(g_tune_mu);
-    g_tune[key] = {p->ts_f1, p->ts_f2, p->ts_b2, p->ts_b3, p->ts_b4};
+    g_tune[key] = {p->ts_f1, p->ts_f2, p->ts_b3, p->ts_b4};
   }
   return e;
 }
@@ -543,7 +535,7 @@ dlx_status dlx_plan_create(const dlx_problem_desc* probs, int32_t n_probs, dlx_p
   dlx_status v = dlx_validate(probs, n_probs);
   if (v != DLX_OK) return v;
   if (precision != DLX_FP32 && precision != DLX_BF16X3) return DLX_ERR_INVALID_ARG;
-  if ((flags & ~DLX_FLAG_NO_AUTOTUNE) != 0) return DLX_ERR_INVALID_ARG;
+  if ((flags & ~(DLX_FLAG_NO_AUTOTUNE | DLX_FLAG_SEED_PASS)) != 0) return DLX_ERR_INVALID_ARG;
   if (n_probs > 1) return create_multi(probs, n_probs, precision, flags, workspace_limit_bytes, out);
   const dlx_problem_desc& d = probs[0];
 
@@ -571,7 +563,7 @@ dlx_status dlx_plan_create(const dlx_problem_desc* probs, int32_t n_probs, dlx_p
   // chunk of whole frames whose intermediates fit the budget
   size_t budget = workspace_limit_bytes ? workspace_limit_bytes : kDefaultChunkBudget;
   const size_t psf_bytes = per_psf_bytes(p);
-  const size_t frame_bytes = psf_bytes * p->S * p->L;
+  const size_t frame_bytes = psf_bytes * p->S * p->L + per_frame_bytes(p);
   const size_t fixed = sizeof(float) * 2 * (size_t)p->L *
                        ((size_t)p->No * p->ldNi + (size_t)p->Ni * p->ldNo + (size_t)p->Ni * p->ldNi);
   if (workspace_limit_bytes) {
@@ -587,7 +579,6 @@ dlx_status dlx_plan_create(const dlx_problem_desc* probs, int32_t n_probs, dlx_p
 
   // tiles
   p->ts_f1 = choose_tile(p->No, p->Ni, p->chunk_psf, 1);
-  p->ts_b2 = choose_tile(p->No, p->No, p->chunk_psf, 1);
   p->ts_b3 = choose_tile(p->Ni, p->No, p->chunk_psf, 1);
   const int sl = p->S * p->L;
   p->ts_f2 = choose_tile(p->No, p->No, (long long)p->frames_per_chunk * sl, 1);
@@ -600,10 +591,11 @@ dlx_status dlx_plan_create(const dlx_problem_desc* probs, int32_t n_probs, dlx_p
   }
   derive_tiles(p);
   // partial-sum buffers are sized for the smallest candidate tile (32 x 32) and the largest split
-  p->tiles_b2_cap = ceil_div(p->No, 32) * ceil_div(p->No, 32);
   p->tiles_b4_cap = ceil_div(p->Ni, 32) * ceil_div(p->Ni, 32);
   p->ksplit_cap = 4;
   p->loss_blocks = loss_block_count((long long)p->Nd * p->Nd);
+  p->seed_blocks = seed_block_count((long long)p->Nd * p->Nd);
+  p->seed_pass = (flags & DLX_FLAG_SEED_PASS) || sizeof(float) * (size_t)p->No * p->ldNo > kSeedFuseMaxBytes;
   {
     const long long npix = (long long)p->Ni * p->Ni;
     const long long chunks = (npix + 1023) / 1024;
@@ -699,8 +691,8 @@ int32_t dlx_plan_problems(const dlx_plan* p) { return p ? (p->multi() ? (int32_t
 dlx_status dlx_plan_tiles(const dlx_plan* p, int32_t* tiles) {
   if (!p || !tiles) return DLX_ERR_INVALID_ARG;
   if (p->multi()) return dlx_plan_tiles(p->subs[0], tiles);
-  const TileShape t[5] = {p->ts_f1, p->ts_f2, p->ts_b2, p->ts_b3, p->ts_b4};
-  for (int k = 0; k < 5; ++k) {
+  const TileShape t[4] = {p->ts_f1, p->ts_f2, p->ts_b3, p->ts_b4};
+  for (int k = 0; k < 4; ++k) {
     tiles[2 * k] = t[k].wm;
     tiles[2 * k + 1] = t[k].wn;
   }
@@ -885,11 +877,20 @@ dlx_status dlx_psf_backward(dlx_plan* p, const float* transmission, const float*
       Stage sg(p, st, DLX_STAGE_F1, nc);
       DLX_HIP(run_f1(p, f0, nf, st));
     }
-    {  // B2: recompute E, seed Y = w phi G E
-      Stage sg(p, st, DLX_STAGE_B2, nc);
-      DLX_HIP(run_b2(p, f0, nf, sources, flat, dloss_dmodel, intrapixel, st));
+    {
+      Stage sg(p, st, DLX_STAGE_F2, nc);
+      DLX_HIP(run_f2(p, f0, nf, st));
     }
-    DLX_HIP(run_adjoint(p, c, f0, nf, st));
+    {  // per-source binned images only (for the flux gradient)
+      Stage sg(p, st, DLX_STAGE_BIN, nc);
+      DLX_HIP(launch_intensity(p, f0, nf, sources, intrapixel, flat, nullptr, nullptr, st));
+    }
+    {
+      Stage sg(p, st, DLX_STAGE_SEED, nc);
+      DLX_HIP(launch_seed(p, f0, nf, flat, dloss_dmodel, intrapixel, st));
+      if (p->seed_pass) DLX_HIP(launch_seed_apply(p, f0, nf, sources, st));
+    }
+    DLX_HIP(run_adjoint(p, c, f0, nf, sources, st));
   }
   Stage sg(p, st, DLX_STAGE_GRAD, p->n_psf);
   DLX_HIP(launch_grad_reduce(p, zernike_basis, map_basis, grad_zernike, grad_map, grad_sources, st));
@@ -968,10 +969,11 @@ dlx_status dlx_eval(dlx_plan* p, const dlx_eval_args* a, void* stream) {
                           a->prior_sigma, a->dloss_dmodel, a->grad_flat, st));
     }
     {
-      Stage sg(p, st, DLX_STAGE_B2, nc);
-      DLX_HIP(launch_seed(p, f0, nf, a->sources, a->flat, a->dloss_dmodel, a->intrapixel, st));
+      Stage sg(p, st, DLX_STAGE_SEED, nc);
+      DLX_HIP(launch_seed(p, f0, nf, a->flat, a->dloss_dmodel, a->intrapixel, st));
+      if (p->seed_pass) DLX_HIP(launch_seed_apply(p, f0, nf, a->sources, st));
     }
-    DLX_HIP(run_adjoint(p, c, f0, nf, st));
+    DLX_HIP(run_adjoint(p, c, f0, nf, a->sources, st));
   }
   Stage sg(p, st, DLX_STAGE_GRAD, p->n_psf);
   DLX_HIP(launch_loss_final(p, p->n_chunks, a->loss, st));

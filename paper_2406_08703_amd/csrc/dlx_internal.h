@@ -41,16 +41,16 @@ struct Operand {
 
 // The matrix-Fourier stages of one forward+gradient evaluation.
 //   F1  T = M_l P              (pupil field generated in the operand loader)
-//   F2  E = c T M_l^T          stored (intensity, binning and the adjoint seed read it)
-//   B2  E = c T M_l^T          epilogue: Y = w phi G E stored, flux partial sum G |E|^2
-//   B3  U^T = conj(M_l)^T Y^T  stored
+//   F2  E = c T M_l^T          stored FP32 (intensity, binning and the adjoint read it)
+//   B3  U^T = conj(M_l)^T Y^T  stored; the seed Y = w phi G E is formed in the operand loader
+//                              from E and the frame's seed weights G = K flat r
 //   B4  W = c M_l^H U          epilogue: g = 2 Im(conj(P) W) (2 pi / l) summed over a group; position partials
-enum GemmKind { KIND_F1 = 0, KIND_F2 = 1, KIND_B2 = 2, KIND_B3 = 3, KIND_B4 = 4 };
+enum GemmKind { KIND_F1 = 0, KIND_F2 = 1, KIND_B3 = 3, KIND_B4 = 4 };
 
 struct GemmArgs {
   int M, N, K;          // C[M][N] = sum_k A[i][k] B[j][k] per PSF
   int tiles_m, tiles_n;
-  int n_items;          // PSFs (F1, B2, B3) or PSF groups (F2, B4)
+  int n_items;          // PSFs (F1, F2, B3) or PSF groups (B4)
   int L, S;             // wavelengths, sources
   int psf0;             // global index of the chunk's first PSF
   int frame0;           // first frame of the chunk
@@ -71,7 +71,10 @@ struct GemmArgs {
   int ldp;
   const WlInfo* wl;
   const float* sources;   // [F][S][3]
-  // dense outputs (F1: T, F2: E, B2: Y, B3: U^T), indexed by local PSF;
+  // B3: seed weights G of the chunk's frames [nf][No][ldg]
+  const float* seedw;
+  long long seedw_by_frame;
+  // dense outputs (F1: T, F2: E, B3: U^T), indexed by local PSF;
   // E is FP32, the others are split BF16 under BF16X3
   void* out;
   long long out_plane;
@@ -80,13 +83,8 @@ struct GemmArgs {
   // group partials: B4 dL/dOPD [groups][Ni*Ni]
   float* part;
   int accumulate;
-  // per-(PSF, tile) FP64 partials: B2 flux [n_psf][tiles]; B4 positions [n_psf][tiles][2]
+  // per-(PSF, tile) FP64 partials: B4 positions [n_psf][tiles][2]
   double* red;
-  // detector
-  int Q, n_det;
-  const float* intrapixel;
-  const float* flat;
-  const float* resid;
   const double* xcoord;   // pupil sample coordinates (metres), [Ni]
 };
 
@@ -127,7 +125,7 @@ struct dlx_plan {
   int chunk_psf;        // PSFs in a full chunk
   int n_psf;
   // tiles
-  dlx::TileShape ts_f1, ts_f2, ts_b2, ts_b3, ts_b4;
+  dlx::TileShape ts_f1, ts_f2, ts_b3, ts_b4;
   int b4_gsize, b4_groups_max, b4_ksplit = 1;
   // device memory
   void* pool = nullptr;
@@ -145,18 +143,21 @@ struct dlx_plan {
   float* d_tx = nullptr;   // [n_psf][ldNi] planar
   float* d_ty = nullptr;
   float* d_T = nullptr;    // [chunk_psf][No][ldNi] planar
-  float* d_Y = nullptr;    // [chunk_psf][No][ldNo] planar: E, then the seed Y in place
+  float* d_Y = nullptr;    // [chunk_psf][No][ldNo] planar FP32: the focal fields E
   float* d_UT = nullptr;   // [chunk_psf][Ni][ldNo] planar
-  void* d_Ys = nullptr;    // BF16X3: split seed Y [chunk_psf][No][ldNo] (E stays FP32 in d_Y)
+  float* d_G = nullptr;    // seed weights G = K flat r [frames_per_chunk][No][ldNo]
+  float* d_bs = nullptr;   // per-source binned sum_l w_l K|E|^2 [frames_per_chunk][S][Nd*Nd]
   float* d_gpart = nullptr;    // [b4_groups_max * b4_ksplit][Ni*Ni]
   double* d_gopd = nullptr;    // [Ni*Ni]
-  double* d_flux = nullptr;    // [n_psf][tiles_b2]
+  double* d_flux = nullptr;    // flux gradient partials [F][S][seed blocks]
   double* d_pos = nullptr;     // [n_psf][b4_ksplit][tiles_b4][2]
   double* d_lossblk = nullptr; // [loss blocks]
   double* d_tmp2 = nullptr;    // [Ni][Nmap] for the map gradient
   double* d_zpart = nullptr;   // Zernike projection partials [chunks][Nz]
   int* d_status = nullptr;
   int loss_blocks = 0;
+  int seed_blocks = 0;   // pixel blocks of the seed-weight kernel
+  bool seed_pass = false; // form Y = w phi G E in a separate pass (large frames) instead of in B3's loader
   // stage timing (diagnostics)
   bool profiling = false;
   std::vector<hipEvent_t> ev_pool;
@@ -166,8 +167,8 @@ struct dlx_plan {
   double stage_ms[DLX_N_STAGES] = {};
   long long stage_launches[DLX_N_STAGES] = {};
   long long stage_psfs[DLX_N_STAGES] = {};
-  int tiles_b2 = 0, tiles_b4 = 0;
-  int tiles_b2_cap = 0, tiles_b4_cap = 0, ksplit_cap = 1;   // sizes the partial-sum buffers
+  int tiles_b4 = 0;
+  int tiles_b4_cap = 0, ksplit_cap = 1;   // sizes the partial-sum buffers
   float* d_tune = nullptr;
   bool tuned = false;
   // captured evaluation

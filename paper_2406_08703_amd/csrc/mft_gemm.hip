@@ -8,7 +8,8 @@
 //                       hi*hi + hi*lo + lo*hi (lo*lo dropped), FP32 accumulation,
 //                       K step 32. Operands arrive pre-split in HBM as four bf16
 //                       planes (re hi, re lo, im hi, im lo), the same bytes as
-//                       planar FP32; the F1 pupil field is split at LDS store.
+//                       planar FP32; the operands formed in the loaders (the
+//                       F1 pupil field, the B3 seed) are split at LDS store.
 //
 // Every stage is a "TN" product C[i][j] = sum_k A[i][k] B[j][k] with both
 // operands K-contiguous, so one 128-bit LDS read per operand block feeds the
@@ -24,9 +25,10 @@
 // Re = ArBr - AiBi, Im = ArBi + AiBr (no 3-multiply trick: it loses accuracy
 // on operands of very different size).
 //
-// Stage-specific work is fused into the operand loader (F1: P0^T times the
-// row tilt) and into the epilogues (F1: the column tilt; F2: the focal-field
-// scale; B2: the adjoint seed; B4: the phase gradient and position sums).
+// Stage-specific work is fused into the operand loaders (F1: P0^T times the
+// row tilt; B3: the adjoint seed w phi G E from the stored field E and the
+// frame's seed weights G) and into the epilogues (F1: the column tilt; F2:
+// the focal-field scale; B4: the phase gradient and position sums).
 #include <type_traits>
 
 #include "dlx_internal.h"
@@ -157,8 +159,20 @@ __global__ __launch_bounds__(256) void cgemm_kernel(const GemmArgs a) {
     const el_t* Ab = static_cast<const el_t*>(a.A.base) + (long long)wl * a.A.by_wl + (long long)lb * a.A.by_psf;
     const float* txb = a.tx + (long long)gb * a.ldt;
     const float* tyb = a.ty + (long long)gb * a.ldt;
-    // F1's B operand is the FP32 field P0^T (row tilt applied at store); all others are el_t.
-    using bsrc_t = typename std::conditional<KIND == KIND_F1, float, el_t>::type;
+    // F1's B operand is the FP32 field P0^T (row tilt applied at store), B3's the FP32 field E
+    // (seed applied at store); all others are el_t.
+    constexpr bool kFp32B = KIND == KIND_F1 || KIND == KIND_B3;
+    using bsrc_t = typename std::conditional<kFp32B, float, el_t>::type;
+    // B3 with seed weights: Y = (w phi G) E formed here; without (seedw null) E already holds Y.
+    float wphi = 1.f;
+    const float* gwb = nullptr;
+    if constexpr (KIND == KIND_B3) {
+      if (a.seedw) {
+        const int fs = gb / a.L;
+        wphi = a.wl[wl].w * a.sources[fs * 3 + 2];
+        gwb = a.seedw + (long long)(fs / a.S - a.frame0) * a.seedw_by_frame;
+      }
+    }
     const bsrc_t* Bb = static_cast<const bsrc_t*>(a.B.base) + (long long)wl * a.B.by_wl + (long long)lb * a.B.by_psf;
 
     f4 accr[WM][WN], acci[WM][WN];
@@ -174,8 +188,9 @@ __global__ __launch_bounds__(256) void cgemm_kernel(const GemmArgs a) {
     // A unit = one row, 16 bytes of k per plane: 4 FP32 k (PREC 0) or 8 bf16 k (PREC 1).
     u4 ga[A_U][NPL];
     int ga_k[A_U];
-    // B: el_t planes like A, except F1 which stages FP32 P0^T re/im and the row tilt
-    constexpr int BPL = (KIND == KIND_F1) ? (PREC == 0 ? 4 : 8) : NPL;
+    // B: el_t planes like A, except F1 which stages FP32 P0^T re/im and the row tilt,
+    // and B3 which stages FP32 E re/im and the seed weight
+    constexpr int BPL = (KIND == KIND_F1) ? (PREC == 0 ? 4 : 8) : (KIND == KIND_B3) ? (PREC == 0 ? 3 : 6) : NPL;
     u4 gbv[B_U][BPL];
     int gb_k[B_U];
 
@@ -215,6 +230,16 @@ __global__ __launch_bounds__(256) void cgemm_kernel(const GemmArgs a) {
               gbv[r][1 * V + v] = *reinterpret_cast<const u4*>(p + a.B.plane + 4 * v);
               gbv[r][2 * V + v] = *reinterpret_cast<const u4*>(tyb + gk + 4 * v);
               gbv[r][3 * V + v] = *reinterpret_cast<const u4*>(tyb + a.tilt_plane + gk + 4 * v);
+            }
+          } else if constexpr (KIND == KIND_B3) {
+            // FP32 E re, im and G for 4 (PREC 0) or 8 (PREC 1) consecutive k
+            constexpr int V = PREC == 0 ? 1 : 2;
+#pragma unroll
+            for (int v = 0; v < V; ++v) {
+              gbv[r][0 * V + v] = *reinterpret_cast<const u4*>(p + 4 * v);
+              gbv[r][1 * V + v] = *reinterpret_cast<const u4*>(p + a.B.plane + 4 * v);
+              gbv[r][2 * V + v] = gwb ? *reinterpret_cast<const u4*>(gwb + (long long)gj * a.B.ld + gk + 4 * v)
+                                      : __builtin_bit_cast(u4, f4{1.f, 1.f, 1.f, 1.f});
             }
           } else {
 #pragma unroll
@@ -276,16 +301,23 @@ __global__ __launch_bounds__(256) void cgemm_kernel(const GemmArgs a) {
         const int q = tid + 256 * r;
         if (q < UNITS_B) {
           const int row = q >> 2, kq = q & 3;
-          if constexpr (KIND == KIND_F1) {
-            // P[m][n] / tx[n] = P0^T[n][m] * ty[m]  (row n, k = m); tx is applied in the epilogue
+          if constexpr (kFp32B) {
+            // F1: P[m][n] / tx[n] = P0^T[n][m] * ty[m] (row n, k = m; tx is applied in the epilogue).
+            // B3: Y[l][k] = (w phi G[l][k]) E[l][k].
             constexpr int V = PREC == 0 ? 1 : 2;
             f4 pr[V], pi[V];
 #pragma unroll
             for (int v = 0; v < V; ++v) {
               const f4 xr = __builtin_bit_cast(f4, gbv[r][0 * V + v]), xi = __builtin_bit_cast(f4, gbv[r][1 * V + v]);
-              const f4 yr = __builtin_bit_cast(f4, gbv[r][2 * V + v]), yi = __builtin_bit_cast(f4, gbv[r][3 * V + v]);
-              pr[v] = xr * yr - xi * yi;
-              pi[v] = xr * yi + xi * yr;
+              if constexpr (KIND == KIND_F1) {
+                const f4 yr = __builtin_bit_cast(f4, gbv[r][2 * V + v]), yi = __builtin_bit_cast(f4, gbv[r][3 * V + v]);
+                pr[v] = xr * yr - xi * yi;
+                pi[v] = xr * yi + xi * yr;
+              } else {
+                const f4 sw = wphi * __builtin_bit_cast(f4, gbv[r][2 * V + v]);
+                pr[v] = sw * xr;
+                pi[v] = sw * xi;
+              }
               fix32(pr[v], pi[v], gb_k[r] + 4 * v, false);
             }
             if constexpr (PREC == 0) {
@@ -402,8 +434,6 @@ __global__ __launch_bounds__(256) void cgemm_kernel(const GemmArgs a) {
     }
 
     // ------------------------------------------------------------------ per-PSF epilogue
-    const int f = gb / (a.S * a.L);
-    const int s = (gb / a.L) % a.S;
     const WlInfo wi = a.wl[wl];
     if constexpr (KIND == KIND_F1 || KIND == KIND_F2 || KIND == KIND_B3) {
       // F1: T = acc * tx[n] (column tilt); F2: E = c acc, always FP32; B3: U^T = acc
@@ -441,37 +471,6 @@ __global__ __launch_bounds__(256) void cgemm_kernel(const GemmArgs a) {
             }
           }
         }
-    } else if constexpr (KIND == KIND_B2) {
-      const float phi = a.sources[(f * a.S + s) * 3 + 2];
-      const float wphi = wi.w * phi;
-      const float c = wi.scale;
-      const int Nd = a.n_det, Q = a.Q;
-      const float* rf = a.resid + (long long)f * Nd * Nd;
-      void* ob = (PREC == 0) ? static_cast<void*>(static_cast<float*>(a.out) + (long long)lb * a.out_by_psf)
-                             : static_cast<void*>(static_cast<unsigned short*>(a.out) + (long long)lb * a.out_by_psf);
-      double part = 0.0;
-#pragma unroll
-      for (int bm = 0; bm < WM; ++bm)
-#pragma unroll
-        for (int bn = 0; bn < WN; ++bn) {
-          const int j = col0 + wc * 16 * WN + bn * 16 + (lane & 15);
-#pragma unroll
-          for (int r = 0; r < 4; ++r) {
-            const int i = row0 + wr * 16 * WM + bm * 16 + 4 * (lane >> 4) + r;
-            if (i < M && j < N) {
-              const int p = (i / Q) * Nd + (j / Q);
-              float g = a.flat[p] * rf[p];
-              if (a.intrapixel) g *= a.intrapixel[(i % Q) * Q + (j % Q)];
-              const float er = c * accr[bm][bn][r], ei = c * acci[bm][bn][r];
-              put<PREC>(ob, a.out_plane, (long long)i * a.ldo + j, wphi * g * er, wphi * g * ei);
-              part += (double)g * (double)(er * er + ei * ei);
-            }
-          }
-        }
-      part = wave_sum(part);
-      if (lane == 0) sred[wave] = part;
-      __syncthreads();
-      if (tid == 0) a.red[(long long)gb * tiles + tile] = (double)wi.w * (sred[0] + sred[1] + sred[2] + sred[3]);
     } else if constexpr (KIND == KIND_B4) {
       const float c = wi.scale;
       const float kp = 2.0f * wi.kphase;
@@ -565,7 +564,6 @@ hipError_t launch_prec(int kind, TileShape ts, const GemmArgs& a, int n_wg, hipS
   switch (kind) {
     case KIND_F1: return launch_kind<KIND_F1, PREC>(ts, a, n_wg, st);
     case KIND_F2: return launch_kind<KIND_F2, PREC>(ts, a, n_wg, st);
-    case KIND_B2: return launch_kind<KIND_B2, PREC>(ts, a, n_wg, st);
     case KIND_B3: return launch_kind<KIND_B3, PREC>(ts, a, n_wg, st);
     case KIND_B4: return launch_kind<KIND_B4, PREC>(ts, a, n_wg, st);
     default: return hipErrorInvalidValue;

@@ -3,6 +3,8 @@
 // pixel-response prior and its gradients (Section 4), and the projections of
 // dL/dOPD onto the Zernike basis and the bicubic map. Every reduction runs in
 // FP64 in a fixed order, so results are bitwise reproducible.
+#include <algorithm>
+
 #include "dlx_internal.h"
 
 namespace dlx {
@@ -10,59 +12,68 @@ namespace {
 
 // Intensity, intra-pixel weighting, binning and pixel response (Section 3)
 // from the stored focal fields E of frames [f0, f0 + nf):
-//   binned[f][p] = sum_s sum_l w_l phi_s sum_{a,b<Q} K[a][b] |E[Qp_r + a][Qp_c + b]|^2,
-//   model[f][p] = flat[p] * binned[f][p].
-// Block (64, 4): 64 detector pixels x 4 PSF lanes; lane y sums PSFs
-// y, y + 4, ... and the lanes are added in a fixed order (deterministic).
-// QT > 0 fixes Q at compile time (vector loads along the pixel's rows).
+//   bs[f][s][p] = sum_l w_l sum_{a,b<Q} K[a][b] |E_{f,s,l}[Qp_r + a][Qp_c + b]|^2   (per source, no flux)
+//   binned[f][p] = sum_s phi_s bs[f][s][p],  model[f][p] = flat[p] * binned[f][p]
+// (binned and model may be null: the adjoint only needs bs). Block (64, 4):
+// 64 detector pixels x 4 wavelength lanes; lane y sums wavelengths y, y + 4,
+// ... and the lanes are added in a fixed order (deterministic). QT > 0 fixes
+// Q at compile time (vector loads along the pixel's rows).
 template <int QT>
 __global__ void intensity_kernel(const float* E, long long plane, long long by_psf, int ld, int f0, int F, int S, int L,
                                  int Qr, int Nd, const float* sources, const WlInfo* wl, const float* intrapixel,
-                                 const float* flat, float* binned, float* model) {
+                                 const float* flat, float* bs, float* binned, float* model) {
   __shared__ double sh[4][64];
   const int Q = QT > 0 ? QT : Qr;
   const long long npix = (long long)Nd * Nd;
   const long long p = (long long)blockIdx.x * 64 + threadIdx.x;
   const int f = f0 + blockIdx.y;
   const int y = threadIdx.y;
-  double acc = 0.0;
-  if (p < npix && f < F) {
-    const int pr = (int)(p / Nd), pc = (int)(p - (long long)pr * Nd);
-    const int SL = S * L;
-    for (int q = y; q < SL; q += 4) {
-      const int s = q / L, l = q - s * L;
-      const long long lb = (long long)(f - f0) * SL + q;
-      const float* e = E + lb * by_psf + (long long)(Q * pr) * ld + Q * pc;
-      float part = 0.f;
-      if constexpr (QT == 4 || QT == 2) {
-        typedef float vq __attribute__((ext_vector_type(QT)));
+  const bool live = p < npix && f < F;
+  const int pr = live ? (int)(p / Nd) : 0, pc = live ? (int)(p - (long long)pr * Nd) : 0;
+  double total = 0.0;
+  for (int s = 0; s < S; ++s) {
+    double acc = 0.0;
+    if (live) {
+      for (int l = y; l < L; l += 4) {
+        const long long lb = ((long long)(f - f0) * S + s) * L + l;
+        const float* e = E + lb * by_psf + (long long)(Q * pr) * ld + Q * pc;
+        float part = 0.f;
+        if constexpr (QT == 4 || QT == 2) {
+          typedef float vq __attribute__((ext_vector_type(QT)));
 #pragma unroll
-        for (int a = 0; a < QT; ++a) {
-          const vq vr = *reinterpret_cast<const vq*>(e + (long long)a * ld);
-          const vq vi = *reinterpret_cast<const vq*>(e + plane + (long long)a * ld);
+          for (int a = 0; a < QT; ++a) {
+            const vq vr = *reinterpret_cast<const vq*>(e + (long long)a * ld);
+            const vq vi = *reinterpret_cast<const vq*>(e + plane + (long long)a * ld);
 #pragma unroll
-          for (int b = 0; b < QT; ++b) {
-            float v = vr[b] * vr[b] + vi[b] * vi[b];
-            if (intrapixel) v *= intrapixel[a * QT + b];
-            part += v;
+            for (int b = 0; b < QT; ++b) {
+              float v = vr[b] * vr[b] + vi[b] * vi[b];
+              if (intrapixel) v *= intrapixel[a * QT + b];
+              part += v;
+            }
           }
+        } else {
+          for (int a = 0; a < Q; ++a)
+            for (int b = 0; b < Q; ++b) {
+              const float er = e[(long long)a * ld + b], ei = e[plane + (long long)a * ld + b];
+              float v = er * er + ei * ei;
+              if (intrapixel) v *= intrapixel[a * Q + b];
+              part += v;
+            }
         }
-      } else {
-        for (int a = 0; a < Q; ++a)
-          for (int b = 0; b < Q; ++b) {
-            const float er = e[(long long)a * ld + b], ei = e[plane + (long long)a * ld + b];
-            float v = er * er + ei * ei;
-            if (intrapixel) v *= intrapixel[a * Q + b];
-            part += v;
-          }
+        acc += (double)wl[l].w * (double)part;
       }
-      acc += (double)(wl[l].w * sources[((long long)f * S + s) * 3 + 2]) * (double)part;
     }
+    sh[y][threadIdx.x] = acc;
+    __syncthreads();
+    if (y == 0 && live) {
+      const double v = sh[0][threadIdx.x] + sh[1][threadIdx.x] + sh[2][threadIdx.x] + sh[3][threadIdx.x];
+      bs[((long long)(f - f0) * S + s) * npix + p] = (float)v;
+      total += (double)sources[((long long)f * S + s) * 3 + 2] * v;
+    }
+    __syncthreads();
   }
-  sh[y][threadIdx.x] = acc;
-  __syncthreads();
-  if (y == 0 && p < npix && f < F) {
-    const float bv = (float)(sh[0][threadIdx.x] + sh[1][threadIdx.x] + sh[2][threadIdx.x] + sh[3][threadIdx.x]);
+  if (y == 0 && live && binned) {
+    const float bv = (float)total;
     binned[(long long)f * npix + p] = bv;
     model[(long long)f * npix + p] = flat[p] * bv;
   }
@@ -142,81 +153,66 @@ __global__ void final_sum_kernel(const double* blk, int n, double* out) {
   if (threadIdx.x == 0) out[0] = t;
 }
 
-// Adjoint seed from stored focal fields (fused evaluation): in place
-// Y = w phi G E with G[k][l] = K[k%Q][l%Q] flat[p] r_f[p], p = (k/Q, l/Q);
-// per (PSF, row block) FP64 partial of w sum G |E|^2 (the flux gradient).
-// With a split output (BF16X3) the seed is written as bf16 hi/lo planes to Ys
-// and E is left in place.
-template <int SPLIT>
-__global__ void seed_kernel(float* Y, long long plane, long long by_psf, int ld, int psf0, int No, int Q, int Nd,
-                            int S, int L, const float* sources, const WlInfo* wl, const float* flat, const float* resid,
-                            const float* intrapixel, int rows_per_blk, int nblk, double* flux, unsigned short* Ys) {
-  typedef float f4 __attribute__((ext_vector_type(4)));
-  __shared__ double sh[4];
-  const int lb = blockIdx.x / nblk;
-  const int blk = blockIdx.x - lb * nblk;
-  const int gb = psf0 + lb;
-  const int l_idx = gb % L;
-  const int fs = gb / L;
-  const int f = fs / S;
-  const WlInfo wi = wl[l_idx];
-  const float wphi = wi.w * sources[fs * 3 + 2];
-  const float* rf = resid + (long long)f * Nd * Nd;
-  float* yb = Y + (long long)lb * by_psf;
-  const int k0 = blk * rows_per_blk;
-  const int k1 = min(No, k0 + rows_per_blk);
-  const int nq = (No + 3) / 4;                       // groups of 4 columns per row (ld is a multiple of 16)
-  const long long n = (long long)(k1 > k0 ? k1 - k0 : 0) * nq;
-  double part = 0.0;
-  for (long long t = threadIdx.x; t < n; t += blockDim.x) {
-    const int k = k0 + (int)(t / nq);
-    const int l0 = 4 * (int)(t - (long long)(k - k0) * nq);
-    const long long off = (long long)k * ld + l0;
-    f4 er = *reinterpret_cast<const f4*>(yb + off);
-    f4 ei = *reinterpret_cast<const f4*>(yb + plane + off);
-    f4 yr, yi;
-#pragma unroll
-    for (int e = 0; e < 4; ++e) {
-      const int l = l0 + e;
-      float g = 0.f;
-      if (l < No) {
-        const int p = (k / Q) * Nd + (l / Q);
-        g = flat[p] * rf[p];
-        if (intrapixel) g *= intrapixel[(k % Q) * Q + (l % Q)];
-      } else {
-        er[e] = 0.f;
-        ei[e] = 0.f;
-      }
-      yr[e] = wphi * g * er[e];
-      yi[e] = wphi * g * ei[e];
-      part += (double)g * (double)(er[e] * er[e] + ei[e] * ei[e]);
-    }
-    if constexpr (SPLIT == 0) {
-      *reinterpret_cast<f4*>(yb + off) = yr;
-      *reinterpret_cast<f4*>(yb + plane + off) = yi;
-    } else {
-      typedef unsigned short us4 __attribute__((ext_vector_type(4)));
-      us4 hr, lr, hi, li;
-#pragma unroll
-      for (int e = 0; e < 4; ++e) {
-        const __bf16 a = (__bf16)yr[e], b = (__bf16)yi[e];
-        hr[e] = __builtin_bit_cast(unsigned short, a);
-        lr[e] = __builtin_bit_cast(unsigned short, (__bf16)(yr[e] - (float)a));
-        hi[e] = __builtin_bit_cast(unsigned short, b);
-        li[e] = __builtin_bit_cast(unsigned short, (__bf16)(yi[e] - (float)b));
-      }
-      unsigned short* o = Ys + (long long)lb * by_psf + off;
-      *reinterpret_cast<us4*>(o) = hr;
-      *reinterpret_cast<us4*>(o + plane) = lr;
-      *reinterpret_cast<us4*>(o + 2 * plane) = hi;
-      *reinterpret_cast<us4*>(o + 3 * plane) = li;
-    }
+constexpr int kSeedThreads = 256;
+
+// Seed weights of the adjoint (Section 4) for frames [f0, f0 + nf): per
+// detector pixel p = (pr, pc) and focal sample (Q pr + a, Q pc + b),
+//   G[f][Q pr + a][Q pc + b] = K[a][b] flat[p] r_f[p]
+// (the B3 loader forms Y = w_l phi_s G E from it), and the flux gradient
+// partials sum_p flat[p] r_f[p] bs[f][s][p] = sum_l w_l sum G |E_{f,s,l}|^2 per
+// (frame, source) and pixel block, at flux[(f S + s) nblk + block].
+__global__ void seed_weight_kernel(const float* resid, const float* flat, const float* intrapixel, const float* bs,
+                                   int f0, int Q, int Nd, int S, int ldg, long long g_by_frame, float* G, int nblk,
+                                   double* flux) {
+  __shared__ double sh[kSeedThreads / 64];
+  const long long npix = (long long)Nd * Nd;
+  const long long p = (long long)blockIdx.x * kSeedThreads + threadIdx.x;
+  const int fl = blockIdx.y;   // frame within the chunk
+  const int f = f0 + fl;
+  float h = 0.f;
+  if (p < npix) {
+    const int pr = (int)(p / Nd), pc = (int)(p - (long long)pr * Nd);
+    h = flat[p] * resid[(long long)f * npix + p];
+    float* g = G + fl * g_by_frame + (long long)(Q * pr) * ldg + Q * pc;
+    for (int a = 0; a < Q; ++a)
+      for (int b = 0; b < Q; ++b) g[(long long)a * ldg + b] = intrapixel ? h * intrapixel[a * Q + b] : h;
   }
+  for (int s = 0; s < S; ++s) {
+    double v = 0.0;
+    if (p < npix) v = (double)h * (double)bs[((long long)fl * S + s) * npix + p];
 #pragma unroll
-  for (int o = 32; o > 0; o >>= 1) part += __shfl_xor(part, o, 64);
-  if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = part;
-  __syncthreads();
-  if (threadIdx.x == 0) flux[(long long)gb * nblk + blk] = (double)wi.w * (sh[0] + sh[1] + sh[2] + sh[3]);
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+    if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = v;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      double t = 0.0;
+      for (int w = 0; w < kSeedThreads / 64; ++w) t += sh[w];
+      flux[((long long)f * S + s) * nblk + blockIdx.x] = t;
+    }
+    __syncthreads();
+  }
+}
+
+// Y = (w_l phi_s G_f) E in place for the chunk's PSFs: the separate seed pass,
+// used instead of the B3 loader when a frame's seed weights are too large to
+// stay cached while B3 streams them. Same arithmetic as the loader.
+__global__ void seed_apply_kernel(float* E, long long plane, long long by_psf, const float* G, long long g_by_frame,
+                                  long long n4, int blocks_per_psf, int psf0, int f0, int S, int L,
+                                  const float* sources, const WlInfo* wl) {
+  typedef float f4 __attribute__((ext_vector_type(4)));
+  const int lb = blockIdx.x / blocks_per_psf;
+  const int bx = blockIdx.x - lb * blocks_per_psf;
+  const int gb = psf0 + lb;
+  const int fs = gb / L;
+  const float wphi = wl[gb % L].w * sources[fs * 3 + 2];
+  const f4* g = reinterpret_cast<const f4*>(G + (long long)(fs / S - f0) * g_by_frame);
+  f4* er = reinterpret_cast<f4*>(E + (long long)lb * by_psf);
+  f4* ei = reinterpret_cast<f4*>(E + plane + (long long)lb * by_psf);
+  for (long long i = (long long)bx * blockDim.x + threadIdx.x; i < n4; i += (long long)blocks_per_psf * blockDim.x) {
+    const f4 sw = wphi * g[i];
+    er[i] = sw * er[i];
+    ei[i] = sw * ei[i];
+  }
 }
 
 // gopd[p] = sum_g gpart[g][p]
@@ -304,9 +300,10 @@ __global__ void map_grad2_kernel(const double* tmp2, const float* Bm, int Ni, in
   grad[(long long)j * Nmap + k] = acc;
 }
 
-// grad_sources[f][s] = (sum over wavelengths and tiles of the position and flux
-// partials), one 64-thread block per (frame, star), fixed reduction order.
-__global__ void src_reduce_kernel(const double* flux, int tiles_b2, const double* pos, int tiles_b4, int L,
+// grad_sources[f][s] = (sum over wavelengths and tiles of the position partials,
+// sum over pixel blocks of the flux partials), one block per (frame, star),
+// fixed reduction order.
+__global__ void src_reduce_kernel(const double* flux, int seed_blocks, const double* pos, int tiles_b4, int L,
                                   double* grad) {
   __shared__ double sh[3][4];
   const int fs = blockIdx.x;
@@ -317,7 +314,7 @@ __global__ void src_reduce_kernel(const double* flux, int tiles_b2, const double
     ga += pos[q];
     gbt += pos[q + 1];
   }
-  for (int i = threadIdx.x; i < L * tiles_b2; i += 256) gp += flux[b0 * tiles_b2 + i];
+  for (int i = threadIdx.x; i < seed_blocks; i += 256) gp += flux[(long long)fs * seed_blocks + i];
   for (int o = 32; o > 0; o >>= 1) {
     ga += __shfl_xor(ga, o, 64);
     gbt += __shfl_xor(gbt, o, 64);
@@ -342,7 +339,7 @@ hipError_t launch_intensity(dlx_plan* p, int f0, int nf, const float* sources, c
   const long long plane = (long long)p->chunk_psf * p->No * p->ldNo, by = (long long)p->No * p->ldNo;
 #define DLX_INTENSITY(QT)                                                                                         \
   hipLaunchKernelGGL(intensity_kernel<QT>, grid, blk, 0, st, p->d_Y, plane, by, p->ldNo, f0, p->F, p->S, p->L, \
-                     p->Q, p->Nd, sources, p->d_wl, intrapixel, flat, binned, model)
+                     p->Q, p->Nd, sources, p->d_wl, intrapixel, flat, p->d_bs, binned, model)
   switch (p->Q) {
     case 2: DLX_INTENSITY(2); break;
     case 4: DLX_INTENSITY(4); break;
@@ -352,20 +349,23 @@ hipError_t launch_intensity(dlx_plan* p, int f0, int nf, const float* sources, c
   return hipGetLastError();
 }
 
-hipError_t launch_seed(dlx_plan* p, int f0, int nf, const float* sources, const float* flat, const float* resid,
-                       const float* intrapixel, hipStream_t st) {
+int seed_block_count(long long npix) { return (int)((npix + kSeedThreads - 1) / kSeedThreads); }
+
+hipError_t launch_seed(dlx_plan* p, int f0, int nf, const float* flat, const float* resid, const float* intrapixel,
+                       hipStream_t st) {
+  hipLaunchKernelGGL(seed_weight_kernel, dim3(p->seed_blocks, nf), dim3(kSeedThreads), 0, st, resid, flat, intrapixel,
+                     p->d_bs, f0, p->Q, p->Nd, p->S, p->ldNo, (long long)p->No * p->ldNo, p->d_G, p->seed_blocks,
+                     p->d_flux);
+  return hipGetLastError();
+}
+
+hipError_t launch_seed_apply(dlx_plan* p, int f0, int nf, const float* sources, hipStream_t st) {
   const int nc = nf * p->S * p->L;
-  const int nblk = p->tiles_b2;
-  const int rows = (p->No + nblk - 1) / nblk;
-  const long long plane = (long long)p->chunk_psf * p->No * p->ldNo, by = (long long)p->No * p->ldNo;
-  if (p->bf16())
-    hipLaunchKernelGGL(seed_kernel<1>, dim3(nc * nblk), dim3(256), 0, st, p->d_Y, plane, by, p->ldNo,
-                       f0 * p->S * p->L, p->No, p->Q, p->Nd, p->S, p->L, sources, p->d_wl, flat, resid, intrapixel,
-                       rows, nblk, p->d_flux, static_cast<unsigned short*>(p->d_Ys));
-  else
-    hipLaunchKernelGGL(seed_kernel<0>, dim3(nc * nblk), dim3(256), 0, st, p->d_Y, plane, by, p->ldNo,
-                       f0 * p->S * p->L, p->No, p->Q, p->Nd, p->S, p->L, sources, p->d_wl, flat, resid, intrapixel,
-                       rows, nblk, p->d_flux, nullptr);
+  const long long n4 = (long long)p->No * p->ldNo / 4;
+  const int bpp = (int)std::min<long long>(64, (n4 + 255) / 256);
+  hipLaunchKernelGGL(seed_apply_kernel, dim3(nc * bpp), dim3(256), 0, st, p->d_Y,
+                     (long long)p->chunk_psf * p->No * p->ldNo, (long long)p->No * p->ldNo, p->d_G,
+                     (long long)p->No * p->ldNo, n4, bpp, f0 * p->S * p->L, f0, p->S, p->L, sources, p->d_wl);
   return hipGetLastError();
 }
 
@@ -420,7 +420,7 @@ hipError_t launch_grad_reduce(dlx_plan* p, const float* Z, const float* Bm, doub
     hipLaunchKernelGGL(map_grad2_kernel, dim3(p->Nmap), dim3((p->Nmap + 63) / 64 * 64), 0, st, p->d_tmp2, Bm, p->Ni,
                        p->Nmap, gmap);
   }
-  hipLaunchKernelGGL(src_reduce_kernel, dim3(p->F * p->S), dim3(256), 0, st, p->d_flux, p->tiles_b2, p->d_pos,
+  hipLaunchKernelGGL(src_reduce_kernel, dim3(p->F * p->S), dim3(256), 0, st, p->d_flux, p->seed_blocks, p->d_pos,
                      p->tiles_b4 * p->b4_ksplit, p->L, gsrc);
   return hipGetLastError();
 }

@@ -30,6 +30,7 @@ DLX_LOSS_CHI2 = 1
 
 # Every symbol include/dlx.h declares.
 DLX_FLAG_NO_AUTOTUNE = 1
+DLX_FLAG_SEED_PASS = 2
 
 EXPORTS = ("dlx_validate", "dlx_plan_create", "dlx_plan_destroy", "dlx_plan_workspace_bytes", "dlx_plan_tiles",
            "dlx_plan_sync",
@@ -40,7 +41,7 @@ EXPORTS = ("dlx_validate", "dlx_plan_create", "dlx_plan_destroy", "dlx_plan_work
 OFFSET_FIELDS = ("transmission", "zernike_basis", "map_basis", "zernike_coeffs", "phase_map", "sources", "flat",
                  "intrapixel", "images", "loss")
 
-STAGES = ("PREP", "F1", "F2", "BIN", "LOSS", "B2", "B3", "B4", "GRAD")
+STAGES = ("PREP", "F1", "F2", "BIN", "LOSS", "SEED", "B3", "B4", "GRAD")
 
 
 class dlx_problem_desc(ctypes.Structure):
@@ -189,9 +190,9 @@ def dlx_plan_workspace_bytes(plan: int) -> int:
 
 def dlx_plan_tiles(plan: int) -> dict:
     """{stage: (rows, cols)} of each MFT stage's workgroup output tile."""
-    t = (ctypes.c_int32 * 10)()
+    t = (ctypes.c_int32 * 8)()
     _chk(lib().dlx_plan_tiles(_p(plan), ctypes.addressof(t)), "dlx_plan_tiles")
-    return {k: (32 * t[2 * i], 32 * t[2 * i + 1]) for i, k in enumerate(("F1", "F2", "B2", "B3", "B4"))}
+    return {k: (32 * t[2 * i], 32 * t[2 * i + 1]) for i, k in enumerate(("F1", "F2", "B3", "B4"))}
 
 
 def dlx_plan_sync(plan: int, stream: int = 0) -> int:

@@ -59,7 +59,8 @@ class PsfPlan:
     """
 
     def __init__(self, geom: Geometry, transmission, zbasis, map_basis=None, intrapixel=None,
-                 precision: str = "fp32", workspace_limit: int = 0, device="cuda", autotune: bool = True):
+                 precision: str = "fp32", workspace_limit: int = 0, device="cuda", autotune: bool = True,
+                 seed_pass: bool = False):
         if not torch.cuda.is_available():
             raise RuntimeError("libdlx needs a ROCm GPU")
         self.geom = geom
@@ -74,7 +75,7 @@ class PsfPlan:
                                         g.n_frames, g.n_zernike, g.n_map, g.diameter, g.focal_pixel)
         prec = {"fp32": _c.DLX_FP32, "bf16x3": _c.DLX_BF16X3}[precision]
         with torch.cuda.device(self.device):
-            flags = 0 if autotune else _c.DLX_FLAG_NO_AUTOTUNE
+            flags = (0 if autotune else _c.DLX_FLAG_NO_AUTOTUNE) | (_c.DLX_FLAG_SEED_PASS if seed_pass else 0)
             self.plan = _c.dlx_plan_create(desc, 1, prec, flags, int(workspace_limit))
         self.precision = precision
 

@@ -242,3 +242,22 @@ def test_bf16x3_standalone_calls_and_chunking():
     plan.close()
     compare(got, oracle_eval("c3-small", "eval", "poisson"), tol_grad=TOL_BF16X3, tol_resid=TOL_BF16X3,
             tol_img=TOL_BF16X3, sources=w.sources)
+
+
+@pytest.mark.parametrize("prec", ["fp32", "bf16x3"])
+@pytest.mark.parametrize("case", ["c3-small", "c2-odd"])
+def test_separate_seed_pass_is_bitwise_identical(case, prec):
+    """The adjoint seed formed by its own pass (the large-frame path) or in B3's loader: same bits."""
+    from tests.gpu_helpers import make_plan, run_eval
+    print(f"seed pass {case} {prec}", flush=True)
+    w, _ = workload(case)
+    outs = []
+    for seed_pass in (False, True):
+        plan = make_plan(w, prec, autotune=False, seed_pass=seed_pass)
+        outs.append(run_eval(w, plan=plan))
+        plan.close()
+    for k, v in outs[0].items():
+        if isinstance(v, np.ndarray):
+            assert np.array_equal(v, outs[1][k]), k
+        else:
+            assert v == outs[1][k], k
