@@ -27,7 +27,7 @@ hipError_t launch_loss(dlx_plan* p, int f0, int nf, int chunk, const float* mode
                        hipStream_t st);
 hipError_t launch_loss_final(dlx_plan* p, int n_chunks, double* loss, hipStream_t st);
 hipError_t launch_grad_reduce(dlx_plan* p, const float* Z, const float* Bm, double* gz, double* gmap, double* gsrc,
-                              hipStream_t st);
+                              double* loss, int loss_chunks, hipStream_t st);
 int loss_block_count(long long npix);
 int seed_block_count(long long npix);
 int zproj_chunks(long long npix, int Nz);
@@ -86,7 +86,7 @@ void layout(dlx_plan* p, Pool& pool) {
   p->d_MN = pool.take<float>(2 * L * No * ldNi);
   p->d_MT = pool.take<float>(2 * L * Ni * ldNo);
   p->d_x = pool.take<double>(Ni);
-  p->d_opd = pool.take<double>((size_t)p->opd_splits * Ni * Ni);
+  p->d_opd = pool.take<double>((size_t)Ni * Ni);
   p->d_maptmp = pool.take<float>(std::max<size_t>(1, (size_t)p->Nmap * Ni));
   p->d_norm = pool.take<double>(p->n_norm_part);
   p->d_P0T = pool.take<float>(2 * L * Ni * ldNi);
@@ -598,8 +598,6 @@ dlx_status dlx_plan_create(const dlx_problem_desc* probs, int32_t n_probs, dlx_p
   p->seed_pass = (flags & DLX_FLAG_SEED_PASS) || sizeof(float) * (size_t)p->No * p->ldNo > kSeedFuseMaxBytes;
   {
     const long long npix = (long long)p->Ni * p->Ni;
-    const long long chunks = (npix + 1023) / 1024;
-    p->opd_splits = (int)std::max<long long>(1, std::min<long long>((512 + chunks - 1) / chunks, std::max(1, p->Nz)));
     p->n_norm_part = (int)std::max<long long>(1, std::min<long long>(256, (npix + 4095) / 4096));
   }
 
@@ -893,7 +891,7 @@ dlx_status dlx_psf_backward(dlx_plan* p, const float* transmission, const float*
     DLX_HIP(run_adjoint(p, c, f0, nf, sources, st));
   }
   Stage sg(p, st, DLX_STAGE_GRAD, p->n_psf);
-  DLX_HIP(launch_grad_reduce(p, zernike_basis, map_basis, grad_zernike, grad_map, grad_sources, st));
+  DLX_HIP(launch_grad_reduce(p, zernike_basis, map_basis, grad_zernike, grad_map, grad_sources, nullptr, 0, st));
   return DLX_OK;
 }
 
@@ -976,8 +974,8 @@ dlx_status dlx_eval(dlx_plan* p, const dlx_eval_args* a, void* stream) {
     DLX_HIP(run_adjoint(p, c, f0, nf, a->sources, st));
   }
   Stage sg(p, st, DLX_STAGE_GRAD, p->n_psf);
-  DLX_HIP(launch_loss_final(p, p->n_chunks, a->loss, st));
-  DLX_HIP(launch_grad_reduce(p, a->zernike_basis, a->map_basis, a->grad_zernike, a->grad_map, a->grad_sources, st));
+  DLX_HIP(launch_grad_reduce(p, a->zernike_basis, a->map_basis, a->grad_zernike, a->grad_map, a->grad_sources, a->loss,
+                             p->n_chunks, st));
   return DLX_OK;
 }
 

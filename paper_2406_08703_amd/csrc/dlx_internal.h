@@ -134,8 +134,7 @@ struct dlx_plan {
   float* d_MN = nullptr;   // [L][No][ldNi] planar
   float* d_MT = nullptr;   // [L][Ni][ldNo] planar
   double* d_x = nullptr;   // [Ni]
-  double* d_opd = nullptr;    // OPD partial sums [opd_splits][Ni*Ni]
-  int opd_splits = 1;
+  double* d_opd = nullptr;    // OPD [Ni*Ni]
   float* d_maptmp = nullptr;  // [Nmap][Ni]
   double* d_norm = nullptr;   // partial sums of A^2 [n_norm_part]
   int n_norm_part = 1;

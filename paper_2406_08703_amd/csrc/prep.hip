@@ -72,21 +72,6 @@ __global__ void coords_kernel(double* x, int Ni, double dx) {
   if (n < Ni) x[n] = ((double)n - 0.5 * (double)(Ni - 1)) * dx;
 }
 
-// Partial sums of A^2 (FP64), one per block; consumers add them in a fixed order.
-__global__ void norm_partial_kernel(const float* A, long long n, double* part) {
-  __shared__ double sh[4];
-  double acc = 0.0;
-  for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long long)gridDim.x * blockDim.x) {
-    const double v = A[i];
-    acc += v * v;
-  }
-#pragma unroll
-  for (int o = 32; o > 0; o >>= 1) acc += __shfl_xor(acc, o, 64);
-  if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = acc;
-  __syncthreads();
-  if (threadIdx.x == 0) part[blockIdx.x] = sh[0] + sh[1] + sh[2] + sh[3];
-}
-
 // tmp[j][n] = sum_k C[j][k] B[n][k]   (first half of B C B^T)
 __global__ void map_tmp_kernel(const float* C, const float* Bm, float* tmp, int Nmap, int Ni) {
   const int n = blockIdx.x * blockDim.x + threadIdx.x;
@@ -97,56 +82,9 @@ __global__ void map_tmp_kernel(const float* C, const float* Bm, float* tmp, int 
   tmp[(long long)j * Ni + n] = (float)acc;
 }
 
-// OPD partial sums: block (chunk of 4 x 256 pixels, term split s) adds
-// c_j Z_j over its terms j = s, s + J, s + 2J, ...; split 0 also adds the map
-// term sum_j B[m][j] tmp[j][n]. The pupil kernel adds the J partials in order.
-__global__ void opd_partial_kernel(const float* Z, const float* c, int Nz, long long npix, int Ni, const float* Bm,
-                                   const float* tmp, int Nmap, int J, double* part) {
-  const int split = blockIdx.y;
-  const long long p0 = ((long long)blockIdx.x * blockDim.x + threadIdx.x) * 4;
-  if (p0 >= npix) return;
-  double acc[4] = {0.0, 0.0, 0.0, 0.0};
-  const bool vec = (p0 + 4 <= npix) && ((npix & 3) == 0);
-  for (int j = split; j < Nz; j += J) {
-    const double cj = c[j];
-    const float* z = Z + (long long)j * npix + p0;
-    if (vec && ((reinterpret_cast<uintptr_t>(z) & 15) == 0)) {
-      const float4 v = *reinterpret_cast<const float4*>(z);
-      acc[0] += cj * v.x;
-      acc[1] += cj * v.y;
-      acc[2] += cj * v.z;
-      acc[3] += cj * v.w;
-    } else {
-      for (int e = 0; e < 4; ++e)
-        if (p0 + e < npix) acc[e] += cj * (double)z[e];
-    }
-  }
-  if (split == 0 && Nmap > 0) {
-    for (int e = 0; e < 4; ++e) {
-      const long long p = p0 + e;
-      if (p >= npix) break;
-      const int m = (int)(p / Ni), n = (int)(p - (long long)m * Ni);
-      double a = 0.0;
-      for (int j = 0; j < Nmap; ++j) a += (double)Bm[(long long)m * Nmap + j] * (double)tmp[(long long)j * Ni + n];
-      acc[e] += a;
-    }
-  }
-  for (int e = 0; e < 4; ++e)
-    if (p0 + e < npix) part[(long long)split * npix + p0 + e] = acc[e];
-}
-
-// OPD[p] = sum of the J partials (fixed order), once for all wavelengths.
-__global__ void opd_sum_kernel(double* part, int J, long long npix) {
-  const long long p = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-  if (p >= npix || J <= 1) return;
-  double o = part[p];
-  for (int s = 1; s < J; ++s) o += part[(long long)s * npix + p];
-  part[p] = o;
-}
-
 // P0T_l[n][m] = A[m][n] / sqrt(sum A^2) * exp(i 2 pi OPD[m][n] / lambda_l), one block per
-// (32 x 32 tile, wavelength), transposed through LDS. OPD = sum of the J partials.
-__global__ void pupil_kernel(const float* A, const double* opd_part, int J, const double* norm_part, int n_norm,
+// (32 x 32 tile, wavelength), transposed through LDS.
+__global__ void pupil_kernel(const float* A, const double* opd, const double* norm_part, int n_norm,
                              const WlInfo* wl, int Ni, int ldp, float* P0T, long long plane, long long by_wl) {
   __shared__ float tr[32][33], ti[32][33];
   __shared__ double snorm;
@@ -166,7 +104,7 @@ __global__ void pupil_kernel(const float* A, const double* opd_part, int J, cons
     float re = 0.f, im = 0.f;
     if (m < Ni && n < Ni) {
       const long long p = (long long)m * Ni + n;
-      const double t0 = opd_part[p] * inv;   // phase in cycles (partials already summed into slot 0)
+      const double t0 = opd[p] * inv;   // phase in cycles
       const double fr = t0 - rint(t0);
       double sn, cs;
       sincospi(2.0 * fr, &sn, &cs);
@@ -188,11 +126,9 @@ __global__ void pupil_kernel(const float* A, const double* opd_part, int J, cons
   }
 }
 
-// Tilt vectors of all PSFs, psf = (f S + s) L + l, one thread per (psf, n).
-__global__ void tilt_kernel(const float* sources, const WlInfo* wl, const double* x, int S, int L, int Ni, int ldt,
-                            long long count, float* tx, float* ty, long long plane) {
-  const long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-  if (t >= count * ldt) return;
+// Tilt vectors of all PSFs, psf = (f S + s) L + l: element t = psf * ldt + n.
+__device__ void tilt_at(long long t, const float* sources, const WlInfo* wl, const double* x, int L, int Ni, int ldt,
+                        float* tx, float* ty, long long plane) {
   const int gb = (int)(t / ldt);
   const int n = (int)(t - (long long)gb * ldt);
   const int l = gb % L;
@@ -202,22 +138,73 @@ __global__ void tilt_kernel(const float* sources, const WlInfo* wl, const double
   if (n < Ni) {
     const double inv = 1.0 / wl[l].lam;
     double sn, cs;
-    double t = x[n] * alpha * inv;
-    t -= rint(t);
-    sincospi(2.0 * t, &sn, &cs);
+    double u = x[n] * alpha * inv;
+    u -= rint(u);
+    sincospi(2.0 * u, &sn, &cs);
     xr = (float)cs;
     xi = (float)sn;
-    t = x[n] * beta * inv;
-    t -= rint(t);
-    sincospi(2.0 * t, &sn, &cs);
+    u = x[n] * beta * inv;
+    u -= rint(u);
+    sincospi(2.0 * u, &sn, &cs);
     yr = (float)cs;
     yi = (float)sn;
   }
-  const long long o = (long long)gb * ldt + n;
-  tx[o] = xr;
-  tx[plane + o] = xi;
-  ty[o] = yr;
-  ty[plane + o] = yi;
+  tx[t] = xr;
+  tx[plane + t] = xi;
+  ty[t] = yr;
+  ty[plane + t] = yi;
+}
+
+// The parameter-dependent inputs of the MFT in one launch (256 threads),
+// three independent jobs by block range:
+//   [0, nb_opd):              OPD[p] = sum_j c_j Z_j[p] (+ sum_j B[m][j] tmp[j][n]),
+//                             one pixel per thread, FP64 accumulation in term order;
+//   [nb_opd, nb_opd + n_norm): partial sums of A^2 (grid-stride over the pixels),
+//                             one per block, added by the pupil kernel in order;
+//   the rest:                 the tilt vectors tx, ty of every PSF.
+__global__ void prep_kernel(const float* Z, const float* c, int Nz, long long npix, int Ni, const float* Bm,
+                            const float* tmp, int Nmap, double* opd, int nb_opd, const float* A, double* norm_part,
+                            int n_norm, const float* sources, const WlInfo* wl, const double* x, int L, int ldt,
+                            long long n_tilt, float* tx, float* ty, long long tplane) {
+  const int b = blockIdx.x;
+  if (b < nb_opd) {
+    const long long p = (long long)b * blockDim.x + threadIdx.x;
+    if (p >= npix) return;
+    double acc = 0.0;
+    const float* z = Z + p;
+    int j = 0;
+    for (; j + 8 <= Nz; j += 8) {
+      float v[8];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) v[u] = z[(long long)(j + u) * npix];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) acc += (double)c[j + u] * (double)v[u];
+    }
+    for (; j < Nz; ++j) acc += (double)c[j] * (double)z[(long long)j * npix];
+    if (Nmap > 0) {
+      const int m = (int)(p / Ni), n = (int)(p - (long long)m * Ni);
+      double a = 0.0;
+      for (int k = 0; k < Nmap; ++k) a += (double)Bm[(long long)m * Nmap + k] * (double)tmp[(long long)k * Ni + n];
+      acc += a;
+    }
+    opd[p] = acc;
+  } else if (b < nb_opd + n_norm) {
+    __shared__ double sh[4];
+    const int nb = b - nb_opd;
+    double acc = 0.0;
+    for (long long i = (long long)nb * blockDim.x + threadIdx.x; i < npix; i += (long long)n_norm * blockDim.x) {
+      const double v = A[i];
+      acc += v * v;
+    }
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) acc += __shfl_xor(acc, o, 64);
+    if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = acc;
+    __syncthreads();
+    if (threadIdx.x == 0) norm_part[nb] = sh[0] + sh[1] + sh[2] + sh[3];
+  } else {
+    const long long t = (long long)(b - nb_opd - n_norm) * blockDim.x + threadIdx.x;
+    if (t < n_tilt) tilt_at(t, sources, wl, x, L, Ni, ldt, tx, ty, tplane);
+  }
 }
 
 }  // namespace
@@ -245,25 +232,20 @@ hipError_t launch_dft(dlx_plan* p, hipStream_t st) {
 hipError_t launch_prep(dlx_plan* p, const float* A, const float* Z, const float* Bm, const float* c, const float* C,
                        const float* sources, hipStream_t st) {
   const long long npix = (long long)p->Ni * p->Ni;
-  hipLaunchKernelGGL(norm_partial_kernel, dim3(p->n_norm_part), dim3(256), 0, st, A, npix, p->d_norm);
   if (p->Nmap > 0) {
     hipLaunchKernelGGL(map_tmp_kernel, dim3((p->Ni + 255) / 256, p->Nmap), dim3(256), 0, st, C, Bm, p->d_maptmp,
                        p->Nmap, p->Ni);
   }
-  const long long chunks = (npix + 1023) / 1024;
-  hipLaunchKernelGGL(opd_partial_kernel, dim3((unsigned)chunks, p->opd_splits), dim3(256), 0, st, Z, c, p->Nz, npix,
-                     p->Ni, Bm, p->d_maptmp, p->Nmap, p->opd_splits, p->d_opd);
-  if (p->opd_splits > 1)
-    hipLaunchKernelGGL(opd_sum_kernel, dim3((unsigned)((npix + 255) / 256)), dim3(256), 0, st, p->d_opd, p->opd_splits,
-                       npix);
+  const int nb_opd = (int)((npix + 255) / 256);
+  const long long nt = (long long)p->n_psf * p->ldNi;
+  const int nb_tilt = (int)((nt + 255) / 256);
+  hipLaunchKernelGGL(prep_kernel, dim3(nb_opd + p->n_norm_part + nb_tilt), dim3(256), 0, st, Z, c, p->Nz, npix, p->Ni,
+                     Bm, p->d_maptmp, p->Nmap, p->d_opd, nb_opd, A, p->d_norm, p->n_norm_part, sources, p->d_wl,
+                     p->d_x, p->L, p->ldNi, nt, p->d_tx, p->d_ty, nt);
   const long long p0_by_wl = 2LL * p->Ni * p->ldNi;
   hipLaunchKernelGGL(pupil_kernel, dim3((p->Ni + 31) / 32, (p->ldNi + 31) / 32, p->L), dim3(32, 8), 0, st, A,
-                     p->d_opd, p->opd_splits, p->d_norm, p->n_norm_part, p->d_wl, p->Ni, p->ldNi, p->d_P0T,
-                     (long long)p->Ni * p->ldNi, p0_by_wl);
-  const long long tplane = (long long)p->n_psf * p->ldNi;
-  const long long nt = (long long)p->n_psf * p->ldNi;
-  hipLaunchKernelGGL(tilt_kernel, dim3((unsigned)((nt + 255) / 256)), dim3(256), 0, st, sources, p->d_wl, p->d_x,
-                     p->S, p->L, p->Ni, p->ldNi, (long long)p->n_psf, p->d_tx, p->d_ty, tplane);
+                     p->d_opd, p->d_norm, p->n_norm_part, p->d_wl, p->Ni, p->ldNi, p->d_P0T, (long long)p->Ni * p->ldNi,
+                     p0_by_wl);
   return hipGetLastError();
 }
 

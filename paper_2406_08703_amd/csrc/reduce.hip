@@ -270,16 +270,6 @@ __global__ void zproj_partial_kernel(const float* Z, const double* gopd, int Nz,
   }
 }
 
-// one 64-thread wave per term: strided partial sums, then a fixed butterfly
-__global__ void zproj_final_kernel(const double* part, int Nz, int nchunks, double* grad) {
-  const int j = blockIdx.x;
-  double acc = 0.0;
-  for (int c = threadIdx.x; c < nchunks; c += 64) acc += part[(long long)c * Nz + j];
-#pragma unroll
-  for (int o = 32; o > 0; o >>= 1) acc += __shfl_xor(acc, o, 64);
-  if (threadIdx.x == 0) grad[j] = acc;
-}
-
 // tmp2[m][k] = sum_n gopd[m][n] B[n][k]
 __global__ void map_grad1_kernel(const double* gopd, const float* Bm, int Ni, int Nmap, double* tmp2) {
   const int m = blockIdx.x;
@@ -300,34 +290,56 @@ __global__ void map_grad2_kernel(const double* tmp2, const float* Bm, int Ni, in
   grad[(long long)j * Nmap + k] = acc;
 }
 
-// grad_sources[f][s] = (sum over wavelengths and tiles of the position partials,
-// sum over pixel blocks of the flux partials), one block per (frame, star),
-// fixed reduction order.
-__global__ void src_reduce_kernel(const double* flux, int seed_blocks, const double* pos, int tiles_b4, int L,
-                                  double* grad) {
+// The last reductions of an evaluation in one launch, 256 threads per block,
+// each a fixed-order FP64 sum:
+//   blocks [0, Nz):          dL/dc_j = sum over pixel chunks of the projection partials;
+//   blocks [Nz, Nz + F S):   grad_sources[f][s] = position partials summed over
+//                            wavelengths and tiles, flux partials over pixel blocks;
+//   block Nz + F S (if loss): L = sum of the loss block partials.
+__global__ void finalize_kernel(const double* zpart, int Nz, int nchunks, double* gz, const double* flux,
+                                int seed_blocks, const double* pos, int tiles_b4, int L, int FS, double* gsrc,
+                                const double* lossblk, int nloss, double* loss) {
   __shared__ double sh[3][4];
-  const int fs = blockIdx.x;
-  const long long b0 = (long long)fs * L;
-  double ga = 0.0, gbt = 0.0, gp = 0.0;
-  for (int i = threadIdx.x; i < L * tiles_b4; i += 256) {
-    const long long q = (b0 * tiles_b4 + i) * 2;
-    ga += pos[q];
-    gbt += pos[q + 1];
-  }
-  for (int i = threadIdx.x; i < seed_blocks; i += 256) gp += flux[(long long)fs * seed_blocks + i];
-  for (int o = 32; o > 0; o >>= 1) {
-    ga += __shfl_xor(ga, o, 64);
-    gbt += __shfl_xor(gbt, o, 64);
-    gp += __shfl_xor(gp, o, 64);
-  }
+  const int b = blockIdx.x;
   const int w = threadIdx.x >> 6;
+  double v0 = 0.0, v1 = 0.0, v2 = 0.0;
+  if (b < Nz) {
+    for (int c = threadIdx.x; c < nchunks; c += 256) v0 += zpart[(long long)c * Nz + b];
+  } else if (b < Nz + FS) {
+    const int fs = b - Nz;
+    const long long b0 = (long long)fs * L;
+    for (int i = threadIdx.x; i < L * tiles_b4; i += 256) {
+      const long long q = (b0 * tiles_b4 + i) * 2;
+      v0 += pos[q];
+      v1 += pos[q + 1];
+    }
+    for (int i = threadIdx.x; i < seed_blocks; i += 256) v2 += flux[(long long)fs * seed_blocks + i];
+  } else {
+    for (int i = threadIdx.x; i < nloss; i += 256) v0 += lossblk[i];
+  }
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) {
+    v0 += __shfl_xor(v0, o, 64);
+    v1 += __shfl_xor(v1, o, 64);
+    v2 += __shfl_xor(v2, o, 64);
+  }
   if ((threadIdx.x & 63) == 0) {
-    sh[0][w] = ga;
-    sh[1][w] = gbt;
-    sh[2][w] = gp;
+    sh[0][w] = v0;
+    sh[1][w] = v1;
+    sh[2][w] = v2;
   }
   __syncthreads();
-  if (threadIdx.x < 3) grad[fs * 3 + threadIdx.x] = sh[threadIdx.x][0] + sh[threadIdx.x][1] + sh[threadIdx.x][2] + sh[threadIdx.x][3];
+  if (threadIdx.x < 3) {
+    const int k = threadIdx.x;
+    const double t = sh[k][0] + sh[k][1] + sh[k][2] + sh[k][3];
+    if (b < Nz) {
+      if (k == 0) gz[b] = t;
+    } else if (b < Nz + FS) {
+      gsrc[(b - Nz) * 3 + k] = t;
+    } else if (k == 0) {
+      loss[0] = t;
+    }
+  }
 }
 
 }  // namespace
@@ -401,18 +413,20 @@ int zproj_chunks(long long npix, int Nz) {
   return (int)(c < maxc ? c : maxc);
 }
 
+// dL/dOPD, its projections and the source gradients; with `loss` also the
+// loss of dlx_eval's n_chunks block-partial slots.
 hipError_t launch_grad_reduce(dlx_plan* p, const float* Z, const float* Bm, double* gz, double* gmap, double* gsrc,
-                              hipStream_t st) {
+                              double* loss, int loss_chunks, hipStream_t st) {
   const long long npix = (long long)p->Ni * p->Ni;
   const int G = p->b4_groups_max * p->b4_ksplit;
   hipLaunchKernelGGL(gopd_reduce_kernel, dim3((unsigned)((npix + 255) / 256)), dim3(256), 0, st, p->d_gpart, G, npix,
                      p->d_gopd);
+  int nch = 1;
   if (p->Nz > 0) {
-    const int nch = zproj_chunks(npix, p->Nz);
+    nch = zproj_chunks(npix, p->Nz);
     const long long chunk = ((npix + nch - 1) / nch + 1023) / 1024 * 1024;
     hipLaunchKernelGGL(zproj_partial_kernel, dim3((p->Nz + kZGroup - 1) / kZGroup, nch), dim3(256), 0, st, Z,
                        p->d_gopd, p->Nz, npix, chunk, p->d_zpart);
-    hipLaunchKernelGGL(zproj_final_kernel, dim3(p->Nz), dim3(64), 0, st, p->d_zpart, p->Nz, nch, gz);
   }
   if (p->Nmap > 0) {
     hipLaunchKernelGGL(map_grad1_kernel, dim3(p->Ni), dim3((p->Nmap + 63) / 64 * 64), 0, st, p->d_gopd, Bm, p->Ni,
@@ -420,8 +434,10 @@ hipError_t launch_grad_reduce(dlx_plan* p, const float* Z, const float* Bm, doub
     hipLaunchKernelGGL(map_grad2_kernel, dim3(p->Nmap), dim3((p->Nmap + 63) / 64 * 64), 0, st, p->d_tmp2, Bm, p->Ni,
                        p->Nmap, gmap);
   }
-  hipLaunchKernelGGL(src_reduce_kernel, dim3(p->F * p->S), dim3(256), 0, st, p->d_flux, p->seed_blocks, p->d_pos,
-                     p->tiles_b4 * p->b4_ksplit, p->L, gsrc);
+  const int FS = p->F * p->S;
+  hipLaunchKernelGGL(finalize_kernel, dim3(p->Nz + FS + (loss ? 1 : 0)), dim3(256), 0, st, p->d_zpart, p->Nz, nch, gz,
+                     p->d_flux, p->seed_blocks, p->d_pos, p->tiles_b4 * p->b4_ksplit, p->L, FS, gsrc, p->d_lossblk,
+                     p->loss_blocks * loss_chunks, loss);
   return hipGetLastError();
 }
 
