@@ -232,8 +232,9 @@ dlx_status dlx_graph_launch(dlx_plan* plan, void* stream);
  * pupil field and the tilt vectors; F1/F2 are the two MFT products of the
  * forward pass (F2 stores the focal fields E); BIN forms the intensity, the
  * intra-pixel weighting and the binning (per source, and the model with the
- * flat); LOSS is the loss and residual; SEED expands the adjoint seed
- * weights G = K flat r and the flux-gradient partials; B3/B4 are the two
+ * flat); LOSS is the loss and residual (in dlx_eval also the adjoint seed
+ * weights G = K flat r and the flux-gradient partials); SEED forms those in
+ * dlx_psf_backward, and the separate seed pass w phi G E where it runs; B3/B4 are the two
  * adjoint MFT products (B3 forms w phi G E in its loader, B4 has the
  * phase-gradient epilogue); GRAD reduces dL/dOPD and projects it onto the
  * Zernike basis, the map, positions and fluxes. */

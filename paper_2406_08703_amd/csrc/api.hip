@@ -24,7 +24,7 @@ hipError_t launch_seed(dlx_plan* p, int f0, int nf, const float* flat, const flo
 hipError_t launch_seed_apply(dlx_plan* p, int f0, int nf, const float* sources, hipStream_t st);
 hipError_t launch_loss(dlx_plan* p, int f0, int nf, int chunk, const float* model, const float* binned,
                        const float* data, const float* flat, int kind, double mu, double sigma, float* r, double* gflat,
-                       hipStream_t st);
+                       const float* const* seed_intrapixel_or_none, hipStream_t st);
 hipError_t launch_loss_final(dlx_plan* p, int n_chunks, double* loss, hipStream_t st);
 hipError_t launch_grad_reduce(dlx_plan* p, const float* Z, const float* Bm, double* gz, double* gmap, double* gsrc,
                               double* loss, int loss_chunks, hipStream_t st);
@@ -835,7 +835,7 @@ dlx_status dlx_loss_grad(dlx_plan* p, const float* model, const float* binned, c
   hipStream_t st = reinterpret_cast<hipStream_t>(stream);
   Stage sg(p, st, DLX_STAGE_LOSS, p->n_psf);
   DLX_HIP(launch_loss(p, 0, p->F, 0, model, binned, data, flat, (int)kind, prior_mu, prior_sigma, dloss_dmodel,
-                      grad_flat, st));
+                      grad_flat, nullptr, st));
   DLX_HIP(launch_loss_final(p, 1, loss_out, st));
   return DLX_OK;
 }
@@ -961,15 +961,14 @@ dlx_status dlx_eval(dlx_plan* p, const dlx_eval_args* a, void* stream) {
       Stage sg(p, st, DLX_STAGE_BIN, nc);
       DLX_HIP(launch_intensity(p, f0, nf, a->sources, a->intrapixel, a->flat, a->binned, a->model, st));
     }
-    {
+    {  // loss, residual and the adjoint seed weights in one pass over the pixels
       Stage sg(p, st, DLX_STAGE_LOSS, nc);
       DLX_HIP(launch_loss(p, f0, nf, c, a->model, a->binned, a->data, a->flat, (int)a->loss_kind, a->prior_mu,
-                          a->prior_sigma, a->dloss_dmodel, a->grad_flat, st));
+                          a->prior_sigma, a->dloss_dmodel, a->grad_flat, &a->intrapixel, st));
     }
-    {
+    if (p->seed_pass) {
       Stage sg(p, st, DLX_STAGE_SEED, nc);
-      DLX_HIP(launch_seed(p, f0, nf, a->flat, a->dloss_dmodel, a->intrapixel, st));
-      if (p->seed_pass) DLX_HIP(launch_seed_apply(p, f0, nf, a->sources, st));
+      DLX_HIP(launch_seed_apply(p, f0, nf, a->sources, st));
     }
     DLX_HIP(run_adjoint(p, c, f0, nf, a->sources, st));
   }

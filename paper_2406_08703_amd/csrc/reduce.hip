@@ -14,15 +14,18 @@ namespace {
 // from the stored focal fields E of frames [f0, f0 + nf):
 //   bs[f][s][p] = sum_l w_l sum_{a,b<Q} K[a][b] |E_{f,s,l}[Qp_r + a][Qp_c + b]|^2   (per source, no flux)
 //   binned[f][p] = sum_s phi_s bs[f][s][p],  model[f][p] = flat[p] * binned[f][p]
-// (binned and model may be null: the adjoint only needs bs). Block (64, 4):
-// 64 detector pixels x 4 wavelength lanes; lane y sums wavelengths y, y + 4,
-// ... and the lanes are added in a fixed order (deterministic). QT > 0 fixes
-// Q at compile time (vector loads along the pixel's rows).
+// (binned and model may be null: the adjoint only needs bs). Block (64,
+// kLanes): 64 detector pixels x kLanes wavelength lanes; lane y sums
+// wavelengths y, y + kLanes, ... and the lanes are added in a fixed order
+// (deterministic). QT > 0 fixes Q at compile time (vector loads along the
+// pixel's rows).
+constexpr int kLanes = 8;
+
 template <int QT>
 __global__ void intensity_kernel(const float* E, long long plane, long long by_psf, int ld, int f0, int F, int S, int L,
                                  int Qr, int Nd, const float* sources, const WlInfo* wl, const float* intrapixel,
                                  const float* flat, float* bs, float* binned, float* model) {
-  __shared__ double sh[4][64];
+  __shared__ double sh[kLanes][64];
   const int Q = QT > 0 ? QT : Qr;
   const long long npix = (long long)Nd * Nd;
   const long long p = (long long)blockIdx.x * 64 + threadIdx.x;
@@ -34,7 +37,7 @@ __global__ void intensity_kernel(const float* E, long long plane, long long by_p
   for (int s = 0; s < S; ++s) {
     double acc = 0.0;
     if (live) {
-      for (int l = y; l < L; l += 4) {
+      for (int l = y; l < L; l += kLanes) {
         const long long lb = ((long long)(f - f0) * S + s) * L + l;
         const float* e = E + lb * by_psf + (long long)(Q * pr) * ld + Q * pc;
         float part = 0.f;
@@ -66,7 +69,9 @@ __global__ void intensity_kernel(const float* E, long long plane, long long by_p
     sh[y][threadIdx.x] = acc;
     __syncthreads();
     if (y == 0 && live) {
-      const double v = sh[0][threadIdx.x] + sh[1][threadIdx.x] + sh[2][threadIdx.x] + sh[3][threadIdx.x];
+      double v = 0.0;
+#pragma unroll
+      for (int k = 0; k < kLanes; ++k) v += sh[k][threadIdx.x];
       bs[((long long)(f - f0) * S + s) * npix + p] = (float)v;
       total += (double)sources[((long long)f * S + s) * 3 + 2] * v;
     }
@@ -94,20 +99,36 @@ __device__ __forceinline__ double block_sum(double v, double* sh) {
   return t;
 }
 
+// Outputs of the adjoint seed, when the loss kernel also forms it (fused
+// evaluation): seed weights G and flux partials, as seed_weight_kernel below.
+struct SeedOut {
+  const float* intrapixel;
+  const float* bs;        // per-source binned [nf][S][npix]
+  int Q, Nd, S, ldg;
+  long long g_by_frame;
+  float* G;               // [nf][No][ldg]
+  double* flux;           // [F][S][gridDim.x]
+};
+
 // Per pixel p: loop over frames f0 <= f < f1, l = m - d ln m (or
 // (m-d)^2/(2 max(d,1))), r = dl/dm, and grad_flat[p] = sum_f r B + (F - mu)/sigma^2.
 // With `accumulate` the frame sum is added to grad_flat and the prior is left
 // out (it was counted by the first frame range); block partials of L go to blk.
+// SEED: per frame also G = K flat r (from the stored float r) and the flux
+// partials sum_p flat r bs_s of this block.
+template <bool SEED>
 __global__ void loss_kernel(const float* model, const float* binned, const float* data, const float* flat, int f0,
                             int f1, long long npix, int kind, double mu, double inv_s2, float* r_out,
-                            double* grad_flat, int accumulate, double* blk, int* status) {
+                            double* grad_flat, int accumulate, double* blk, int* status, SeedOut so) {
   __shared__ double sh[kLossThreads / 64];
   const long long p = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-  double lsum = 0.0;
+  const bool live = p < npix;
+  const float fp = live ? flat[p] : 0.f;
+  double lsum = 0.0, gf = 0.0;
   int flags = 0;
-  if (p < npix) {
-    double gf = 0.0;
-    for (int f = f0; f < f1; ++f) {
+  for (int f = f0; f < f1; ++f) {
+    float rf = 0.f;
+    if (live) {
       const long long q = (long long)f * npix + p;
       double m = model[q];
       const double d = data[q];
@@ -128,13 +149,32 @@ __global__ void loss_kernel(const float* model, const float* binned, const float
         r = dm / w;
       }
       lsum += ell;
-      r_out[q] = (float)r;
+      rf = (float)r;
+      r_out[q] = rf;
       gf += r * b;
     }
+    if constexpr (SEED) {
+      const int fl = f - f0;
+      const float h = fp * rf;
+      if (live) {
+        const int pr = (int)(p / so.Nd), pc = (int)(p - (long long)pr * so.Nd);
+        float* g = so.G + fl * so.g_by_frame + (long long)(so.Q * pr) * so.ldg + so.Q * pc;
+        for (int a = 0; a < so.Q; ++a)
+          for (int b = 0; b < so.Q; ++b)
+            g[(long long)a * so.ldg + b] = so.intrapixel ? h * so.intrapixel[a * so.Q + b] : h;
+      }
+      for (int s = 0; s < so.S; ++s) {
+        const double v = live ? (double)h * (double)so.bs[((long long)fl * so.S + s) * npix + p] : 0.0;
+        const double t = block_sum(v, sh);
+        if (threadIdx.x == 0) so.flux[((long long)f * so.S + s) * gridDim.x + blockIdx.x] = t;
+      }
+    }
+  }
+  if (live) {
     if (accumulate) {
       grad_flat[p] += gf;
     } else {
-      const double dfl = (double)flat[p] - mu;
+      const double dfl = (double)fp - mu;
       lsum += 0.5 * dfl * dfl * inv_s2;
       grad_flat[p] = gf + dfl * inv_s2;
     }
@@ -347,7 +387,7 @@ __global__ void finalize_kernel(const double* zpart, int Nz, int nchunks, double
 hipError_t launch_intensity(dlx_plan* p, int f0, int nf, const float* sources, const float* intrapixel,
                             const float* flat, float* binned, float* model, hipStream_t st) {
   const long long npix = (long long)p->Nd * p->Nd;
-  const dim3 grid((unsigned)((npix + 63) / 64), nf), blk(64, 4);
+  const dim3 grid((unsigned)((npix + 63) / 64), nf), blk(64, kLanes);
   const long long plane = (long long)p->chunk_psf * p->No * p->ldNo, by = (long long)p->No * p->ldNo;
 #define DLX_INTENSITY(QT)                                                                                         \
   hipLaunchKernelGGL(intensity_kernel<QT>, grid, blk, 0, st, p->d_Y, plane, by, p->ldNo, f0, p->F, p->S, p->L, \
@@ -384,15 +424,26 @@ hipError_t launch_seed_apply(dlx_plan* p, int f0, int nf, const float* sources, 
 int loss_block_count(long long npix) { return (int)((npix + kLossThreads - 1) / kLossThreads); }
 
 // Loss terms of frames [f0, f0 + nf); block partials at slot `chunk`. The
-// loss itself is summed by launch_loss_final over `n_chunks` slots.
+// loss itself is summed over the slots by launch_loss_final or the finalize
+// kernel. With seed_intrapixel_or_none non-null (pointing at the intra-pixel
+// kernel, itself possibly null) the adjoint seed weights and flux partials
+// of these frames are formed as well.
 hipError_t launch_loss(dlx_plan* p, int f0, int nf, int chunk, const float* model, const float* binned,
                        const float* data, const float* flat, int kind, double mu, double sigma, float* r, double* gflat,
-                       hipStream_t st) {
+                       const float* const* seed_intrapixel_or_none, hipStream_t st) {
   const long long npix = (long long)p->Nd * p->Nd;
   const int nb = loss_block_count(npix);
-  hipLaunchKernelGGL(loss_kernel, dim3(nb), dim3(kLossThreads), 0, st, model, binned, data, flat, f0, f0 + nf, npix,
-                     kind, mu, 1.0 / (sigma * sigma), r, gflat, chunk > 0 ? 1 : 0, p->d_lossblk + (long long)chunk * nb,
-                     p->d_status);
+  const double inv_s2 = 1.0 / (sigma * sigma);
+  double* blk = p->d_lossblk + (long long)chunk * nb;
+  if (seed_intrapixel_or_none) {
+    const SeedOut so{*seed_intrapixel_or_none, p->d_bs, p->Q, p->Nd, p->S, p->ldNo, (long long)p->No * p->ldNo,
+                     p->d_G, p->d_flux};
+    hipLaunchKernelGGL(loss_kernel<true>, dim3(nb), dim3(kLossThreads), 0, st, model, binned, data, flat, f0, f0 + nf,
+                       npix, kind, mu, inv_s2, r, gflat, chunk > 0 ? 1 : 0, blk, p->d_status, so);
+  } else {
+    hipLaunchKernelGGL(loss_kernel<false>, dim3(nb), dim3(kLossThreads), 0, st, model, binned, data, flat, f0,
+                       f0 + nf, npix, kind, mu, inv_s2, r, gflat, chunk > 0 ? 1 : 0, blk, p->d_status, SeedOut{});
+  }
   return hipGetLastError();
 }
 
