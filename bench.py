@@ -67,6 +67,26 @@ def measured_traffic(config, precision, stage, tile):
     return round(1024.0 * (f * float(fields["fetch_scale"]) + w * float(fields["write_scale"])))
 
 
+def timed_steps(torch, fn, k):
+    """Wall time of k steps between two device synchronisations, and each step's device time
+    from HIP events recorded on the current stream between the steps."""
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(k + 1)]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    ev[0].record()
+    for i in range(k):
+        fn()
+        ev[i + 1].record()
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    return wall, [ev[i].elapsed_time(ev[i + 1]) for i in range(k)]
+
+
+def step_stats(per):
+    import statistics
+    return {"median": round(statistics.median(per), 5), "min": round(min(per), 5), "max": round(max(per), 5)}
+
+
 def stage_flops(P, stage):
     ni, no = P.n_pupil, P.n_focal
     return {"F1": 8.0 * no * ni * ni, "F2": 8.0 * no * no * ni,
@@ -150,12 +170,7 @@ def main():
         evaluate(plan, c, pm, s, fl, d, "poisson", w.prior_mu, w.prior_sigma, out=ebuf)
 
     def timed(fn, k):
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        for _ in range(k):
-            fn()
-        torch.cuda.synchronize()
-        return time.perf_counter() - t0
+        return timed_steps(torch, fn, k)[0]
 
     for i in range(args.warmup):
         step()
@@ -173,12 +188,14 @@ def main():
         cap = CapturedEval(plan, c, pm, s, fl, d, "poisson", w.prior_mu, w.prior_sigma)
         for _ in range(args.warmup):
             cap.replay()
-        t_graph = timed(cap.replay, args.steps)
+        t_graph, per_step = timed_steps(torch, cap.replay, args.steps)
         log(f"graph: {args.steps} replays in {t_graph:.4f} s")
         out_buf = cap.out
         m, loss, gF, gz, gs = out_buf.model, out_buf.loss, out_buf.grad_flat, out_buf.grad_zernike, out_buf.grad_sources
     else:
         m, loss, gF, gz, gs = ebuf.model, ebuf.loss, ebuf.grad_flat, ebuf.grad_zernike, ebuf.grad_sources
+    if t_graph is None:
+        per_step = None
     t1, t0 = (t_graph if t_graph is not None else t_eager), 0.0
     ms_step = (t1 - t0) * 1e3 / args.steps
     n_psf = P.n_psf
@@ -273,7 +290,8 @@ def main():
            "mft_tflops": {"algorithmic": round(tf_alg, 3), "executed": round(tf_exec, 3),
                           "frac_fp32_mfma_peak_algorithmic": round(tf_alg / FP32_MFMA_PEAK_TFLOPS, 4),
                           "frac_fp32_mfma_peak_executed": round(tf_exec / FP32_MFMA_PEAK_TFLOPS, 4)},
-           "mode": args.mode, "eager_ms_per_step": round(t_eager * 1e3 / args.steps, 4),
+           "mode": args.mode, "step_ms": step_stats(per_step) if per_step else None,
+           "eager_ms_per_step": round(t_eager * 1e3 / args.steps, 4),
            "tiles": {k: f"{v[0]}x{v[1]}" for k, v in plan.tiles.items()},
            "stage_ms_per_step": {k: round(v["ms_per_step"], 5) for k, v in table.items()},
            "gemm_share_of_step": round(gemm_ms / all_ms, 4) if all_ms else None,
@@ -311,12 +329,7 @@ def bench_batch(args):
     mu, sigma = ws[0].prior_mu, ws[0].prior_sigma
 
     def timed(fn, k):
-        torch.cuda.synchronize()
-        t1 = time.perf_counter()
-        for _ in range(k):
-            fn()
-        torch.cuda.synchronize()
-        return time.perf_counter() - t1
+        return timed_steps(torch, fn, k)[0]
 
     # plain FP32: problem after problem on the current stream
     t1 = time.perf_counter()
@@ -366,7 +379,7 @@ def bench_batch(args):
     bp.capture(a)
     for _ in range(args.warmup):
         bp.replay()
-    t_batch = timed(bp.replay, args.steps)
+    t_batch, per_step = timed_steps(torch, bp.replay, args.steps)
     assert bp.sync() == 0
     batch_loss = [float(v[0]) for v in bp.unpack("loss", out["loss"].cpu())]
     bp.close()
@@ -416,7 +429,8 @@ def bench_batch(args):
                       "precision": args.precision},
            "mft_tflops": {"algorithmic": round(tf_alg, 3),
                           "frac_fp32_mfma_peak_algorithmic": round(tf_alg / FP32_MFMA_PEAK_TFLOPS, 4)},
-           "mode": "graph", "plain_fp32_ms_per_step": round(t_plain * 1e3 / args.steps, 4),
+           "mode": "graph", "step_ms": step_stats(per_step),
+           "plain_fp32_ms_per_step": round(t_plain * 1e3 / args.steps, 4),
            "speedup_vs_plain_fp32": round(t_plain / t_batch, 3),
            "max_rel_loss_diff_vs_plain": float(f"{loss_dev:.3e}"),
            "stage_ms_per_step_plain": {k: round(v["ms_per_step"], 5) for k, v in table.items()},

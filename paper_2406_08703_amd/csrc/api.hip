@@ -451,6 +451,22 @@ dlx_status create_multi(const dlx_problem_desc* probs, int32_t n, dlx_precision 
     o.images += (long long)d.n_frames * nd * nd;
     o.loss += 1;
   }
+  // Longest-processing-time assignment: problems by MFT work, largest first, each to the
+  // side stream with the least work so far.
+  std::vector<double> cost(n), load(kSideStreams, 0.0);
+  for (int k = 0; k < n; ++k) {
+    const dlx_plan* q = p->subs[k];
+    cost[k] = (double)q->n_psf * q->No * q->Ni * (double)(q->Ni + q->No);
+  }
+  p->order.resize(n);
+  for (int k = 0; k < n; ++k) p->order[k] = k;
+  std::stable_sort(p->order.begin(), p->order.end(), [&](int a, int b) { return cost[a] > cost[b]; });
+  p->lane.assign(n, 0);
+  for (int k : p->order) {
+    const int s = (int)(std::min_element(load.begin(), load.end()) - load.begin());
+    p->lane[k] = s;
+    load[s] += cost[k];
+  }
   p->side.resize(kSideStreams, nullptr);
   p->joins.resize(kSideStreams, nullptr);
   bool ok = hipEventCreateWithFlags(&p->fork, hipEventDisableTiming) == hipSuccess;
@@ -466,16 +482,18 @@ dlx_status create_multi(const dlx_problem_desc* probs, int32_t n, dlx_precision 
   return DLX_OK;
 }
 
-// Run fn(k, sub, stream) for every problem, spread over the side streams,
-// ordered after prior work on `st` and joined back into `st` (also under
-// stream capture, where it records parallel branches).
+// Run fn(k, sub, stream) for every problem, spread over the side streams
+// (balanced by MFT work), ordered after prior work on `st` and joined back
+// into `st` (also under stream capture, where it records parallel branches).
 template <class Fn>
 dlx_status run_multi(dlx_plan* p, hipStream_t st, Fn fn) {
   DLX_HIP(hipEventRecord(p->fork, st));
   for (hipStream_t s : p->side) DLX_HIP(hipStreamWaitEvent(s, p->fork, 0));
   dlx_status status = DLX_OK;
-  for (size_t k = 0; k < p->subs.size() && status == DLX_OK; ++k)
-    status = fn((int)k, p->subs[k], p->side[k % p->side.size()]);
+  for (size_t i = 0; i < p->order.size() && status == DLX_OK; ++i) {
+    const int k = p->order[i];
+    status = fn(k, p->subs[k], p->side[p->lane[k]]);
+  }
   for (size_t i = 0; i < p->side.size(); ++i) {
     DLX_HIP(hipEventRecord(p->joins[i], p->side[i]));
     DLX_HIP(hipStreamWaitEvent(st, p->joins[i], 0));

@@ -108,6 +108,7 @@ struct dlx_plan {
   std::vector<dlx_plan*> subs;
   std::vector<dlx_offsets> offs;
   std::vector<hipStream_t> side;
+  std::vector<int> order, lane;   // issue order (largest first) and side stream of each problem
   hipEvent_t fork = nullptr;
   std::vector<hipEvent_t> joins;
   bool multi() const { return !subs.empty(); }
