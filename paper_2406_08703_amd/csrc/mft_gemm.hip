@@ -48,6 +48,19 @@ __device__ __forceinline__ f4 mfma_bf16(u4 a, u4 b, f4 c) {
   return __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf8, a), __builtin_bit_cast(bf8, b), c, 0, 0, 0);
 }
 
+typedef __bf16 bf2 __attribute__((ext_vector_type(2)));
+typedef float f2 __attribute__((ext_vector_type(2)));
+
+// RNE split of two FP32 values into packed bf16 pairs hi = bf16(x), lo = bf16(x - hi)
+// (element 0 in the low half), the same rounding as split_bf16 below.
+__device__ __forceinline__ void split_pair(float a, float b, unsigned int& hi, unsigned int& lo) {
+  const f2 x = {a, b};
+  const bf2 h = __builtin_convertvector(x, bf2);
+  const f2 r = x - __builtin_convertvector(h, f2);
+  hi = __builtin_bit_cast(unsigned int, h);
+  lo = __builtin_bit_cast(unsigned int, __builtin_convertvector(r, bf2));
+}
+
 // RNE split of an FP32 value into bf16 hi + lo (as 16-bit patterns).
 __device__ __forceinline__ void split_bf16(float x, unsigned short& hi, unsigned short& lo) {
   const __bf16 h = (__bf16)x;
@@ -324,19 +337,17 @@ __global__ __launch_bounds__(256) void cgemm_kernel(const GemmArgs a) {
               *reinterpret_cast<f4*>(&Bs[row * LDK + 4 * (kq ^ lds_swz(row))]) = pr[0];
               *reinterpret_cast<f4*>(&Bs[(BN + row) * LDK + 4 * (kq ^ lds_swz(row))]) = pi[0];
             } else {
-              unsigned short h[4][8];
+              unsigned int w[4][4];   // re hi, re lo, im hi, im lo: 8 k each, two per word
 #pragma unroll
-              for (int e = 0; e < 8; ++e) {
-                split_bf16(pr[e >> 2][e & 3], h[0][e], h[1][e]);
-                split_bf16(pi[e >> 2][e & 3], h[2][e], h[3][e]);
+              for (int e = 0; e < 4; ++e) {
+                const int v = e >> 1, c = 2 * (e & 1);
+                split_pair(pr[v][c], pr[v][c + 1], w[0][e], w[1][e]);
+                split_pair(pi[v][c], pi[v][c + 1], w[2][e], w[3][e]);
               }
 #pragma unroll
-              for (int pl = 0; pl < 4; ++pl) {
-                u4 w;
-#pragma unroll
-                for (int e = 0; e < 4; ++e) w[e] = (unsigned int)h[pl][2 * e] | ((unsigned int)h[pl][2 * e + 1] << 16);
-                *reinterpret_cast<u4*>(&Bs[(pl * BN + row) * LDK + 8 * (kq ^ lds_swz(row))]) = w;
-              }
+              for (int pl = 0; pl < 4; ++pl)
+                *reinterpret_cast<u4*>(&Bs[(pl * BN + row) * LDK + 8 * (kq ^ lds_swz(row))]) =
+                    u4{w[pl][0], w[pl][1], w[pl][2], w[pl][3]};
             }
           } else if constexpr (PREC == 0) {
             f4 vr = __builtin_bit_cast(f4, gbv[r][0]), vi = __builtin_bit_cast(f4, gbv[r][1]);
