@@ -87,6 +87,23 @@ def step_stats(per):
     return {"median": round(statistics.median(per), 5), "min": round(min(per), 5), "max": round(max(per), 5)}
 
 
+def stage_bytes(P, stage):
+    """Algorithmic HBM bytes per evaluation of the memory-bound stages of dlx_eval (each array
+    read or written once; FP32 unless noted)."""
+    ni, no, nd, F, S, L = P.n_pupil, P.n_focal, P.n_det, P.n_frames, P.n_sources, P.n_wavelengths
+    nz, nmap, npsf = P.n_zernike, P.n_map, P.n_psf
+    return {
+        # OPD (Z, A read), pupil field P0 per wavelength (planar complex), tilt vectors per PSF
+        "PREP": 4.0 * (nz + 1) * ni * ni + 8.0 * L * ni * ni + 16.0 * npsf * ni + 4.0 * nmap * ni,
+        # E read once; per-star binned images, binned and model written
+        "BIN": 8.0 * npsf * no * no + 4.0 * F * (S + 2) * nd * nd,
+        # model, binned, data, per-star binned read; r written; seed weights G written
+        "LOSS": 4.0 * F * (4 + S) * nd * nd + 4.0 * F * no * no + 12.0 * nd * nd,
+        # Zernike basis re-read for the projection, dL/dOPD (FP64) written and read
+        "GRAD": 4.0 * nz * ni * ni + 16.0 * ni * ni,
+    }.get(stage)
+
+
 def stage_flops(P, stage):
     ni, no = P.n_pupil, P.n_focal
     return {"F1": 8.0 * no * ni * ni, "F2": 8.0 * no * no * ni,
@@ -295,6 +312,10 @@ def main():
            "tiles": {k: f"{v[0]}x{v[1]}" for k, v in plan.tiles.items()},
            "stage_ms_per_step": {k: round(v["ms_per_step"], 5) for k, v in table.items()},
            "gemm_share_of_step": round(gemm_ms / all_ms, 4) if all_ms else None,
+           "hbm_stages": {k: {"bytes_per_step": stage_bytes(P, k),
+                              "GB/s": round(stage_bytes(P, k) / (v["ms_per_step"] * 1e-3) / 1e9, 1),
+                              "frac_of_8TB/s": round(stage_bytes(P, k) / (v["ms_per_step"] * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)}
+                          for k, v in table.items() if stage_bytes(P, k)},
            "roofline": roofline, "rel_err_vs_fp64": parity, "cpu_baseline": cpu}
     plan.close()
     print(json.dumps(out), flush=True)

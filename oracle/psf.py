@@ -28,6 +28,10 @@ Parseval, Airy and annular-Airy closed forms, shift theorem, piston and
 even-mode invariances, adjoint dot product, Euler identity for the flux
 gradient, library log-pmf/log-pdf for the loss, matrix-form binning, and
 central finite differences of every gradient block.
+The integer-dither form (``forward_dithered`` / ``backward_dithered``,
+Section 3: one PSF computation on an enlarged plane, each frame a window of
+it) is pinned to the per-frame form with the dithers folded into the star
+positions, by the shift theorem on the focal grid.
 Parity unpinned beyond finite differences: the bicubic map term and the
 chi-squared data term (definitions, not results).
 """
@@ -268,3 +272,61 @@ def binned_pixels(prob: OracleProblem, coeffs, phase_map, sources, frame, pixels
                 E = focal_field(P, x, x, cols, rows, lam, prob.dx * prob.focal_pixel / lam)
                 out[i] += w * phi * np.sum(K * np.abs(E) ** 2)
     return out
+
+
+def dither_windows(dithers, margin):
+    """Top-left corner (row, col) of each frame's window in the enlarged plane.
+
+    ``dithers`` [F, 2] are integer detector-pixel offsets (dx, dy) of the scene
+    in frame f; the enlarged plane has ``margin`` extra pixels on every side,
+    so detector pixel p of frame f is enlarged-plane pixel p + margin - d_f.
+    """
+    d = np.asarray(dithers, np.int64)
+    if np.any(np.abs(d) > margin):
+        raise ValueError("dither larger than the margin")
+    return np.stack([margin - d[:, 1], margin - d[:, 0]], axis=1)
+
+
+def forward_dithered(prob_big: OracleProblem, coeffs, phase_map, sources, flat, dithers, margin):
+    """Integer-dithered frames from one enlarged plane (Section 3).
+
+    Every (star, wavelength) PSF is computed once on the enlarged focal grid
+    of ``prob_big`` (N_det + 2 margin detector pixels, same pitch), binned
+    there, and frame f's binned image is its window at ``dither_windows``.
+    ``sources`` is [S, 3] (shared by all frames). Returns (binned, model)
+    [F, Nd, Nd].
+    """
+    flat = np.asarray(flat, np.float64)
+    nd = flat.shape[0]
+    if prob_big.n_det != nd + 2 * margin:
+        raise ValueError("enlarged plane size")
+    big, _ = forward(prob_big, coeffs, phase_map, np.asarray(sources, np.float64)[None], np.ones((prob_big.n_det,) * 2))
+    win = dither_windows(dithers, margin)
+    binned = np.stack([big[0, r:r + nd, c:c + nd] for r, c in win])
+    return binned, flat[None] * binned
+
+
+def backward_dithered(prob_big: OracleProblem, coeffs, phase_map, sources, flat, r, dithers, margin):
+    """Adjoint of ``forward_dithered``: dL/dB_big = sum_f (flat * r_f) placed in frame f's window,
+    then the adjoint of one enlarged frame with unit pixel response.
+    Returns (grad_coeffs, grad_map, grad_sources [S, 3])."""
+    flat = np.asarray(flat, np.float64)
+    r = np.asarray(r, np.float64)
+    nd = flat.shape[0]
+    nb = prob_big.n_det
+    rb = np.zeros((nb, nb))
+    for f, (r0, c0) in enumerate(dither_windows(dithers, margin)):
+        rb[r0:r0 + nd, c0:c0 + nd] += flat * r[f]
+    g_c, g_map, g_src = backward(prob_big, coeffs, phase_map, np.asarray(sources, np.float64)[None],
+                                 np.ones((nb, nb)), rb[None])
+    return g_c, g_map, g_src[0]
+
+
+def value_and_grad_dithered(prob_big, coeffs, phase_map, sources, flat, data, dithers, margin, kind="poisson",
+                            prior_mu=1.0, prior_sigma=0.1):
+    """``value_and_grad`` for integer-dithered frames of one scene."""
+    B, m = forward_dithered(prob_big, coeffs, phase_map, sources, flat, dithers, margin)
+    L, r, gF, bad = loss_grad(m, B, data, flat, kind, prior_mu, prior_sigma)
+    g_c, g_map, g_src = backward_dithered(prob_big, coeffs, phase_map, sources, flat, r, dithers, margin)
+    return dict(binned=B, model=m, loss=L, r=r, grad_flat=gF, grad_coeffs=g_c, grad_map=g_map,
+                grad_sources=g_src, domain=bad)

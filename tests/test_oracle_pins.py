@@ -394,3 +394,55 @@ def test_bicubic_matrix_reproduces_quadratics_in_interior():
     q = lambda t: 3.0 + 2.0 * t - 7.0 * t ** 2
     interior = (xp > xn[1]) & (xp < xn[-2])
     np.testing.assert_allclose((B @ q(xn))[interior], q(xp)[interior], atol=1e-12)
+
+
+def _dither_case():
+    ni, nd, Q, margin = 16, 6, 2, 2
+    D = 0.5
+    pix = 600e-9 / (2 * D)
+    lam = np.array([550e-9, 650e-9])
+    wts = np.array([0.5, 0.5])
+    trans = aperture(ni, D, 0.3, 1.0)
+    Z = zernike_basis([4, 5, 6, 7, 8], ni, D)
+    rng = np.random.default_rng(41)
+    K = 1.0 + 0.05 * rng.normal(size=(Q, Q))
+    small = O.OracleProblem.from_arrays(ni, Q * nd, Q, D, pix / Q, lam, wts, trans, Z, None, K)
+    big = O.OracleProblem.from_arrays(ni, Q * (nd + 2 * margin), Q, D, pix / Q, lam, wts, trans, Z, None, K)
+    pos = np.array([[0.4, -0.7, 3e4], [-1.1, 0.6, 1e4]])
+    pos[:, :2] *= pix
+    dithers = np.array([[0, 0], [2, -1], [-2, 2], [1, 0]])
+    coeffs = 30e-9 * rng.normal(size=5)
+    flat = 1.0 + 0.05 * rng.normal(size=(nd, nd))
+    per_frame = np.repeat(pos[None], len(dithers), axis=0)
+    per_frame[:, :, 0] += dithers[:, 0][:, None] * pix
+    per_frame[:, :, 1] += dithers[:, 1][:, None] * pix
+    return small, big, pos, per_frame, dithers, margin, coeffs, flat, rng
+
+
+def test_dithered_frames_from_enlarged_plane_equal_per_frame_model():
+    # Section 3's integer dithers: a window of one enlarged plane equals the frame
+    # computed with the dither added to every star's position (shift theorem on the grid).
+    small, big, pos, per_frame, dithers, margin, coeffs, flat, _ = _dither_case()
+    Bd, md = O.forward_dithered(big, coeffs, None, pos, flat, dithers, margin)
+    Bs, ms = O.forward(small, coeffs, None, per_frame, flat)
+    assert rel_l2(Bd, Bs) < 1e-12
+    assert rel_l2(md, ms) < 1e-12
+
+
+def test_dithered_gradients_equal_frame_sums_of_per_frame_gradients():
+    small, big, pos, per_frame, dithers, margin, coeffs, flat, rng = _dither_case()
+    _, m = O.forward(small, coeffs, None, per_frame, flat)
+    data = rng.poisson(m).astype(np.float64)
+    a = O.value_and_grad_dithered(big, coeffs, None, pos, flat, data, dithers, margin, "poisson", 1.0, 0.05)
+    b = O.value_and_grad(small, coeffs, None, per_frame, flat, data, "poisson", 1.0, 0.05)
+    assert abs(a["loss"] - b["loss"]) < 1e-12 * abs(b["loss"])
+    assert rel_l2(a["r"], b["r"]) < 1e-12
+    assert rel_l2(a["grad_flat"], b["grad_flat"]) < 1e-12
+    assert rel_l2(a["grad_coeffs"], b["grad_coeffs"]) < 1e-11
+    assert rel_l2(a["grad_sources"], b["grad_sources"].sum(axis=0)) < 1e-11
+
+
+def test_dither_windows_reject_dithers_beyond_the_margin():
+    with pytest.raises(ValueError):
+        O.dither_windows([[3, 0]], 2)
+    assert O.dither_windows([[1, -2]], 2).tolist() == [[4, 1]]
