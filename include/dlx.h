@@ -83,6 +83,19 @@ typedef struct {
   double focal_pixel_rad;/* focal-grid pitch in radians, > 0 */
   const double* wavelengths_m;    /* host [n_wavelengths], each > 0 */
   const double* spectral_weights; /* host [n_wavelengths] */
+  /* Integer-dither mode (the paper's own run, Section 3): NULL for frames
+   * with independent sources. Otherwise host int32 [n_frames][2], the shift
+   * (dx, dy) of the scene in each frame in whole detector pixels, with
+   * |dx|, |dy| <= dither_margin. The frames then share one set of stars
+   * (sources and grad_sources are [S][3]); every (star, wavelength) PSF is
+   * computed once on an enlarged focal grid of Q (N_det + 2 dither_margin)
+   * samples per side, and frame f is the N_det x N_det window of its binned
+   * image whose pixel p is enlarged-plane pixel p + dither_margin - d_f.
+   * The result equals independent frames with d_f added to every star's
+   * position, at 1/n_frames of the propagation work. The array is copied at
+   * plan creation. */
+  const int32_t* frame_dithers;
+  int32_t dither_margin;          /* >= 0; ignored when frame_dithers is NULL */
 } dlx_problem_desc;
 
 typedef struct dlx_plan dlx_plan;
@@ -128,7 +141,8 @@ size_t dlx_plan_workspace_bytes(const dlx_plan* plan);
  * for several problems (all zero for k = 0). Sizes per problem:
  * transmission Ni^2, zernike_basis Nz Ni^2, map_basis Ni n_map,
  * zernike_coeffs / grad_zernike Nz, phase_map / grad_map n_map^2,
- * sources / grad_sources 3 F S, flat / grad_flat Nd^2, intrapixel Q^2,
+ * sources / grad_sources 3 F S (3 S in integer-dither mode), flat /
+ * grad_flat Nd^2, intrapixel Q^2,
  * images (data, binned, model, dloss_dmodel) F Nd^2, loss 1. */
 typedef struct {
   int64_t transmission, zernike_basis, map_basis, zernike_coeffs, phase_map, sources, flat, intrapixel, images,
@@ -155,7 +169,8 @@ dlx_status dlx_plan_sync(dlx_plan* plan, void* stream);
  *   zernike_coeffs [Nz]          c (metres)
  *   phase_map [n_map][n_map]     C (metres; NULL iff n_map == 0)
  *   sources [F][S][3]            per frame and star: alpha, beta (radians,
- *                                dither included), photons phi
+ *                                dither included), photons phi; [S][3] in
+ *                                integer-dither mode (positions of frame 0)
  *   flat [Nd][Nd]                pixel response F
  *   intrapixel [Q][Q]            intra-pixel kernel K, NULL = all ones
  * Outputs (may not alias inputs):
@@ -183,7 +198,8 @@ dlx_status dlx_loss_grad(dlx_plan* plan, const float* model, const float* binned
  * Outputs (double, FP64-reduced):
  *   grad_zernike [Nz]              dL/dc
  *   grad_map [n_map][n_map]        dL/dC (NULL iff n_map == 0)
- *   grad_sources [F][S][3]         dL/dalpha, dL/dbeta, dL/dphi per frame and star */
+ *   grad_sources [F][S][3]         dL/dalpha, dL/dbeta, dL/dphi per frame and star
+ *                                  ([S][3], summed over frames, in integer-dither mode) */
 dlx_status dlx_psf_backward(dlx_plan* plan, const float* transmission, const float* zernike_basis,
                             const float* map_basis, const float* zernike_coeffs, const float* phase_map,
                             const float* sources, const float* flat, const float* intrapixel,

@@ -22,6 +22,9 @@ hipError_t launch_intensity(dlx_plan* p, int f0, int nf, const float* sources, c
 hipError_t launch_seed(dlx_plan* p, int f0, int nf, const float* flat, const float* resid, const float* intrapixel,
                        hipStream_t st);
 hipError_t launch_seed_apply(dlx_plan* p, int f0, int nf, const float* sources, hipStream_t st);
+hipError_t launch_window(dlx_plan* p, const float* flat, float* binned, float* model, hipStream_t st);
+hipError_t launch_seed_gather(dlx_plan* p, const float* flat, const float* resid, const float* intrapixel,
+                              hipStream_t st);
 hipError_t launch_loss(dlx_plan* p, int f0, int nf, int chunk, const float* model, const float* binned,
                        const float* data, const float* flat, int kind, double mu, double sigma, float* r, double* gflat,
                        const float* const* seed_intrapixel_or_none, hipStream_t st);
@@ -97,6 +100,10 @@ void layout(dlx_plan* p, Pool& pool) {
   p->d_UT = pool.take<float>(2 * CP * Ni * ldNo);
   p->d_G = pool.take<float>((size_t)p->frames_per_chunk * No * ldNo);
   p->d_bs = pool.take<float>((size_t)p->frames_per_chunk * p->S * p->Nd * p->Nd);
+  if (p->dither) {
+    p->d_Bbig = pool.take<float>((size_t)p->Nd * p->Nd);
+    p->d_win = pool.take<int>(p->win.size());
+  }
   p->d_gpart = pool.take<float>((size_t)p->b4_groups_max * p->ksplit_cap * Ni * Ni);
   p->d_gopd = pool.take<double>(Ni * Ni);
   p->d_flux = pool.take<double>((size_t)p->F * p->S * p->seed_blocks);
@@ -445,7 +452,7 @@ dlx_status create_multi(const dlx_problem_desc* probs, int32_t n, dlx_precision 
     o.map_basis += (long long)d.n_pupil * d.n_map;
     o.zernike_coeffs += d.n_zernike;
     o.phase_map += (long long)d.n_map * d.n_map;
-    o.sources += 3LL * d.n_frames * d.n_sources;
+    o.sources += 3LL * (d.frame_dithers ? 1 : d.n_frames) * d.n_sources;
     o.flat += nd * nd;
     o.intrapixel += (long long)d.oversample * d.oversample;
     o.images += (long long)d.n_frames * nd * nd;
@@ -541,6 +548,15 @@ dlx_status dlx_validate(const dlx_problem_desc* probs, int32_t n_probs) {
     }
     if (d.n_focal % d.oversample != 0) return DLX_ERR_SHAPE;
     if (d.n_pupil > kMaxSide || d.n_focal > kMaxSide) return DLX_ERR_SHAPE;
+    if (d.frame_dithers) {
+      if (d.dither_margin < 0) return DLX_ERR_INVALID_ARG;
+      if ((long long)d.n_focal + 2LL * d.oversample * d.dither_margin > kMaxSide) return DLX_ERR_SHAPE;
+      for (int f = 0; f < d.n_frames; ++f)
+        for (int c = 0; c < 2; ++c) {
+          const int v = d.frame_dithers[2 * f + c];
+          if (v > d.dither_margin || v < -d.dither_margin) return DLX_ERR_INVALID_ARG;
+        }
+    }
     if ((long long)d.n_frames * d.n_sources * d.n_wavelengths > (1LL << 24)) return DLX_ERR_SHAPE;
   }
   return DLX_OK;
@@ -566,6 +582,20 @@ dlx_status dlx_plan_create(const dlx_problem_desc* probs, int32_t n_probs, dlx_p
   p->L = d.n_wavelengths;
   p->S = d.n_sources;
   p->F = d.n_frames;
+  p->F_img = d.n_frames;
+  p->Nd_img = p->Nd;
+  if (d.frame_dithers) {  // one enlarged frame for the MFT stages; the images are its windows
+    p->dither = true;
+    p->margin = d.dither_margin;
+    p->Nd = p->Nd_img + 2 * p->margin;
+    p->No = p->Q * p->Nd;
+    p->F = 1;
+    p->win.resize(2 * (size_t)p->F_img);
+    for (int f = 0; f < p->F_img; ++f) {
+      p->win[2 * f] = p->margin - d.frame_dithers[2 * f + 1];
+      p->win[2 * f + 1] = p->margin - d.frame_dithers[2 * f];
+    }
+  }
   p->Nz = d.n_zernike;
   p->Nmap = d.n_map;
   p->D = d.diameter_m;
@@ -611,7 +641,7 @@ dlx_status dlx_plan_create(const dlx_problem_desc* probs, int32_t n_probs, dlx_p
   // partial-sum buffers are sized for the smallest candidate tile (32 x 32) and the largest split
   p->tiles_b4_cap = ceil_div(p->Ni, 32) * ceil_div(p->Ni, 32);
   p->ksplit_cap = 4;
-  p->loss_blocks = loss_block_count((long long)p->Nd * p->Nd);
+  p->loss_blocks = loss_block_count((long long)p->Nd_img * p->Nd_img);
   p->seed_blocks = seed_block_count((long long)p->Nd * p->Nd);
   p->seed_pass = (flags & DLX_FLAG_SEED_PASS) || sizeof(float) * (size_t)p->No * p->ldNo > kSeedFuseMaxBytes;
   {
@@ -648,6 +678,8 @@ dlx_status dlx_plan_create(const dlx_problem_desc* probs, int32_t n_probs, dlx_p
   }
   hipError_t e = hipMemset(p->pool, 0, p->pool_bytes);
   if (e == hipSuccess) e = hipMemcpy(p->d_wl, wl.data(), sizeof(WlInfo) * p->L, hipMemcpyHostToDevice);
+  if (e == hipSuccess && p->dither)
+    e = hipMemcpy(p->d_win, p->win.data(), sizeof(int) * p->win.size(), hipMemcpyHostToDevice);
   if (e == hipSuccess) e = launch_dft(p, nullptr);
   if (e == hipSuccess && !(flags & DLX_FLAG_NO_AUTOTUNE)) e = autotune_cached(p);
   if (e == hipSuccess) e = hipMemset(p->d_status, 0, sizeof(int));
@@ -831,7 +863,12 @@ dlx_status dlx_psf_forward(dlx_plan* p, const float* transmission, const float* 
       DLX_HIP(run_f2(p, f0, nf, st));
     }
     Stage sg(p, st, DLX_STAGE_BIN, nc);
-    DLX_HIP(launch_intensity(p, f0, nf, sources, intrapixel, flat, binned_out, model_out, st));
+    if (p->dither) {  // bin the enlarged plane once, then cut every frame's window
+      DLX_HIP(launch_intensity(p, f0, nf, sources, intrapixel, nullptr, p->d_Bbig, nullptr, st));
+      DLX_HIP(launch_window(p, flat, binned_out, model_out, st));
+    } else {
+      DLX_HIP(launch_intensity(p, f0, nf, sources, intrapixel, flat, binned_out, model_out, st));
+    }
   }
   return DLX_OK;
 }
@@ -852,7 +889,7 @@ dlx_status dlx_loss_grad(dlx_plan* p, const float* model, const float* binned, c
   if (!(prior_sigma > 0.0) || !std::isfinite(prior_sigma) || !std::isfinite(prior_mu)) return DLX_ERR_INVALID_ARG;
   hipStream_t st = reinterpret_cast<hipStream_t>(stream);
   Stage sg(p, st, DLX_STAGE_LOSS, p->n_psf);
-  DLX_HIP(launch_loss(p, 0, p->F, 0, model, binned, data, flat, (int)kind, prior_mu, prior_sigma, dloss_dmodel,
+  DLX_HIP(launch_loss(p, 0, p->F_img, 0, model, binned, data, flat, (int)kind, prior_mu, prior_sigma, dloss_dmodel,
                       grad_flat, nullptr, st));
   DLX_HIP(launch_loss_final(p, 1, loss_out, st));
   return DLX_OK;
@@ -903,7 +940,10 @@ dlx_status dlx_psf_backward(dlx_plan* p, const float* transmission, const float*
     }
     {
       Stage sg(p, st, DLX_STAGE_SEED, nc);
-      DLX_HIP(launch_seed(p, f0, nf, flat, dloss_dmodel, intrapixel, st));
+      if (p->dither)
+        DLX_HIP(launch_seed_gather(p, flat, dloss_dmodel, intrapixel, st));
+      else
+        DLX_HIP(launch_seed(p, f0, nf, flat, dloss_dmodel, intrapixel, st));
       if (p->seed_pass) DLX_HIP(launch_seed_apply(p, f0, nf, sources, st));
     }
     DLX_HIP(run_adjoint(p, c, f0, nf, sources, st));
@@ -975,18 +1015,34 @@ dlx_status dlx_eval(dlx_plan* p, const dlx_eval_args* a, void* stream) {
       Stage sg(p, st, DLX_STAGE_F2, nc);
       DLX_HIP(run_f2(p, f0, nf, st));
     }
-    {
-      Stage sg(p, st, DLX_STAGE_BIN, nc);
-      DLX_HIP(launch_intensity(p, f0, nf, a->sources, a->intrapixel, a->flat, a->binned, a->model, st));
-    }
-    {  // loss, residual and the adjoint seed weights in one pass over the pixels
-      Stage sg(p, st, DLX_STAGE_LOSS, nc);
-      DLX_HIP(launch_loss(p, f0, nf, c, a->model, a->binned, a->data, a->flat, (int)a->loss_kind, a->prior_mu,
-                          a->prior_sigma, a->dloss_dmodel, a->grad_flat, &a->intrapixel, st));
-    }
-    if (p->seed_pass) {
+    if (p->dither) {
+      {  // the enlarged plane once, then every frame's window
+        Stage sg(p, st, DLX_STAGE_BIN, nc);
+        DLX_HIP(launch_intensity(p, f0, nf, a->sources, a->intrapixel, nullptr, p->d_Bbig, nullptr, st));
+        DLX_HIP(launch_window(p, a->flat, a->binned, a->model, st));
+      }
+      {
+        Stage sg(p, st, DLX_STAGE_LOSS, nc);
+        DLX_HIP(launch_loss(p, 0, p->F_img, c, a->model, a->binned, a->data, a->flat, (int)a->loss_kind,
+                            a->prior_mu, a->prior_sigma, a->dloss_dmodel, a->grad_flat, nullptr, st));
+      }
       Stage sg(p, st, DLX_STAGE_SEED, nc);
-      DLX_HIP(launch_seed_apply(p, f0, nf, a->sources, st));
+      DLX_HIP(launch_seed_gather(p, a->flat, a->dloss_dmodel, a->intrapixel, st));
+      if (p->seed_pass) DLX_HIP(launch_seed_apply(p, f0, nf, a->sources, st));
+    } else {
+      {
+        Stage sg(p, st, DLX_STAGE_BIN, nc);
+        DLX_HIP(launch_intensity(p, f0, nf, a->sources, a->intrapixel, a->flat, a->binned, a->model, st));
+      }
+      {  // loss, residual and the adjoint seed weights in one pass over the pixels
+        Stage sg(p, st, DLX_STAGE_LOSS, nc);
+        DLX_HIP(launch_loss(p, f0, nf, c, a->model, a->binned, a->data, a->flat, (int)a->loss_kind, a->prior_mu,
+                            a->prior_sigma, a->dloss_dmodel, a->grad_flat, &a->intrapixel, st));
+      }
+      if (p->seed_pass) {
+        Stage sg(p, st, DLX_STAGE_SEED, nc);
+        DLX_HIP(launch_seed_apply(p, f0, nf, a->sources, st));
+      }
     }
     DLX_HIP(run_adjoint(p, c, f0, nf, a->sources, st));
   }

@@ -112,8 +112,14 @@ struct dlx_plan {
   hipEvent_t fork = nullptr;
   std::vector<hipEvent_t> joins;
   bool multi() const { return !subs.empty(); }
-  // problem
+  // problem. In integer-dither mode the MFT stages see one frame of an enlarged
+  // detector (F = 1, Nd = N_det + 2 margin, No = Q Nd) and the images are
+  // F_img windows of N_det_img pixels; otherwise F_img = F and Nd_img = Nd.
   int Ni, No, Q, Nd, L, S, F, Nz, Nmap;
+  int F_img = 0, Nd_img = 0;
+  bool dither = false;
+  int margin = 0;
+  std::vector<int> win;   // [F_img][2] window corners (row, col) in the enlarged plane
   double D, du, dx;
   std::vector<double> lam, wts;
   dlx_precision prec;
@@ -147,6 +153,8 @@ struct dlx_plan {
   float* d_UT = nullptr;   // [chunk_psf][Ni][ldNo] planar
   float* d_G = nullptr;    // seed weights G = K flat r [frames_per_chunk][No][ldNo]
   float* d_bs = nullptr;   // per-source binned sum_l w_l K|E|^2 [frames_per_chunk][S][Nd*Nd]
+  float* d_Bbig = nullptr; // integer-dither mode: binned enlarged plane [Nd*Nd]
+  int* d_win = nullptr;    // integer-dither mode: window corners [F_img][2]
   float* d_gpart = nullptr;    // [b4_groups_max * b4_ksplit][Ni*Ni]
   double* d_gopd = nullptr;    // [Ni*Ni]
   double* d_flux = nullptr;    // flux gradient partials [F][S][seed blocks]

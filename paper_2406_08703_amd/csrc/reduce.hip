@@ -14,7 +14,7 @@ namespace {
 // from the stored focal fields E of frames [f0, f0 + nf):
 //   bs[f][s][p] = sum_l w_l sum_{a,b<Q} K[a][b] |E_{f,s,l}[Qp_r + a][Qp_c + b]|^2   (per source, no flux)
 //   binned[f][p] = sum_s phi_s bs[f][s][p],  model[f][p] = flat[p] * binned[f][p]
-// (binned and model may be null: the adjoint only needs bs). Block (64,
+// (binned and model may each be null: the adjoint only needs bs). Block (64,
 // kLanes): 64 detector pixels x kLanes wavelength lanes; lane y sums
 // wavelengths y, y + kLanes, ... and the lanes are added in a fixed order
 // (deterministic). QT > 0 fixes Q at compile time (vector loads along the
@@ -77,10 +77,10 @@ __global__ void intensity_kernel(const float* E, long long plane, long long by_p
     }
     __syncthreads();
   }
-  if (y == 0 && live && binned) {
+  if (y == 0 && live) {
     const float bv = (float)total;
-    binned[(long long)f * npix + p] = bv;
-    model[(long long)f * npix + p] = flat[p] * bv;
+    if (binned) binned[(long long)f * npix + p] = bv;
+    if (model) model[(long long)f * npix + p] = flat[p] * bv;
   }
 }
 
@@ -255,6 +255,62 @@ __global__ void seed_apply_kernel(float* E, long long plane, long long by_psf, c
   }
 }
 
+// Integer-dither mode (Section 3): frame f's images are the N_det x N_det
+// window of the enlarged binned plane Bbig [Nb][Nb] at corner win[f]:
+//   binned[f][p] = Bbig[win_r + p_r][win_c + p_c],  model[f][p] = flat[p] binned[f][p].
+__global__ void window_kernel(const float* Bbig, int Nb, const int* win, int Nd, const float* flat, float* binned,
+                              float* model) {
+  const long long npix = (long long)Nd * Nd;
+  const long long p = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  const int f = blockIdx.y;
+  if (p >= npix) return;
+  const int pr = (int)(p / Nd), pc = (int)(p - (long long)pr * Nd);
+  const float b = Bbig[(long long)(win[2 * f] + pr) * Nb + win[2 * f + 1] + pc];
+  binned[(long long)f * npix + p] = b;
+  model[(long long)f * npix + p] = flat[p] * b;
+}
+
+// Seed weights of the enlarged plane (integer-dither mode): the adjoint of the
+// windows gathers, for enlarged pixel q, h[q] = sum over the frames whose window
+// holds q (p = q - win_f) of flat[p] r_f[p], in frame order; then
+//   G[Q q_r + a][Q q_c + b] = K[a][b] h[q]
+// and the flux partials sum_q h[q] bs_s[q] of this block (one enlarged frame),
+// at flux[s nblk + block].
+__global__ void seed_gather_kernel(const float* resid, const float* flat, const float* intrapixel, const float* bs,
+                                   const int* win, int F, int Nd, int Nb, int Q, int S, int ldg, float* G,
+                                   double* flux) {
+  __shared__ double sh[kSeedThreads / 64];
+  const long long nb2 = (long long)Nb * Nb, npix = (long long)Nd * Nd;
+  const long long q = (long long)blockIdx.x * kSeedThreads + threadIdx.x;
+  float h = 0.f;
+  if (q < nb2) {
+    const int qr = (int)(q / Nb), qc = (int)(q - (long long)qr * Nb);
+    for (int f = 0; f < F; ++f) {
+      const int pr = qr - win[2 * f], pc = qc - win[2 * f + 1];
+      if (pr >= 0 && pr < Nd && pc >= 0 && pc < Nd) {
+        const long long p = (long long)pr * Nd + pc;
+        h += flat[p] * resid[(long long)f * npix + p];
+      }
+    }
+    float* g = G + (long long)(Q * qr) * ldg + Q * qc;
+    for (int a = 0; a < Q; ++a)
+      for (int b = 0; b < Q; ++b) g[(long long)a * ldg + b] = intrapixel ? h * intrapixel[a * Q + b] : h;
+  }
+  for (int s = 0; s < S; ++s) {
+    double v = q < nb2 ? (double)h * (double)bs[(long long)s * nb2 + q] : 0.0;
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+    if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = v;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      double t = 0.0;
+      for (int w = 0; w < kSeedThreads / 64; ++w) t += sh[w];
+      flux[(long long)s * gridDim.x + blockIdx.x] = t;
+    }
+    __syncthreads();
+  }
+}
+
 // gopd[p] = sum_g gpart[g][p]
 __global__ void gopd_reduce_kernel(const float* gpart, int G, long long npix, double* gopd) {
   const long long p = (long long)blockIdx.x * blockDim.x + threadIdx.x;
@@ -421,6 +477,20 @@ hipError_t launch_seed_apply(dlx_plan* p, int f0, int nf, const float* sources, 
   return hipGetLastError();
 }
 
+hipError_t launch_window(dlx_plan* p, const float* flat, float* binned, float* model, hipStream_t st) {
+  const long long npix = (long long)p->Nd_img * p->Nd_img;
+  hipLaunchKernelGGL(window_kernel, dim3((unsigned)((npix + 255) / 256), p->F_img), dim3(256), 0, st, p->d_Bbig,
+                     p->Nd, p->d_win, p->Nd_img, flat, binned, model);
+  return hipGetLastError();
+}
+
+hipError_t launch_seed_gather(dlx_plan* p, const float* flat, const float* resid, const float* intrapixel,
+                              hipStream_t st) {
+  hipLaunchKernelGGL(seed_gather_kernel, dim3(p->seed_blocks), dim3(kSeedThreads), 0, st, resid, flat, intrapixel,
+                     p->d_bs, p->d_win, p->F_img, p->Nd_img, p->Nd, p->Q, p->S, p->ldNo, p->d_G, p->d_flux);
+  return hipGetLastError();
+}
+
 int loss_block_count(long long npix) { return (int)((npix + kLossThreads - 1) / kLossThreads); }
 
 // Loss terms of frames [f0, f0 + nf); block partials at slot `chunk`. The
@@ -431,7 +501,7 @@ int loss_block_count(long long npix) { return (int)((npix + kLossThreads - 1) / 
 hipError_t launch_loss(dlx_plan* p, int f0, int nf, int chunk, const float* model, const float* binned,
                        const float* data, const float* flat, int kind, double mu, double sigma, float* r, double* gflat,
                        const float* const* seed_intrapixel_or_none, hipStream_t st) {
-  const long long npix = (long long)p->Nd * p->Nd;
+  const long long npix = (long long)p->Nd_img * p->Nd_img;
   const int nb = loss_block_count(npix);
   const double inv_s2 = 1.0 / (sigma * sigma);
   double* blk = p->d_lossblk + (long long)chunk * nb;
@@ -448,8 +518,7 @@ hipError_t launch_loss(dlx_plan* p, int f0, int nf, int chunk, const float* mode
 }
 
 hipError_t launch_loss_final(dlx_plan* p, int n_chunks, double* loss, hipStream_t st) {
-  const int nb = loss_block_count((long long)p->Nd * p->Nd);
-  hipLaunchKernelGGL(final_sum_kernel, dim3(1), dim3(1024), 0, st, p->d_lossblk, nb * n_chunks, loss);
+  hipLaunchKernelGGL(final_sum_kernel, dim3(1), dim3(1024), 0, st, p->d_lossblk, p->loss_blocks * n_chunks, loss);
   return hipGetLastError();
 }
 

@@ -51,6 +51,7 @@ class dlx_problem_desc(ctypes.Structure):
         ("n_zernike", ctypes.c_int32), ("n_map", ctypes.c_int32),
         ("diameter_m", ctypes.c_double), ("focal_pixel_rad", ctypes.c_double),
         ("wavelengths_m", ctypes.POINTER(ctypes.c_double)), ("spectral_weights", ctypes.POINTER(ctypes.c_double)),
+        ("frame_dithers", ctypes.POINTER(ctypes.c_int32)), ("dither_margin", ctypes.c_int32),
     ]
 
 
@@ -129,16 +130,24 @@ def lib() -> ctypes.CDLL:
 
 
 def make_desc(n_pupil, n_focal, oversample, wavelengths, weights, n_sources, n_frames, n_zernike, n_map,
-              diameter, focal_pixel):
-    """Build a dlx_problem_desc; the returned tuple keeps the host arrays alive."""
+              diameter, focal_pixel, dithers=None, margin=0):
+    """Build a dlx_problem_desc; the returned tuple keeps the host arrays alive.
+
+    ``dithers`` [n_frames][2] (dx, dy) whole detector pixels selects the integer-dither mode."""
     nl = len(wavelengths)
     lam = (ctypes.c_double * nl)(*[float(v) for v in wavelengths])
     wts = (ctypes.c_double * len(weights))(*[float(v) for v in weights])
+    dith = None
+    if dithers is not None and len(dithers):
+        flat = [int(v) for pair in dithers for v in pair]
+        dith = (ctypes.c_int32 * len(flat))(*flat)
     d = dlx_problem_desc(int(n_pupil), int(n_focal), int(oversample), nl, int(n_sources), int(n_frames),
                          int(n_zernike), int(n_map), float(diameter), float(focal_pixel),
                          ctypes.cast(lam, ctypes.POINTER(ctypes.c_double)),
-                         ctypes.cast(wts, ctypes.POINTER(ctypes.c_double)))
-    return d, (lam, wts)
+                         ctypes.cast(wts, ctypes.POINTER(ctypes.c_double)),
+                         ctypes.cast(dith, ctypes.POINTER(ctypes.c_int32)) if dith is not None else None,
+                         int(margin))
+    return d, (lam, wts, dith)
 
 
 def _chk(status: int, where: str) -> int:

@@ -27,10 +27,17 @@ class Geometry:
     n_map: int
     diameter: float
     focal_pixel: float
+    dithers: tuple = ()      # integer-dither mode: ((dx, dy), ...) per frame, whole detector pixels
+    margin: int = 0          # enlarged-plane margin in detector pixels (>= every |dither|)
 
     @property
     def n_det(self) -> int:
         return self.n_focal // self.oversample
+
+    @property
+    def sources_shape(self) -> tuple:
+        """[F, S, 3], or [S, 3] in integer-dither mode (one set of stars for all frames)."""
+        return (self.n_sources, 3) if self.dithers else (self.n_frames, self.n_sources, 3)
 
 
 def _f32(t: torch.Tensor, shape, name: str) -> torch.Tensor:
@@ -72,7 +79,8 @@ class PsfPlan:
         Q = g.oversample
         self.intrapixel = None if intrapixel is None else _f32(intrapixel, (Q, Q), "intrapixel")
         desc, self._keep = _c.make_desc(g.n_pupil, g.n_focal, g.oversample, g.wavelengths, g.weights, g.n_sources,
-                                        g.n_frames, g.n_zernike, g.n_map, g.diameter, g.focal_pixel)
+                                        g.n_frames, g.n_zernike, g.n_map, g.diameter, g.focal_pixel,
+                                        g.dithers, g.margin)
         prec = {"fp32": _c.DLX_FP32, "bf16x3": _c.DLX_BF16X3}[precision]
         with torch.cuda.device(self.device):
             flags = (0 if autotune else _c.DLX_FLAG_NO_AUTOTUNE) | (_c.DLX_FLAG_SEED_PASS if seed_pass else 0)
@@ -107,7 +115,7 @@ class PsfPlan:
         g = self.geom
         c = _f32(coeffs, (g.n_zernike,), "zernike_coeffs") if g.n_zernike else None
         pm = _f32(phase_map, (g.n_map, g.n_map), "phase_map") if g.n_map else None
-        s = _f32(sources, (g.n_frames, g.n_sources, 3), "sources")
+        s = _f32(sources, g.sources_shape, "sources")
         fl = _f32(flat, (g.n_det, g.n_det), "flat")
         return c, pm, s, fl
 
@@ -151,7 +159,7 @@ class PsfPlan:
         if out is None:
             gz = torch.empty(max(g.n_zernike, 1), dtype=torch.float64, device=self.device)
             gm = torch.empty((g.n_map, g.n_map), dtype=torch.float64, device=self.device) if g.n_map else None
-            gs = torch.empty((g.n_frames, g.n_sources, 3), dtype=torch.float64, device=self.device)
+            gs = torch.empty(g.sources_shape, dtype=torch.float64, device=self.device)
         else:
             gz, gm, gs = out
         _c.dlx_psf_backward(self.plan, _ptr(self.transmission), _ptr(self.zbasis), _ptr(self.map_basis), _ptr(c),
@@ -173,7 +181,7 @@ class EvalBuffers:
         self.grad_flat = torch.empty((g.n_det, g.n_det), dtype=torch.float64, device=dv)
         self.grad_zernike = torch.empty(max(g.n_zernike, 1), dtype=torch.float64, device=dv)
         self.grad_map = torch.empty((g.n_map, g.n_map), dtype=torch.float64, device=dv) if g.n_map else None
-        self.grad_sources = torch.empty((g.n_frames, g.n_sources, 3), dtype=torch.float64, device=dv)
+        self.grad_sources = torch.empty(g.sources_shape, dtype=torch.float64, device=dv)
 
 
 def _eval_args(plan: "PsfPlan", coeffs, phase_map, sources, flat, data, kind, prior_mu, prior_sigma,
@@ -285,7 +293,8 @@ class BatchPlan:
         self._keep = []
         for k, g in enumerate(self.geoms):
             d, keep = _c.make_desc(g.n_pupil, g.n_focal, g.oversample, g.wavelengths, g.weights, g.n_sources,
-                                   g.n_frames, g.n_zernike, g.n_map, g.diameter, g.focal_pixel)
+                                   g.n_frames, g.n_zernike, g.n_map, g.diameter, g.focal_pixel,
+                                   g.dithers, g.margin)
             descs[k] = d
             self._keep.append(keep)
         prec = {"fp32": _c.DLX_FP32, "bf16x3": _c.DLX_BF16X3}[precision]
@@ -305,7 +314,7 @@ class BatchPlan:
         g = self.geoms[k]
         return {"transmission": (g.n_pupil, g.n_pupil), "zernike_basis": (g.n_zernike, g.n_pupil, g.n_pupil),
                 "map_basis": (g.n_pupil, g.n_map), "zernike_coeffs": (g.n_zernike,),
-                "phase_map": (g.n_map, g.n_map), "sources": (g.n_frames, g.n_sources, 3),
+                "phase_map": (g.n_map, g.n_map), "sources": g.sources_shape,
                 "flat": (g.n_det, g.n_det), "intrapixel": (g.oversample, g.oversample),
                 "images": (g.n_frames, g.n_det, g.n_det), "loss": (1,)}[field]
 

@@ -311,3 +311,123 @@ def _c4_problem(k, ni, no, q, nl, nz, ns) -> Workload:
                     flat_true=f32(1.0 + 0.05 * rf.normal(size=(nd, nd))), sources_true=f32(src_true),
                     coeffs=np.zeros(nz, np.float32), phase_map=None, flat=np.ones((nd, nd), np.float32),
                     sources=f32(src_eval), prior_mu=1.0, prior_sigma=0.05, _data_seed=ss.spawn(6)[5])
+
+
+@dataclass
+class DitheredWorkload:
+    """One scene imaged in several frames offset by whole detector pixels (the paper's run, Section 3).
+
+    The PSFs are those of an enlarged plane: ``problem`` has n_focal =
+    Q (n_det + 2 margin) and one frame; frame f is the window of that plane
+    shifted by ``dithers[f]`` = (dx, dy) detector pixels. Sources are shared
+    by all frames: [S, 3] = alpha, beta (radians), photons per frame.
+    """
+    problem: Problem
+    n_det: int
+    margin: int
+    dithers: np.ndarray                # int32 [F, 2]
+    transmission: np.ndarray
+    zbasis: np.ndarray
+    coeffs_true: np.ndarray
+    flat_true: np.ndarray              # [n_det, n_det]
+    sources_true: np.ndarray           # [S, 3]
+    coeffs: np.ndarray
+    flat: np.ndarray
+    sources: np.ndarray
+    prior_mu: float
+    prior_sigma: float
+    map_basis: np.ndarray | None = None
+    intrapixel: np.ndarray | None = None
+    data: np.ndarray | None = None     # [F, n_det, n_det]
+    _data_seed: object = field(default=None, repr=False)
+
+    @property
+    def n_frames(self) -> int:
+        return len(self.dithers)
+
+    def per_frame_sources(self, sources) -> np.ndarray:
+        """[F, S, 3] sources of the equivalent per-frame problem: dither added to every position."""
+        src = np.repeat(np.asarray(sources, np.float64)[None], self.n_frames, axis=0)
+        pix = self.problem.focal_pixel * self.problem.oversample
+        src[:, :, 0] += self.dithers[:, 0][:, None] * pix
+        src[:, :, 1] += self.dithers[:, 1][:, None] * pix
+        return src.astype(np.float32)
+
+    def with_data(self, image: np.ndarray) -> "DitheredWorkload":
+        rng = np.random.default_rng(self._data_seed)
+        lam = np.clip(np.asarray(image, dtype=np.float64), 0.0, None)
+        return dataclasses.replace(self, data=rng.poisson(lam).astype(np.float32))
+
+    def eval_params(self) -> dict:
+        return dict(coeffs=self.coeffs, phase_map=None, flat=self.flat, sources=self.sources)
+
+    def truth_params(self) -> dict:
+        return dict(coeffs=self.coeffs_true, phase_map=None, flat=self.flat_true, sources=self.sources_true)
+
+
+_P0 = dict(n_pupil=512, n_det=1024, oversample=1, margin=20, wavelengths=(545e-9, 595e-9, 645e-9), n_sources=20,
+           noll=tuple(range(4, 11)), zsigma=20e-9, inner_radius=0.1, det_pixel_mas=12.0, flat_sigma=0.1,
+           flux=(1e7, 1e8),
+           dithers=((0, 0), (20, 20), (20, -20), (-20, 20), (-20, -20)))
+
+
+def make_dithered_workload(**overrides) -> DitheredWorkload:
+    """The paper's own run (Section 3) as synthetic inputs: 20 stars, 3 wavelengths, 7 Zernikes
+    (Noll 4-10, 20 nm), a 512-pixel pupil with a central obstruction of radius D/10, a 1024-pixel
+    detector of 12 mas pixels, a pixel response 1 + 0.1 N(0, 1), and 5 frames: undithered and
+    dithered by (+-20, +-20) pixels, all from one 1064-pixel plane. Stars are placed uniformly
+    at least ``margin`` + 12 pixels inside the detector, fluxes log-uniform in ``flux``. Sizes can be
+    overridden for tests. Seeds: ``SeedSequence([2406, 8703, 5])``, children in the order Zernike
+    truth, flat truth, sources, (unused), Poisson data, evaluation-point perturbation.
+    """
+    s = dict(_P0)
+    for k, v in overrides.items():
+        if k not in s:
+            raise KeyError(f"unknown override {k!r}")
+        s[k] = v
+    ss = np.random.SeedSequence([2406, 8703, 5])
+    ch = ss.spawn(8)
+    rz, rf, rs, _, rpois, rinit = (np.random.default_rng(c) for c in ch[:6])
+    Ni, Nd, Q, m = s["n_pupil"], s["n_det"], s["oversample"], s["margin"]
+    lam = np.asarray(s["wavelengths"], np.float64)
+    det_pix = s["det_pixel_mas"] * np.pi / 180 / 3600 / 1000
+    D = DEFAULT_DIAMETER
+    S = s["n_sources"]
+    P = Problem(n_pupil=Ni, n_focal=Q * (Nd + 2 * m), oversample=Q, wavelengths=lam,
+                weights=np.full(len(lam), 1.0 / len(lam)), n_sources=S, n_frames=1, n_zernike=len(s["noll"]),
+                diameter=D, focal_pixel=det_pix / Q, obstruction=2 * s["inner_radius"], spider_px=0.0,
+                noll=tuple(s["noll"]))
+    trans = aperture(Ni, D, P.obstruction, 0.0)
+    zb = zernike_basis(list(P.noll), Ni, D)
+    coeffs_true = rz.normal(0.0, s["zsigma"], P.n_zernike)
+    flat_true = 1.0 + s["flat_sigma"] * rf.normal(size=(Nd, Nd))
+    lim = max(Nd / 2 - m - 12, 1.0)
+    pos = rs.uniform(-lim, lim, size=(S, 2)) * det_pix
+    lo, hi = np.log10(s["flux"][0]), np.log10(s["flux"][1])
+    flux = 10 ** rs.uniform(lo, hi, size=S)
+    src_true = np.concatenate([pos, flux[:, None]], axis=1)
+    src_eval = src_true.copy()
+    src_eval[:, :2] += rinit.normal(0.0, 1.0, size=(S, 2)) * det_pix
+    src_eval[:, 2] *= rinit.normal(1.0, 0.1, size=S)
+    f32 = lambda a: np.ascontiguousarray(a, dtype=np.float32)
+    return DitheredWorkload(problem=P, n_det=Nd, margin=m, dithers=np.asarray(s["dithers"], np.int32),
+                            transmission=f32(trans), zbasis=f32(zb), coeffs_true=f32(coeffs_true),
+                            flat_true=f32(flat_true), sources_true=f32(src_true),
+                            coeffs=np.zeros(P.n_zernike, np.float32), flat=np.ones((Nd, Nd), np.float32),
+                            sources=f32(src_eval), prior_mu=1.0, prior_sigma=float(s["flat_sigma"]),
+                            _data_seed=ch[4])
+
+
+def dithered_standin_image(w: DitheredWorkload) -> np.ndarray:
+    """Smooth stand-in image [F, n_det, n_det] (one Gaussian per star at its dithered true position)."""
+    P = w.problem
+    det_pix = P.focal_pixel * P.oversample
+    xd = (np.arange(w.n_det) - (w.n_det - 1) / 2.0) * det_pix
+    sig = 0.45 * float(np.mean(P.wavelengths)) / P.diameter
+    src = w.per_frame_sources(w.sources_true)
+    out = np.zeros((w.n_frames, w.n_det, w.n_det))
+    for f in range(w.n_frames):
+        for a, b, phi in src[f].astype(np.float64):
+            img = np.outer(np.exp(-0.5 * ((xd - b) / sig) ** 2), np.exp(-0.5 * ((xd - a) / sig) ** 2))
+            out[f] += phi * img / max(img.sum(), 1e-300)
+    return out * w.flat_true[None].astype(np.float64) + 1.0

@@ -28,11 +28,11 @@ def test_library_loads_and_exports_every_declared_symbol():
 
 def _desc(**kw):
     base = dict(n_pupil=64, n_focal=64, oversample=2, wavelengths=[600e-9], weights=[1.0], n_sources=1,
-                n_frames=1, n_zernike=10, n_map=0, diameter=0.5, focal_pixel=3e-7)
+                n_frames=1, n_zernike=10, n_map=0, diameter=0.5, focal_pixel=3e-7, dithers=None, margin=0)
     base.update(kw)
     return dlx.make_desc(base["n_pupil"], base["n_focal"], base["oversample"], base["wavelengths"],
                          base["weights"], base["n_sources"], base["n_frames"], base["n_zernike"], base["n_map"],
-                         base["diameter"], base["focal_pixel"])
+                         base["diameter"], base["focal_pixel"], base["dithers"], base["margin"])
 
 
 def test_status_strings():
@@ -112,3 +112,17 @@ def test_multi_problem_validation_and_null_plan():
     with pytest.raises(dlx.DlxError):
         dlx.dlx_plan_offsets(0, 0)
     assert dlx.lib().dlx_plan_offsets(None, 0, ctypes.byref(dlx.dlx_offsets())) == dlx.DLX_ERR_INVALID_ARG
+
+
+def test_validate_integer_dither_mode():
+    ok, k1 = _desc(n_frames=3, dithers=[(0, 0), (2, -2), (-1, 1)], margin=2)
+    assert dlx.dlx_validate(ok) == dlx.DLX_OK
+    beyond, k2 = _desc(n_frames=2, dithers=[(0, 0), (3, 0)], margin=2)
+    assert dlx.dlx_validate(beyond) == dlx.DLX_ERR_INVALID_ARG
+    negative, k3 = _desc(n_frames=1, dithers=[(0, 0)], margin=-1)
+    assert dlx.dlx_validate(negative) == dlx.DLX_ERR_INVALID_ARG
+    too_big, k4 = _desc(n_frames=1, n_focal=16000, oversample=2, dithers=[(0, 0)], margin=500)
+    assert dlx.dlx_validate(too_big) == dlx.DLX_ERR_SHAPE
+    with pytest.raises(dlx.DlxError) as e:
+        dlx.dlx_plan_create(beyond)
+    assert e.value.status == dlx.DLX_ERR_INVALID_ARG

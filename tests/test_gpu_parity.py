@@ -60,7 +60,7 @@ def flux_scale(want, sources):
     return rm[:, None] / np.asarray(sources, np.float64)[..., 2]
 
 
-def compare(got, want, tol_grad=TOL, tol_resid=TOL, tol_img=TOL, verbose=True, sources=None):
+def compare(got, want, tol_grad=TOL, tol_resid=TOL, tol_img=TOL, verbose=True, sources=None, fscale=None):
     errs = {}
     F = want["binned"].shape[0]
     errs["binned"] = max(rel_l2(got["binned"][f], want["binned"][f]) for f in range(F))
@@ -80,9 +80,12 @@ def compare(got, want, tol_grad=TOL, tol_resid=TOL, tol_img=TOL, verbose=True, s
         assert errs[k] < tol_img, (k, errs[k])
     for k in ("r", "grad_flat"):
         assert errs[k] < tol_resid, (k, errs[k])
-    if sources is not None:   # condition-aware flux check (see flux_scale)
+    if fscale is None and sources is not None:
+        fscale = flux_scale(want, sources)
+    if fscale is not None:   # condition-aware flux check (see flux_scale)
+        sources = True
         d = np.abs(got["grad_sources"][..., 2] - want["grad_sources"][..., 2])
-        errs["grad_flux_cond"] = float(np.max(d / flux_scale(want, sources)))
+        errs["grad_flux_cond"] = float(np.max(d / fscale))
         print(f"grad_flux_cond={errs['grad_flux_cond']:.2e}", flush=True)
     for k in ("grad_coeffs", "grad_pos", "grad_flux", "grad_map"):
         if k in errs and not (k == "grad_flux" and sources is not None):
