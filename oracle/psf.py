@@ -240,6 +240,34 @@ def backward(prob: OracleProblem, coeffs, phase_map, sources, flat, r):
     return g_c, g_map, g_src
 
 
+def intrapixel_grad(prob: OracleProblem, coeffs, phase_map, sources, flat, r):
+    """dL/dK [Q, Q] of the intra-pixel kernel (Section 6 names fitting it as future work).
+
+    B_f[p] = sum_ab K[a, b] I_f[Qp + (a, b)] is linear in K, so
+    dL/dK[a, b] = sum_f sum_p flat[p] r_f[p] I_f[Qp + (a, b)], with I_f the
+    unbinned focal intensity sum_s sum_lambda w phi |E|^2 (recomputed here).
+    """
+    sources = np.asarray(sources, np.float64)
+    flat = np.asarray(flat, np.float64)
+    r = np.asarray(r, np.float64)
+    x, u = _grids(prob)
+    opd = opd_map(prob.zbasis, coeffs, prob.map_basis, phase_map)
+    F, S = sources.shape[:2]
+    Q = prob.oversample
+    No = prob.n_focal
+    g = np.zeros((Q, Q))
+    for f in range(F):
+        I = np.zeros((No, No))
+        for s in range(S):
+            a, b, phi = sources[f, s]
+            for lam, w in zip(prob.wavelengths, prob.weights):
+                _, E, _ = _psf_field(prob, opd, x, u, a, b, lam)
+                I += w * phi * np.abs(E) ** 2
+        h = flat * r[f]
+        g += (np.kron(h, np.ones((Q, Q))) * I).reshape(prob.n_det, Q, prob.n_det, Q).sum(axis=(0, 2))
+    return g
+
+
 def value_and_grad(prob, coeffs, phase_map, sources, flat, data, kind="poisson", prior_mu=1.0, prior_sigma=0.1):
     """Forward, loss and all gradients in one call (a convenience for tests and the baseline)."""
     B, m = forward(prob, coeffs, phase_map, sources, flat)
@@ -330,3 +358,16 @@ def value_and_grad_dithered(prob_big, coeffs, phase_map, sources, flat, data, di
     g_c, g_map, g_src = backward_dithered(prob_big, coeffs, phase_map, sources, flat, r, dithers, margin)
     return dict(binned=B, model=m, loss=L, r=r, grad_flat=gF, grad_coeffs=g_c, grad_map=g_map,
                 grad_sources=g_src, domain=bad)
+
+
+def intrapixel_grad_dithered(prob_big: OracleProblem, coeffs, phase_map, sources, flat, r, dithers, margin):
+    """dL/dK for integer-dithered frames: the enlarged plane's intensity against sum_f (flat r_f) in its window."""
+    flat = np.asarray(flat, np.float64)
+    r = np.asarray(r, np.float64)
+    nd = flat.shape[0]
+    nb = prob_big.n_det
+    rb = np.zeros((nb, nb))
+    for f, (r0, c0) in enumerate(dither_windows(dithers, margin)):
+        rb[r0:r0 + nd, c0:c0 + nd] += flat * r[f]
+    return intrapixel_grad(prob_big, coeffs, phase_map, np.asarray(sources, np.float64)[None], np.ones((nb, nb)),
+                           rb[None])

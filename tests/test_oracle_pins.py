@@ -446,3 +446,40 @@ def test_dither_windows_reject_dithers_beyond_the_margin():
     with pytest.raises(ValueError):
         O.dither_windows([[3, 0]], 2)
     assert O.dither_windows([[1, -2]], 2).tolist() == [[4, 1]]
+
+
+@pytest.mark.parametrize("kind", ["poisson", "chi2"])
+def test_intrapixel_gradient_matches_central_differences_and_euler(kind):
+    # the binned image is linear in K: central differences of L in each K entry, and
+    # sum_ab K dL/dK = sum_f sum_p F r B (Euler)
+    w, prob = _setup_small("c3", **SMALL["c3"])
+    p = w.eval_params()
+    K0 = np.array(prob.intrapixel)
+    base = O.value_and_grad(prob, p["coeffs"], None, p["sources"], p["flat"], w.data, kind, w.prior_mu, w.prior_sigma)
+    gK = O.intrapixel_grad(prob, p["coeffs"], None, p["sources"], p["flat"], base["r"])
+
+    def loss_at(K):
+        pr = O.OracleProblem(**{**prob.__dict__, "intrapixel": K})
+        B, m = O.forward(pr, p["coeffs"], None, p["sources"], p["flat"])
+        return O.loss_grad(m, B, w.data, p["flat"], kind, w.prior_mu, w.prior_sigma)[0]
+
+    Q = prob.oversample
+    for a, b in [(0, 0), (1, 2), (Q - 1, 0)]:
+        def fk(t, a=a, b=b):
+            K = K0.copy()
+            K[a, b] = t
+            return loss_at(K)
+        fd = _fd(fk, K0[a, b], 1e-4)
+        assert abs(fd - gK[a, b]) <= 1e-6 * max(abs(gK[a, b]), 1e-3 * np.abs(gK).max())
+    euler = np.sum(np.asarray(p["flat"], np.float64)[None] * base["r"] * base["binned"])
+    assert abs(np.sum(K0 * gK) - euler) <= 1e-10 * np.sum(np.abs(K0 * gK))
+
+
+def test_dithered_intrapixel_gradient_equals_per_frame_sum():
+    small, big, pos, per_frame, dithers, margin, coeffs, flat, rng = _dither_case()
+    _, m = O.forward(small, coeffs, None, per_frame, flat)
+    data = rng.poisson(m).astype(np.float64)
+    ref = O.value_and_grad(small, coeffs, None, per_frame, flat, data, "poisson", 1.0, 0.05)
+    a = O.intrapixel_grad_dithered(big, coeffs, None, pos, flat, ref["r"], dithers, margin)
+    b = O.intrapixel_grad(small, coeffs, None, per_frame, flat, ref["r"])
+    assert rel_l2(a, b) < 1e-11
