@@ -199,12 +199,15 @@ dlx_status dlx_loss_grad(dlx_plan* plan, const float* model, const float* binned
  *   grad_zernike [Nz]              dL/dc
  *   grad_map [n_map][n_map]        dL/dC (NULL iff n_map == 0)
  *   grad_sources [F][S][3]         dL/dalpha, dL/dbeta, dL/dphi per frame and star
- *                                  ([S][3], summed over frames, in integer-dither mode) */
+ *                                  ([S][3], summed over frames, in integer-dither mode)
+ *   grad_intrapixel [Q][Q]         dL/dK of the intra-pixel kernel (fitting it is the
+ *                                  extension Section 6 proposes); NULL = not computed.
+ *                                  Needs Q <= 4 (else DLX_ERR_UNSUPPORTED). */
 dlx_status dlx_psf_backward(dlx_plan* plan, const float* transmission, const float* zernike_basis,
                             const float* map_basis, const float* zernike_coeffs, const float* phase_map,
                             const float* sources, const float* flat, const float* intrapixel,
                             const float* dloss_dmodel, double* grad_zernike, double* grad_map,
-                            double* grad_sources, void* stream);
+                            double* grad_sources, double* grad_intrapixel, void* stream);
 
 /* Every pointer of one full evaluation (forward, loss, backward); the
  * meanings, shapes and NULL rules are those of dlx_psf_forward,
@@ -230,6 +233,7 @@ typedef struct {
   double* grad_zernike; /* [Nz] */
   double* grad_map;     /* [n_map][n_map] */
   double* grad_sources; /* [F][S][3] */
+  double* grad_intrapixel; /* [Q][Q], NULL = not computed */
 } dlx_eval_args;
 
 /* Value and gradient of Section 4's objective in one call: dlx_psf_forward,

@@ -30,7 +30,9 @@ hipError_t launch_loss(dlx_plan* p, int f0, int nf, int chunk, const float* mode
                        const float* const* seed_intrapixel_or_none, hipStream_t st);
 hipError_t launch_loss_final(dlx_plan* p, int n_chunks, double* loss, hipStream_t st);
 hipError_t launch_grad_reduce(dlx_plan* p, const float* Z, const float* Bm, double* gz, double* gmap, double* gsrc,
-                              double* loss, int loss_chunks, hipStream_t st);
+                              double* loss, int loss_chunks, double* gK, hipStream_t st);
+hipError_t launch_kgrad(dlx_plan* p, int f0, int nf, const float* sources, const float* flat, const float* resid,
+                        hipStream_t st);
 int loss_block_count(long long npix);
 int seed_block_count(long long npix);
 int zproj_chunks(long long npix, int Nz);
@@ -43,6 +45,7 @@ namespace {
 constexpr size_t kDefaultChunkBudget = size_t(8) << 30;  // bytes of per-chunk intermediates
 constexpr int kMaxSide = 16384;
 constexpr int kTargetWG = 1024;
+constexpr int kMaxKgradQ = 4;   // the intra-pixel gradient kernel is compiled for Q <= 4
 // A frame's seed weights larger than this (bytes) are applied in a separate
 // pass rather than streamed by every B3 workgroup (about one XCD's L2).
 constexpr size_t kSeedFuseMaxBytes = size_t(4) << 20;
@@ -107,6 +110,7 @@ void layout(dlx_plan* p, Pool& pool) {
   p->d_gpart = pool.take<float>((size_t)p->b4_groups_max * p->ksplit_cap * Ni * Ni);
   p->d_gopd = pool.take<double>(Ni * Ni);
   p->d_flux = pool.take<double>((size_t)p->F * p->S * p->seed_blocks);
+  p->d_kpart = pool.take<double>((size_t)p->F * p->seed_blocks * p->Q * p->Q);
   p->d_pos = pool.take<double>((size_t)p->n_psf * p->ksplit_cap * p->tiles_b4_cap * 2);
   p->d_lossblk = pool.take<double>((size_t)p->loss_blocks * p->n_chunks);
   p->d_tmp2 = pool.take<double>(std::max<size_t>(1, Ni * (size_t)p->Nmap));
@@ -899,7 +903,7 @@ dlx_status dlx_psf_backward(dlx_plan* p, const float* transmission, const float*
                             const float* map_basis, const float* zernike_coeffs, const float* phase_map,
                             const float* sources, const float* flat, const float* intrapixel,
                             const float* dloss_dmodel, double* grad_zernike, double* grad_map, double* grad_sources,
-                            void* stream) {
+                            double* grad_intrapixel, void* stream) {
   if (!p || !transmission || !sources || !flat || !dloss_dmodel || !grad_sources) return DLX_ERR_INVALID_ARG;
   if (p->multi()) {
     return run_multi(p, reinterpret_cast<hipStream_t>(stream), [&](int k, dlx_plan* q, hipStream_t s) {
@@ -910,10 +914,12 @@ dlx_status dlx_psf_backward(dlx_plan* p, const float* transmission, const float*
                               q->Nmap ? at(phase_map, o.phase_map) : nullptr, at(sources, o.sources), at(flat, o.flat),
                               at(intrapixel, o.intrapixel), at(dloss_dmodel, o.images),
                               q->Nz ? at(grad_zernike, o.zernike_coeffs) : nullptr,
-                              q->Nmap ? at(grad_map, o.phase_map) : nullptr, at(grad_sources, o.sources), s);
+                              q->Nmap ? at(grad_map, o.phase_map) : nullptr, at(grad_sources, o.sources),
+                              at(grad_intrapixel, o.intrapixel), s);
     });
   }
   if (p->Nz > 0 && (!zernike_basis || !zernike_coeffs || !grad_zernike)) return DLX_ERR_INVALID_ARG;
+  if (grad_intrapixel && p->Q > kMaxKgradQ) return DLX_ERR_UNSUPPORTED;
   if ((p->Nmap > 0) != (map_basis != nullptr) || (p->Nmap > 0) != (phase_map != nullptr) ||
       (p->Nmap > 0) != (grad_map != nullptr))
     return DLX_ERR_INVALID_ARG;
@@ -944,12 +950,14 @@ dlx_status dlx_psf_backward(dlx_plan* p, const float* transmission, const float*
         DLX_HIP(launch_seed_gather(p, flat, dloss_dmodel, intrapixel, st));
       else
         DLX_HIP(launch_seed(p, f0, nf, flat, dloss_dmodel, intrapixel, st));
+      if (grad_intrapixel) DLX_HIP(launch_kgrad(p, f0, nf, sources, flat, dloss_dmodel, st));   // reads E
       if (p->seed_pass) DLX_HIP(launch_seed_apply(p, f0, nf, sources, st));
     }
     DLX_HIP(run_adjoint(p, c, f0, nf, sources, st));
   }
   Stage sg(p, st, DLX_STAGE_GRAD, p->n_psf);
-  DLX_HIP(launch_grad_reduce(p, zernike_basis, map_basis, grad_zernike, grad_map, grad_sources, nullptr, 0, st));
+  DLX_HIP(launch_grad_reduce(p, zernike_basis, map_basis, grad_zernike, grad_map, grad_sources, nullptr, 0,
+                             grad_intrapixel, st));
   return DLX_OK;
 }
 
@@ -984,6 +992,7 @@ dlx_status dlx_eval(dlx_plan* p, const dlx_eval_args* a, void* stream) {
       b.grad_zernike = q->Nz ? at(a->grad_zernike, o.zernike_coeffs) : nullptr;
       b.grad_map = q->Nmap ? at(a->grad_map, o.phase_map) : nullptr;
       b.grad_sources = at(a->grad_sources, o.sources);
+      b.grad_intrapixel = at(a->grad_intrapixel, o.intrapixel);
       return dlx_eval(q, &b, s);
     });
   }
@@ -995,6 +1004,7 @@ dlx_status dlx_eval(dlx_plan* p, const dlx_eval_args* a, void* stream) {
       (p->Nmap > 0) != (a->grad_map != nullptr))
     return DLX_ERR_INVALID_ARG;
   if (a->loss_kind != DLX_LOSS_POISSON && a->loss_kind != DLX_LOSS_CHI2) return DLX_ERR_INVALID_ARG;
+  if (a->grad_intrapixel && p->Q > kMaxKgradQ) return DLX_ERR_UNSUPPORTED;
   if (!(a->prior_sigma > 0.0) || !std::isfinite(a->prior_sigma) || !std::isfinite(a->prior_mu))
     return DLX_ERR_INVALID_ARG;
   hipStream_t st = reinterpret_cast<hipStream_t>(stream);
@@ -1028,6 +1038,7 @@ dlx_status dlx_eval(dlx_plan* p, const dlx_eval_args* a, void* stream) {
       }
       Stage sg(p, st, DLX_STAGE_SEED, nc);
       DLX_HIP(launch_seed_gather(p, a->flat, a->dloss_dmodel, a->intrapixel, st));
+      if (a->grad_intrapixel) DLX_HIP(launch_kgrad(p, f0, nf, a->sources, a->flat, a->dloss_dmodel, st));
       if (p->seed_pass) DLX_HIP(launch_seed_apply(p, f0, nf, a->sources, st));
     } else {
       {
@@ -1039,16 +1050,17 @@ dlx_status dlx_eval(dlx_plan* p, const dlx_eval_args* a, void* stream) {
         DLX_HIP(launch_loss(p, f0, nf, c, a->model, a->binned, a->data, a->flat, (int)a->loss_kind, a->prior_mu,
                             a->prior_sigma, a->dloss_dmodel, a->grad_flat, &a->intrapixel, st));
       }
-      if (p->seed_pass) {
+      if (a->grad_intrapixel || p->seed_pass) {
         Stage sg(p, st, DLX_STAGE_SEED, nc);
-        DLX_HIP(launch_seed_apply(p, f0, nf, a->sources, st));
+        if (a->grad_intrapixel) DLX_HIP(launch_kgrad(p, f0, nf, a->sources, a->flat, a->dloss_dmodel, st));
+        if (p->seed_pass) DLX_HIP(launch_seed_apply(p, f0, nf, a->sources, st));
       }
     }
     DLX_HIP(run_adjoint(p, c, f0, nf, a->sources, st));
   }
   Stage sg(p, st, DLX_STAGE_GRAD, p->n_psf);
   DLX_HIP(launch_grad_reduce(p, a->zernike_basis, a->map_basis, a->grad_zernike, a->grad_map, a->grad_sources, a->loss,
-                             p->n_chunks, st));
+                             p->n_chunks, a->grad_intrapixel, st));
   return DLX_OK;
 }
 

@@ -158,6 +158,7 @@ struct dlx_plan {
   float* d_gpart = nullptr;    // [b4_groups_max * b4_ksplit][Ni*Ni]
   double* d_gopd = nullptr;    // [Ni*Ni]
   double* d_flux = nullptr;    // flux gradient partials [F][S][seed blocks]
+  double* d_kpart = nullptr;   // intra-pixel kernel gradient partials [F][seed blocks][Q*Q]
   double* d_pos = nullptr;     // [n_psf][b4_ksplit][tiles_b4][2]
   double* d_lossblk = nullptr; // [loss blocks]
   double* d_tmp2 = nullptr;    // [Ni][Nmap] for the map gradient

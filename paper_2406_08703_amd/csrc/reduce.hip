@@ -311,6 +311,72 @@ __global__ void seed_gather_kernel(const float* resid, const float* flat, const 
   }
 }
 
+// Partials of dL/dK, the gradient with respect to the intra-pixel kernel (it
+// enters the binning linearly): per detector pixel p of frame f (one thread),
+//   h = flat[p] r_f[p]   (integer-dither mode: the window gather of the
+//                         enlarged plane, as in seed_gather_kernel)
+//   v[a][b] = h sum_s sum_l w_l phi_s |E_{f,s,l}[Q p_r + a][Q p_c + b]|^2,
+// summed over the block's pixels into part[(f nblk + block) Q^2 + a Q + b].
+template <int QT>
+__global__ void kgrad_kernel(const float* E, long long plane, long long by_psf, int ld, int f0, int S, int L,
+                             int Nd, const float* sources, const WlInfo* wl, const float* flat, const float* resid,
+                             const int* win, int F_img, int Nd_img, double* part) {
+  constexpr int Q2 = QT * QT;
+  __shared__ double sh[Q2][kSeedThreads / 64];
+  const long long npix = (long long)Nd * Nd;
+  const long long p = (long long)blockIdx.x * kSeedThreads + threadIdx.x;
+  const int fl = blockIdx.y;
+  const int f = f0 + fl;
+  double acc[Q2];
+#pragma unroll
+  for (int k = 0; k < Q2; ++k) acc[k] = 0.0;
+  if (p < npix) {
+    const int pr = (int)(p / Nd), pc = (int)(p - (long long)pr * Nd);
+    float h = 0.f;
+    if (win) {
+      const long long nimg = (long long)Nd_img * Nd_img;
+      for (int g = 0; g < F_img; ++g) {
+        const int ir = pr - win[2 * g], ic = pc - win[2 * g + 1];
+        if (ir >= 0 && ir < Nd_img && ic >= 0 && ic < Nd_img) {
+          const long long q = (long long)ir * Nd_img + ic;
+          h += flat[q] * resid[(long long)g * nimg + q];
+        }
+      }
+    } else {
+      h = flat[p] * resid[(long long)f * npix + p];
+    }
+    for (int s = 0; s < S; ++s) {
+      const float phi = sources[((long long)f * S + s) * 3 + 2];
+      for (int l = 0; l < L; ++l) {
+        const float* e = E + (((long long)fl * S + s) * L + l) * by_psf + (long long)(QT * pr) * ld + QT * pc;
+        const float wphi = wl[l].w * phi;
+#pragma unroll
+        for (int a = 0; a < QT; ++a)
+#pragma unroll
+          for (int b = 0; b < QT; ++b) {
+            const float er = e[(long long)a * ld + b], ei = e[plane + (long long)a * ld + b];
+            acc[a * QT + b] += (double)(wphi * (er * er + ei * ei));
+          }
+      }
+    }
+#pragma unroll
+    for (int k = 0; k < Q2; ++k) acc[k] *= (double)h;
+  }
+#pragma unroll
+  for (int k = 0; k < Q2; ++k) {
+    double v = acc[k];
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+    if ((threadIdx.x & 63) == 0) sh[k][threadIdx.x >> 6] = v;
+  }
+  __syncthreads();
+  if (threadIdx.x < Q2) {
+    double t = 0.0;
+    for (int w = 0; w < kSeedThreads / 64; ++w) t += sh[threadIdx.x][w];
+    part[((long long)f * gridDim.x + blockIdx.x) * Q2 + threadIdx.x] = t;
+  }
+}
+
 // gopd[p] = sum_g gpart[g][p]
 __global__ void gopd_reduce_kernel(const float* gpart, int G, long long npix, double* gopd) {
   const long long p = (long long)blockIdx.x * blockDim.x + threadIdx.x;
@@ -391,10 +457,12 @@ __global__ void map_grad2_kernel(const double* tmp2, const float* Bm, int Ni, in
 //   blocks [0, Nz):          dL/dc_j = sum over pixel chunks of the projection partials;
 //   blocks [Nz, Nz + F S):   grad_sources[f][s] = position partials summed over
 //                            wavelengths and tiles, flux partials over pixel blocks;
-//   block Nz + F S (if loss): L = sum of the loss block partials.
+//   block Nz + F S (if loss): L = sum of the loss block partials;
+//   the last Q^2 blocks (if gK): dL/dK[a][b] = sum of the intra-pixel partials.
 __global__ void finalize_kernel(const double* zpart, int Nz, int nchunks, double* gz, const double* flux,
                                 int seed_blocks, const double* pos, int tiles_b4, int L, int FS, double* gsrc,
-                                const double* lossblk, int nloss, double* loss) {
+                                const double* lossblk, int nloss, double* loss, const double* kpart, int nkpart,
+                                int Q2, double* gK) {
   __shared__ double sh[3][4];
   const int b = blockIdx.x;
   const int w = threadIdx.x >> 6;
@@ -410,8 +478,11 @@ __global__ void finalize_kernel(const double* zpart, int Nz, int nchunks, double
       v1 += pos[q + 1];
     }
     for (int i = threadIdx.x; i < seed_blocks; i += 256) v2 += flux[(long long)fs * seed_blocks + i];
-  } else {
+  } else if (loss && b == Nz + FS) {
     for (int i = threadIdx.x; i < nloss; i += 256) v0 += lossblk[i];
+  } else {
+    const int k = b - Nz - FS - (loss ? 1 : 0);
+    for (int i = threadIdx.x; i < nkpart; i += 256) v0 += kpart[(long long)i * Q2 + k];
   }
 #pragma unroll
   for (int o = 32; o > 0; o >>= 1) {
@@ -432,8 +503,10 @@ __global__ void finalize_kernel(const double* zpart, int Nz, int nchunks, double
       if (k == 0) gz[b] = t;
     } else if (b < Nz + FS) {
       gsrc[(b - Nz) * 3 + k] = t;
+    } else if (loss && b == Nz + FS) {
+      if (k == 0) loss[0] = t;
     } else if (k == 0) {
-      loss[0] = t;
+      gK[b - Nz - FS - (loss ? 1 : 0)] = t;
     }
   }
 }
@@ -491,6 +564,26 @@ hipError_t launch_seed_gather(dlx_plan* p, const float* flat, const float* resid
   return hipGetLastError();
 }
 
+// dL/dK partials of frames [f0, f0 + nf) (one enlarged frame in integer-dither mode); Q <= 4.
+hipError_t launch_kgrad(dlx_plan* p, int f0, int nf, const float* sources, const float* flat, const float* resid,
+                        hipStream_t st) {
+  const long long plane = (long long)p->chunk_psf * p->No * p->ldNo, by = (long long)p->No * p->ldNo;
+  const dim3 grid(p->seed_blocks, nf), blk(kSeedThreads);
+  const int* win = p->dither ? p->d_win : nullptr;
+#define DLX_KGRAD(QT)                                                                                          \
+  hipLaunchKernelGGL(kgrad_kernel<QT>, grid, blk, 0, st, p->d_Y, plane, by, p->ldNo, f0, p->S, p->L, p->Nd,  \
+                     sources, p->d_wl, flat, resid, win, p->F_img, p->Nd_img, p->d_kpart)
+  switch (p->Q) {
+    case 1: DLX_KGRAD(1); break;
+    case 2: DLX_KGRAD(2); break;
+    case 3: DLX_KGRAD(3); break;
+    case 4: DLX_KGRAD(4); break;
+    default: return hipErrorInvalidValue;
+  }
+#undef DLX_KGRAD
+  return hipGetLastError();
+}
+
 int loss_block_count(long long npix) { return (int)((npix + kLossThreads - 1) / kLossThreads); }
 
 // Loss terms of frames [f0, f0 + nf); block partials at slot `chunk`. The
@@ -536,7 +629,7 @@ int zproj_chunks(long long npix, int Nz) {
 // dL/dOPD, its projections and the source gradients; with `loss` also the
 // loss of dlx_eval's n_chunks block-partial slots.
 hipError_t launch_grad_reduce(dlx_plan* p, const float* Z, const float* Bm, double* gz, double* gmap, double* gsrc,
-                              double* loss, int loss_chunks, hipStream_t st) {
+                              double* loss, int loss_chunks, double* gK, hipStream_t st) {
   const long long npix = (long long)p->Ni * p->Ni;
   const int G = p->b4_groups_max * p->b4_ksplit;
   hipLaunchKernelGGL(gopd_reduce_kernel, dim3((unsigned)((npix + 255) / 256)), dim3(256), 0, st, p->d_gpart, G, npix,
@@ -555,9 +648,11 @@ hipError_t launch_grad_reduce(dlx_plan* p, const float* Z, const float* Bm, doub
                        p->Nmap, gmap);
   }
   const int FS = p->F * p->S;
-  hipLaunchKernelGGL(finalize_kernel, dim3(p->Nz + FS + (loss ? 1 : 0)), dim3(256), 0, st, p->d_zpart, p->Nz, nch, gz,
-                     p->d_flux, p->seed_blocks, p->d_pos, p->tiles_b4 * p->b4_ksplit, p->L, FS, gsrc, p->d_lossblk,
-                     p->loss_blocks * loss_chunks, loss);
+  const int Q2 = p->Q * p->Q;
+  hipLaunchKernelGGL(finalize_kernel, dim3(p->Nz + FS + (loss ? 1 : 0) + (gK ? Q2 : 0)), dim3(256), 0, st,
+                     p->d_zpart, p->Nz, nch, gz, p->d_flux, p->seed_blocks, p->d_pos, p->tiles_b4 * p->b4_ksplit, p->L,
+                     FS, gsrc, p->d_lossblk, p->loss_blocks * loss_chunks, loss, p->d_kpart, p->F * p->seed_blocks, Q2,
+                     gK);
   return hipGetLastError();
 }
 

@@ -60,7 +60,7 @@ class dlx_eval_args(ctypes.Structure):
                                                  "phase_map", "sources", "flat", "intrapixel", "data")] + [
         ("loss_kind", ctypes.c_int), ("prior_mu", ctypes.c_double), ("prior_sigma", ctypes.c_double)] + [
         (n, ctypes.c_void_p) for n in ("binned", "model", "dloss_dmodel", "loss", "grad_flat", "grad_zernike",
-                                       "grad_map", "grad_sources")]
+                                       "grad_map", "grad_sources", "grad_intrapixel")]
 
 
 class dlx_offsets(ctypes.Structure):
@@ -110,7 +110,7 @@ def lib() -> ctypes.CDLL:
         L.dlx_loss_grad.argtypes = [_vp, _vp, _vp, _vp, _vp, ctypes.c_int, ctypes.c_double, ctypes.c_double,
                                     _vp, _vp, _vp, _vp]
         L.dlx_psf_backward.restype = ctypes.c_int
-        L.dlx_psf_backward.argtypes = [_vp] * 14
+        L.dlx_psf_backward.argtypes = [_vp] * 15
         L.dlx_eval.restype = ctypes.c_int
         L.dlx_eval.argtypes = [_vp, ctypes.POINTER(dlx_eval_args), _vp]
         L.dlx_graph_capture.restype = ctypes.c_int
@@ -224,10 +224,12 @@ def dlx_loss_grad(plan, model, binned, data, flat, kind, prior_mu, prior_sigma, 
 
 
 def dlx_psf_backward(plan, transmission, zernike_basis, map_basis, zernike_coeffs, phase_map, sources, flat,
-                     intrapixel, dloss_dmodel, grad_zernike, grad_map, grad_sources, stream=0) -> None:
+                     intrapixel, dloss_dmodel, grad_zernike, grad_map, grad_sources, grad_intrapixel=0,
+                     stream=0) -> None:
     _chk(lib().dlx_psf_backward(_p(plan), _p(transmission), _p(zernike_basis), _p(map_basis), _p(zernike_coeffs),
                                 _p(phase_map), _p(sources), _p(flat), _p(intrapixel), _p(dloss_dmodel),
-                                _p(grad_zernike), _p(grad_map), _p(grad_sources), _p(stream)), "dlx_psf_backward")
+                                _p(grad_zernike), _p(grad_map), _p(grad_sources), _p(grad_intrapixel), _p(stream)),
+         "dlx_psf_backward")
 
 
 def dlx_plan_profile(plan: int, enable: bool) -> None:

@@ -151,8 +151,10 @@ class PsfPlan:
                          _ptr(r), _ptr(gF), _stream(self.device))
         return loss, r, gF
 
-    def backward(self, coeffs, phase_map, sources, flat, r, out=None):
-        """dlx_psf_backward: returns (grad_zernike [Nz], grad_map [n_map,n_map] or None, grad_sources [F,S,3]), double."""
+    def backward(self, coeffs, phase_map, sources, flat, r, out=None, grad_intrapixel=None):
+        """dlx_psf_backward: returns (grad_zernike [Nz], grad_map [n_map,n_map] or None, grad_sources [F,S,3]), double.
+
+        ``grad_intrapixel``: an optional float64 [Q, Q] device tensor that receives dL/dK."""
         g = self.geom
         c, pm, s, fl = self._params(coeffs, phase_map, sources, flat)
         rr = _f32(r, (g.n_frames, g.n_det, g.n_det), "dloss_dmodel")
@@ -162,9 +164,14 @@ class PsfPlan:
             gs = torch.empty(g.sources_shape, dtype=torch.float64, device=self.device)
         else:
             gz, gm, gs = out
+        gk = None
+        if grad_intrapixel is not None:
+            if grad_intrapixel.dtype != torch.float64 or tuple(grad_intrapixel.shape) != (g.oversample, g.oversample):
+                raise ValueError("grad_intrapixel must be a float64 [Q, Q] tensor")
+            gk = grad_intrapixel
         _c.dlx_psf_backward(self.plan, _ptr(self.transmission), _ptr(self.zbasis), _ptr(self.map_basis), _ptr(c),
                             _ptr(pm), _ptr(s), _ptr(fl), _ptr(self.intrapixel), _ptr(rr),
-                            _ptr(gz) if g.n_zernike else 0, _ptr(gm), _ptr(gs), _stream(self.device))
+                            _ptr(gz) if g.n_zernike else 0, _ptr(gm), _ptr(gs), _ptr(gk), _stream(self.device))
         return (gz[:g.n_zernike], gm, gs)
 
 
@@ -182,10 +189,11 @@ class EvalBuffers:
         self.grad_zernike = torch.empty(max(g.n_zernike, 1), dtype=torch.float64, device=dv)
         self.grad_map = torch.empty((g.n_map, g.n_map), dtype=torch.float64, device=dv) if g.n_map else None
         self.grad_sources = torch.empty(g.sources_shape, dtype=torch.float64, device=dv)
+        self.grad_intrapixel = torch.empty((g.oversample, g.oversample), dtype=torch.float64, device=dv)
 
 
 def _eval_args(plan: "PsfPlan", coeffs, phase_map, sources, flat, data, kind, prior_mu, prior_sigma,
-               out: EvalBuffers):
+               out: EvalBuffers, intrapixel_grad: bool = False):
     g = plan.geom
     c, pm, s, fl = plan._params(coeffs, phase_map, sources, flat)
     d = _f32(data, (g.n_frames, g.n_det, g.n_det), "data")
@@ -199,15 +207,18 @@ def _eval_args(plan: "PsfPlan", coeffs, phase_map, sources, flat, data, kind, pr
     a.grad_flat = _ptr(out.grad_flat)
     a.grad_zernike = _ptr(out.grad_zernike) if g.n_zernike else None
     a.grad_map, a.grad_sources = _ptr(out.grad_map), _ptr(out.grad_sources)
+    a.grad_intrapixel = _ptr(out.grad_intrapixel) if intrapixel_grad else None
     keep = (c, pm, s, fl, d)
     return a, keep
 
 
 def evaluate(plan: "PsfPlan", coeffs, phase_map, sources, flat, data, kind="poisson", prior_mu=1.0, prior_sigma=0.1,
-             out: EvalBuffers | None = None) -> EvalBuffers:
-    """dlx_eval: forward, loss and backward in one call; returns the output buffers."""
+             out: EvalBuffers | None = None, intrapixel_grad: bool = False) -> EvalBuffers:
+    """dlx_eval: forward, loss and backward in one call; returns the output buffers
+    (``out.grad_intrapixel`` is filled only with ``intrapixel_grad``)."""
     out = out or EvalBuffers(plan)
-    a, keep = _eval_args(plan, coeffs, phase_map, sources, flat, data, kind, prior_mu, prior_sigma, out)
+    a, keep = _eval_args(plan, coeffs, phase_map, sources, flat, data, kind, prior_mu, prior_sigma, out,
+                         intrapixel_grad)
     _c.dlx_eval(plan.plan, a, _stream(plan.device))
     return out
 

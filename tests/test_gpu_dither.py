@@ -181,3 +181,21 @@ def test_dither_problem_inside_a_multi_problem_plan():
     bp.close()
     assert rel_l2(gs, ref["grad_sources"]) < TOL
     assert abs(loss - ref["loss"]) < TOL * abs(ref["loss"])
+
+
+def test_dither_mode_intrapixel_gradient_matches_oracle():
+    from paper_2406_08703_amd import evaluate
+    from tests.gpu_helpers import dev
+    print("dither intrapixel grad", flush=True)
+    w, ref = case("q2-k")
+    p = w.eval_params()
+    want = O.intrapixel_grad_dithered(oracle_big(w), p["coeffs"], None, p["sources"], p["flat"], ref["r"], w.dithers,
+                                      w.margin)
+    plan = plan_for(w)
+    got = evaluate(plan, dev(p["coeffs"]), None, dev(p["sources"]), dev(p["flat"]), dev(w.data), "poisson",
+                   w.prior_mu, w.prior_sigma, intrapixel_grad=True).grad_intrapixel.cpu().numpy()
+    assert plan.sync() == 0
+    plan.close()
+    Q = w.problem.oversample
+    scale = np.sum(np.abs(np.asarray(p["flat"], np.float64)[None] * ref["r"]) * ref["binned"]) / (Q * Q)
+    assert np.max(np.abs(got - want)) / scale < TOL

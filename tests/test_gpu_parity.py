@@ -264,3 +264,54 @@ def test_separate_seed_pass_is_bitwise_identical(case, prec):
             assert np.array_equal(v, outs[1][k]), k
         else:
             assert v == outs[1][k], k
+
+
+def _kgrad_scale(w, ref):
+    """Per-entry size of the terms of dL/dK: sum_f sum_p |flat r| I (I from the oracle's binned image)."""
+    Q = w.problem.oversample
+    return np.sum(np.abs(np.asarray(w.eval_params()["flat"], np.float64)[None] * ref["r"]) * ref["binned"]) / (Q * Q)
+
+
+@pytest.mark.parametrize("fused", [False, True])
+@pytest.mark.parametrize("case", ["c3-small", "c2-odd", "c1"])
+def test_intrapixel_gradient_matches_oracle(case, fused):
+    import torch
+    from paper_2406_08703_amd import evaluate
+    from tests.gpu_helpers import dev, make_plan
+    print(f"intrapixel grad {case} fused={fused}", flush=True)
+    w, prob = workload(case)
+    ref = oracle_eval(case, "eval", "poisson")
+    p = w.eval_params()
+    want = O.intrapixel_grad(prob, p["coeffs"], p["phase_map"], p["sources"], p["flat"], ref["r"])
+    plan = make_plan(w, workspace_limit=0)
+    c, pm, s, fl, d = dev(p["coeffs"]), dev(p["phase_map"]), dev(p["sources"]), dev(p["flat"]), dev(w.data)
+    if fused:
+        got = evaluate(plan, c, pm, s, fl, d, "poisson", w.prior_mu, w.prior_sigma, intrapixel_grad=True).grad_intrapixel
+    else:
+        B, m = plan.forward(c, pm, s, fl)
+        L, r, gF = plan.loss_grad(m, B, d, fl, "poisson", w.prior_mu, w.prior_sigma)
+        Q = w.problem.oversample
+        got = torch.empty((Q, Q), dtype=torch.float64, device="cuda")
+        plan.backward(c, pm, s, fl, r, grad_intrapixel=got)
+    assert plan.sync() == 0
+    plan.close()
+    got = got.cpu().numpy()
+    err = np.max(np.abs(got - want)) / _kgrad_scale(w, ref)
+    print(f"dL/dK rel={rel_l2(got, want):.2e} cond={err:.2e}", flush=True)
+    assert err < TOL
+
+
+def test_intrapixel_gradient_rejects_large_oversampling():
+    import torch
+    from paper_2406_08703_amd import dlx as C
+    from tests.gpu_helpers import dev, make_plan
+    w = make_workload("c1", n_pupil=16, n_focal=10, oversample=5, noll=())
+    plan = make_plan(w)
+    P = w.problem
+    p = w.eval_params()
+    gk = torch.empty((5, 5), dtype=torch.float64, device="cuda")
+    r = torch.zeros((P.n_frames, P.n_det, P.n_det), dtype=torch.float32, device="cuda")
+    with pytest.raises(C.DlxError) as e:
+        plan.backward(None, None, dev(p["sources"]), dev(p["flat"]), r, grad_intrapixel=gk)
+    assert e.value.status == C.DLX_ERR_UNSUPPORTED
+    plan.close()
