@@ -34,8 +34,8 @@ WORKLOADS = {
           "frames, 256 Zernikes + 64x64 bicubic map",
     "c4": "128 independent uneven problems in one plan: pupils 128-512, focal 63-256 (Q 2-4), 8-64 "
           "wavelengths 450-800 nm, 16-128 Zernikes, 1-3 stars, 1 frame each",
-    "p0": "the paper's run: 512x512 pupil (obstruction radius D/10), 20 stars, 3 wavelengths 545/595/645 nm, "
-          "7 Zernikes (Noll 4-10), 1024x1024 detector of 12 mas pixels, 5 frames dithered by (+-20, +-20) px, "
+    "p0": "the paper's run: 512x512 pupil (obstruction radius D/10) with a binary half-wave phase plate (stand-in), "
+          "20 stars, 3 wavelengths 545/595/645 nm, 7 Zernikes (Noll 4-10), 1024x1024 detector of 12 mas pixels, 5 frames dithered by (+-20, +-20) px, "
           "integer-dither mode on a 1064x1064 plane",
 }
 
@@ -495,6 +495,7 @@ def bench_dither(args):
                         P.n_sources, w.n_frames, P.n_zernike, 0, P.diameter, P.focal_pixel,
                         tuple(map(tuple, w.dithers.tolist())) if dith else (), w.margin if dith else 0)
         plan = PsfPlan(geom, dev(w.transmission), dev(w.zbasis), precision=args.precision)
+        plan.set_phase_screen(dev(w.phase_screen))
         s = dev(ep["sources"] if dith else w.per_frame_sources(ep["sources"]))
         roof = None
         if dith:   # eager pass with per-stage HIP events for the roofline of the dominant GEMM
@@ -535,7 +536,8 @@ def bench_dither(args):
         import oracle as O
         from threadpoolctl import threadpool_info
         big = O.OracleProblem.from_arrays(P.n_pupil, P.n_focal, P.oversample, P.diameter, P.focal_pixel,
-                                          P.wavelengths[:1], np.ones(1), w.transmission, w.zbasis)
+                                          P.wavelengths[:1], np.ones(1), w.transmission, w.zbasis,
+                                          phase_screen=w.phase_screen)
         ns, dt = 1, 0.0
         while True:
             t1 = time.perf_counter()

@@ -158,6 +158,19 @@ int32_t dlx_plan_problems(const dlx_plan* plan);
  * k = F1, F2, B3, B4 (host int32_t[8]). */
 dlx_status dlx_plan_tiles(const dlx_plan* plan, int32_t* tiles);
 
+/* Static pupil phase screen of one problem (Section 3, the optical layers: the
+ * paper's system carries a fixed phase optic, the Toliman pupil's binary phase
+ * plate, after the Zernike aperture). `screen` is a device array [Ni][Ni] of
+ * phases in radians, row-major on the pupil grid, applied to every wavelength
+ * (achromatic) on top of the OPD's 2 pi OPD / lambda; NULL clears it. The plan
+ * copies the values on `stream` (the caller may free its array once the stream
+ * has passed the copy); they hold for every later forward, backward and fused
+ * call, including graph replays captured before or after. The screen is a fixed
+ * input: no gradient is returned for it. Every plan starts with a zero screen.
+ * `problem` is 0 for a one-problem plan. Errors: DLX_ERR_INVALID_ARG for a
+ * null plan or a problem index out of range. */
+dlx_status dlx_plan_set_phase_screen(dlx_plan* plan, int32_t problem, const float* screen, void* stream);
+
 /* Synchronise `stream`, then return and clear the plan's device status word
  * (DLX_OK, DLX_ERR_NONFINITE or DLX_ERR_DOMAIN). */
 dlx_status dlx_plan_sync(dlx_plan* plan, void* stream);

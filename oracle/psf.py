@@ -58,14 +58,15 @@ class OracleProblem:
     zbasis: np.ndarray                # [Nz, Ni, Ni]
     map_basis: np.ndarray | None = None   # [Ni, n_map]
     intrapixel: np.ndarray | None = None  # [Q, Q]
+    phase_screen: np.ndarray | None = None  # [Ni, Ni] static achromatic phase, radians
 
     @staticmethod
     def from_arrays(n_pupil, n_focal, oversample, diameter, focal_pixel, wavelengths, weights,
-                    transmission, zbasis, map_basis=None, intrapixel=None) -> "OracleProblem":
+                    transmission, zbasis, map_basis=None, intrapixel=None, phase_screen=None) -> "OracleProblem":
         f64 = lambda a: None if a is None else np.asarray(a, dtype=np.float64)
         return OracleProblem(int(n_pupil), int(n_focal), int(oversample), float(diameter), float(focal_pixel),
                              f64(wavelengths), f64(weights), f64(transmission), f64(zbasis),
-                             f64(map_basis), f64(intrapixel))
+                             f64(map_basis), f64(intrapixel), f64(phase_screen))
 
     @property
     def n_det(self) -> int:
@@ -108,13 +109,18 @@ def opd_map(zbasis, coeffs, map_basis=None, phase_map=None):
     return o
 
 
-def pupil_field(transmission, opd, x, y, alpha, beta, lam):
-    """Unit-power pupil field A/sqrt(sum A^2) * exp(i 2 pi/lambda (OPD + x alpha + y beta)).
+def pupil_field(transmission, opd, x, y, alpha, beta, lam, screen=None):
+    """Unit-power pupil field A/sqrt(sum A^2) * exp(i 2 pi/lambda (OPD + x alpha + y beta)) [* exp(i screen)].
 
     The source at angular offset (alpha, beta) tilts the incoming wavefront.
+    ``screen`` is a static phase optic in radians, the same at every
+    wavelength (Section 3's system applies such a layer, a binary phase
+    plate, after the Zernike aperture).
     """
     amp = transmission / np.sqrt(np.sum(transmission ** 2))
     phase = (TWO_PI / lam) * (opd + x[None, :] * alpha + y[:, None] * beta)
+    if screen is not None:
+        phase = phase + screen
     return amp * np.exp(1j * phase)
 
 
@@ -141,7 +147,7 @@ def _grids(prob: OracleProblem):
 
 
 def _psf_field(prob, opd, x, u, alpha, beta, lam):
-    P = pupil_field(prob.transmission, opd, x, x, alpha, beta, lam)
+    P = pupil_field(prob.transmission, opd, x, x, alpha, beta, lam, prob.phase_screen)
     c = prob.dx * prob.focal_pixel / lam
     return P, focal_field(P, x, x, u, u, lam, c), c
 
@@ -293,7 +299,7 @@ def binned_pixels(prob: OracleProblem, coeffs, phase_map, sources, frame, pixels
     for s in range(sources.shape[1]):
         a, b, phi = sources[frame, s]
         for lam, w in zip(prob.wavelengths, prob.weights):
-            P = pupil_field(prob.transmission, opd, x, x, a, b, lam)
+            P = pupil_field(prob.transmission, opd, x, x, a, b, lam, prob.phase_screen)
             for i, (p, q) in enumerate(pixels):
                 rows = u[Q * p:Q * p + Q]
                 cols = u[Q * q:Q * q + Q]

@@ -15,6 +15,7 @@
 
 namespace dlx {
 hipError_t launch_dft(dlx_plan* p, hipStream_t st);
+hipError_t launch_zero(float* x, long long n, hipStream_t st);
 hipError_t launch_prep(dlx_plan* p, const float* A, const float* Z, const float* Bm, const float* c, const float* C,
                        const float* sources, hipStream_t st);
 hipError_t launch_intensity(dlx_plan* p, int f0, int nf, const float* sources, const float* intrapixel,
@@ -93,6 +94,7 @@ void layout(dlx_plan* p, Pool& pool) {
   p->d_MT = pool.take<float>(2 * L * Ni * ldNo);
   p->d_x = pool.take<double>(Ni);
   p->d_opd = pool.take<double>((size_t)Ni * Ni);
+  p->d_screen = pool.take<float>((size_t)Ni * Ni);
   p->d_maptmp = pool.take<float>(std::max<size_t>(1, (size_t)p->Nmap * Ni));
   p->d_norm = pool.take<double>(p->n_norm_part);
   p->d_P0T = pool.take<float>(2 * L * Ni * ldNi);
@@ -805,6 +807,23 @@ dlx_status dlx_plan_stage_times(dlx_plan* p, double* total_ms, int64_t* launches
     p->stage_ms[i] = 0.0;
     p->stage_launches[i] = 0;
     p->stage_psfs[i] = 0;
+  }
+  return DLX_OK;
+}
+
+dlx_status dlx_plan_set_phase_screen(dlx_plan* p, int32_t problem, const float* screen, void* stream) {
+  if (!p) return DLX_ERR_INVALID_ARG;
+  if (p->multi()) {
+    if (problem < 0 || problem >= (int32_t)p->subs.size()) return DLX_ERR_INVALID_ARG;
+    return dlx_plan_set_phase_screen(p->subs[problem], 0, screen, stream);
+  }
+  if (problem != 0) return DLX_ERR_INVALID_ARG;
+  hipStream_t st = reinterpret_cast<hipStream_t>(stream);
+  const long long n = (long long)p->Ni * p->Ni;
+  if (screen) {
+    DLX_HIP(hipMemcpyAsync(p->d_screen, screen, sizeof(float) * n, hipMemcpyDeviceToDevice, st));
+  } else {
+    DLX_HIP(launch_zero(p->d_screen, n, st));
   }
   return DLX_OK;
 }

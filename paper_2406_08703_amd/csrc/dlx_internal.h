@@ -142,6 +142,7 @@ struct dlx_plan {
   float* d_MT = nullptr;   // [L][Ni][ldNo] planar
   double* d_x = nullptr;   // [Ni]
   double* d_opd = nullptr;    // OPD [Ni*Ni]
+  float* d_screen = nullptr;  // static pupil phase screen, radians [Ni*Ni] (zero unless set)
   float* d_maptmp = nullptr;  // [Nmap][Ni]
   double* d_norm = nullptr;   // partial sums of A^2 [n_norm_part]
   int n_norm_part = 1;

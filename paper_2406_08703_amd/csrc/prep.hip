@@ -84,8 +84,9 @@ __global__ void map_tmp_kernel(const float* C, const float* Bm, float* tmp, int 
 
 // P0T_l[n][m] = A[m][n] / sqrt(sum A^2) * exp(i 2 pi OPD[m][n] / lambda_l), one block per
 // (32 x 32 tile, wavelength), transposed through LDS.
-__global__ void pupil_kernel(const float* A, const double* opd, const double* norm_part, int n_norm,
-                             const WlInfo* wl, int Ni, int ldp, float* P0T, long long plane, long long by_wl) {
+__global__ void pupil_kernel(const float* A, const double* opd, const float* screen, const double* norm_part,
+                             int n_norm, const WlInfo* wl, int Ni, int ldp, float* P0T, long long plane,
+                             long long by_wl) {
   __shared__ float tr[32][33], ti[32][33];
   __shared__ double snorm;
   const int tx = threadIdx.x, ty = threadIdx.y;  // 32 x 8
@@ -104,7 +105,8 @@ __global__ void pupil_kernel(const float* A, const double* opd, const double* no
     float re = 0.f, im = 0.f;
     if (m < Ni && n < Ni) {
       const long long p = (long long)m * Ni + n;
-      const double t0 = opd[p] * inv;   // phase in cycles
+      // phase in cycles: the OPD's plus the static screen's (achromatic, radians)
+      const double t0 = opd[p] * inv + (double)screen[p] * 0.15915494309189533577;
       const double fr = t0 - rint(t0);
       double sn, cs;
       sincospi(2.0 * fr, &sn, &cs);
@@ -229,6 +231,17 @@ hipError_t launch_dft(dlx_plan* p, hipStream_t st) {
   return hipGetLastError();
 }
 
+__global__ void zero_kernel(float* x, long long n) {
+  const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) x[i] = 0.f;
+}
+
+hipError_t launch_zero(float* x, long long n, hipStream_t st) {
+  if (n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(zero_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, x, n);
+  return hipGetLastError();
+}
+
 hipError_t launch_prep(dlx_plan* p, const float* A, const float* Z, const float* Bm, const float* c, const float* C,
                        const float* sources, hipStream_t st) {
   const long long npix = (long long)p->Ni * p->Ni;
@@ -244,7 +257,7 @@ hipError_t launch_prep(dlx_plan* p, const float* A, const float* Z, const float*
                      p->d_x, p->L, p->ldNi, nt, p->d_tx, p->d_ty, nt);
   const long long p0_by_wl = 2LL * p->Ni * p->ldNi;
   hipLaunchKernelGGL(pupil_kernel, dim3((p->Ni + 31) / 32, (p->ldNi + 31) / 32, p->L), dim3(32, 8), 0, st, A,
-                     p->d_opd, p->d_norm, p->n_norm_part, p->d_wl, p->Ni, p->ldNi, p->d_P0T, (long long)p->Ni * p->ldNi,
+                     p->d_opd, p->d_screen, p->d_norm, p->n_norm_part, p->d_wl, p->Ni, p->ldNi, p->d_P0T, (long long)p->Ni * p->ldNi,
                      p0_by_wl);
   return hipGetLastError();
 }

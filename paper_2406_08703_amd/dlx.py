@@ -36,7 +36,7 @@ EXPORTS = ("dlx_validate", "dlx_plan_create", "dlx_plan_destroy", "dlx_plan_work
            "dlx_plan_sync",
            "dlx_psf_forward", "dlx_loss_grad", "dlx_psf_backward", "dlx_eval", "dlx_graph_capture",
            "dlx_graph_launch", "dlx_plan_profile", "dlx_plan_stage_times", "dlx_status_string",
-           "dlx_plan_offsets", "dlx_plan_problems")
+           "dlx_plan_offsets", "dlx_plan_problems", "dlx_plan_set_phase_screen")
 
 OFFSET_FIELDS = ("transmission", "zernike_basis", "map_basis", "zernike_coeffs", "phase_map", "sources", "flat",
                  "intrapixel", "images", "loss")
@@ -125,6 +125,8 @@ def lib() -> ctypes.CDLL:
         L.dlx_plan_offsets.argtypes = [_vp, ctypes.c_int32, ctypes.POINTER(dlx_offsets)]
         L.dlx_plan_problems.restype = ctypes.c_int32
         L.dlx_plan_problems.argtypes = [_vp]
+        L.dlx_plan_set_phase_screen.restype = ctypes.c_int
+        L.dlx_plan_set_phase_screen.argtypes = [_vp, ctypes.c_int32, _vp, _vp]
         _LIB = L
     return _LIB
 
@@ -202,6 +204,12 @@ def dlx_plan_tiles(plan: int) -> dict:
     t = (ctypes.c_int32 * 8)()
     _chk(lib().dlx_plan_tiles(_p(plan), ctypes.addressof(t)), "dlx_plan_tiles")
     return {k: (32 * t[2 * i], 32 * t[2 * i + 1]) for i, k in enumerate(("F1", "F2", "B3", "B4"))}
+
+
+def dlx_plan_set_phase_screen(plan: int, problem: int, screen, stream: int = 0) -> None:
+    """Copy a static pupil phase screen (device pointer to [Ni][Ni] FP32 radians, or None to clear)."""
+    _chk(lib().dlx_plan_set_phase_screen(_p(plan), int(problem), _p(screen), _p(stream)),
+         "dlx_plan_set_phase_screen")
 
 
 def dlx_plan_sync(plan: int, stream: int = 0) -> int:

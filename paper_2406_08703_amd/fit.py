@@ -193,6 +193,8 @@ def _main():
                     P.n_sources, w.n_frames, P.n_zernike, 0, P.diameter, P.focal_pixel,
                     tuple(map(tuple, w.dithers.tolist())), w.margin)
     plan = PsfPlan(geom, dev(w.transmission), dev(w.zbasis), precision=args.precision)
+    if w.phase_screen is not None:
+        plan.set_phase_screen(dev(w.phase_screen))
     # data: photon noise on the model at the truth, as in the paper's simulation
     _, m_true = plan.forward(dev(w.coeffs_true), None, dev(w.sources_true), dev(w.flat_true))
     gen = torch.Generator(device="cuda").manual_seed(2406)

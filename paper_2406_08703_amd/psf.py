@@ -110,6 +110,13 @@ class PsfPlan:
     def sync(self) -> int:
         return _c.dlx_plan_sync(self.plan, _stream(self.device))
 
+    def set_phase_screen(self, screen=None) -> None:
+        """Static achromatic pupil phase (radians, [n_pupil, n_pupil]) applied to every later call; None clears."""
+        n = self.geom.n_pupil
+        t = None if screen is None else _f32(screen, (n, n), "phase_screen")
+        _c.dlx_plan_set_phase_screen(self.plan, 0, None if t is None else t.data_ptr(), _stream(self.device))
+        self._screen = t  # kept alive until the copy on the stream has run
+
     # ------------------------------------------------------------------ calls
     def _params(self, coeffs, phase_map, sources, flat):
         g = self.geom
@@ -409,6 +416,14 @@ class BatchPlan:
 
     def sync(self) -> int:
         return _c.dlx_plan_sync(self.plan, _stream(self.device))
+
+    def set_phase_screen(self, problem: int, screen=None) -> None:
+        """Static achromatic pupil phase of problem ``problem`` (radians, [n_pupil, n_pupil]); None clears."""
+        n = self.geoms[problem].n_pupil
+        t = None if screen is None else _f32(screen, (n, n), "phase_screen")
+        _c.dlx_plan_set_phase_screen(self.plan, problem, None if t is None else t.data_ptr(), _stream(self.device))
+        self._screens = getattr(self, "_screens", {})
+        self._screens[problem] = t
 
     @property
     def workspace_bytes(self) -> int:

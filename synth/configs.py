@@ -23,7 +23,7 @@ from dataclasses import dataclass, field
 
 import numpy as np
 
-from .geometry import aperture, keys_bicubic_matrix, zernike_basis
+from .geometry import aperture, binary_phase_screen, keys_bicubic_matrix, zernike_basis
 
 DEFAULT_DIAMETER = 0.5  # metres, the paper's listing in Section 3
 CONFIG_NAMES = ("c1", "c2", "c3", "c5")
@@ -338,6 +338,7 @@ class DitheredWorkload:
     prior_sigma: float
     map_basis: np.ndarray | None = None
     intrapixel: np.ndarray | None = None
+    phase_screen: np.ndarray | None = None  # [n_pupil, n_pupil] static phase, radians
     data: np.ndarray | None = None     # [F, n_det, n_det]
     _data_seed: object = field(default=None, repr=False)
 
@@ -368,7 +369,7 @@ class DitheredWorkload:
 _P0 = dict(n_pupil=512, n_det=1024, oversample=1, margin=20, wavelengths=(545e-9, 595e-9, 645e-9), n_sources=20,
            noll=tuple(range(4, 11)), zsigma=20e-9, inner_radius=0.1, det_pixel_mas=12.0, flat_sigma=0.1,
            flux=(1e7, 1e8),
-           dithers=((0, 0), (20, 20), (20, -20), (-20, 20), (-20, -20)))
+           dithers=((0, 0), (20, 20), (20, -20), (-20, 20), (-20, -20)), mask=True)
 
 
 def make_dithered_workload(**overrides) -> DitheredWorkload:
@@ -377,8 +378,10 @@ def make_dithered_workload(**overrides) -> DitheredWorkload:
     detector of 12 mas pixels, a pixel response 1 + 0.1 N(0, 1), and 5 frames: undithered and
     dithered by (+-20, +-20) pixels, all from one 1064-pixel plane. Stars are placed uniformly
     at least ``margin`` + 12 pixels inside the detector, fluxes log-uniform in ``flux``. Sizes can be
-    overridden for tests. Seeds: ``SeedSequence([2406, 8703, 5])``, children in the order Zernike
-    truth, flat truth, sources, (unused), Poisson data, evaluation-point perturbation.
+    overridden for tests. The paper's binary phase plate (its mask file is not available) is
+    stood in for by ``binary_phase_screen`` (``mask=False`` leaves it out). Seeds:
+    ``SeedSequence([2406, 8703, 5])``, children in the order Zernike truth, flat truth, sources,
+    (unused), Poisson data, evaluation-point perturbation, phase plate.
     """
     s = dict(_P0)
     for k, v in overrides.items():
@@ -387,7 +390,7 @@ def make_dithered_workload(**overrides) -> DitheredWorkload:
         s[k] = v
     ss = np.random.SeedSequence([2406, 8703, 5])
     ch = ss.spawn(8)
-    rz, rf, rs, _, rpois, rinit = (np.random.default_rng(c) for c in ch[:6])
+    rz, rf, rs, _, rpois, rinit, rmask = (np.random.default_rng(c) for c in ch[:7])
     Ni, Nd, Q, m = s["n_pupil"], s["n_det"], s["oversample"], s["margin"]
     lam = np.asarray(s["wavelengths"], np.float64)
     det_pix = s["det_pixel_mas"] * np.pi / 180 / 3600 / 1000
@@ -415,6 +418,7 @@ def make_dithered_workload(**overrides) -> DitheredWorkload:
                             flat_true=f32(flat_true), sources_true=f32(src_true),
                             coeffs=np.zeros(P.n_zernike, np.float32), flat=np.ones((Nd, Nd), np.float32),
                             sources=f32(src_eval), prior_mu=1.0, prior_sigma=float(s["flat_sigma"]),
+                            phase_screen=binary_phase_screen(Ni, rmask) if s["mask"] else None,
                             _data_seed=ch[4])
 
 

@@ -98,6 +98,19 @@ def zernike_basis(noll: list[int] | np.ndarray, n: int, diameter: float) -> np.n
     return out
 
 
+def binary_phase_screen(n: int, rng: np.random.Generator, n_waves: int = 6, max_cycles: float = 6.0) -> np.ndarray:
+    """Stand-in for a binary diffractive pupil: phase 0 or pi (a half-wave step) on regions bounded by the
+    zero set of a sum of ``n_waves`` random plane waves of up to ``max_cycles`` cycles across the pupil.
+    Returned as FP32 radians [n, n]; the real plate's layout is not used."""
+    t = (np.arange(n) - (n - 1) / 2.0) / n
+    yy, xx = np.meshgrid(t, t, indexing="ij")
+    f = np.zeros((n, n))
+    for _ in range(n_waves):
+        kx, ky = rng.uniform(-max_cycles, max_cycles, size=2)
+        f += np.cos(2 * np.pi * (kx * xx + ky * yy) + rng.uniform(0, 2 * np.pi))
+    return np.where(f > 0, np.pi, 0.0).astype(np.float32)
+
+
 def keys_weight(t: np.ndarray, a: float = -0.5) -> np.ndarray:
     """Keys (1981) cubic convolution kernel with parameter ``a``."""
     t = np.abs(t)

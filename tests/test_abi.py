@@ -95,6 +95,9 @@ def test_calls_on_null_plan_are_rejected():
         dlx.dlx_loss_grad(0, 1, 1, 1, 1, 0, 1.0, 0.1, 1, 1, 1)
     with pytest.raises(dlx.DlxError):
         dlx.dlx_psf_backward(0, 1, 1, 0, 1, 0, 1, 1, 0, 1, 1, 0, 1)
+    with pytest.raises(dlx.DlxError) as e:
+        dlx.dlx_plan_set_phase_screen(0, 0, None)
+    assert e.value.status == dlx.DLX_ERR_INVALID_ARG
 
 
 def test_multi_problem_validation_and_null_plan():

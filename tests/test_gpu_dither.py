@@ -48,7 +48,8 @@ def case(name):
 def oracle_big(w):
     P = w.problem
     return O.OracleProblem.from_arrays(P.n_pupil, P.n_focal, P.oversample, P.diameter, P.focal_pixel,
-                                       P.wavelengths, P.weights, w.transmission, w.zbasis, None, w.intrapixel)
+                                       P.wavelengths, P.weights, w.transmission, w.zbasis, None, w.intrapixel,
+                                       w.phase_screen)
 
 
 def geometry(w, dither=True):
@@ -62,8 +63,11 @@ def geometry(w, dither=True):
 def plan_for(w, precision="fp32", dither=True, **kw):
     from paper_2406_08703_amd import PsfPlan
     from tests.gpu_helpers import dev
-    return PsfPlan(geometry(w, dither), dev(w.transmission), dev(w.zbasis), None, dev(w.intrapixel),
+    plan = PsfPlan(geometry(w, dither), dev(w.transmission), dev(w.zbasis), None, dev(w.intrapixel),
                    precision=precision, **kw)
+    if w.phase_screen is not None:
+        plan.set_phase_screen(dev(w.phase_screen))
+    return plan
 
 
 def to_np(out):
@@ -167,6 +171,7 @@ def test_dither_problem_inside_a_multi_problem_plan():
     t = lambda a: torch.from_numpy(np.ascontiguousarray(a, np.float32))
     bp = BatchPlan([plain_geometry(v), geometry(w)], [t(v.transmission), t(w.transmission)], [t(v.zbasis), t(w.zbasis)])
     assert bp.offsets[1]["sources"] == 3 * v.problem.n_frames * v.problem.n_sources
+    bp.set_phase_screen(1, t(w.phase_screen).cuda())   # the paper's run carries its phase plate
     pv, pw = v.eval_params(), w.eval_params()
     vd = np.ones((v.problem.n_frames, v.problem.n_det, v.problem.n_det), np.float32) * 3.0
     c = bp.pack("zernike_coeffs", [t(pv["coeffs"]), t(pw["coeffs"])])

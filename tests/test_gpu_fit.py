@@ -89,7 +89,7 @@ def _resolved_case():
     field, the positions here are constrained to a few thousandths of a pixel."""
     from synth import make_dithered_workload
     w = make_dithered_workload(n_pupil=48, n_det=64, margin=6, n_sources=4, det_pixel_mas=60.0,
-                               dithers=((0, 0), (6, 6), (6, -6), (-6, 6), (-6, -6)))
+                               dithers=((0, 0), (6, 6), (6, -6), (-6, 6), (-6, -6)), mask=False)
     _, m = O.forward_dithered(oracle_big(w), w.coeffs_true, None, w.sources_true, w.flat_true, w.dithers,
                               w.margin)
     return w.with_data(m)

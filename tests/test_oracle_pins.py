@@ -483,3 +483,102 @@ def test_dithered_intrapixel_gradient_equals_per_frame_sum():
     a = O.intrapixel_grad_dithered(big, coeffs, None, pos, flat, ref["r"], dithers, margin)
     b = O.intrapixel_grad(small, coeffs, None, per_frame, flat, ref["r"])
     assert rel_l2(a, b) < 1e-11
+
+
+# --------------------------------------------------------------------------- static phase screen, Fresnel defocus
+def _screen_case():
+    D, ni, no, lam = 0.5, 24, 30, 600e-9
+    A = aperture(ni, D, 0.2, 0.0)
+    Z = zernike_basis([4, 7, 8], ni, D)
+    opd = O.opd_map(Z, [20e-9, -15e-9, 10e-9])
+    x = O.pixel_grid(ni, D / ni)
+    du = lam / (2 * D) / 2
+    u = O.pixel_grid(no, du)
+    return D, ni, lam, A, Z, opd, x, u, (D / ni) * du / lam
+
+
+def test_constant_phase_screen_is_a_global_phase():
+    D, ni, lam, A, Z, opd, x, u, c = _screen_case()
+    E0 = O.focal_field(O.pupil_field(A, opd, x, x, 1e-7, -2e-7, lam), x, x, u, u, lam, c)
+    Es = O.focal_field(O.pupil_field(A, opd, x, x, 1e-7, -2e-7, lam, np.full((ni, ni), 1.3)), x, x, u, u, lam, c)
+    assert rel_l2(Es, E0 * np.exp(1.3j)) < 1e-13
+
+
+def test_phase_screen_in_radians_equals_the_same_opd_at_one_wavelength():
+    # a screen phi acts like an OPD phi * lambda / (2 pi) at that wavelength: pins the unit and the sign
+    D, ni, lam, A, Z, opd, x, u, c = _screen_case()
+    extra = O.opd_map(Z, [-31e-9, 12e-9, 25e-9])
+    Eo = O.focal_field(O.pupil_field(A, opd + extra, x, x, 0.0, 0.0, lam), x, x, u, u, lam, c)
+    Es = O.focal_field(O.pupil_field(A, opd, x, x, 0.0, 0.0, lam, 2 * np.pi * extra / lam), x, x, u, u, lam, c)
+    assert rel_l2(Es, Eo) < 1e-13
+
+
+def test_binary_half_wave_screen_flips_the_sign_of_its_region():
+    # exp(i pi) = -1 on the plate's region R: by linearity of the transform E = E(P) - 2 E(P restricted to R)
+    D, ni, lam, A, Z, opd, x, u, c = _screen_case()
+    from synth import binary_phase_screen
+    R = binary_phase_screen(ni, np.random.default_rng(7)) > 1.0
+    assert 0.2 < R.mean() < 0.8
+    scr = np.where(R, np.pi, 0.0)     # exact pi in FP64 (the stand-in itself is FP32)
+    P = O.pupil_field(A, opd, x, x, 0.0, 0.0, lam)
+    Es = O.focal_field(O.pupil_field(A, opd, x, x, 0.0, 0.0, lam, scr), x, x, u, u, lam, c)
+    want = O.focal_field(P, x, x, u, u, lam, c) - 2.0 * O.focal_field(P * R, x, x, u, u, lam, c)
+    assert rel_l2(Es, want) < 1e-13
+
+
+def test_screened_model_gradients_match_central_differences():
+    w = make_workload("c1", n_pupil=24, n_focal=16, noll=(2, 4, 7, 8))
+    prob = oracle_problem(w)
+    from synth import binary_phase_screen
+    import dataclasses
+    prob = dataclasses.replace(prob, phase_screen=binary_phase_screen(24, np.random.default_rng(3)).astype(np.float64))
+    p = w.eval_params()
+    _, m = O.forward(prob, w.coeffs_true, None, w.sources_true, w.flat_true)
+    d = np.round(m)
+    ref = O.value_and_grad(prob, p["coeffs"], None, p["sources"], p["flat"], d, "poisson", w.prior_mu, w.prior_sigma)
+    L = lambda cc, ss: O.value_and_grad(prob, cc, None, ss, p["flat"], d, "poisson", w.prior_mu,
+                                        w.prior_sigma)["loss"]
+    c0 = np.asarray(p["coeffs"], np.float64)
+    s0 = np.asarray(p["sources"], np.float64)
+    h = 1e-12
+    for j in range(c0.size):
+        e = np.zeros_like(c0)
+        e[j] = h
+        fd = (8 * (L(c0 + e, s0) - L(c0 - e, s0)) - (L(c0 + 2 * e, s0) - L(c0 - 2 * e, s0))) / (12 * h)
+        assert abs(fd - ref["grad_coeffs"][j]) < 1e-6 * np.max(np.abs(ref["grad_coeffs"])) + 1e-9
+    hp = 1e-4 * w.problem.focal_pixel
+    for k in range(2):
+        e = np.zeros_like(s0)
+        e[0, 0, k] = hp
+        fd = (8 * (L(c0, s0 + e) - L(c0, s0 - e)) - (L(c0, s0 + 2 * e) - L(c0, s0 - 2 * e))) / (12 * hp)
+        assert abs(fd - ref["grad_sources"][0, 0, k]) < 1e-6 * abs(ref["grad_sources"][0, 0, k]) + 1e-3
+
+
+def test_fresnel_defocus_basis_matches_angular_spectrum_propagation():
+    # Odd pupil, full-period focal grid (N_o = N_pad, du = lambda / (N_pad dx)): the focal field is an exact
+    # periodic DFT of the pupil, so propagating it a distance delta by its angular spectrum (paraxial
+    # transfer function exp(-i pi lambda delta kappa^2) in this sign convention, where a +alpha tilt images
+    # at +alpha) is exact, and must equal the focal field of the pupil with the defocus OPD added.
+    from paper_2406_08703_amd.optics import fresnel_defocus_basis
+    D, ni, lam, f = 0.5, 33, 600e-9, 8.0
+    npad = 66
+    dx = D / ni
+    du = lam / (npad * dx)
+    x = O.pixel_grid(ni, dx)
+    u = O.pixel_grid(npad, du)       # u = 0 lies between samples (even N): shifted below by half a pixel
+    u = (np.arange(npad) - npad // 2) * du
+    A = aperture(ni, D, 0.15, 0.0)
+    Z = zernike_basis([4, 7, 8, 11], ni, D)
+    opd = O.opd_map(Z, [15e-9, -20e-9, 8e-9, 5e-9])
+    c = dx * du / lam
+    E0 = O.focal_field(O.pupil_field(A, opd, x, x, 0.0, 0.0, lam), x, x, u, u, lam, c)
+    dX = f * du
+    kap = np.fft.fftfreq(npad, d=dX)
+    for delta in (2e-3, -3.5e-3):
+        H = np.exp(-1j * np.pi * lam * delta * (kap[None, :] ** 2 + kap[:, None] ** 2))
+        Ed = np.fft.fftshift(np.fft.ifft2(np.fft.fft2(np.fft.ifftshift(E0)) * H))
+        B = fresnel_defocus_basis(ni, D, f).astype(np.float64)
+        Ep = O.focal_field(O.pupil_field(A, opd + delta * B, x, x, 0.0, 0.0, lam), x, x, u, u, lam, c)
+        assert np.max(np.abs(delta * B)) > 0.2 * lam          # a visible defocus, not a no-op
+        assert rel_l2(Ed, Ep) < 1e-5   # FP32 basis values
+        assert rel_l2(np.abs(Ed) ** 2, np.abs(E0) ** 2) > 0.1
