@@ -302,10 +302,19 @@ def main():
             if dt >= args.cpu_seconds or nl >= P.n_wavelengths:
                 break
             nl = min(P.n_wavelengths, max(nl + 1, int(nl * args.cpu_seconds / max(dt, 1e-3) * 0.9)))
+        # a sample shorter than the target (the whole frame fits) is repeated up to the target time
+        reps = 1
+        while dt < args.cpu_seconds:
+            t = time.perf_counter()
+            O.value_and_grad(sub, ep["coeffs"], ep["phase_map"], src0, ep["flat"], w.data[:1], "poisson",
+                             w.prior_mu, w.prior_sigma)
+            dt += time.perf_counter() - t
+            reps += 1
         threads = max([i.get("num_threads", 1) for i in threadpool_info()] + [1])
-        cpu = {"value": round(npsf_s / dt, 4), "unit": "PSF evals/s", "cores": threads, "kind": "oracle",
-               "sample": f"FP64 NumPy oracle forward+loss+gradient on {sample_desc} "
-                         f"({npsf_s} PSFs, {dt:.2f} s)", "host_cpus": os.cpu_count()}
+        cpu = {"value": round(npsf_s * reps / dt, 4), "unit": "PSF evals/s", "cores": threads, "kind": "oracle",
+               "sample": f"FP64 NumPy oracle forward+loss+gradient on {sample_desc}"
+                         f"{f', {reps} times' if reps > 1 else ''} ({npsf_s * reps} PSFs, {dt:.2f} s)",
+               "host_cpus": os.cpu_count()}
         log(f"cpu baseline: {cpu}")
 
     out = {"metric": METRIC, "value": round(evals, 3), "unit": "PSF evals/s", "n_gpus": 1, "steps": args.steps,
