@@ -104,3 +104,85 @@ def test_fullsize_loss_matches_oracle(name):
     assert rel_l2(r.cpu().numpy(), rr) < 1e-7
     assert rel_l2(gF.cpu().numpy(), gFr) < 1e-7
     assert P.n_det ** 2 == gF.numel()
+
+
+# ------------------------------------------------------------------ the paper's run and the batched configuration
+@functools.lru_cache(maxsize=None)
+def p0_reference():
+    """The paper's run at its full size (integer-dither mode, phase plate), with the benchmark's data."""
+    from synth import dithered_standin_image, make_dithered_workload
+    w = make_dithered_workload()
+    w = w.with_data(dithered_standin_image(w))
+    P = w.problem
+    big = O.OracleProblem.from_arrays(P.n_pupil, P.n_focal, P.oversample, P.diameter, P.focal_pixel,
+                                      P.wavelengths, P.weights, w.transmission, w.zbasis,
+                                      phase_screen=w.phase_screen)
+    p = w.eval_params()
+    ref = O.value_and_grad_dithered(big, p["coeffs"], None, p["sources"], p["flat"], w.data, w.dithers, w.margin,
+                                    "poisson", w.prior_mu, w.prior_sigma)
+    return w, ref
+
+
+@pytest.mark.parametrize("prec", ["fp32", "bf16x3"])
+def test_fullsize_paper_run_matches_oracle(prec):
+    from tests.test_gpu_dither import plan_for, run
+    from tests.test_gpu_parity import compare
+    print(f"full size p0 {prec}", flush=True)
+    w, ref = p0_reference()
+    plan = plan_for(w, prec)
+    got = run(w, plan, fused=True)     # checks the device status word
+    plan.close()
+    tol = TOL[prec]
+    # the flux gradient sums terms of both signs over all frames: scale by the size of its terms
+    rm = np.sum(np.abs(ref["r"] * ref["model"]))
+    fscale = rm / np.asarray(w.eval_params()["sources"], np.float64)[:, 2]
+    compare(got, ref, tol_grad=tol, tol_resid=tol, tol_img=tol, fscale=fscale)
+
+
+def test_fullsize_batched_configuration_sampled_problems():
+    """All 128 problems of the batched configuration in one plan, as benchmarked; the three cheapest
+    problems for the oracle and the largest pupil among the 20 cheapest are checked against it."""
+    import torch
+    from paper_2406_08703_amd import BatchPlan
+    from synth import make_c4_workloads
+    from tests.gpu_helpers import geometry
+    from tests.test_gpu_parity import compare
+    print("full size c4", flush=True)
+    ws = [w.with_data(standin_image(w)) for w in make_c4_workloads()]
+    cost = [w.problem.n_psf * w.problem.mft_flops() for w in ws]
+    order = np.argsort(cost)
+    picks = list(order[:3])
+    big = max(order[:20], key=lambda k: ws[k].problem.n_pupil)
+    if big not in picks:
+        picks.append(big)
+    t = lambda a: torch.from_numpy(np.ascontiguousarray(a, dtype=np.float32))
+    bp = BatchPlan([geometry(w) for w in ws], [t(w.transmission) for w in ws], [t(w.zbasis) for w in ws])
+    eps = [w.eval_params() for w in ws]
+    c = bp.pack("zernike_coeffs", [t(e["coeffs"]) for e in eps])
+    s = bp.pack("sources", [t(e["sources"]) for e in eps])
+    fl = bp.pack("flat", [t(e["flat"]) for e in eps])
+    d = bp.pack("images", [t(w.data) for w in ws])
+    out = bp.buffers()
+    a = bp.eval_args(c, None, s, fl, d, out, "poisson", ws[0].prior_mu, ws[0].prior_sigma)
+    bp.capture(a)
+    bp.replay()
+    torch.cuda.synchronize()
+    assert bp.sync() == 0
+    views = {n: bp.unpack(f, out[k]) for n, k, f in (
+        ("binned", "binned", "images"), ("model", "model", "images"), ("r", "r", "images"),
+        ("loss", "loss", "loss"), ("grad_flat", "grad_flat", "flat"),
+        ("grad_coeffs", "grad_zernike", "zernike_coeffs"), ("grad_sources", "grad_sources", "sources"))}
+    got_all = {k: {n: v[k].cpu().numpy().astype(np.float64) for n, v in views.items()} for k in picks}
+    bp.close()
+    for k in picks:
+        w = ws[k]
+        print(f"problem {k}: pupil {w.problem.n_pupil}, focal {w.problem.n_focal}, {w.problem.n_psf} PSFs",
+              flush=True)
+        prob = oracle_problem(w)
+        e = eps[k]
+        ref = O.value_and_grad(prob, e["coeffs"], None, e["sources"], e["flat"], w.data, "poisson", w.prior_mu,
+                               w.prior_sigma)
+        g = got_all[k]
+        g["loss"] = float(g["loss"][0])
+        g["grad_map"] = None
+        compare(g, ref, sources=e["sources"])
