@@ -32,6 +32,12 @@ The integer-dither form (``forward_dithered`` / ``backward_dithered``,
 Section 3: one PSF computation on an enlarged plane, each frame a window of
 it) is pinned to the per-frame form with the dithers folded into the star
 positions, by the shift theorem on the focal grid.
+The static phase screen (Section 3's fixed phase optic) is pinned by a
+constant screen acting as a global phase, by its equivalence with an OPD
+at one wavelength, by the sign flip a half-wave plate gives its region
+(linearity of the transform) and by finite differences; the Fresnel
+defocus basis row is pinned by angular-spectrum propagation of the focal
+field on a full-period grid.
 Parity unpinned beyond finite differences: the bicubic map term and the
 chi-squared data term (definitions, not results).
 """
