@@ -302,10 +302,15 @@ hipError_t run_adjoint(dlx_plan* p, int c, int f0, int nf, const float* sources,
   return run_b4(p, c, f0, nf, st);
 }
 
-// Tile-dependent derived sizes: partial-sum tile counts and B4's split of K.
-void derive_tiles(dlx_plan* p) {
+// Tile-dependent derived sizes: partial-sum tile counts and B4's split of K (`ksplit` > 0 sets it,
+// as the autotuner does; otherwise K = No is split when the groups alone cannot fill the chip,
+// keeping >= 128 per split).
+void derive_tiles(dlx_plan* p, int ksplit = 0) {
   p->tiles_b4 = ceil_div(p->Ni, p->ts_b4.bm()) * ceil_div(p->Ni, p->ts_b4.bn());
-  // split B4's K (= No) when its groups alone cannot fill the chip, keeping >= 128 per split
+  if (ksplit > 0) {
+    p->b4_ksplit = ksplit;
+    return;
+  }
   const long long wg = (long long)p->tiles_b4 * p->b4_groups_max;
   int ks = 1;
   while (ks < 4 && wg * ks < kTargetWG && p->No / (2 * ks) >= 128) ks *= 2;
@@ -347,10 +352,16 @@ hipError_t autotune(dlx_plan* p) {
   for (int kind : kinds) {
     TileShape* ts = stage_tile(p, kind);
     TileShape best = *ts;
+    int best_ks = 0;
     float best_ms = 1e30f;
-    for (const TileShape& cand : kTileShapes) {
+    // B4 also tries each split of its K (= No) into 1, 2 or 4 ranges of at least 64
+    const int n_ks = kind == KIND_B4 ? 3 : 1;
+    for (int ci = 0; ci < (int)(sizeof(kTileShapes) / sizeof(kTileShapes[0])) * n_ks && e == hipSuccess; ++ci) {
+      const TileShape& cand = kTileShapes[ci / n_ks];
+      const int ks = kind == KIND_B4 ? (1 << (ci % n_ks)) : 0;
+      if (ks > 1 && p->No / ks < 64) continue;
       *ts = cand;
-      derive_tiles(p);
+      derive_tiles(p, ks);
       if ((e = run_stage_for_tuning(p, kind, nullptr)) != hipSuccess) break;   // warm-up
       if ((e = hipEventRecord(t0, nullptr)) != hipSuccess) break;
       for (int r = 0; r < 2 && e == hipSuccess; ++r) e = run_stage_for_tuning(p, kind, nullptr);
@@ -360,14 +371,17 @@ hipError_t autotune(dlx_plan* p) {
       float ms = 0.f;
       if ((e = hipEventElapsedTime(&ms, t0, t1)) != hipSuccess) break;
       if (log)
-        std::fprintf(stderr, "dlx tune: stage %d tile %dx%d: %.4f ms per launch\n", kind, cand.bm(), cand.bn(), ms / 2);
+        std::fprintf(stderr, "dlx tune: stage %d tile %dx%d ksplit %d: %.4f ms per launch\n", kind, cand.bm(),
+                     cand.bn(), p->b4_ksplit, ms / 2);
       if (ms < best_ms) {
         best_ms = ms;
         best = cand;
+        best_ks = ks;
       }
     }
     *ts = best;
-    derive_tiles(p);
+    derive_tiles(p, best_ks);
+    if (kind == KIND_B4) p->b4_ksplit_tuned = best_ks;
     if (e != hipSuccess) break;
   }
   (void)hipEventDestroy(t0);
@@ -381,7 +395,11 @@ hipError_t autotune(dlx_plan* p) {
 // process, so plans of a shape already seen skip the timing runs.
 using TuneKey = std::array<long long, 12>;
 std::mutex g_tune_mu;
-std::map<TuneKey, std::array<TileShape, 4>> g_tune;
+struct Tuned {
+  std::array<TileShape, 4> tiles;   // F1, F2, B3, B4
+  int b4_ksplit;
+};
+std::map<TuneKey, Tuned> g_tune;
 
 TuneKey tune_key(const dlx_plan* p) {
   int dev = 0;
@@ -396,11 +414,12 @@ hipError_t autotune_cached(dlx_plan* p) {
     std::lock_guard<std::mutex> lock(g_tune_mu);
     auto it = g_tune.find(key);
     if (it != g_tune.end()) {
-      p->ts_f1 = it->second[0];
-      p->ts_f2 = it->second[1];
-      p->ts_b3 = it->second[2];
-      p->ts_b4 = it->second[3];
-      derive_tiles(p);
+      p->ts_f1 = it->second.tiles[0];
+      p->ts_f2 = it->second.tiles[1];
+      p->ts_b3 = it->second.tiles[2];
+      p->ts_b4 = it->second.tiles[3];
+      p->b4_ksplit_tuned = it->second.b4_ksplit;
+      derive_tiles(p, p->b4_ksplit_tuned);
       p->tuned = true;
       return hipSuccess;
     }
@@ -408,7 +427,7 @@ hipError_t autotune_cached(dlx_plan* p) {
   const hipError_t e = autotune(p);
   if (e == hipSuccess) {
     std::lock_guard<std::mutex> lock(g_tune_mu);
-    g_tune[key] = {p->ts_f1, p->ts_f2, p->ts_b3, p->ts_b4};
+    g_tune[key] = Tuned{{p->ts_f1, p->ts_f2, p->ts_b3, p->ts_b4}, p->b4_ksplit_tuned};
   }
   return e;
 }

@@ -134,6 +134,7 @@ struct dlx_plan {
   // tiles
   dlx::TileShape ts_f1, ts_f2, ts_b3, ts_b4;
   int b4_gsize, b4_groups_max, b4_ksplit = 1;
+  int b4_ksplit_tuned = 0;   // B4's K split chosen by the autotuner (0: the heuristic)
   // device memory
   void* pool = nullptr;
   size_t pool_bytes = 0;
