@@ -318,6 +318,28 @@ def main():
                "host_cpus": os.cpu_count()}
         log(f"cpu baseline: {cpu}")
 
+    separate = None
+    if small and not args.no_plain:
+        # the three-call boundary path (forward, loss_grad, backward), recomputing the focal fields in
+        # backward and with them stored by the forward call (DLX_FLAG_STORE_FIELDS); timing only
+        separate = {}
+        for sf in (False, True):
+            q = PsfPlan(geom, dev(w.transmission), dev(w.zbasis), dev(w.map_basis), dev(w.intrapixel),
+                        precision=args.precision, store_fields=sf)
+
+            def calls():
+                B_, m_ = q.forward(c, pm, s, fl)
+                _, r_, _ = q.loss_grad(m_, B_, d, fl, "poisson", w.prior_mu, w.prior_sigma)
+                q.backward(c, pm, s, fl, r_)
+
+            for _ in range(args.warmup):
+                calls()
+            t_sep = timed(calls, args.steps)
+            assert q.sync() == 0
+            q.close()
+            separate["stored_fields" if sf else "recompute"] = round(t_sep * 1e3 / args.steps, 4)
+        log(f"separate calls ms/step: {separate}")
+
     plain = None
     if small and P.n_sources == 1 and P.n_frames == 1 and P.n_map == 0 and not args.no_plain:
         # the plain form: one FP32 plan per PSF (here per wavelength), evaluated one after another on
@@ -361,7 +383,8 @@ def main():
                               "GB/s": round(stage_bytes(P, k) / (v["ms_per_step"] * 1e-3) / 1e9, 1),
                               "frac_of_8TB/s": round(stage_bytes(P, k) / (v["ms_per_step"] * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)}
                           for k, v in table.items() if stage_bytes(P, k)},
-           "roofline": roofline, "rel_err_vs_fp64": parity, "cpu_baseline": cpu, "plain_fp32": plain}
+           "roofline": roofline, "rel_err_vs_fp64": parity, "cpu_baseline": cpu, "plain_fp32": plain,
+           "separate_calls_ms_per_step": separate}
     plan.close()
     print(json.dumps(out), flush=True)
 

@@ -112,7 +112,20 @@ dlx_status dlx_validate(const dlx_problem_desc* probs, int32_t n_probs);
  * operand loader unless a frame's seed weights G exceed 4 MiB, in which case
  * a separate elementwise pass forms it first; DLX_FLAG_SEED_PASS forces the
  * separate pass (same results, bit for bit). */
-enum { DLX_FLAG_NO_AUTOTUNE = 1, DLX_FLAG_SEED_PASS = 2 };
+enum { DLX_FLAG_NO_AUTOTUNE = 1, DLX_FLAG_SEED_PASS = 2, DLX_FLAG_STORE_FIELDS = 4 };
+
+/* DLX_FLAG_STORE_FIELDS keeps the focal fields E of every PSF (and the
+ * per-star binned images) in the plan from one dlx_psf_forward to the next
+ * dlx_psf_backward, which then runs only the adjoint products: 2 MFTs per
+ * PSF for a forward + backward pair instead of 3 (the choice between
+ * recomputing and storing E). The whole problem is then one frame chunk:
+ * the workspace holds every PSF's T, E and U^T (for c3 of the benchmark,
+ * 4096 PSFs of 768^2, about 45 GB); without workspace_limit_bytes the plan
+ * may use up to 80% of the free device memory, and DLX_ERR_OOM is returned
+ * if the problem does not fit. The backward call must receive the same
+ * parameter arrays, unchanged, as the forward call it follows; any other
+ * call on the plan in between (dlx_eval, dlx_graph_launch, another
+ * backward) discards the stored fields and the backward recomputes them. */
 
 /* Create a plan: validates, picks kernel tiles, allocates every workspace on
  * the current device and builds the DFT matrices of each wavelength (FP64

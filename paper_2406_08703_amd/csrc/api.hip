@@ -594,7 +594,7 @@ dlx_status dlx_plan_create(const dlx_problem_desc* probs, int32_t n_probs, dlx_p
   dlx_status v = dlx_validate(probs, n_probs);
   if (v != DLX_OK) return v;
   if (precision != DLX_FP32 && precision != DLX_BF16X3) return DLX_ERR_INVALID_ARG;
-  if ((flags & ~(DLX_FLAG_NO_AUTOTUNE | DLX_FLAG_SEED_PASS)) != 0) return DLX_ERR_INVALID_ARG;
+  if ((flags & ~(DLX_FLAG_NO_AUTOTUNE | DLX_FLAG_SEED_PASS | DLX_FLAG_STORE_FIELDS)) != 0) return DLX_ERR_INVALID_ARG;
   if (n_probs > 1) return create_multi(probs, n_probs, precision, flags, workspace_limit_bytes, out);
   const dlx_problem_desc& d = probs[0];
 
@@ -633,8 +633,17 @@ dlx_status dlx_plan_create(const dlx_problem_desc* probs, int32_t n_probs, dlx_p
   p->ldNo = round_up(p->No, 16);
   p->n_psf = p->F * p->S * p->L;
 
-  // chunk of whole frames whose intermediates fit the budget
+  // chunk of whole frames whose intermediates fit the budget (stored fields: every frame in one chunk)
+  p->store_fields = (flags & DLX_FLAG_STORE_FIELDS) != 0;
   size_t budget = workspace_limit_bytes ? workspace_limit_bytes : kDefaultChunkBudget;
+  if (p->store_fields && !workspace_limit_bytes) {
+    size_t free_b = 0, total_b = 0;
+    if (hipMemGetInfo(&free_b, &total_b) != hipSuccess) {
+      delete p;
+      return DLX_ERR_HIP;
+    }
+    budget = free_b / 10 * 8;
+  }
   const size_t psf_bytes = per_psf_bytes(p);
   const size_t frame_bytes = psf_bytes * p->S * p->L + per_frame_bytes(p);
   const size_t fixed = sizeof(float) * 2 * (size_t)p->L *
@@ -647,6 +656,10 @@ dlx_status dlx_plan_create(const dlx_problem_desc* probs, int32_t n_probs, dlx_p
     budget -= fixed;
   }
   p->frames_per_chunk = (int)std::max<size_t>(1, std::min<size_t>(p->F, budget / frame_bytes));
+  if (p->store_fields && p->frames_per_chunk < p->F) {
+    delete p;
+    return DLX_ERR_OOM;
+  }
   p->n_chunks = ceil_div(p->F, p->frames_per_chunk);
   p->chunk_psf = p->frames_per_chunk * p->S * p->L;
 
@@ -912,6 +925,7 @@ dlx_status dlx_psf_forward(dlx_plan* p, const float* transmission, const float* 
       DLX_HIP(launch_intensity(p, f0, nf, sources, intrapixel, flat, binned_out, model_out, st));
     }
   }
+  p->fields_valid = p->store_fields;   // one chunk: E, the pupil pieces and the binned images stay
   return DLX_OK;
 }
 
@@ -962,7 +976,11 @@ dlx_status dlx_psf_backward(dlx_plan* p, const float* transmission, const float*
       (p->Nmap > 0) != (grad_map != nullptr))
     return DLX_ERR_INVALID_ARG;
   hipStream_t st = reinterpret_cast<hipStream_t>(stream);
-  {
+  // stored fields: the preceding forward left the pupil pieces, E and the per-star binned
+  // images of every PSF in the workspace (one chunk); only the adjoint runs
+  const bool reuse = p->store_fields && p->fields_valid;
+  p->fields_valid = false;
+  if (!reuse) {
     Stage sg(p, st, DLX_STAGE_PREP, p->n_psf);
     DLX_HIP(launch_prep(p, transmission, zernike_basis, map_basis, zernike_coeffs, phase_map, sources, st));
   }
@@ -970,17 +988,19 @@ dlx_status dlx_psf_backward(dlx_plan* p, const float* transmission, const float*
     const int f0 = c * p->frames_per_chunk;
     const int nf = std::min(p->frames_per_chunk, p->F - f0);
     const int nc = nf * p->S * p->L;
-    {
-      Stage sg(p, st, DLX_STAGE_F1, nc);
-      DLX_HIP(run_f1(p, f0, nf, st));
-    }
-    {
-      Stage sg(p, st, DLX_STAGE_F2, nc);
-      DLX_HIP(run_f2(p, f0, nf, st));
-    }
-    {  // per-source binned images only (for the flux gradient)
-      Stage sg(p, st, DLX_STAGE_BIN, nc);
-      DLX_HIP(launch_intensity(p, f0, nf, sources, intrapixel, flat, nullptr, nullptr, st));
+    if (!reuse) {
+      {
+        Stage sg(p, st, DLX_STAGE_F1, nc);
+        DLX_HIP(run_f1(p, f0, nf, st));
+      }
+      {
+        Stage sg(p, st, DLX_STAGE_F2, nc);
+        DLX_HIP(run_f2(p, f0, nf, st));
+      }
+      {  // per-source binned images only (for the flux gradient)
+        Stage sg(p, st, DLX_STAGE_BIN, nc);
+        DLX_HIP(launch_intensity(p, f0, nf, sources, intrapixel, flat, nullptr, nullptr, st));
+      }
     }
     {
       Stage sg(p, st, DLX_STAGE_SEED, nc);
@@ -1046,6 +1066,7 @@ dlx_status dlx_eval(dlx_plan* p, const dlx_eval_args* a, void* stream) {
   if (!(a->prior_sigma > 0.0) || !std::isfinite(a->prior_sigma) || !std::isfinite(a->prior_mu))
     return DLX_ERR_INVALID_ARG;
   hipStream_t st = reinterpret_cast<hipStream_t>(stream);
+  p->fields_valid = false;
   {
     Stage sg(p, st, DLX_STAGE_PREP, p->n_psf);
     DLX_HIP(launch_prep(p, a->transmission, a->zernike_basis, a->map_basis, a->zernike_coeffs, a->phase_map,
@@ -1138,6 +1159,8 @@ dlx_status dlx_graph_capture(dlx_plan* p, const dlx_eval_args* a) {
 
 dlx_status dlx_graph_launch(dlx_plan* p, void* stream) {
   if (!p || !p->graph_exec) return DLX_ERR_INVALID_ARG;
+  p->fields_valid = false;   // the replay overwrites the workspace
+  for (dlx_plan* sub : p->subs) sub->fields_valid = false;
   DLX_HIP(hipGraphLaunch(p->graph_exec, reinterpret_cast<hipStream_t>(stream)));
   return DLX_OK;
 }

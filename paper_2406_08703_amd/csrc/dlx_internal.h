@@ -182,6 +182,8 @@ struct dlx_plan {
   int tiles_b4_cap = 0, ksplit_cap = 1;   // sizes the partial-sum buffers
   float* d_tune = nullptr;
   bool tuned = false;
+  bool store_fields = false;  // keep E and the per-star binned images from forward to backward
+  bool fields_valid = false;  // the workspace holds the fields of the last dlx_psf_forward
   // captured evaluation
   hipStream_t cap_stream = nullptr;
   hipGraph_t graph = nullptr;

@@ -62,12 +62,15 @@ class PsfPlan:
     """A libdlx plan plus the static inputs of one problem.
 
     Static inputs (transmission, Zernike basis, bicubic matrix, intra-pixel
-    kernel) are bound once; parameters are passed per call.
+    kernel) are bound once; parameters are passed per call. ``store_fields``
+    keeps every PSF's focal field from ``forward`` to the next ``backward``
+    (which must get the same parameters), so that pair costs two MFTs per PSF
+    instead of three, at the price of holding all PSFs in the workspace.
     """
 
     def __init__(self, geom: Geometry, transmission, zbasis, map_basis=None, intrapixel=None,
                  precision: str = "fp32", workspace_limit: int = 0, device="cuda", autotune: bool = True,
-                 seed_pass: bool = False):
+                 seed_pass: bool = False, store_fields: bool = False):
         if not torch.cuda.is_available():
             raise RuntimeError("libdlx needs a ROCm GPU")
         self.geom = geom
@@ -83,7 +86,8 @@ class PsfPlan:
                                         g.dithers, g.margin)
         prec = {"fp32": _c.DLX_FP32, "bf16x3": _c.DLX_BF16X3}[precision]
         with torch.cuda.device(self.device):
-            flags = (0 if autotune else _c.DLX_FLAG_NO_AUTOTUNE) | (_c.DLX_FLAG_SEED_PASS if seed_pass else 0)
+            flags = ((0 if autotune else _c.DLX_FLAG_NO_AUTOTUNE) | (_c.DLX_FLAG_SEED_PASS if seed_pass else 0)
+                     | (_c.DLX_FLAG_STORE_FIELDS if store_fields else 0))
             self.plan = _c.dlx_plan_create(desc, 1, prec, flags, int(workspace_limit))
         self.precision = precision
 
