@@ -134,8 +134,8 @@ enum { DLX_FLAG_NO_AUTOTUNE = 1, DLX_FLAG_SEED_PASS = 2, DLX_FLAG_STORE_FIELDS =
  * uneven size): every per-call array of dlx_psf_forward / dlx_loss_grad /
  * dlx_psf_backward / dlx_eval then packs the problems' arrays one after the
  * other, problem k starting at the element offsets dlx_plan_offsets reports
- * (loss_out holds one loss per problem). flags: an OR of DLX_FLAG_NO_AUTOTUNE
- * and DLX_FLAG_SEED_PASS (other bits: DLX_ERR_INVALID_ARG). Results do not depend on the tiles chosen
+ * (loss_out holds one loss per problem). flags: an OR of DLX_FLAG_NO_AUTOTUNE,
+ * DLX_FLAG_SEED_PASS and DLX_FLAG_STORE_FIELDS (other bits: DLX_ERR_INVALID_ARG). Results do not depend on the tiles chosen
  * except for the order of FP32/FP64 partial sums in the gradient
  * reductions. workspace_limit_bytes: 0 = no limit;
  * otherwise the frame-chunk size is reduced until the workspace fits, and
@@ -219,8 +219,9 @@ dlx_status dlx_loss_grad(dlx_plan* plan, const float* model, const float* binned
 
 /* Gradient through the optics given r = dL/dm (Sections 3-4). The inputs are
  * those of dlx_psf_forward; the focal fields are recomputed (one chunk of
- * frames at a time in the plan's workspace), nothing from the forward call
- * is kept.
+ * frames at a time in the plan's workspace), unless the plan was created with
+ * DLX_FLAG_STORE_FIELDS and this call directly follows dlx_psf_forward with
+ * the same inputs, in which case that call's fields are used.
  * Outputs (double, FP64-reduced):
  *   grad_zernike [Nz]              dL/dc
  *   grad_map [n_map][n_map]        dL/dC (NULL iff n_map == 0)

@@ -303,7 +303,7 @@ class BatchPlan:
                "intrapixel", "images", "loss")
 
     def __init__(self, geoms, transmissions, zbases, map_bases=None, intrapixels=None, precision: str = "fp32",
-                 workspace_limit: int = 0, device="cuda", autotune: bool = True):
+                 workspace_limit: int = 0, device="cuda", autotune: bool = True, store_fields: bool = False):
         if not torch.cuda.is_available():
             raise RuntimeError("libdlx needs a ROCm GPU")
         self.geoms = list(geoms)
@@ -321,7 +321,7 @@ class BatchPlan:
             self._keep.append(keep)
         prec = {"fp32": _c.DLX_FP32, "bf16x3": _c.DLX_BF16X3}[precision]
         with torch.cuda.device(self.device):
-            flags = 0 if autotune else _c.DLX_FLAG_NO_AUTOTUNE
+            flags = (0 if autotune else _c.DLX_FLAG_NO_AUTOTUNE) | (_c.DLX_FLAG_STORE_FIELDS if store_fields else 0)
             self.plan = _c.dlx_plan_create(descs, n, prec, flags, int(workspace_limit))
         self.precision = precision
         self.offsets = [_c.dlx_plan_offsets(self.plan, k) for k in range(_c.dlx_plan_problems(self.plan))]
