@@ -8,5 +8,5 @@ from .psf import (  # noqa: F401
     OracleProblem, pixel_grid, dft_matrix, focal_field, focal_field_adjoint, opd_map, pupil_field,
     bin_detector, expand_detector, forward, loss_grad, backward, value_and_grad, binned_pixels,
     dither_windows, forward_dithered, backward_dithered, value_and_grad_dithered, intrapixel_grad,
-    intrapixel_grad_dithered,
+    intrapixel_grad_dithered, kernel_on_focal_grid,
 )

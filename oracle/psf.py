@@ -63,7 +63,7 @@ class OracleProblem:
     transmission: np.ndarray          # [Ni, Ni]
     zbasis: np.ndarray                # [Nz, Ni, Ni]
     map_basis: np.ndarray | None = None   # [Ni, n_map]
-    intrapixel: np.ndarray | None = None  # [Q, Q]
+    intrapixel: np.ndarray | None = None  # [Q, Q] shared by every pixel, or [Nd, Nd, Q, Q] per pixel
     phase_screen: np.ndarray | None = None  # [Ni, Ni] static achromatic phase, radians
 
     @staticmethod
@@ -130,19 +130,28 @@ def pupil_field(transmission, opd, x, y, alpha, beta, lam, screen=None):
     return amp * np.exp(1j * phase)
 
 
+def kernel_on_focal_grid(K, n, Q):
+    """The intra-pixel kernel laid on the focal grid: K[a, b] at sample (Qp + a, Qq + b) of every pixel
+    (p, q) for a shared kernel [Q, Q], or K[p, q, a, b] for one kernel per pixel [n, n, Q, Q]."""
+    K = np.asarray(K, np.float64)
+    if K.ndim == 2:
+        return np.tile(K, (n, n))
+    return K.transpose(0, 2, 1, 3).reshape(n * Q, n * Q)
+
+
 def bin_detector(I, Q, K=None):
-    """B[p, q] = sum_{a,b<Q} K[a, b] I[Qp+a, Qq+b] (K = 1 if None)."""
+    """B[p, q] = sum_{a,b<Q} K[a, b] I[Qp+a, Qq+b] (K = 1 if None; K[p, q, a, b] if per pixel)."""
     n = I.shape[-1] // Q
     if K is not None:
-        I = I * np.tile(K, (n, n))
+        I = I * kernel_on_focal_grid(K, n, Q)
     return I.reshape(n, Q, n, Q).sum(axis=(1, 3))
 
 
 def expand_detector(G, Q, K=None):
-    """Adjoint of ``bin_detector``: G[k, l] = K[k%Q, l%Q] * g[k//Q, l//Q]."""
+    """Adjoint of ``bin_detector``: G[k, l] = K[k%Q, l%Q] * g[k//Q, l//Q] (per pixel: K[k//Q, l//Q, ...])."""
     out = np.kron(G, np.ones((Q, Q)))
     if K is not None:
-        out = out * np.tile(K, G.shape)
+        out = out * kernel_on_focal_grid(K, G.shape[0], Q)
     return out
 
 
@@ -253,11 +262,13 @@ def backward(prob: OracleProblem, coeffs, phase_map, sources, flat, r):
 
 
 def intrapixel_grad(prob: OracleProblem, coeffs, phase_map, sources, flat, r):
-    """dL/dK [Q, Q] of the intra-pixel kernel (Section 6 names fitting it as future work).
+    """dL/dK of the intra-pixel kernel (Section 6: recovering intra-pixel sensitivity).
 
     B_f[p] = sum_ab K[a, b] I_f[Qp + (a, b)] is linear in K, so
     dL/dK[a, b] = sum_f sum_p flat[p] r_f[p] I_f[Qp + (a, b)], with I_f the
-    unbinned focal intensity sum_s sum_lambda w phi |E|^2 (recomputed here).
+    unbinned focal intensity sum_s sum_lambda w phi |E|^2 (recomputed here):
+    [Q, Q] for a shared kernel. With one kernel per pixel (prob.intrapixel
+    [Nd, Nd, Q, Q]) the sum over p is dropped: [Nd, Nd, Q, Q].
     """
     sources = np.asarray(sources, np.float64)
     flat = np.asarray(flat, np.float64)
@@ -267,7 +278,9 @@ def intrapixel_grad(prob: OracleProblem, coeffs, phase_map, sources, flat, r):
     F, S = sources.shape[:2]
     Q = prob.oversample
     No = prob.n_focal
-    g = np.zeros((Q, Q))
+    per_pixel = prob.intrapixel is not None and np.ndim(prob.intrapixel) == 4
+    n = prob.n_det
+    g = np.zeros((n, n, Q, Q) if per_pixel else (Q, Q))
     for f in range(F):
         I = np.zeros((No, No))
         for s in range(S):
@@ -276,7 +289,8 @@ def intrapixel_grad(prob: OracleProblem, coeffs, phase_map, sources, flat, r):
                 _, E, _ = _psf_field(prob, opd, x, u, a, b, lam)
                 I += w * phi * np.abs(E) ** 2
         h = flat * r[f]
-        g += (np.kron(h, np.ones((Q, Q))) * I).reshape(prob.n_det, Q, prob.n_det, Q).sum(axis=(0, 2))
+        v = (np.kron(h, np.ones((Q, Q))) * I).reshape(n, Q, n, Q)
+        g += v.transpose(0, 2, 1, 3) if per_pixel else v.sum(axis=(0, 2))
     return g
 
 
@@ -300,7 +314,7 @@ def binned_pixels(prob: OracleProblem, coeffs, phase_map, sources, frame, pixels
     x, u = _grids(prob)
     opd = opd_map(prob.zbasis, coeffs, prob.map_basis, phase_map)
     Q = prob.oversample
-    K = prob.intrapixel if prob.intrapixel is not None else np.ones((Q, Q))
+    Kf = kernel_on_focal_grid(prob.intrapixel if prob.intrapixel is not None else np.ones((Q, Q)), prob.n_det, Q)
     out = np.zeros(len(pixels))
     for s in range(sources.shape[1]):
         a, b, phi = sources[frame, s]
@@ -310,7 +324,7 @@ def binned_pixels(prob: OracleProblem, coeffs, phase_map, sources, frame, pixels
                 rows = u[Q * p:Q * p + Q]
                 cols = u[Q * q:Q * q + Q]
                 E = focal_field(P, x, x, cols, rows, lam, prob.dx * prob.focal_pixel / lam)
-                out[i] += w * phi * np.sum(K * np.abs(E) ** 2)
+                out[i] += w * phi * np.sum(Kf[Q * p:Q * p + Q, Q * q:Q * q + Q] * np.abs(E) ** 2)
     return out
 
 

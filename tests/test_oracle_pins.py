@@ -582,3 +582,72 @@ def test_fresnel_defocus_basis_matches_angular_spectrum_propagation():
         assert np.max(np.abs(delta * B)) > 0.2 * lam          # a visible defocus, not a no-op
         assert rel_l2(Ed, Ep) < 1e-5   # FP32 basis values
         assert rel_l2(np.abs(Ed) ** 2, np.abs(E0) ** 2) > 0.1
+
+
+# --------------------------------------------------------------------------- one intra-pixel kernel per pixel
+def test_kernel_on_focal_grid_layout_brute_force():
+    rng = np.random.default_rng(5)
+    n, Q = 3, 4
+    K = rng.normal(size=(n, n, Q, Q))
+    want = np.zeros((n * Q, n * Q))
+    for p in range(n):
+        for q in range(n):
+            for a in range(Q):
+                for b in range(Q):
+                    want[Q * p + a, Q * q + b] = K[p, q, a, b]
+    assert np.array_equal(O.kernel_on_focal_grid(K, n, Q), want)
+    Ks = rng.normal(size=(Q, Q))
+    assert np.array_equal(O.kernel_on_focal_grid(np.broadcast_to(Ks, (n, n, Q, Q)), n, Q),
+                          O.kernel_on_focal_grid(Ks, n, Q))
+
+
+def _per_pixel_case():
+    import dataclasses
+    w, prob = _setup_small("c3", **SMALL["c3"])
+    n, Q = prob.n_det, prob.oversample
+    rng = np.random.default_rng(17)
+    Kp = np.asarray(prob.intrapixel)[None, None] * (1 + 0.02 * rng.normal(size=(n, n, Q, Q)))
+    return w, prob, dataclasses.replace(prob, intrapixel=Kp), Kp
+
+
+def test_per_pixel_kernel_equal_everywhere_reduces_to_the_shared_kernel():
+    import dataclasses
+    w, prob, _, _ = _per_pixel_case()
+    n, Q = prob.n_det, prob.oversample
+    same = dataclasses.replace(prob, intrapixel=np.broadcast_to(prob.intrapixel, (n, n, Q, Q)).copy())
+    p = w.eval_params()
+    a = O.value_and_grad(prob, p["coeffs"], None, p["sources"], p["flat"], w.data, "poisson", w.prior_mu,
+                         w.prior_sigma)
+    b = O.value_and_grad(same, p["coeffs"], None, p["sources"], p["flat"], w.data, "poisson", w.prior_mu,
+                         w.prior_sigma)
+    for k in ("binned", "grad_flat", "grad_coeffs", "grad_sources"):
+        assert rel_l2(b[k], a[k]) < 1e-13, k
+    gs = O.intrapixel_grad(prob, p["coeffs"], None, p["sources"], p["flat"], a["r"])
+    gp = O.intrapixel_grad(same, p["coeffs"], None, p["sources"], p["flat"], a["r"])
+    assert gp.shape == (n, n, Q, Q)
+    assert rel_l2(gp.sum(axis=(0, 1)), gs) < 1e-13
+
+
+def test_per_pixel_kernel_gradient_central_differences_and_euler():
+    w, _, prob, Kp = _per_pixel_case()
+    p = w.eval_params()
+    base = O.value_and_grad(prob, p["coeffs"], None, p["sources"], p["flat"], w.data, "poisson", w.prior_mu,
+                            w.prior_sigma)
+    g = O.intrapixel_grad(prob, p["coeffs"], None, p["sources"], p["flat"], base["r"])
+
+    def loss_at(K):
+        pr = O.OracleProblem(**{**prob.__dict__, "intrapixel": K})
+        B, m = O.forward(pr, p["coeffs"], None, p["sources"], p["flat"])
+        return O.loss_grad(m, B, w.data, p["flat"], "poisson", w.prior_mu, w.prior_sigma)[0]
+
+    n, Q = prob.n_det, prob.oversample
+    peak = np.unravel_index(np.argmax(np.abs(g)), g.shape)
+    for idx in [peak, (n // 2, n // 3, 0, Q - 1), (1, n - 2, Q - 1, 1)]:
+        def fk(t, idx=idx):
+            K = Kp.copy()
+            K[idx] = t
+            return loss_at(K)
+        fd = _fd(fk, Kp[idx], 1e-4)
+        assert abs(fd - g[idx]) <= 1e-6 * max(abs(g[idx]), 1e-3 * np.abs(g).max()), idx
+    euler = np.sum(np.asarray(p["flat"], np.float64)[None] * base["r"] * base["binned"])
+    assert abs(np.sum(Kp * g) - euler) <= 1e-10 * np.sum(np.abs(Kp * g))
