@@ -112,7 +112,15 @@ dlx_status dlx_validate(const dlx_problem_desc* probs, int32_t n_probs);
  * operand loader unless a frame's seed weights G exceed 4 MiB, in which case
  * a separate elementwise pass forms it first; DLX_FLAG_SEED_PASS forces the
  * separate pass (same results, bit for bit). */
-enum { DLX_FLAG_NO_AUTOTUNE = 1, DLX_FLAG_SEED_PASS = 2, DLX_FLAG_STORE_FIELDS = 4 };
+enum { DLX_FLAG_NO_AUTOTUNE = 1, DLX_FLAG_SEED_PASS = 2, DLX_FLAG_STORE_FIELDS = 4, DLX_FLAG_PIXEL_KERNEL = 8 };
+
+/* DLX_FLAG_PIXEL_KERNEL gives every detector pixel its own intra-pixel kernel
+ * (Section 6: intra-pixel sensitivity, recoverable at this sampling): every
+ * `intrapixel` argument is then [Nd][Nd][Q][Q] (pixel p's kernel K_p[a][b])
+ * and `grad_intrapixel` receives dL/dK_p[a][b] as [Nd][Nd][Q][Q] (FP64, Q <= 4),
+ * the per-pixel terms of the shared kernel's gradient. Not available in
+ * integer-dither mode (DLX_ERR_UNSUPPORTED at plan creation), where one
+ * binned plane serves frames whose pixels see it through different windows. */
 
 /* DLX_FLAG_STORE_FIELDS keeps the focal fields E of every PSF (and the
  * per-star binned images) in the plan from one dlx_psf_forward to the next
@@ -135,7 +143,8 @@ enum { DLX_FLAG_NO_AUTOTUNE = 1, DLX_FLAG_SEED_PASS = 2, DLX_FLAG_STORE_FIELDS =
  * dlx_psf_backward / dlx_eval then packs the problems' arrays one after the
  * other, problem k starting at the element offsets dlx_plan_offsets reports
  * (loss_out holds one loss per problem). flags: an OR of DLX_FLAG_NO_AUTOTUNE,
- * DLX_FLAG_SEED_PASS and DLX_FLAG_STORE_FIELDS (other bits: DLX_ERR_INVALID_ARG). Results do not depend on the tiles chosen
+ * DLX_FLAG_SEED_PASS, DLX_FLAG_STORE_FIELDS and DLX_FLAG_PIXEL_KERNEL (other bits:
+ * DLX_ERR_INVALID_ARG). Results do not depend on the tiles chosen
  * except for the order of FP32/FP64 partial sums in the gradient
  * reductions. workspace_limit_bytes: 0 = no limit;
  * otherwise the frame-chunk size is reduced until the workspace fits, and
@@ -155,7 +164,7 @@ size_t dlx_plan_workspace_bytes(const dlx_plan* plan);
  * transmission Ni^2, zernike_basis Nz Ni^2, map_basis Ni n_map,
  * zernike_coeffs / grad_zernike Nz, phase_map / grad_map n_map^2,
  * sources / grad_sources 3 F S (3 S in integer-dither mode), flat /
- * grad_flat Nd^2, intrapixel Q^2,
+ * grad_flat Nd^2, intrapixel Q^2 (Nd^2 Q^2 with DLX_FLAG_PIXEL_KERNEL),
  * images (data, binned, model, dloss_dmodel) F Nd^2, loss 1. */
 typedef struct {
   int64_t transmission, zernike_basis, map_basis, zernike_coeffs, phase_map, sources, flat, intrapixel, images,
@@ -199,6 +208,7 @@ dlx_status dlx_plan_sync(dlx_plan* plan, void* stream);
  *                                integer-dither mode (positions of frame 0)
  *   flat [Nd][Nd]                pixel response F
  *   intrapixel [Q][Q]            intra-pixel kernel K, NULL = all ones
+ *                                ([Nd][Nd][Q][Q] with DLX_FLAG_PIXEL_KERNEL)
  * Outputs (may not alias inputs):
  *   binned_out [F][Nd][Nd]       B_f = bin_Q(K * sum_s sum_l w_l phi_s |E|^2)
  *   model_out  [F][Nd][Nd]       m_f = F * B_f */
@@ -227,7 +237,8 @@ dlx_status dlx_loss_grad(dlx_plan* plan, const float* model, const float* binned
  *   grad_map [n_map][n_map]        dL/dC (NULL iff n_map == 0)
  *   grad_sources [F][S][3]         dL/dalpha, dL/dbeta, dL/dphi per frame and star
  *                                  ([S][3], summed over frames, in integer-dither mode)
- *   grad_intrapixel [Q][Q]         dL/dK of the intra-pixel kernel (fitting it is the
+ *   grad_intrapixel [Q][Q]         dL/dK of the intra-pixel kernel, [Nd][Nd][Q][Q] with
+ *                                  DLX_FLAG_PIXEL_KERNEL (fitting it is the
  *                                  extension Section 6 proposes); NULL = not computed.
  *                                  Needs Q <= 4 (else DLX_ERR_UNSUPPORTED). */
 dlx_status dlx_psf_backward(dlx_plan* plan, const float* transmission, const float* zernike_basis,

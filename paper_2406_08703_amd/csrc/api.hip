@@ -33,7 +33,7 @@ hipError_t launch_loss_final(dlx_plan* p, int n_chunks, double* loss, hipStream_
 hipError_t launch_grad_reduce(dlx_plan* p, const float* Z, const float* Bm, double* gz, double* gmap, double* gsrc,
                               double* loss, int loss_chunks, double* gK, hipStream_t st);
 hipError_t launch_kgrad(dlx_plan* p, int f0, int nf, const float* sources, const float* flat, const float* resid,
-                        hipStream_t st);
+                        double* gK, hipStream_t st);
 int loss_block_count(long long npix);
 int seed_block_count(long long npix);
 int zproj_chunks(long long npix, int Nz);
@@ -479,7 +479,7 @@ dlx_status create_multi(const dlx_problem_desc* probs, int32_t n, dlx_precision 
     o.phase_map += (long long)d.n_map * d.n_map;
     o.sources += 3LL * (d.frame_dithers ? 1 : d.n_frames) * d.n_sources;
     o.flat += nd * nd;
-    o.intrapixel += (long long)d.oversample * d.oversample;
+    o.intrapixel += (long long)d.oversample * d.oversample * ((flags & DLX_FLAG_PIXEL_KERNEL) ? nd * nd : 1);
     o.images += (long long)d.n_frames * nd * nd;
     o.loss += 1;
   }
@@ -594,7 +594,8 @@ dlx_status dlx_plan_create(const dlx_problem_desc* probs, int32_t n_probs, dlx_p
   dlx_status v = dlx_validate(probs, n_probs);
   if (v != DLX_OK) return v;
   if (precision != DLX_FP32 && precision != DLX_BF16X3) return DLX_ERR_INVALID_ARG;
-  if ((flags & ~(DLX_FLAG_NO_AUTOTUNE | DLX_FLAG_SEED_PASS | DLX_FLAG_STORE_FIELDS)) != 0) return DLX_ERR_INVALID_ARG;
+  if ((flags & ~(DLX_FLAG_NO_AUTOTUNE | DLX_FLAG_SEED_PASS | DLX_FLAG_STORE_FIELDS | DLX_FLAG_PIXEL_KERNEL)) != 0)
+    return DLX_ERR_INVALID_ARG;
   if (n_probs > 1) return create_multi(probs, n_probs, precision, flags, workspace_limit_bytes, out);
   const dlx_problem_desc& d = probs[0];
 
@@ -635,6 +636,11 @@ dlx_status dlx_plan_create(const dlx_problem_desc* probs, int32_t n_probs, dlx_p
 
   // chunk of whole frames whose intermediates fit the budget (stored fields: every frame in one chunk)
   p->store_fields = (flags & DLX_FLAG_STORE_FIELDS) != 0;
+  p->k_per_pixel = (flags & DLX_FLAG_PIXEL_KERNEL) != 0;
+  if (p->k_per_pixel && p->dither) {   // the windows would need a frame-dependent binning
+    delete p;
+    return DLX_ERR_UNSUPPORTED;
+  }
   size_t budget = workspace_limit_bytes ? workspace_limit_bytes : kDefaultChunkBudget;
   if (p->store_fields && !workspace_limit_bytes) {
     size_t free_b = 0, total_b = 0;
@@ -1008,7 +1014,7 @@ dlx_status dlx_psf_backward(dlx_plan* p, const float* transmission, const float*
         DLX_HIP(launch_seed_gather(p, flat, dloss_dmodel, intrapixel, st));
       else
         DLX_HIP(launch_seed(p, f0, nf, flat, dloss_dmodel, intrapixel, st));
-      if (grad_intrapixel) DLX_HIP(launch_kgrad(p, f0, nf, sources, flat, dloss_dmodel, st));   // reads E
+      if (grad_intrapixel) DLX_HIP(launch_kgrad(p, f0, nf, sources, flat, dloss_dmodel, grad_intrapixel, st));
       if (p->seed_pass) DLX_HIP(launch_seed_apply(p, f0, nf, sources, st));
     }
     DLX_HIP(run_adjoint(p, c, f0, nf, sources, st));
@@ -1097,7 +1103,7 @@ dlx_status dlx_eval(dlx_plan* p, const dlx_eval_args* a, void* stream) {
       }
       Stage sg(p, st, DLX_STAGE_SEED, nc);
       DLX_HIP(launch_seed_gather(p, a->flat, a->dloss_dmodel, a->intrapixel, st));
-      if (a->grad_intrapixel) DLX_HIP(launch_kgrad(p, f0, nf, a->sources, a->flat, a->dloss_dmodel, st));
+      if (a->grad_intrapixel) DLX_HIP(launch_kgrad(p, f0, nf, a->sources, a->flat, a->dloss_dmodel, a->grad_intrapixel, st));
       if (p->seed_pass) DLX_HIP(launch_seed_apply(p, f0, nf, a->sources, st));
     } else {
       {
@@ -1111,7 +1117,7 @@ dlx_status dlx_eval(dlx_plan* p, const dlx_eval_args* a, void* stream) {
       }
       if (a->grad_intrapixel || p->seed_pass) {
         Stage sg(p, st, DLX_STAGE_SEED, nc);
-        if (a->grad_intrapixel) DLX_HIP(launch_kgrad(p, f0, nf, a->sources, a->flat, a->dloss_dmodel, st));
+        if (a->grad_intrapixel) DLX_HIP(launch_kgrad(p, f0, nf, a->sources, a->flat, a->dloss_dmodel, a->grad_intrapixel, st));
         if (p->seed_pass) DLX_HIP(launch_seed_apply(p, f0, nf, a->sources, st));
       }
     }

@@ -182,6 +182,7 @@ struct dlx_plan {
   int tiles_b4_cap = 0, ksplit_cap = 1;   // sizes the partial-sum buffers
   float* d_tune = nullptr;
   bool tuned = false;
+  bool k_per_pixel = false;   // one intra-pixel kernel per detector pixel ([Nd][Nd][Q][Q])
   bool store_fields = false;  // keep E and the per-star binned images from forward to backward
   bool fields_valid = false;  // the workspace holds the fields of the last dlx_psf_forward
   // captured evaluation

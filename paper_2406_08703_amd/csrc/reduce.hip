@@ -21,10 +21,13 @@ namespace {
 // pixel's rows).
 constexpr int kLanes = 8;
 
+// element stride of the intra-pixel kernel between detector pixels: 0 (one kernel) or Q^2 (one per pixel)
+long long kstride(const dlx_plan* p) { return p->k_per_pixel ? (long long)p->Q * p->Q : 0; }
+
 template <int QT>
 __global__ void intensity_kernel(const float* E, long long plane, long long by_psf, int ld, int f0, int F, int S, int L,
                                  int Qr, int Nd, const float* sources, const WlInfo* wl, const float* intrapixel,
-                                 const float* flat, float* bs, float* binned, float* model) {
+                                 long long kst, const float* flat, float* bs, float* binned, float* model) {
   __shared__ double sh[kLanes][64];
   const int Q = QT > 0 ? QT : Qr;
   const long long npix = (long long)Nd * Nd;
@@ -33,6 +36,8 @@ __global__ void intensity_kernel(const float* E, long long plane, long long by_p
   const int y = threadIdx.y;
   const bool live = p < npix && f < F;
   const int pr = live ? (int)(p / Nd) : 0, pc = live ? (int)(p - (long long)pr * Nd) : 0;
+  // the intra-pixel kernel of this pixel: shared (kst = 0) or one per pixel (kst = Q^2)
+  const float* kp = intrapixel ? intrapixel + (live ? p : 0) * kst : nullptr;
   double total = 0.0;
   for (int s = 0; s < S; ++s) {
     double acc = 0.0;
@@ -50,7 +55,7 @@ __global__ void intensity_kernel(const float* E, long long plane, long long by_p
 #pragma unroll
             for (int b = 0; b < QT; ++b) {
               float v = vr[b] * vr[b] + vi[b] * vi[b];
-              if (intrapixel) v *= intrapixel[a * QT + b];
+              if (kp) v *= kp[a * QT + b];
               part += v;
             }
           }
@@ -59,7 +64,7 @@ __global__ void intensity_kernel(const float* E, long long plane, long long by_p
             for (int b = 0; b < Q; ++b) {
               const float er = e[(long long)a * ld + b], ei = e[plane + (long long)a * ld + b];
               float v = er * er + ei * ei;
-              if (intrapixel) v *= intrapixel[a * Q + b];
+              if (kp) v *= kp[a * Q + b];
               part += v;
             }
         }
@@ -103,6 +108,7 @@ __device__ __forceinline__ double block_sum(double v, double* sh) {
 // evaluation): seed weights G and flux partials, as seed_weight_kernel below.
 struct SeedOut {
   const float* intrapixel;
+  long long kst;          // 0: one kernel for all pixels, Q^2: one per pixel
   const float* bs;        // per-source binned [nf][S][npix]
   int Q, Nd, S, ldg;
   long long g_by_frame;
@@ -161,7 +167,7 @@ __global__ void loss_kernel(const float* model, const float* binned, const float
         float* g = so.G + fl * so.g_by_frame + (long long)(so.Q * pr) * so.ldg + so.Q * pc;
         for (int a = 0; a < so.Q; ++a)
           for (int b = 0; b < so.Q; ++b)
-            g[(long long)a * so.ldg + b] = so.intrapixel ? h * so.intrapixel[a * so.Q + b] : h;
+            g[(long long)a * so.ldg + b] = so.intrapixel ? h * so.intrapixel[p * so.kst + a * so.Q + b] : h;
       }
       for (int s = 0; s < so.S; ++s) {
         const double v = live ? (double)h * (double)so.bs[((long long)fl * so.S + s) * npix + p] : 0.0;
@@ -201,9 +207,9 @@ constexpr int kSeedThreads = 256;
 // (the B3 loader forms Y = w_l phi_s G E from it), and the flux gradient
 // partials sum_p flat[p] r_f[p] bs[f][s][p] = sum_l w_l sum G |E_{f,s,l}|^2 per
 // (frame, source) and pixel block, at flux[(f S + s) nblk + block].
-__global__ void seed_weight_kernel(const float* resid, const float* flat, const float* intrapixel, const float* bs,
-                                   int f0, int Q, int Nd, int S, int ldg, long long g_by_frame, float* G, int nblk,
-                                   double* flux) {
+__global__ void seed_weight_kernel(const float* resid, const float* flat, const float* intrapixel, long long kst,
+                                   const float* bs, int f0, int Q, int Nd, int S, int ldg, long long g_by_frame,
+                                   float* G, int nblk, double* flux) {
   __shared__ double sh[kSeedThreads / 64];
   const long long npix = (long long)Nd * Nd;
   const long long p = (long long)blockIdx.x * kSeedThreads + threadIdx.x;
@@ -215,7 +221,7 @@ __global__ void seed_weight_kernel(const float* resid, const float* flat, const 
     h = flat[p] * resid[(long long)f * npix + p];
     float* g = G + fl * g_by_frame + (long long)(Q * pr) * ldg + Q * pc;
     for (int a = 0; a < Q; ++a)
-      for (int b = 0; b < Q; ++b) g[(long long)a * ldg + b] = intrapixel ? h * intrapixel[a * Q + b] : h;
+      for (int b = 0; b < Q; ++b) g[(long long)a * ldg + b] = intrapixel ? h * intrapixel[p * kst + a * Q + b] : h;
   }
   for (int s = 0; s < S; ++s) {
     double v = 0.0;
@@ -317,51 +323,68 @@ __global__ void seed_gather_kernel(const float* resid, const float* flat, const 
 //                         enlarged plane, as in seed_gather_kernel)
 //   v[a][b] = h sum_s sum_l w_l phi_s |E_{f,s,l}[Q p_r + a][Q p_c + b]|^2,
 // summed over the block's pixels into part[(f nblk + block) Q^2 + a Q + b].
+// With one kernel per pixel (gpix non-null) the pixel sum is dropped: the block runs every frame
+// of the chunk (grid.y = 1) and writes gpix[p][a][b], or adds to it for a chunk after the first.
 template <int QT>
 __global__ void kgrad_kernel(const float* E, long long plane, long long by_psf, int ld, int f0, int S, int L,
                              int Nd, const float* sources, const WlInfo* wl, const float* flat, const float* resid,
-                             const int* win, int F_img, int Nd_img, double* part) {
+                             const int* win, int F_img, int Nd_img, double* part, double* gpix, int nf_pix,
+                             int accumulate) {
   constexpr int Q2 = QT * QT;
   __shared__ double sh[Q2][kSeedThreads / 64];
   const long long npix = (long long)Nd * Nd;
   const long long p = (long long)blockIdx.x * kSeedThreads + threadIdx.x;
-  const int fl = blockIdx.y;
-  const int f = f0 + fl;
   double acc[Q2];
 #pragma unroll
   for (int k = 0; k < Q2; ++k) acc[k] = 0.0;
-  if (p < npix) {
-    const int pr = (int)(p / Nd), pc = (int)(p - (long long)pr * Nd);
-    float h = 0.f;
-    if (win) {
-      const long long nimg = (long long)Nd_img * Nd_img;
-      for (int g = 0; g < F_img; ++g) {
-        const int ir = pr - win[2 * g], ic = pc - win[2 * g + 1];
-        if (ir >= 0 && ir < Nd_img && ic >= 0 && ic < Nd_img) {
-          const long long q = (long long)ir * Nd_img + ic;
-          h += flat[q] * resid[(long long)g * nimg + q];
+  // frames of this block: one (blockIdx.y) for the shared kernel, all nf_pix of the chunk per pixel
+  const int fl0 = gpix ? 0 : blockIdx.y, fl1 = gpix ? nf_pix : blockIdx.y + 1;
+  for (int fl = fl0; fl < fl1; ++fl) {
+    const int f = f0 + fl;
+    if (p < npix) {
+      const int pr = (int)(p / Nd), pc = (int)(p - (long long)pr * Nd);
+      float h = 0.f;
+      if (win) {
+        const long long nimg = (long long)Nd_img * Nd_img;
+        for (int g = 0; g < F_img; ++g) {
+          const int ir = pr - win[2 * g], ic = pc - win[2 * g + 1];
+          if (ir >= 0 && ir < Nd_img && ic >= 0 && ic < Nd_img) {
+            const long long q = (long long)ir * Nd_img + ic;
+            h += flat[q] * resid[(long long)g * nimg + q];
+          }
+        }
+      } else {
+        h = flat[p] * resid[(long long)f * npix + p];
+      }
+      double v[Q2];
+#pragma unroll
+      for (int k = 0; k < Q2; ++k) v[k] = 0.0;
+      for (int s = 0; s < S; ++s) {
+        const float phi = sources[((long long)f * S + s) * 3 + 2];
+        for (int l = 0; l < L; ++l) {
+          const float* e = E + (((long long)fl * S + s) * L + l) * by_psf + (long long)(QT * pr) * ld + QT * pc;
+          const float wphi = wl[l].w * phi;
+#pragma unroll
+          for (int a = 0; a < QT; ++a)
+#pragma unroll
+            for (int b = 0; b < QT; ++b) {
+              const float er = e[(long long)a * ld + b], ei = e[plane + (long long)a * ld + b];
+              v[a * QT + b] += (double)(wphi * (er * er + ei * ei));
+            }
         }
       }
-    } else {
-      h = flat[p] * resid[(long long)f * npix + p];
+#pragma unroll
+      for (int k = 0; k < Q2; ++k) acc[k] += v[k] * (double)h;
     }
-    for (int s = 0; s < S; ++s) {
-      const float phi = sources[((long long)f * S + s) * 3 + 2];
-      for (int l = 0; l < L; ++l) {
-        const float* e = E + (((long long)fl * S + s) * L + l) * by_psf + (long long)(QT * pr) * ld + QT * pc;
-        const float wphi = wl[l].w * phi;
-#pragma unroll
-        for (int a = 0; a < QT; ++a)
-#pragma unroll
-          for (int b = 0; b < QT; ++b) {
-            const float er = e[(long long)a * ld + b], ei = e[plane + (long long)a * ld + b];
-            acc[a * QT + b] += (double)(wphi * (er * er + ei * ei));
-          }
-      }
-    }
-#pragma unroll
-    for (int k = 0; k < Q2; ++k) acc[k] *= (double)h;
   }
+  if (gpix) {
+    if (p < npix) {
+#pragma unroll
+      for (int k = 0; k < Q2; ++k) gpix[p * Q2 + k] = (accumulate ? gpix[p * Q2 + k] : 0.0) + acc[k];
+    }
+    return;
+  }
+  const int f = f0 + blockIdx.y;
 #pragma unroll
   for (int k = 0; k < Q2; ++k) {
     double v = acc[k];
@@ -520,7 +543,7 @@ hipError_t launch_intensity(dlx_plan* p, int f0, int nf, const float* sources, c
   const long long plane = (long long)p->chunk_psf * p->No * p->ldNo, by = (long long)p->No * p->ldNo;
 #define DLX_INTENSITY(QT)                                                                                         \
   hipLaunchKernelGGL(intensity_kernel<QT>, grid, blk, 0, st, p->d_Y, plane, by, p->ldNo, f0, p->F, p->S, p->L, \
-                     p->Q, p->Nd, sources, p->d_wl, intrapixel, flat, p->d_bs, binned, model)
+                     p->Q, p->Nd, sources, p->d_wl, intrapixel, kstride(p), flat, p->d_bs, binned, model)
   switch (p->Q) {
     case 2: DLX_INTENSITY(2); break;
     case 4: DLX_INTENSITY(4); break;
@@ -535,7 +558,7 @@ int seed_block_count(long long npix) { return (int)((npix + kSeedThreads - 1) / 
 hipError_t launch_seed(dlx_plan* p, int f0, int nf, const float* flat, const float* resid, const float* intrapixel,
                        hipStream_t st) {
   hipLaunchKernelGGL(seed_weight_kernel, dim3(p->seed_blocks, nf), dim3(kSeedThreads), 0, st, resid, flat, intrapixel,
-                     p->d_bs, f0, p->Q, p->Nd, p->S, p->ldNo, (long long)p->No * p->ldNo, p->d_G, p->seed_blocks,
+                     kstride(p), p->d_bs, f0, p->Q, p->Nd, p->S, p->ldNo, (long long)p->No * p->ldNo, p->d_G, p->seed_blocks,
                      p->d_flux);
   return hipGetLastError();
 }
@@ -565,14 +588,17 @@ hipError_t launch_seed_gather(dlx_plan* p, const float* flat, const float* resid
 }
 
 // dL/dK partials of frames [f0, f0 + nf) (one enlarged frame in integer-dither mode); Q <= 4.
+// gK: the caller's [Nd][Nd][Q][Q] output when the plan has one kernel per pixel (written by the
+// first chunk, added to by the others); otherwise ignored and the partials go to d_kpart.
 hipError_t launch_kgrad(dlx_plan* p, int f0, int nf, const float* sources, const float* flat, const float* resid,
-                        hipStream_t st) {
+                        double* gK, hipStream_t st) {
   const long long plane = (long long)p->chunk_psf * p->No * p->ldNo, by = (long long)p->No * p->ldNo;
-  const dim3 grid(p->seed_blocks, nf), blk(kSeedThreads);
+  const dim3 grid(p->seed_blocks, p->k_per_pixel ? 1 : nf), blk(kSeedThreads);
   const int* win = p->dither ? p->d_win : nullptr;
+  double* gpix = p->k_per_pixel ? gK : nullptr;
 #define DLX_KGRAD(QT)                                                                                          \
   hipLaunchKernelGGL(kgrad_kernel<QT>, grid, blk, 0, st, p->d_Y, plane, by, p->ldNo, f0, p->S, p->L, p->Nd,  \
-                     sources, p->d_wl, flat, resid, win, p->F_img, p->Nd_img, p->d_kpart)
+                     sources, p->d_wl, flat, resid, win, p->F_img, p->Nd_img, p->d_kpart, gpix, nf, f0 > 0 ? 1 : 0)
   switch (p->Q) {
     case 1: DLX_KGRAD(1); break;
     case 2: DLX_KGRAD(2); break;
@@ -599,7 +625,7 @@ hipError_t launch_loss(dlx_plan* p, int f0, int nf, int chunk, const float* mode
   const double inv_s2 = 1.0 / (sigma * sigma);
   double* blk = p->d_lossblk + (long long)chunk * nb;
   if (seed_intrapixel_or_none) {
-    const SeedOut so{*seed_intrapixel_or_none, p->d_bs, p->Q, p->Nd, p->S, p->ldNo, (long long)p->No * p->ldNo,
+    const SeedOut so{*seed_intrapixel_or_none, kstride(p), p->d_bs, p->Q, p->Nd, p->S, p->ldNo, (long long)p->No * p->ldNo,
                      p->d_G, p->d_flux};
     hipLaunchKernelGGL(loss_kernel<true>, dim3(nb), dim3(kLossThreads), 0, st, model, binned, data, flat, f0, f0 + nf,
                        npix, kind, mu, inv_s2, r, gflat, chunk > 0 ? 1 : 0, blk, p->d_status, so);
@@ -649,6 +675,8 @@ hipError_t launch_grad_reduce(dlx_plan* p, const float* Z, const float* Bm, doub
   }
   const int FS = p->F * p->S;
   const int Q2 = p->Q * p->Q;
+  // one kernel per pixel: launch_kgrad already wrote gK in full
+  if (p->k_per_pixel) gK = nullptr;
   hipLaunchKernelGGL(finalize_kernel, dim3(p->Nz + FS + (loss ? 1 : 0) + (gK ? Q2 : 0)), dim3(256), 0, st,
                      p->d_zpart, p->Nz, nch, gz, p->d_flux, p->seed_blocks, p->d_pos, p->tiles_b4 * p->b4_ksplit, p->L,
                      FS, gsrc, p->d_lossblk, p->loss_blocks * loss_chunks, loss, p->d_kpart, p->F * p->seed_blocks, Q2,

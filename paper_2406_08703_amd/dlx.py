@@ -32,6 +32,7 @@ DLX_LOSS_CHI2 = 1
 DLX_FLAG_NO_AUTOTUNE = 1
 DLX_FLAG_SEED_PASS = 2
 DLX_FLAG_STORE_FIELDS = 4
+DLX_FLAG_PIXEL_KERNEL = 8
 
 EXPORTS = ("dlx_validate", "dlx_plan_create", "dlx_plan_destroy", "dlx_plan_workspace_bytes", "dlx_plan_tiles",
            "dlx_plan_sync",

@@ -70,7 +70,7 @@ class PsfPlan:
 
     def __init__(self, geom: Geometry, transmission, zbasis, map_basis=None, intrapixel=None,
                  precision: str = "fp32", workspace_limit: int = 0, device="cuda", autotune: bool = True,
-                 seed_pass: bool = False, store_fields: bool = False):
+                 seed_pass: bool = False, store_fields: bool = False, pixel_kernel: bool = False):
         if not torch.cuda.is_available():
             raise RuntimeError("libdlx needs a ROCm GPU")
         self.geom = geom
@@ -80,14 +80,17 @@ class PsfPlan:
         self.zbasis = _f32(zbasis, (g.n_zernike, g.n_pupil, g.n_pupil), "zernike_basis") if g.n_zernike else None
         self.map_basis = _f32(map_basis, (g.n_pupil, g.n_map), "map_basis") if g.n_map else None
         Q = g.oversample
-        self.intrapixel = None if intrapixel is None else _f32(intrapixel, (Q, Q), "intrapixel")
+        self.pixel_kernel = pixel_kernel
+        self.k_shape = (g.n_det, g.n_det, Q, Q) if pixel_kernel else (Q, Q)
+        self.intrapixel = None if intrapixel is None else _f32(intrapixel, self.k_shape, "intrapixel")
         desc, self._keep = _c.make_desc(g.n_pupil, g.n_focal, g.oversample, g.wavelengths, g.weights, g.n_sources,
                                         g.n_frames, g.n_zernike, g.n_map, g.diameter, g.focal_pixel,
                                         g.dithers, g.margin)
         prec = {"fp32": _c.DLX_FP32, "bf16x3": _c.DLX_BF16X3}[precision]
         with torch.cuda.device(self.device):
             flags = ((0 if autotune else _c.DLX_FLAG_NO_AUTOTUNE) | (_c.DLX_FLAG_SEED_PASS if seed_pass else 0)
-                     | (_c.DLX_FLAG_STORE_FIELDS if store_fields else 0))
+                     | (_c.DLX_FLAG_STORE_FIELDS if store_fields else 0)
+                     | (_c.DLX_FLAG_PIXEL_KERNEL if pixel_kernel else 0))
             self.plan = _c.dlx_plan_create(desc, 1, prec, flags, int(workspace_limit))
         self.precision = precision
 
@@ -165,7 +168,8 @@ class PsfPlan:
     def backward(self, coeffs, phase_map, sources, flat, r, out=None, grad_intrapixel=None):
         """dlx_psf_backward: returns (grad_zernike [Nz], grad_map [n_map,n_map] or None, grad_sources [F,S,3]), double.
 
-        ``grad_intrapixel``: an optional float64 [Q, Q] device tensor that receives dL/dK."""
+        ``grad_intrapixel``: an optional float64 device tensor that receives dL/dK ([Q, Q], or
+        [Nd, Nd, Q, Q] for a plan with one kernel per pixel)."""
         g = self.geom
         c, pm, s, fl = self._params(coeffs, phase_map, sources, flat)
         rr = _f32(r, (g.n_frames, g.n_det, g.n_det), "dloss_dmodel")
@@ -177,8 +181,8 @@ class PsfPlan:
             gz, gm, gs = out
         gk = None
         if grad_intrapixel is not None:
-            if grad_intrapixel.dtype != torch.float64 or tuple(grad_intrapixel.shape) != (g.oversample, g.oversample):
-                raise ValueError("grad_intrapixel must be a float64 [Q, Q] tensor")
+            if grad_intrapixel.dtype != torch.float64 or tuple(grad_intrapixel.shape) != self.k_shape:
+                raise ValueError(f"grad_intrapixel must be a float64 {list(self.k_shape)} tensor")
             gk = grad_intrapixel
         _c.dlx_psf_backward(self.plan, _ptr(self.transmission), _ptr(self.zbasis), _ptr(self.map_basis), _ptr(c),
                             _ptr(pm), _ptr(s), _ptr(fl), _ptr(self.intrapixel), _ptr(rr),
@@ -200,7 +204,7 @@ class EvalBuffers:
         self.grad_zernike = torch.empty(max(g.n_zernike, 1), dtype=torch.float64, device=dv)
         self.grad_map = torch.empty((g.n_map, g.n_map), dtype=torch.float64, device=dv) if g.n_map else None
         self.grad_sources = torch.empty(g.sources_shape, dtype=torch.float64, device=dv)
-        self.grad_intrapixel = torch.empty((g.oversample, g.oversample), dtype=torch.float64, device=dv)
+        self.grad_intrapixel = torch.empty(plan.k_shape, dtype=torch.float64, device=dv)
 
 
 def _eval_args(plan: "PsfPlan", coeffs, phase_map, sources, flat, data, kind, prior_mu, prior_sigma,

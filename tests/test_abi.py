@@ -81,9 +81,10 @@ def test_plan_create_rejects_bad_precision_and_flags():
         dlx.dlx_plan_create(d, precision=7)
     assert e.value.status == dlx.DLX_ERR_INVALID_ARG
     with pytest.raises(dlx.DlxError) as e:
-        dlx.dlx_plan_create(d, flags=8)   # an undefined bit
+        dlx.dlx_plan_create(d, flags=16)   # an undefined bit
     assert e.value.status == dlx.DLX_ERR_INVALID_ARG
-    assert (dlx.DLX_FLAG_NO_AUTOTUNE | dlx.DLX_FLAG_SEED_PASS | dlx.DLX_FLAG_STORE_FIELDS) == 7
+    assert (dlx.DLX_FLAG_NO_AUTOTUNE | dlx.DLX_FLAG_SEED_PASS | dlx.DLX_FLAG_STORE_FIELDS
+            | dlx.DLX_FLAG_PIXEL_KERNEL) == 15
 
 
 def test_calls_on_null_plan_are_rejected():
