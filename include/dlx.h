@@ -112,7 +112,22 @@ dlx_status dlx_validate(const dlx_problem_desc* probs, int32_t n_probs);
  * operand loader unless a frame's seed weights G exceed 4 MiB, in which case
  * a separate elementwise pass forms it first; DLX_FLAG_SEED_PASS forces the
  * separate pass (same results, bit for bit). */
-enum { DLX_FLAG_NO_AUTOTUNE = 1, DLX_FLAG_SEED_PASS = 2, DLX_FLAG_STORE_FIELDS = 4, DLX_FLAG_PIXEL_KERNEL = 8 };
+enum {
+  DLX_FLAG_NO_AUTOTUNE = 1,
+  DLX_FLAG_SEED_PASS = 2,
+  DLX_FLAG_STORE_FIELDS = 4,
+  DLX_FLAG_PIXEL_KERNEL = 8,
+  DLX_FLAG_DENSE_MFT = 16
+};
+
+/* The MFT products use the symmetry of the pixel-centred grids (Section 3's
+ * coordinates are centred on the optical axis, so every sample x has a
+ * partner -x): the DFT matrix equals its own conjugate under reversal of
+ * either index, and each product is computed from the pair sums and
+ * differences of its data over half the depth and half the output rows, a
+ * quarter of the multiply-adds of the dense complex product, with the same
+ * results up to rounding. DLX_FLAG_DENSE_MFT selects the dense products
+ * instead (for comparison; same results up to rounding). */
 
 /* DLX_FLAG_PIXEL_KERNEL gives every detector pixel its own intra-pixel kernel
  * (Section 6: intra-pixel sensitivity, recoverable at this sampling): every

@@ -63,11 +63,12 @@ int ceil_div(long long a, long long b) { return (int)((a + b - 1) / b); }
 // gives enough workgroups to fill the chip, otherwise the smallest valid w.
 // With q > 1 the wave tile edge must be divisible by q, so that each
 // detector pixel's q x q focal samples stay inside one wave's tile.
-TileShape choose_tile(int M, int N, long long items, int q) {
+TileShape choose_tile(int M, int N, long long items, int q, bool fold = false) {
   const int cand[3] = {4, 3, 2};
   int smallest = 0;
   for (int w : cand) {
     if (q > 1 ? ((16 * w) % q != 0) : (w == 3)) continue;
+    if (fold && w == 4) continue;   // folded 128 x 128 tiles are not compiled
     const long long wg = (long long)ceil_div(M, 32 * w) * ceil_div(N, 32 * w) * items;
     if (wg >= 2 * kTargetWG) return TileShape{w, w};
     smallest = w;
@@ -217,12 +218,25 @@ void set_tiles(GemmArgs& a, TileShape ts) {
   a.tiles_n = ceil_div(a.N, ts.bn());
 }
 
+// Symmetric fold of one stage: the DFT side's output rows and the contracted length are halved
+// (mirror_n and the contracted length k_full are the unfolded sizes); output columns c >= out_h
+// are stored at c + out_s.
+void set_fold(const dlx_plan* p, GemmArgs& a, int mirror_n, int k_full, int out_h, int out_s) {
+  if (!p->fold) return;
+  a.fold = 1;
+  a.mirror_n = mirror_n;
+  a.kodd = k_full & 1;
+  a.out_h = out_h;
+  a.out_s = out_s;
+}
+
 // F1: T = M_l P for every PSF of frames [f0, f0 + nf)
 hipError_t run_f1(dlx_plan* p, int f0, int nf, hipStream_t st) {
   GemmArgs a = base_args(p, f0, nf);
-  a.M = p->No;
+  a.M = p->fold ? p->hNo() : p->No;
   a.N = p->Ni;
-  a.K = p->Ni;
+  a.K = p->fold ? p->hNi() : p->Ni;
+  set_fold(p, a, p->No, p->Ni, p->hNi(), p->sNi());
   a.n_items = a.n_chunk_psf;
   a.A = op_MN(p);
   a.B = Operand{p->d_P0T, (long long)p->Ni * p->ldNi, 2LL * p->Ni * p->ldNi, 0, p->ldNi};
@@ -240,6 +254,12 @@ GemmArgs e_args(dlx_plan* p, int f0, int nf, TileShape ts);
 hipError_t run_f2(dlx_plan* p, int f0, int nf, hipStream_t st) {
   GemmArgs a = e_args(p, f0, nf, p->ts_f2);
   a.n_items = nf * p->S * p->L;
+  if (p->fold) {
+    a.N = p->hNo();
+    a.K = p->hNi();
+    set_fold(p, a, p->No, p->Ni, p->hNo(), p->sNo());
+    set_tiles(a, p->ts_f2);
+  }
   a.out = p->d_Y;
   a.out_plane = (long long)p->chunk_psf * p->No * p->ldNo;
   a.out_by_psf = (long long)p->No * p->ldNo;
@@ -251,9 +271,10 @@ hipError_t run_f2(dlx_plan* p, int f0, int nf, hipStream_t st) {
 // formed in the loader from E and the seed weights G.
 hipError_t run_b3(dlx_plan* p, int f0, int nf, const float* sources, hipStream_t st) {
   GemmArgs a = base_args(p, f0, nf);
-  a.M = p->Ni;
+  a.M = p->fold ? p->hNi() : p->Ni;
   a.N = p->No;
-  a.K = p->No;
+  a.K = p->fold ? p->hNo() : p->No;
+  set_fold(p, a, p->Ni, p->No, p->hNo(), p->sNo());
   a.n_items = nf * p->S * p->L;
   a.A = op_MT(p);
   a.conj_a = 1;
@@ -273,9 +294,10 @@ hipError_t run_b3(dlx_plan* p, int f0, int nf, const float* sources, hipStream_t
 hipError_t run_b4(dlx_plan* p, int c, int f0, int nf, hipStream_t st) {
   const int nc = nf * p->S * p->L;
   GemmArgs a = base_args(p, f0, nf);
-  a.M = p->Ni;
+  a.M = p->fold ? p->hNi() : p->Ni;
   a.N = p->Ni;
-  a.K = p->No;
+  a.K = p->fold ? p->hNo() : p->No;
+  set_fold(p, a, p->Ni, p->No, p->Ni, 0);
   a.A = op_MT(p);
   a.conj_a = 1;
   a.B = op_UT(p);
@@ -306,14 +328,15 @@ hipError_t run_adjoint(dlx_plan* p, int c, int f0, int nf, const float* sources,
 // as the autotuner does; otherwise K = No is split when the groups alone cannot fill the chip,
 // keeping >= 128 per split).
 void derive_tiles(dlx_plan* p, int ksplit = 0) {
-  p->tiles_b4 = ceil_div(p->Ni, p->ts_b4.bm()) * ceil_div(p->Ni, p->ts_b4.bn());
+  p->tiles_b4 = ceil_div(p->fold ? p->hNi() : p->Ni, p->ts_b4.bm()) * ceil_div(p->Ni, p->ts_b4.bn());
   if (ksplit > 0) {
     p->b4_ksplit = ksplit;
     return;
   }
   const long long wg = (long long)p->tiles_b4 * p->b4_groups_max;
   int ks = 1;
-  while (ks < 4 && wg * ks < kTargetWG && p->No / (2 * ks) >= 128) ks *= 2;
+  const int kb4 = p->fold ? p->hNo() : p->No;
+  while (ks < 4 && wg * ks < kTargetWG && kb4 / (2 * ks) >= 128) ks *= 2;
   p->b4_ksplit = ks;
 }
 
@@ -359,7 +382,8 @@ hipError_t autotune(dlx_plan* p) {
     for (int ci = 0; ci < (int)(sizeof(kTileShapes) / sizeof(kTileShapes[0])) * n_ks && e == hipSuccess; ++ci) {
       const TileShape& cand = kTileShapes[ci / n_ks];
       const int ks = kind == KIND_B4 ? (1 << (ci % n_ks)) : 0;
-      if (ks > 1 && p->No / ks < 64) continue;
+      if (ks > 1 && (p->fold ? p->hNo() : p->No) / ks < 64) continue;
+      if (!tile_supported(kind, p->bf16(), p->fold, cand)) continue;
       *ts = cand;
       derive_tiles(p, ks);
       if ((e = run_stage_for_tuning(p, kind, nullptr)) != hipSuccess) break;   // warm-up
@@ -405,7 +429,7 @@ TuneKey tune_key(const dlx_plan* p) {
   int dev = 0;
   (void)hipGetDevice(&dev);
   return {dev, (long long)p->prec, p->Ni, p->No, p->Q, p->L, p->S, p->F, p->frames_per_chunk, p->Nz, p->Nmap,
-          p->seed_pass ? 1 : 0};
+          (p->seed_pass ? 1 : 0) | (p->fold ? 2 : 0)};
 }
 
 hipError_t autotune_cached(dlx_plan* p) {
@@ -594,7 +618,8 @@ dlx_status dlx_plan_create(const dlx_problem_desc* probs, int32_t n_probs, dlx_p
   dlx_status v = dlx_validate(probs, n_probs);
   if (v != DLX_OK) return v;
   if (precision != DLX_FP32 && precision != DLX_BF16X3) return DLX_ERR_INVALID_ARG;
-  if ((flags & ~(DLX_FLAG_NO_AUTOTUNE | DLX_FLAG_SEED_PASS | DLX_FLAG_STORE_FIELDS | DLX_FLAG_PIXEL_KERNEL)) != 0)
+  if ((flags & ~(DLX_FLAG_NO_AUTOTUNE | DLX_FLAG_SEED_PASS | DLX_FLAG_STORE_FIELDS | DLX_FLAG_PIXEL_KERNEL |
+                 DLX_FLAG_DENSE_MFT)) != 0)
     return DLX_ERR_INVALID_ARG;
   if (n_probs > 1) return create_multi(probs, n_probs, precision, flags, workspace_limit_bytes, out);
   const dlx_problem_desc& d = probs[0];
@@ -632,6 +657,7 @@ dlx_status dlx_plan_create(const dlx_problem_desc* probs, int32_t n_probs, dlx_p
   p->prec = precision;
   p->ldNi = round_up(p->Ni, 16);
   p->ldNo = round_up(p->No, 16);
+  p->fold = (flags & DLX_FLAG_DENSE_MFT) == 0;
   p->n_psf = p->F * p->S * p->L;
 
   // chunk of whole frames whose intermediates fit the budget (stored fields: every frame in one chunk)
@@ -670,16 +696,18 @@ dlx_status dlx_plan_create(const dlx_problem_desc* probs, int32_t n_probs, dlx_p
   p->chunk_psf = p->frames_per_chunk * p->S * p->L;
 
   // tiles
-  p->ts_f1 = choose_tile(p->No, p->Ni, p->chunk_psf, 1);
-  p->ts_b3 = choose_tile(p->Ni, p->No, p->chunk_psf, 1);
+  const bool fo = p->fold;
+  const int mNo = fo ? p->hNo() : p->No, mNi = fo ? p->hNi() : p->Ni;   // folded DFT-side sizes
+  p->ts_f1 = choose_tile(mNo, p->Ni, p->chunk_psf, 1, fo);
+  p->ts_b3 = choose_tile(mNi, p->No, p->chunk_psf, 1, fo);
   const int sl = p->S * p->L;
-  p->ts_f2 = choose_tile(p->No, p->No, (long long)p->frames_per_chunk * sl, 1);
+  p->ts_f2 = choose_tile(p->No, mNo, (long long)p->frames_per_chunk * sl, 1, fo);
   {
-    const int t = ceil_div(p->Ni, 128) * ceil_div(p->Ni, 128);
+    const int t = ceil_div(mNi, 128) * ceil_div(p->Ni, 128);
     const int g = std::max(1, std::min(ceil_div(kTargetWG, t), p->chunk_psf));
     p->b4_gsize = ceil_div(p->chunk_psf, g);
     p->b4_groups_max = ceil_div(p->chunk_psf, p->b4_gsize);
-    p->ts_b4 = choose_tile(p->Ni, p->Ni, p->b4_groups_max, 1);
+    p->ts_b4 = choose_tile(mNi, p->Ni, p->b4_groups_max, 1, fo);
   }
   derive_tiles(p);
   // partial-sum buffers are sized for the smallest candidate tile (32 x 32) and the largest split

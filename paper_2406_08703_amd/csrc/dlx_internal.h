@@ -45,6 +45,16 @@ struct Operand {
 //   B3  U^T = conj(M_l)^T Y^T  stored; the seed Y = w phi G E is formed in the operand loader
 //                              from E and the frame's seed weights G = K flat r
 //   B4  W = c M_l^H U          epilogue: g = 2 Im(conj(P) W) (2 pi / l) summed over a group; position partials
+//
+// Symmetric fold. On the pixel-centred grids the coordinates pair up, x[N-1-n] = -x[n], so the
+// DFT matrix D[a][k] = Dr + i Di satisfies D[a][K-1-k] = conj(D[a][k]) = D[A-1-a][k]. A product
+// sum_k D[a][k] X[k] then needs only the sums Xe[k] = X[k] + X[K-1-k] and differences
+// Xo[k] = X[k] - X[K-1-k] for k < ceil(K/2):
+//   P = sum Dr Xe,  R = sum Di Xo,   out[a] = P + i R,   out[A-1-a] = P - i R,
+// four real products of half the depth over half the DFT rows: a quarter of the dense work.
+// The data operands of the fold (pupil field, T, E, G, U^T) keep the lower half of each row in
+// place and move the upper half to end at the leading dimension ld (column c >= ceil(N/2) at
+// c + ld - N), so the mirror of the 16-byte chunk at k is the chunk at ld - 4 - k, reversed.
 enum GemmKind { KIND_F1 = 0, KIND_F2 = 1, KIND_B3 = 3, KIND_B4 = 4 };
 
 struct GemmArgs {
@@ -86,6 +96,13 @@ struct GemmArgs {
   // per-(PSF, tile) FP64 partials: B4 positions [n_psf][tiles][2]
   double* red;
   const double* xcoord;   // pupil sample coordinates (metres), [Ni]
+  // symmetric fold (fold = 1): M, N, K above are the folded sizes; the DFT side's output index a
+  // pairs with mirror_n - 1 - a, the contracted index k with K_full - 1 - k (kodd: K_full odd, its
+  // middle term has no partner). Output columns c are stored at c < out_h ? c : c + out_s.
+  int fold;
+  int mirror_n;
+  int kodd;
+  int out_h, out_s;
 };
 
 // Tile shape of one GEMM launch: 4 waves (2 x 2), each WM x WN blocks of 16 x 16.
@@ -99,7 +116,7 @@ struct TileShape {
 constexpr TileShape kTileShapes[] = {{4, 4}, {3, 3}, {2, 2}, {4, 2}, {2, 4}, {2, 1}, {1, 2}};
 
 hipError_t launch_gemm(int kind, int prec, TileShape ts, const GemmArgs& a, int n_wg, hipStream_t st);
-bool tile_supported(int kind, TileShape ts);
+bool tile_supported(int kind, int prec, bool fold, TileShape ts);
 
 }  // namespace dlx
 
@@ -126,6 +143,13 @@ struct dlx_plan {
   int bf16() const { return prec == DLX_BF16X3 ? 1 : 0; }
   // padded leading dimensions
   int ldNi, ldNo;
+  // symmetric fold of the MFT products (off: dense complex products). Folded data rows keep
+  // columns c < h at c and move c >= h to c + ld - N, with h = ceil(N / 2).
+  bool fold = true;
+  int hNi() const { return (Ni + 1) / 2; }
+  int hNo() const { return (No + 1) / 2; }
+  int sNi() const { return fold ? ldNi - Ni : 0; }
+  int sNo() const { return fold ? ldNo - No : 0; }
   // chunking
   int frames_per_chunk;
   int n_chunks;

@@ -551,11 +551,581 @@ __global__ __launch_bounds__(256) void cgemm_kernel(const GemmArgs a) {
   }
 }
 
+// ------------------------------------------------------------------------------------------------
+// Folded stages (see the symmetric fold in dlx_internal.h). The DFT operand is A for F1, B3, B4
+// and B for F2; it is read as in the dense kernel, restricted to the first ceil(N/2) rows and
+// columns. The data operand is always FP32 in HBM: its natural chunk at k and its mirror chunk at
+// ld - CH - k are loaded together, the stage's loader product is applied to each (F1: the row
+// tilt ty[k] and its conjugate, which is the tilt at the mirror row; B3: w phi G), and the sum and
+// difference go to LDS as four planes (Xe re, Xe im, Xo re, Xo im), split to bf16 hi/lo under
+// BF16X3. Each 16 x 16 block keeps four accumulators P = (Pr, Pi), R = (Rr, Ri); the epilogue
+// writes out[a] = P + i R and out[mirror a] = P - i R.
+__device__ __forceinline__ f4 rev4(f4 v) { return f4{v[3], v[2], v[1], v[0]}; }
+
+template <int KIND, int WM, int WN, int PREC>
+__global__ __launch_bounds__(256) void fgemm_kernel(const GemmArgs a) {
+  constexpr bool DA = KIND != KIND_F2;   // DFT operand on the A side (rows i), data on the B side
+  constexpr int BM = 32 * WM, BN = 32 * WN;
+  constexpr int BK = PREC == 0 ? 16 : 32;
+  constexpr int CH = PREC == 0 ? 4 : 8;   // k per 16-byte LDS chunk
+  constexpr int LDK = 4 * CH;
+  constexpr int V = CH / 4;               // FP32 source vectors per chunk and plane
+  constexpr int ND = PREC == 0 ? 2 : 4;   // LDS planes of the DFT operand
+  constexpr int NX = PREC == 0 ? 4 : 8;   // LDS planes of the folded data operand
+  constexpr int RD = DA ? BM : BN, RX = DA ? BN : BM;
+  constexpr int D_EL = ND * RD * LDK, X_EL = NX * RX * LDK;
+  constexpr int UNITS_D = RD * 4, UNITS_X = RX * 4;
+  constexpr int D_U = (UNITS_D + 255) / 256, X_U = (UNITS_X + 255) / 256;
+  constexpr bool kW = KIND == KIND_F1 || KIND == KIND_B3;   // loader product with a second source
+  using el_t = typename std::conditional<PREC == 0, float, unsigned short>::type;
+  __shared__ __attribute__((aligned(16))) el_t smem[D_EL + X_EL];
+  __shared__ double sred[8];
+  el_t* Ds = smem;
+  el_t* Xs = smem + D_EL;
+
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int wr = wave >> 1, wc = wave & 1;
+  const int lin = xcd_remap(blockIdx.x, gridDim.x);
+  const int tiles = a.tiles_m * a.tiles_n;
+  const int item = lin / tiles;
+  if (item >= a.n_items) return;
+  const int tile = lin - item * tiles;
+  const int tm = tile / a.tiles_n, tn = tile - tm * a.tiles_n;
+  const int row0 = tm * BM, col0 = tn * BN;
+  const int M = a.M, N = a.N, K = a.K;
+  const int rowD0 = DA ? row0 : col0, rowX0 = DA ? col0 : row0;
+  const int nD = DA ? M : N, nX = DA ? N : M;
+  const Operand& OD = DA ? a.A : a.B;
+  const Operand& OX = DA ? a.B : a.A;
+  const bool conj_d = DA ? a.conj_a : a.conj_b;
+  const int kmid = a.kodd ? K - 1 : -1;   // the unpaired middle term of an odd contracted length
+
+  int p_begin, p_end, grp = 0;
+  if constexpr (KIND == KIND_B4) {
+    grp = item;
+    const int g = item / a.ksplit;
+    p_begin = g * a.group_size;
+    p_end = min(p_begin + a.group_size, a.n_chunk_psf);
+  } else {
+    p_begin = item;
+    p_end = item + 1;
+  }
+
+  f4 slo[WM][WN], shi[WM][WN];   // B4: dL/dOPD of the rows a and mirror a, summed over the group
+#pragma unroll
+  for (int bm = 0; bm < WM; ++bm)
+#pragma unroll
+    for (int bn = 0; bn < WN; ++bn) {
+      slo[bm][bn] = f4{0.f, 0.f, 0.f, 0.f};
+      shi[bm][bn] = f4{0.f, 0.f, 0.f, 0.f};
+    }
+
+  int k_lo = 0, k_hi = K;
+  if constexpr (KIND == KIND_B4) {
+    const int ks = item % a.ksplit;
+    const int kc = ((K + a.ksplit * BK - 1) / (a.ksplit * BK)) * BK;
+    k_lo = ks * kc;
+    k_hi = min(K, k_lo + kc);
+  }
+  const int nk = k_hi > k_lo ? (k_hi - k_lo + BK - 1) / BK : 0;
+
+  for (int lb = p_begin; lb < p_end; ++lb) {
+    const int gb = a.psf0 + lb;
+    const int wl = gb % a.L;
+    const el_t* Db = static_cast<const el_t*>(OD.base) + (long long)wl * OD.by_wl + (long long)lb * OD.by_psf;
+    const float* Xb = static_cast<const float*>(OX.base) + (long long)wl * OX.by_wl + (long long)lb * OX.by_psf;
+    const int ldx = OX.ld;
+    const float* txb = a.tx + (long long)gb * a.ldt;
+    const float* tyb = a.ty + (long long)gb * a.ldt;
+    float wphi = 1.f;
+    const float* gwb = nullptr;
+    if constexpr (KIND == KIND_B3) {
+      if (a.seedw) {
+        const int fs = gb / a.L;
+        wphi = a.wl[wl].w * a.sources[fs * 3 + 2];
+        gwb = a.seedw + (long long)(fs / a.S - a.frame0) * a.seedw_by_frame;
+      }
+    }
+
+    f4 pr_[WM][WN], pi_[WM][WN], rr_[WM][WN], ri_[WM][WN];
+#pragma unroll
+    for (int bm = 0; bm < WM; ++bm)
+#pragma unroll
+      for (int bn = 0; bn < WN; ++bn) {
+        pr_[bm][bn] = f4{0.f, 0.f, 0.f, 0.f};
+        pi_[bm][bn] = f4{0.f, 0.f, 0.f, 0.f};
+        rr_[bm][bn] = f4{0.f, 0.f, 0.f, 0.f};
+        ri_[bm][bn] = f4{0.f, 0.f, 0.f, 0.f};
+      }
+
+    // ------------------------------------------------------------ staging registers
+    u4 gd[D_U][ND];
+    int gd_k[D_U];
+    u4 xn[X_U][2 * V], xm[X_U][2 * V];   // re, im at the natural chunk and at the mirror chunk
+    u4 w0[X_U][V], w1[X_U][V];           // F1: ty re, im at k; B3: G at k and at the mirror
+    int gx_k[X_U];
+
+    auto load_tile = [&](int k0) {
+#pragma unroll
+      for (int r = 0; r < D_U; ++r) {
+        const int q = tid + 256 * r;
+        const int row = q >> 2, kq = q & 3;
+        const int gi = rowD0 + row;
+        const int gk = k0 + CH * kq;
+        gd_k[r] = gk;
+#pragma unroll
+        for (int pl = 0; pl < ND; ++pl) gd[r][pl] = u4{0u, 0u, 0u, 0u};
+        if (q < UNITS_D && gi < nD && gk < k_hi) {
+          const el_t* p = Db + (long long)gi * OD.ld + gk;
+#pragma unroll
+          for (int pl = 0; pl < ND; ++pl) gd[r][pl] = *reinterpret_cast<const u4*>(p + pl * OD.plane);
+        }
+      }
+#pragma unroll
+      for (int r = 0; r < X_U; ++r) {
+        const int q = tid + 256 * r;
+        const int row = q >> 2, kq = q & 3;
+        const int gj = rowX0 + row;
+        const int gk = k0 + CH * kq;
+        gx_k[r] = gk;
+#pragma unroll
+        for (int v = 0; v < 2 * V; ++v) {
+          xn[r][v] = u4{0u, 0u, 0u, 0u};
+          xm[r][v] = u4{0u, 0u, 0u, 0u};
+        }
+#pragma unroll
+        for (int v = 0; v < V; ++v) {
+          w0[r][v] = u4{0u, 0u, 0u, 0u};
+          w1[r][v] = u4{0u, 0u, 0u, 0u};
+        }
+        if (q < UNITS_X && gj < nX && gk < k_hi) {
+          const float* p = Xb + (long long)gj * ldx + gk;
+          const float* pm = Xb + (long long)gj * ldx + (ldx - CH - gk);
+#pragma unroll
+          for (int v = 0; v < V; ++v) {
+            xn[r][v] = *reinterpret_cast<const u4*>(p + 4 * v);
+            xn[r][V + v] = *reinterpret_cast<const u4*>(p + OX.plane + 4 * v);
+            xm[r][v] = *reinterpret_cast<const u4*>(pm + 4 * v);
+            xm[r][V + v] = *reinterpret_cast<const u4*>(pm + OX.plane + 4 * v);
+          }
+          if constexpr (KIND == KIND_F1) {
+#pragma unroll
+            for (int v = 0; v < V; ++v) {
+              w0[r][v] = *reinterpret_cast<const u4*>(tyb + gk + 4 * v);
+              w1[r][v] = *reinterpret_cast<const u4*>(tyb + a.tilt_plane + gk + 4 * v);
+            }
+          } else if constexpr (KIND == KIND_B3) {
+            const f4 one = f4{1.f, 1.f, 1.f, 1.f};
+#pragma unroll
+            for (int v = 0; v < V; ++v) {
+              w0[r][v] = gwb ? *reinterpret_cast<const u4*>(gwb + (long long)gj * ldx + gk + 4 * v)
+                             : __builtin_bit_cast(u4, one);
+              w1[r][v] = gwb ? *reinterpret_cast<const u4*>(gwb + (long long)gj * ldx + (ldx - CH - gk) + 4 * v)
+                             : __builtin_bit_cast(u4, one);
+            }
+          }
+        }
+      }
+    };
+
+    auto store_tile = [&]() {
+      // DFT operand: as the dense kernel (K tail masked, conjugated for the adjoint)
+#pragma unroll
+      for (int r = 0; r < D_U; ++r) {
+        const int q = tid + 256 * r;
+        if (q < UNITS_D) {
+          const int row = q >> 2, kq = q & 3;
+          if constexpr (PREC == 0) {
+            f4 vr = __builtin_bit_cast(f4, gd[r][0]), vi = __builtin_bit_cast(f4, gd[r][1]);
+            const int gk = gd_k[r];
+            if (gk + 4 > k_hi) {
+#pragma unroll
+              for (int e = 0; e < 4; ++e)
+                if (gk + e >= k_hi) {
+                  vr[e] = 0.f;
+                  vi[e] = 0.f;
+                }
+            }
+            if (conj_d) vi = -vi;
+            *reinterpret_cast<f4*>(&Ds[row * LDK + 4 * (kq ^ lds_swz(row))]) = vr;
+            *reinterpret_cast<f4*>(&Ds[(RD + row) * LDK + 4 * (kq ^ lds_swz(row))]) = vi;
+          } else {
+            u4* pl = gd[r];
+            const int gk = gd_k[r];
+            if (gk + 8 > k_hi) {
+#pragma unroll
+              for (int e = 0; e < 8; ++e)
+                if (gk + e >= k_hi) {
+                  const unsigned int mask = (e & 1) ? 0x0000ffffu : 0xffff0000u;
+#pragma unroll
+                  for (int c = 0; c < 4; ++c) pl[c][e >> 1] &= mask;
+                }
+            }
+            if (conj_d) {
+              pl[2] ^= u4{0x80008000u, 0x80008000u, 0x80008000u, 0x80008000u};
+              pl[3] ^= u4{0x80008000u, 0x80008000u, 0x80008000u, 0x80008000u};
+            }
+#pragma unroll
+            for (int c = 0; c < 4; ++c)
+              *reinterpret_cast<u4*>(&Ds[(c * RD + row) * LDK + 8 * (kq ^ lds_swz(row))]) = pl[c];
+          }
+        }
+      }
+      // data operand: loader product at k and at the mirror, then sum and difference
+#pragma unroll
+      for (int r = 0; r < X_U; ++r) {
+        const int q = tid + 256 * r;
+        if (q < UNITS_X) {
+          const int row = q >> 2, kq = q & 3;
+          f4 er[V], ei[V], odr[V], odi[V];
+#pragma unroll
+          for (int v = 0; v < V; ++v) {
+            f4 xr = __builtin_bit_cast(f4, xn[r][v]), xi = __builtin_bit_cast(f4, xn[r][V + v]);
+            // the mirror of natural element 4v + e is element 3 - e of mirror vector V - 1 - v
+            f4 yr = rev4(__builtin_bit_cast(f4, xm[r][V - 1 - v]));
+            f4 yi = rev4(__builtin_bit_cast(f4, xm[r][2 * V - 1 - v]));
+            if constexpr (KIND == KIND_F1) {
+              // P[k] = P0[k] ty[k]; at the mirror row the tilt is conj(ty[k])
+              const f4 tr = __builtin_bit_cast(f4, w0[r][v]), ti = __builtin_bit_cast(f4, w1[r][v]);
+              const f4 ar = xr * tr - xi * ti, ai = xr * ti + xi * tr;
+              const f4 br = yr * tr + yi * ti, bi = yi * tr - yr * ti;
+              xr = ar;
+              xi = ai;
+              yr = br;
+              yi = bi;
+            } else if constexpr (KIND == KIND_B3) {
+              const f4 g = wphi * __builtin_bit_cast(f4, w0[r][v]);
+              const f4 gm = wphi * rev4(__builtin_bit_cast(f4, w1[r][V - 1 - v]));
+              xr = g * xr;
+              xi = g * xi;
+              yr = gm * yr;
+              yi = gm * yi;
+            }
+            // K tail and the unpaired middle term (assigned after the products: padding is not read)
+            const int kb = gx_k[r] + 4 * v;
+#pragma unroll
+            for (int e = 0; e < 4; ++e) {
+              if (kb + e >= k_hi) {
+                xr[e] = 0.f;
+                xi[e] = 0.f;
+                yr[e] = 0.f;
+                yi[e] = 0.f;
+              }
+              if (kb + e == kmid) {
+                yr[e] = 0.f;
+                yi[e] = 0.f;
+              }
+            }
+            er[v] = xr + yr;
+            ei[v] = xi + yi;
+            odr[v] = xr - yr;
+            odi[v] = xi - yi;
+          }
+          if constexpr (PREC == 0) {
+            const int o = 4 * (kq ^ lds_swz(row));
+            *reinterpret_cast<f4*>(&Xs[(0 * RX + row) * LDK + o]) = er[0];
+            *reinterpret_cast<f4*>(&Xs[(1 * RX + row) * LDK + o]) = ei[0];
+            *reinterpret_cast<f4*>(&Xs[(2 * RX + row) * LDK + o]) = odr[0];
+            *reinterpret_cast<f4*>(&Xs[(3 * RX + row) * LDK + o]) = odi[0];
+          } else {
+            // planes: Xe re hi, lo; Xe im hi, lo; Xo re hi, lo; Xo im hi, lo (8 k each, two per word)
+            unsigned int w[8][4];
+#pragma unroll
+            for (int e = 0; e < 4; ++e) {
+              const int v = e >> 1, c = 2 * (e & 1);
+              split_pair(er[v][c], er[v][c + 1], w[0][e], w[1][e]);
+              split_pair(ei[v][c], ei[v][c + 1], w[2][e], w[3][e]);
+              split_pair(odr[v][c], odr[v][c + 1], w[4][e], w[5][e]);
+              split_pair(odi[v][c], odi[v][c + 1], w[6][e], w[7][e]);
+            }
+            const int o = 8 * (kq ^ lds_swz(row));
+#pragma unroll
+            for (int pl = 0; pl < 8; ++pl)
+              *reinterpret_cast<u4*>(&Xs[(pl * RX + row) * LDK + o]) = u4{w[pl][0], w[pl][1], w[pl][2], w[pl][3]};
+          }
+        }
+      }
+    };
+
+    if (nk > 0) load_tile(k_lo);
+    for (int kt = 0; kt < nk; ++kt) {
+      __syncthreads();
+      store_tile();
+      __syncthreads();
+      if (kt + 1 < nk) load_tile(k_lo + (kt + 1) * BK);
+
+      if constexpr (PREC == 0) {
+        constexpr int WD = DA ? WM : WN, WX = DA ? WN : WM;
+        const int bd = DA ? wr : wc, bx = DA ? wc : wr;
+        f4 dr[WD], di[WD], xf[WX][4];
+#pragma unroll
+        for (int b = 0; b < WD; ++b) {
+          const int r = bd * 16 * WD + b * 16 + (lane & 15);
+          const int o = 4 * ((lane >> 4) ^ lds_swz(r));
+          dr[b] = *reinterpret_cast<const f4*>(&Ds[r * LDK + o]);
+          di[b] = *reinterpret_cast<const f4*>(&Ds[(RD + r) * LDK + o]);
+        }
+#pragma unroll
+        for (int b = 0; b < WX; ++b) {
+          const int r = bx * 16 * WX + b * 16 + (lane & 15);
+          const int o = 4 * ((lane >> 4) ^ lds_swz(r));
+#pragma unroll
+          for (int pl = 0; pl < 4; ++pl) xf[b][pl] = *reinterpret_cast<const f4*>(&Xs[(pl * RX + r) * LDK + o]);
+        }
+#pragma unroll
+        for (int s = 0; s < 4; ++s) {
+#pragma unroll
+          for (int bm = 0; bm < WM; ++bm)
+#pragma unroll
+            for (int bn = 0; bn < WN; ++bn) {
+              const int id = DA ? bm : bn, ix = DA ? bn : bm;
+              if constexpr (DA) {
+                pr_[bm][bn] = mfma_f32(dr[id][s], xf[ix][0][s], pr_[bm][bn]);
+                pi_[bm][bn] = mfma_f32(dr[id][s], xf[ix][1][s], pi_[bm][bn]);
+                rr_[bm][bn] = mfma_f32(di[id][s], xf[ix][2][s], rr_[bm][bn]);
+                ri_[bm][bn] = mfma_f32(di[id][s], xf[ix][3][s], ri_[bm][bn]);
+              } else {
+                pr_[bm][bn] = mfma_f32(xf[ix][0][s], dr[id][s], pr_[bm][bn]);
+                pi_[bm][bn] = mfma_f32(xf[ix][1][s], dr[id][s], pi_[bm][bn]);
+                rr_[bm][bn] = mfma_f32(xf[ix][2][s], di[id][s], rr_[bm][bn]);
+                ri_[bm][bn] = mfma_f32(xf[ix][3][s], di[id][s], ri_[bm][bn]);
+              }
+            }
+        }
+      } else {
+        // each real product as hi*hi + hi*lo + lo*hi
+        if constexpr (DA) {
+          u4 xf[WN][8];
+#pragma unroll
+          for (int bn = 0; bn < WN; ++bn) {
+            const int c = wc * 16 * WN + bn * 16 + (lane & 15);
+            const int o = 8 * ((lane >> 4) ^ lds_swz(c));
+#pragma unroll
+            for (int pl = 0; pl < 8; ++pl) xf[bn][pl] = *reinterpret_cast<const u4*>(&Xs[(pl * RX + c) * LDK + o]);
+          }
+#pragma unroll
+          for (int bm = 0; bm < WM; ++bm) {
+            const int r = wr * 16 * WM + bm * 16 + (lane & 15);
+            const int o = 8 * ((lane >> 4) ^ lds_swz(r));
+            u4 d[4];
+#pragma unroll
+            for (int pl = 0; pl < 4; ++pl) d[pl] = *reinterpret_cast<const u4*>(&Ds[(pl * RD + r) * LDK + o]);
+#pragma unroll
+            for (int bn = 0; bn < WN; ++bn) {
+              pr_[bm][bn] = mfma_bf16(d[0], xf[bn][0], pr_[bm][bn]);
+              pi_[bm][bn] = mfma_bf16(d[0], xf[bn][2], pi_[bm][bn]);
+              rr_[bm][bn] = mfma_bf16(d[2], xf[bn][4], rr_[bm][bn]);
+              ri_[bm][bn] = mfma_bf16(d[2], xf[bn][6], ri_[bm][bn]);
+              pr_[bm][bn] = mfma_bf16(d[0], xf[bn][1], pr_[bm][bn]);
+              pi_[bm][bn] = mfma_bf16(d[0], xf[bn][3], pi_[bm][bn]);
+              rr_[bm][bn] = mfma_bf16(d[2], xf[bn][5], rr_[bm][bn]);
+              ri_[bm][bn] = mfma_bf16(d[2], xf[bn][7], ri_[bm][bn]);
+              pr_[bm][bn] = mfma_bf16(d[1], xf[bn][0], pr_[bm][bn]);
+              pi_[bm][bn] = mfma_bf16(d[1], xf[bn][2], pi_[bm][bn]);
+              rr_[bm][bn] = mfma_bf16(d[3], xf[bn][4], rr_[bm][bn]);
+              ri_[bm][bn] = mfma_bf16(d[3], xf[bn][6], ri_[bm][bn]);
+            }
+          }
+        } else {
+          u4 d[WN][4];
+#pragma unroll
+          for (int bn = 0; bn < WN; ++bn) {
+            const int c = wc * 16 * WN + bn * 16 + (lane & 15);
+            const int o = 8 * ((lane >> 4) ^ lds_swz(c));
+#pragma unroll
+            for (int pl = 0; pl < 4; ++pl) d[bn][pl] = *reinterpret_cast<const u4*>(&Ds[(pl * RD + c) * LDK + o]);
+          }
+#pragma unroll
+          for (int bm = 0; bm < WM; ++bm) {
+            const int r = wr * 16 * WM + bm * 16 + (lane & 15);
+            const int o = 8 * ((lane >> 4) ^ lds_swz(r));
+            u4 x[8];
+#pragma unroll
+            for (int pl = 0; pl < 8; ++pl) x[pl] = *reinterpret_cast<const u4*>(&Xs[(pl * RX + r) * LDK + o]);
+#pragma unroll
+            for (int bn = 0; bn < WN; ++bn) {
+              pr_[bm][bn] = mfma_bf16(x[0], d[bn][0], pr_[bm][bn]);
+              pi_[bm][bn] = mfma_bf16(x[2], d[bn][0], pi_[bm][bn]);
+              rr_[bm][bn] = mfma_bf16(x[4], d[bn][2], rr_[bm][bn]);
+              ri_[bm][bn] = mfma_bf16(x[6], d[bn][2], ri_[bm][bn]);
+              pr_[bm][bn] = mfma_bf16(x[0], d[bn][1], pr_[bm][bn]);
+              pi_[bm][bn] = mfma_bf16(x[2], d[bn][1], pi_[bm][bn]);
+              rr_[bm][bn] = mfma_bf16(x[4], d[bn][3], rr_[bm][bn]);
+              ri_[bm][bn] = mfma_bf16(x[6], d[bn][3], ri_[bm][bn]);
+              pr_[bm][bn] = mfma_bf16(x[1], d[bn][0], pr_[bm][bn]);
+              pi_[bm][bn] = mfma_bf16(x[3], d[bn][0], pi_[bm][bn]);
+              rr_[bm][bn] = mfma_bf16(x[5], d[bn][2], rr_[bm][bn]);
+              ri_[bm][bn] = mfma_bf16(x[7], d[bn][2], ri_[bm][bn]);
+            }
+          }
+        }
+      }
+    }
+
+    // ------------------------------------------------------------------ per-PSF epilogue
+    // out[a] = P + i R = (Pr - Ri, Pi + Rr);  out[mirror a] = P - i R = (Pr + Ri, Pi - Rr)
+    const WlInfo wi = a.wl[wl];
+    if constexpr (KIND == KIND_F1 || KIND == KIND_F2 || KIND == KIND_B3) {
+      float* ob = static_cast<float*>(a.out) + (long long)lb * a.out_by_psf;
+#pragma unroll
+      for (int bm = 0; bm < WM; ++bm)
+#pragma unroll
+        for (int bn = 0; bn < WN; ++bn) {
+          const int j = col0 + wc * 16 * WN + bn * 16 + (lane & 15);
+          float cr = 1.f, ci = 0.f;
+          if constexpr (KIND == KIND_F1) {
+            if (j < N) {
+              cr = txb[j];
+              ci = txb[a.tilt_plane + j];
+            }
+          } else if constexpr (KIND == KIND_F2) {
+            cr = wi.scale;
+          }
+#pragma unroll
+          for (int r = 0; r < 4; ++r) {
+            const int i = row0 + wr * 16 * WM + bm * 16 + 4 * (lane >> 4) + r;
+            if (i < M && j < N) {
+              const float Pr = pr_[bm][bn][r], Pi = pi_[bm][bn][r], Rr = rr_[bm][bn][r], Ri = ri_[bm][bn][r];
+              const float lr = Pr - Ri, li = Pi + Rr, hr = Pr + Ri, hi = Pi - Rr;
+              if constexpr (KIND == KIND_F2) {
+                // mirrored index: the output column
+                const int jm = a.mirror_n - 1 - j;
+                const long long base = (long long)i * a.ldo;
+                const long long i0 = base + (j < a.out_h ? j : j + a.out_s);
+                ob[i0] = cr * lr;
+                ob[a.out_plane + i0] = cr * li;
+                if (jm != j) {
+                  const long long i1 = base + (jm < a.out_h ? jm : jm + a.out_s);
+                  ob[i1] = cr * hr;
+                  ob[a.out_plane + i1] = cr * hi;
+                }
+              } else {
+                // mirrored index: the output row
+                const int im = a.mirror_n - 1 - i;
+                const int jc = j < a.out_h ? j : j + a.out_s;
+                float ar = lr, ai = li, br = hr, bi = hi;
+                if constexpr (KIND == KIND_F1) {   // column tilt tx[n]
+                  ar = lr * cr - li * ci;
+                  ai = lr * ci + li * cr;
+                  br = hr * cr - hi * ci;
+                  bi = hr * ci + hi * cr;
+                }
+                const long long i0 = (long long)i * a.ldo + jc;
+                ob[i0] = ar;
+                ob[a.out_plane + i0] = ai;
+                if (im != i) {
+                  const long long i1 = (long long)im * a.ldo + jc;
+                  ob[i1] = br;
+                  ob[a.out_plane + i1] = bi;
+                }
+              }
+            }
+          }
+        }
+    } else if constexpr (KIND == KIND_B4) {
+      const float c = wi.scale;
+      const float kp = 2.0f * wi.kphase;
+      const float* p0 = a.p0t + (long long)wl * a.p0_by_wl;
+      double px = 0.0, py = 0.0;
+#pragma unroll
+      for (int bm = 0; bm < WM; ++bm)
+#pragma unroll
+        for (int bn = 0; bn < WN; ++bn) {
+          const int j = col0 + wc * 16 * WN + bn * 16 + (lane & 15);       // pupil column n
+          const int i0 = row0 + wr * 16 * WM + bm * 16 + 4 * (lane >> 4);  // pupil rows m = i0 .. i0+3 (< ceil(Ni/2))
+          if (j < N && i0 < M) {
+            // P0^T at rows m and at their mirrors Ni-1-m (stored at ld-1-m), the tilts
+            const float* q = p0 + (long long)j * a.ldp;
+            const f4 qr = *reinterpret_cast<const f4*>(q + i0);
+            const f4 qi = *reinterpret_cast<const f4*>(q + a.p0_plane + i0);
+            const f4 mr = rev4(*reinterpret_cast<const f4*>(q + (a.ldp - 4 - i0)));
+            const f4 mi = rev4(*reinterpret_cast<const f4*>(q + a.p0_plane + (a.ldp - 4 - i0)));
+            const f4 yr = *reinterpret_cast<const f4*>(tyb + i0);
+            const f4 yi = *reinterpret_cast<const f4*>(tyb + a.tilt_plane + i0);
+            const float xr = txb[j], xi = txb[a.tilt_plane + j];
+            const f4 tr = yr * xr - yi * xi, ti = yr * xi + yi * xr;   // ty[m] tx[n]
+            const f4 ur = yr * xr + yi * xi, ui = yr * xi - yi * xr;   // conj(ty[m]) tx[n]
+            const f4 plr = qr * tr - qi * ti, pli = qr * ti + qi * tr;
+            const f4 phr = mr * ur - mi * ui, phi = mr * ui + mi * ur;
+            const double xj = a.xcoord[j];
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+              const int i = i0 + r;
+              if (i < M) {
+                const float Pr = pr_[bm][bn][r], Pi = pi_[bm][bn][r], Rr = rr_[bm][bn][r], Ri = ri_[bm][bn][r];
+                const float g = kp * c * (plr[r] * (Pi + Rr) - pli[r] * (Pr - Ri));
+                const int im = a.mirror_n - 1 - i;
+                const float gm = im != i ? kp * c * (phr[r] * (Pi - Rr) - phi[r] * (Pr + Ri)) : 0.f;
+                slo[bm][bn][r] += g;
+                shi[bm][bn][r] += gm;
+                px += xj * ((double)g + (double)gm);
+                py += a.xcoord[i] * (double)g + a.xcoord[im] * (double)gm;
+              }
+            }
+          }
+        }
+      px = wave_sum(px);
+      py = wave_sum(py);
+      if (lane == 0) {
+        sred[2 * wave] = px;
+        sred[2 * wave + 1] = py;
+      }
+      __syncthreads();
+      if (tid == 0) {
+        double* o = a.red + (((long long)gb * a.ksplit + item % a.ksplit) * tiles + tile) * 2;
+        o[0] = sred[0] + sred[2] + sred[4] + sred[6];
+        o[1] = sred[1] + sred[3] + sred[5] + sred[7];
+      }
+    }
+  }
+
+  // ------------------------------------------------------------------ group epilogue
+  if constexpr (KIND == KIND_B4) {
+    float* dst = a.part + (long long)grp * a.mirror_n * N;
+#pragma unroll
+    for (int bm = 0; bm < WM; ++bm)
+#pragma unroll
+      for (int bn = 0; bn < WN; ++bn) {
+        const int j = col0 + wc * 16 * WN + bn * 16 + (lane & 15);
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const int i = row0 + wr * 16 * WM + bm * 16 + 4 * (lane >> 4) + r;
+          if (i < M && j < N) {
+            float* d = dst + (long long)i * N + j;
+            *d = (a.accumulate ? *d : 0.f) + slo[bm][bn][r];
+            const int im = a.mirror_n - 1 - i;
+            if (im != i) {
+              float* d2 = dst + (long long)im * N + j;
+              *d2 = (a.accumulate ? *d2 : 0.f) + shi[bm][bn][r];
+            }
+          }
+        }
+      }
+  }
+}
+
+// Folded tile shapes: the 4 x 4 tiles (and B4's 3 x 3 under BF16X3) would spill their
+// accumulators and are not compiled.
+constexpr bool fold_tile_ok(int kind, int prec, int wm, int wn) {
+  return !(wm == 4 && wn == 4) && !(kind == KIND_B4 && prec == 1 && wm == 3 && wn == 3);
+}
+
+template <int KIND, int WM, int WN, int PREC>
+hipError_t launch_fold(dim3 grid, dim3 block, const GemmArgs& a, hipStream_t st) {
+  if constexpr (fold_tile_ok(KIND, PREC, WM, WN)) {
+    hipLaunchKernelGGL((fgemm_kernel<KIND, WM, WN, PREC>), grid, block, 0, st, a);
+    return hipGetLastError();
+  } else {
+    return hipErrorInvalidValue;
+  }
+}
+
 template <int KIND, int PREC>
 hipError_t launch_kind(TileShape ts, const GemmArgs& a, int n_wg, hipStream_t st) {
   const dim3 grid(n_wg), block(256);
 #define DLX_TILE(WM_, WN_)                                                                     \
   if (ts.wm == WM_ && ts.wn == WN_) {                                                          \
+    if (a.fold) return launch_fold<KIND, WM_, WN_, PREC>(grid, block, a, st);                \
     hipLaunchKernelGGL((cgemm_kernel<KIND, WM_, WN_, PREC>), grid, block, 0, st, a);          \
     return hipGetLastError();                                                                  \
   }
@@ -583,9 +1153,9 @@ hipError_t launch_prec(int kind, TileShape ts, const GemmArgs& a, int n_wg, hipS
 
 }  // namespace
 
-bool tile_supported(int, TileShape ts) {
+bool tile_supported(int kind, int prec, bool fold, TileShape ts) {
   for (const TileShape& t : kTileShapes)
-    if (t.wm == ts.wm && t.wn == ts.wn) return true;
+    if (t.wm == ts.wm && t.wn == ts.wn) return !fold || fold_tile_ok(kind, prec, ts.wm, ts.wn);
   return false;
 }
 

@@ -83,9 +83,10 @@ __global__ void map_tmp_kernel(const float* C, const float* Bm, float* tmp, int 
 }
 
 // P0T_l[n][m] = A[m][n] / sqrt(sum A^2) * exp(i 2 pi OPD[m][n] / lambda_l), one block per
-// (32 x 32 tile, wavelength), transposed through LDS.
+// (32 x 32 tile, wavelength), transposed through LDS. Row n stores column m at m for m < h and at
+// m + ldp - Ni for h <= m < Ni (the folded layout; h = Ni: natural), zeros elsewhere.
 __global__ void pupil_kernel(const float* A, const double* opd, const float* screen, const double* norm_part,
-                             int n_norm, const WlInfo* wl, int Ni, int ldp, float* P0T, long long plane,
+                             int n_norm, const WlInfo* wl, int Ni, int ldp, int h, float* P0T, long long plane,
                              long long by_wl) {
   __shared__ float tr[32][33], ti[32][33];
   __shared__ double snorm;
@@ -122,8 +123,10 @@ __global__ void pupil_kernel(const float* A, const double* opd, const float* scr
     const int n = n0 + ty + 8 * q, m = m0 + tx;  // output row n, column m
     if (n < Ni && m < ldp) {
       const bool in = m < Ni;
-      P0T[l * by_wl + (long long)n * ldp + m] = in ? tr[tx][ty + 8 * q] : 0.f;
-      P0T[l * by_wl + plane + (long long)n * ldp + m] = in ? ti[tx][ty + 8 * q] : 0.f;
+      // the ldp - Ni padding columns m >= Ni fill the gap [h, h + ldp - Ni)
+      const int c = m < h ? m : (in ? m + (ldp - Ni) : h + (m - Ni));
+      P0T[l * by_wl + (long long)n * ldp + c] = in ? tr[tx][ty + 8 * q] : 0.f;
+      P0T[l * by_wl + plane + (long long)n * ldp + c] = in ? ti[tx][ty + 8 * q] : 0.f;
     }
   }
 }
@@ -257,8 +260,8 @@ hipError_t launch_prep(dlx_plan* p, const float* A, const float* Z, const float*
                      p->d_x, p->L, p->ldNi, nt, p->d_tx, p->d_ty, nt);
   const long long p0_by_wl = 2LL * p->Ni * p->ldNi;
   hipLaunchKernelGGL(pupil_kernel, dim3((p->Ni + 31) / 32, (p->ldNi + 31) / 32, p->L), dim3(32, 8), 0, st, A,
-                     p->d_opd, p->d_screen, p->d_norm, p->n_norm_part, p->d_wl, p->Ni, p->ldNi, p->d_P0T, (long long)p->Ni * p->ldNi,
-                     p0_by_wl);
+                     p->d_opd, p->d_screen, p->d_norm, p->n_norm_part, p->d_wl, p->Ni, p->ldNi,
+                     p->fold ? p->hNi() : p->Ni, p->d_P0T, (long long)p->Ni * p->ldNi, p0_by_wl);
   return hipGetLastError();
 }
 

@@ -24,10 +24,15 @@ constexpr int kLanes = 8;
 // element stride of the intra-pixel kernel between detector pixels: 0 (one kernel) or Q^2 (one per pixel)
 long long kstride(const dlx_plan* p) { return p->k_per_pixel ? (long long)p->Q * p->Q : 0; }
 
+// Stored column of focal-plane column c: the fields E and seed weights G of a folded plan keep
+// columns c < h in place and move c >= h to c + s (s = 0: natural order).
+__device__ __forceinline__ int fcol(int c, int h, int s) { return c < h ? c : c + s; }
+
 template <int QT>
 __global__ void intensity_kernel(const float* E, long long plane, long long by_psf, int ld, int f0, int F, int S, int L,
                                  int Qr, int Nd, const float* sources, const WlInfo* wl, const float* intrapixel,
-                                 long long kst, const float* flat, float* bs, float* binned, float* model) {
+                                 long long kst, int fh, int fs, const float* flat, float* bs, float* binned,
+                                 float* model) {
   __shared__ double sh[kLanes][64];
   const int Q = QT > 0 ? QT : Qr;
   const long long npix = (long long)Nd * Nd;
@@ -38,15 +43,31 @@ __global__ void intensity_kernel(const float* E, long long plane, long long by_p
   const int pr = live ? (int)(p / Nd) : 0, pc = live ? (int)(p - (long long)pr * Nd) : 0;
   // the intra-pixel kernel of this pixel: shared (kst = 0) or one per pixel (kst = Q^2)
   const float* kp = intrapixel ? intrapixel + (live ? p : 0) * kst : nullptr;
+  // this pixel's Q columns: contiguous from cb unless they straddle the fold's split
+  const int c0 = Q * pc;
+  const bool split = fs != 0 && c0 < fh && c0 + Q > fh;
+  const int cb = fcol(c0, fh, fs);
   double total = 0.0;
   for (int s = 0; s < S; ++s) {
     double acc = 0.0;
     if (live) {
       for (int l = y; l < L; l += kLanes) {
         const long long lb = ((long long)(f - f0) * S + s) * L + l;
-        const float* e = E + lb * by_psf + (long long)(Q * pr) * ld + Q * pc;
+        const float* e = E + lb * by_psf + (long long)(Q * pr) * ld;
         float part = 0.f;
-        if constexpr (QT == 4 || QT == 2) {
+        if (split) {   // rare (one pixel column): kept rolled so it costs the common path no registers
+#pragma unroll 1
+          for (int a = 0; a < Q; ++a)
+#pragma unroll 1
+            for (int b = 0; b < Q; ++b) {
+              const int c = fcol(c0 + b, fh, fs);
+              const float er = e[(long long)a * ld + c], ei = e[plane + (long long)a * ld + c];
+              float v = er * er + ei * ei;
+              if (kp) v *= kp[a * Q + b];
+              part += v;
+            }
+        } else if constexpr (QT == 4 || QT == 2) {
+          e += cb;
           typedef float vq __attribute__((ext_vector_type(QT)));
 #pragma unroll
           for (int a = 0; a < QT; ++a) {
@@ -60,6 +81,7 @@ __global__ void intensity_kernel(const float* E, long long plane, long long by_p
             }
           }
         } else {
+          e += cb;
           for (int a = 0; a < Q; ++a)
             for (int b = 0; b < Q; ++b) {
               const float er = e[(long long)a * ld + b], ei = e[plane + (long long)a * ld + b];
@@ -111,6 +133,7 @@ struct SeedOut {
   long long kst;          // 0: one kernel for all pixels, Q^2: one per pixel
   const float* bs;        // per-source binned [nf][S][npix]
   int Q, Nd, S, ldg;
+  int fh, fs;             // stored columns of G (see fcol)
   long long g_by_frame;
   float* G;               // [nf][No][ldg]
   double* flux;           // [F][S][gridDim.x]
@@ -164,10 +187,11 @@ __global__ void loss_kernel(const float* model, const float* binned, const float
       const float h = fp * rf;
       if (live) {
         const int pr = (int)(p / so.Nd), pc = (int)(p - (long long)pr * so.Nd);
-        float* g = so.G + fl * so.g_by_frame + (long long)(so.Q * pr) * so.ldg + so.Q * pc;
+        float* g = so.G + fl * so.g_by_frame + (long long)(so.Q * pr) * so.ldg;
         for (int a = 0; a < so.Q; ++a)
           for (int b = 0; b < so.Q; ++b)
-            g[(long long)a * so.ldg + b] = so.intrapixel ? h * so.intrapixel[p * so.kst + a * so.Q + b] : h;
+            g[(long long)a * so.ldg + fcol(so.Q * pc + b, so.fh, so.fs)] =
+                so.intrapixel ? h * so.intrapixel[p * so.kst + a * so.Q + b] : h;
       }
       for (int s = 0; s < so.S; ++s) {
         const double v = live ? (double)h * (double)so.bs[((long long)fl * so.S + s) * npix + p] : 0.0;
@@ -208,8 +232,8 @@ constexpr int kSeedThreads = 256;
 // partials sum_p flat[p] r_f[p] bs[f][s][p] = sum_l w_l sum G |E_{f,s,l}|^2 per
 // (frame, source) and pixel block, at flux[(f S + s) nblk + block].
 __global__ void seed_weight_kernel(const float* resid, const float* flat, const float* intrapixel, long long kst,
-                                   const float* bs, int f0, int Q, int Nd, int S, int ldg, long long g_by_frame,
-                                   float* G, int nblk, double* flux) {
+                                   const float* bs, int f0, int Q, int Nd, int S, int ldg, int fh, int fs,
+                                   long long g_by_frame, float* G, int nblk, double* flux) {
   __shared__ double sh[kSeedThreads / 64];
   const long long npix = (long long)Nd * Nd;
   const long long p = (long long)blockIdx.x * kSeedThreads + threadIdx.x;
@@ -219,9 +243,10 @@ __global__ void seed_weight_kernel(const float* resid, const float* flat, const 
   if (p < npix) {
     const int pr = (int)(p / Nd), pc = (int)(p - (long long)pr * Nd);
     h = flat[p] * resid[(long long)f * npix + p];
-    float* g = G + fl * g_by_frame + (long long)(Q * pr) * ldg + Q * pc;
+    float* g = G + fl * g_by_frame + (long long)(Q * pr) * ldg;
     for (int a = 0; a < Q; ++a)
-      for (int b = 0; b < Q; ++b) g[(long long)a * ldg + b] = intrapixel ? h * intrapixel[p * kst + a * Q + b] : h;
+      for (int b = 0; b < Q; ++b)
+        g[(long long)a * ldg + fcol(Q * pc + b, fh, fs)] = intrapixel ? h * intrapixel[p * kst + a * Q + b] : h;
   }
   for (int s = 0; s < S; ++s) {
     double v = 0.0;
@@ -283,8 +308,8 @@ __global__ void window_kernel(const float* Bbig, int Nb, const int* win, int Nd,
 // and the flux partials sum_q h[q] bs_s[q] of this block (one enlarged frame),
 // at flux[s nblk + block].
 __global__ void seed_gather_kernel(const float* resid, const float* flat, const float* intrapixel, const float* bs,
-                                   const int* win, int F, int Nd, int Nb, int Q, int S, int ldg, float* G,
-                                   double* flux) {
+                                   const int* win, int F, int Nd, int Nb, int Q, int S, int ldg, int fh, int fs,
+                                   float* G, double* flux) {
   __shared__ double sh[kSeedThreads / 64];
   const long long nb2 = (long long)Nb * Nb, npix = (long long)Nd * Nd;
   const long long q = (long long)blockIdx.x * kSeedThreads + threadIdx.x;
@@ -298,9 +323,10 @@ __global__ void seed_gather_kernel(const float* resid, const float* flat, const 
         h += flat[p] * resid[(long long)f * npix + p];
       }
     }
-    float* g = G + (long long)(Q * qr) * ldg + Q * qc;
+    float* g = G + (long long)(Q * qr) * ldg;
     for (int a = 0; a < Q; ++a)
-      for (int b = 0; b < Q; ++b) g[(long long)a * ldg + b] = intrapixel ? h * intrapixel[a * Q + b] : h;
+      for (int b = 0; b < Q; ++b)
+        g[(long long)a * ldg + fcol(Q * qc + b, fh, fs)] = intrapixel ? h * intrapixel[a * Q + b] : h;
   }
   for (int s = 0; s < S; ++s) {
     double v = q < nb2 ? (double)h * (double)bs[(long long)s * nb2 + q] : 0.0;
@@ -328,8 +354,8 @@ __global__ void seed_gather_kernel(const float* resid, const float* flat, const 
 template <int QT>
 __global__ void kgrad_kernel(const float* E, long long plane, long long by_psf, int ld, int f0, int S, int L,
                              int Nd, const float* sources, const WlInfo* wl, const float* flat, const float* resid,
-                             const int* win, int F_img, int Nd_img, double* part, double* gpix, int nf_pix,
-                             int accumulate) {
+                             const int* win, int F_img, int Nd_img, int fh, int fs, double* part, double* gpix,
+                             int nf_pix, int accumulate) {
   constexpr int Q2 = QT * QT;
   __shared__ double sh[Q2][kSeedThreads / 64];
   const long long npix = (long long)Nd * Nd;
@@ -362,13 +388,14 @@ __global__ void kgrad_kernel(const float* E, long long plane, long long by_psf, 
       for (int s = 0; s < S; ++s) {
         const float phi = sources[((long long)f * S + s) * 3 + 2];
         for (int l = 0; l < L; ++l) {
-          const float* e = E + (((long long)fl * S + s) * L + l) * by_psf + (long long)(QT * pr) * ld + QT * pc;
+          const float* e = E + (((long long)fl * S + s) * L + l) * by_psf + (long long)(QT * pr) * ld;
           const float wphi = wl[l].w * phi;
 #pragma unroll
           for (int a = 0; a < QT; ++a)
 #pragma unroll
             for (int b = 0; b < QT; ++b) {
-              const float er = e[(long long)a * ld + b], ei = e[plane + (long long)a * ld + b];
+              const int c = fcol(QT * pc + b, fh, fs);
+              const float er = e[(long long)a * ld + c], ei = e[plane + (long long)a * ld + c];
               v[a * QT + b] += (double)(wphi * (er * er + ei * ei));
             }
         }
@@ -543,7 +570,8 @@ hipError_t launch_intensity(dlx_plan* p, int f0, int nf, const float* sources, c
   const long long plane = (long long)p->chunk_psf * p->No * p->ldNo, by = (long long)p->No * p->ldNo;
 #define DLX_INTENSITY(QT)                                                                                         \
   hipLaunchKernelGGL(intensity_kernel<QT>, grid, blk, 0, st, p->d_Y, plane, by, p->ldNo, f0, p->F, p->S, p->L, \
-                     p->Q, p->Nd, sources, p->d_wl, intrapixel, kstride(p), flat, p->d_bs, binned, model)
+                     p->Q, p->Nd, sources, p->d_wl, intrapixel, kstride(p), p->hNo(), p->sNo(), flat, p->d_bs,   \
+                     binned, model)
   switch (p->Q) {
     case 2: DLX_INTENSITY(2); break;
     case 4: DLX_INTENSITY(4); break;
@@ -558,8 +586,8 @@ int seed_block_count(long long npix) { return (int)((npix + kSeedThreads - 1) / 
 hipError_t launch_seed(dlx_plan* p, int f0, int nf, const float* flat, const float* resid, const float* intrapixel,
                        hipStream_t st) {
   hipLaunchKernelGGL(seed_weight_kernel, dim3(p->seed_blocks, nf), dim3(kSeedThreads), 0, st, resid, flat, intrapixel,
-                     kstride(p), p->d_bs, f0, p->Q, p->Nd, p->S, p->ldNo, (long long)p->No * p->ldNo, p->d_G, p->seed_blocks,
-                     p->d_flux);
+                     kstride(p), p->d_bs, f0, p->Q, p->Nd, p->S, p->ldNo, p->hNo(), p->sNo(), (long long)p->No * p->ldNo,
+                     p->d_G, p->seed_blocks, p->d_flux);
   return hipGetLastError();
 }
 
@@ -583,7 +611,8 @@ hipError_t launch_window(dlx_plan* p, const float* flat, float* binned, float* m
 hipError_t launch_seed_gather(dlx_plan* p, const float* flat, const float* resid, const float* intrapixel,
                               hipStream_t st) {
   hipLaunchKernelGGL(seed_gather_kernel, dim3(p->seed_blocks), dim3(kSeedThreads), 0, st, resid, flat, intrapixel,
-                     p->d_bs, p->d_win, p->F_img, p->Nd_img, p->Nd, p->Q, p->S, p->ldNo, p->d_G, p->d_flux);
+                     p->d_bs, p->d_win, p->F_img, p->Nd_img, p->Nd, p->Q, p->S, p->ldNo, p->hNo(), p->sNo(), p->d_G,
+                     p->d_flux);
   return hipGetLastError();
 }
 
@@ -598,7 +627,8 @@ hipError_t launch_kgrad(dlx_plan* p, int f0, int nf, const float* sources, const
   double* gpix = p->k_per_pixel ? gK : nullptr;
 #define DLX_KGRAD(QT)                                                                                          \
   hipLaunchKernelGGL(kgrad_kernel<QT>, grid, blk, 0, st, p->d_Y, plane, by, p->ldNo, f0, p->S, p->L, p->Nd,  \
-                     sources, p->d_wl, flat, resid, win, p->F_img, p->Nd_img, p->d_kpart, gpix, nf, f0 > 0 ? 1 : 0)
+                     sources, p->d_wl, flat, resid, win, p->F_img, p->Nd_img, p->hNo(), p->sNo(), p->d_kpart, gpix, \
+                     nf, f0 > 0 ? 1 : 0)
   switch (p->Q) {
     case 1: DLX_KGRAD(1); break;
     case 2: DLX_KGRAD(2); break;
@@ -625,8 +655,8 @@ hipError_t launch_loss(dlx_plan* p, int f0, int nf, int chunk, const float* mode
   const double inv_s2 = 1.0 / (sigma * sigma);
   double* blk = p->d_lossblk + (long long)chunk * nb;
   if (seed_intrapixel_or_none) {
-    const SeedOut so{*seed_intrapixel_or_none, kstride(p), p->d_bs, p->Q, p->Nd, p->S, p->ldNo, (long long)p->No * p->ldNo,
-                     p->d_G, p->d_flux};
+    const SeedOut so{*seed_intrapixel_or_none, kstride(p), p->d_bs, p->Q, p->Nd, p->S, p->ldNo, p->hNo(), p->sNo(),
+                     (long long)p->No * p->ldNo, p->d_G, p->d_flux};
     hipLaunchKernelGGL(loss_kernel<true>, dim3(nb), dim3(kLossThreads), 0, st, model, binned, data, flat, f0, f0 + nf,
                        npix, kind, mu, inv_s2, r, gflat, chunk > 0 ? 1 : 0, blk, p->d_status, so);
   } else {

@@ -28,11 +28,13 @@ DLX_BF16X3 = 1
 DLX_LOSS_POISSON = 0
 DLX_LOSS_CHI2 = 1
 
-# Every symbol include/dlx.h declares.
 DLX_FLAG_NO_AUTOTUNE = 1
 DLX_FLAG_SEED_PASS = 2
 DLX_FLAG_STORE_FIELDS = 4
 DLX_FLAG_PIXEL_KERNEL = 8
+DLX_FLAG_DENSE_MFT = 16
+
+# Every symbol include/dlx.h declares.
 
 EXPORTS = ("dlx_validate", "dlx_plan_create", "dlx_plan_destroy", "dlx_plan_workspace_bytes", "dlx_plan_tiles",
            "dlx_plan_sync",

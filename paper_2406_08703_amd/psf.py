@@ -66,11 +66,14 @@ class PsfPlan:
     keeps every PSF's focal field from ``forward`` to the next ``backward``
     (which must get the same parameters), so that pair costs two MFTs per PSF
     instead of three, at the price of holding all PSFs in the workspace.
+    ``dense_mft`` computes the MFT as dense complex products instead of the
+    symmetric fold (a quarter of the work, same results up to rounding).
     """
 
     def __init__(self, geom: Geometry, transmission, zbasis, map_basis=None, intrapixel=None,
                  precision: str = "fp32", workspace_limit: int = 0, device="cuda", autotune: bool = True,
-                 seed_pass: bool = False, store_fields: bool = False, pixel_kernel: bool = False):
+                 seed_pass: bool = False, store_fields: bool = False, pixel_kernel: bool = False,
+                 dense_mft: bool = False):
         if not torch.cuda.is_available():
             raise RuntimeError("libdlx needs a ROCm GPU")
         self.geom = geom
@@ -90,7 +93,8 @@ class PsfPlan:
         with torch.cuda.device(self.device):
             flags = ((0 if autotune else _c.DLX_FLAG_NO_AUTOTUNE) | (_c.DLX_FLAG_SEED_PASS if seed_pass else 0)
                      | (_c.DLX_FLAG_STORE_FIELDS if store_fields else 0)
-                     | (_c.DLX_FLAG_PIXEL_KERNEL if pixel_kernel else 0))
+                     | (_c.DLX_FLAG_PIXEL_KERNEL if pixel_kernel else 0)
+                     | (_c.DLX_FLAG_DENSE_MFT if dense_mft else 0))
             self.plan = _c.dlx_plan_create(desc, 1, prec, flags, int(workspace_limit))
         self.precision = precision
 
@@ -307,7 +311,8 @@ class BatchPlan:
                "intrapixel", "images", "loss")
 
     def __init__(self, geoms, transmissions, zbases, map_bases=None, intrapixels=None, precision: str = "fp32",
-                 workspace_limit: int = 0, device="cuda", autotune: bool = True, store_fields: bool = False):
+                 workspace_limit: int = 0, device="cuda", autotune: bool = True, store_fields: bool = False,
+                 dense_mft: bool = False):
         if not torch.cuda.is_available():
             raise RuntimeError("libdlx needs a ROCm GPU")
         self.geoms = list(geoms)
@@ -325,7 +330,8 @@ class BatchPlan:
             self._keep.append(keep)
         prec = {"fp32": _c.DLX_FP32, "bf16x3": _c.DLX_BF16X3}[precision]
         with torch.cuda.device(self.device):
-            flags = (0 if autotune else _c.DLX_FLAG_NO_AUTOTUNE) | (_c.DLX_FLAG_STORE_FIELDS if store_fields else 0)
+            flags = ((0 if autotune else _c.DLX_FLAG_NO_AUTOTUNE) | (_c.DLX_FLAG_STORE_FIELDS if store_fields else 0)
+                     | (_c.DLX_FLAG_DENSE_MFT if dense_mft else 0))
             self.plan = _c.dlx_plan_create(descs, n, prec, flags, int(workspace_limit))
         self.precision = precision
         self.offsets = [_c.dlx_plan_offsets(self.plan, k) for k in range(_c.dlx_plan_problems(self.plan))]

@@ -15,10 +15,10 @@ def dev(a):
     return None if a is None else torch.from_numpy(np.ascontiguousarray(a, dtype=np.float32)).cuda()
 
 
-def make_plan(w, precision="fp32", workspace_limit=0, autotune=True, seed_pass=False):
+def make_plan(w, precision="fp32", workspace_limit=0, autotune=True, seed_pass=False, dense_mft=False):
     return PsfPlan(geometry(w), dev(w.transmission), dev(w.zbasis) if w.problem.n_zernike else None,
                    dev(w.map_basis), dev(w.intrapixel), precision=precision, workspace_limit=workspace_limit,
-                   autotune=autotune, seed_pass=seed_pass)
+                   autotune=autotune, seed_pass=seed_pass, dense_mft=dense_mft)
 
 
 def run_gpu(w, params=None, kind="poisson", plan=None, precision="fp32"):

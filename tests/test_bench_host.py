@@ -11,9 +11,15 @@ from synth import make_problem
 
 def test_stage_flops_sum_to_two_mfts_per_psf():
     P = make_problem("c2")
-    total = sum(bench.stage_flops(P, k) for k in ("F1", "F2", "B3", "B4"))
+    total = sum(bench.stage_flops(P, k, fold=False) for k in ("F1", "F2", "B3", "B4"))
     assert total == pytest.approx(2.0 * P.mft_flops())
     assert bench.stage_flops(P, "BIN") is None
+    # the symmetric fold runs a quarter of the dense products on even sizes
+    assert bench.mft_executed_flops(P) == pytest.approx(0.5 * P.mft_flops())
+    # odd sizes: halves rounded up (the middle sample has no partner)
+    Q = make_problem("c2", n_pupil=5, n_focal=7, oversample=1)
+    assert bench.stage_flops(Q, "F1") == 8.0 * 4 * 5 * 3
+    assert bench.stage_flops(Q, "B4") == 8.0 * 3 * 5 * 4
 
 
 def test_roofline_entry_from_launch_times():
@@ -23,7 +29,9 @@ def test_roofline_entry_from_launch_times():
     tiles = {"F1": (64, 32), "F2": (64, 64), "B3": (32, 64), "B4": (64, 32)}
     r = bench.gemm_roofline(P, gemm, tiles, "fp32", "nonexistent-config")
     flops = bench.stage_flops(P, "B3") * 20
-    assert r["kernel"] == "cgemm_kernel<3, 1, 2, 0> (B3)"
+    assert r["kernel"] == "fgemm_kernel<3, 1, 2, 0> (B3)"
+    assert bench.gemm_roofline(P, gemm, tiles, "fp32", "nonexistent-config", fold=False)["achieved"] == \
+        pytest.approx(4 * r["achieved"], rel=1e-3)
     assert r["achieved"] == pytest.approx(flops / 0.2e-3 / 1e12, rel=1e-3)
     assert r["frac"] == pytest.approx(r["achieved"] / 157.3, rel=1e-3)
     assert r["traffic"] is None

@@ -94,12 +94,14 @@ def run(w, plan, fused, sources=None):
     return to_np(out)
 
 
+@pytest.mark.parametrize("dense", [False, True])
 @pytest.mark.parametrize("fused", [False, True])
 @pytest.mark.parametrize("name", list(CASES))
-def test_dither_mode_matches_oracle(name, fused):
-    print(f"dither {name} fused={fused}", flush=True)
+def test_dither_mode_matches_oracle(name, fused, dense):
+    # dense: the dense complex MFT products instead of the symmetric fold
+    print(f"dither {name} fused={fused} dense={dense}", flush=True)
     w, ref = case(name)
-    plan = plan_for(w)
+    plan = plan_for(w, dense_mft=dense)
     got = run(w, plan, fused)
     plan.close()
     assert got["grad_sources"].shape == (w.problem.n_sources, 3)
@@ -131,7 +133,9 @@ def test_dither_mode_equals_per_frame_path_on_gpu():
     pf.close()
     for k in ("binned", "model", "r", "grad_flat", "grad_coeffs"):
         assert rel_l2(a[k], b[k]) < 1e-5, k
-    assert abs(a["loss"] - b["loss"]) < 1e-9 * abs(b["loss"])
+    # to first order the loss moves by sum r dm: an elementwise model error eps (FP32 rounding of the
+    # MFT, about 1e-7 here) bounds |dL| by eps sum |r m|
+    assert abs(a["loss"] - b["loss"]) < 1e-6 * np.sum(np.abs(b["r"] * b["model"]))
     assert rel_l2(a["grad_sources"], b["grad_sources"].sum(axis=0)) < 1e-5
 
 
