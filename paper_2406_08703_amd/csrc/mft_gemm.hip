@@ -562,8 +562,11 @@ __global__ __launch_bounds__(256) void cgemm_kernel(const GemmArgs a) {
 // writes out[a] = P + i R and out[mirror a] = P - i R.
 __device__ __forceinline__ f4 rev4(f4 v) { return f4{v[3], v[2], v[1], v[0]}; }
 
+// FP32: at least two workgroups per CU. The register bound keeps B4's 64 x 64 tile at two waves
+// per SIMD (its epilogue's registers would leave one); the larger FP32 shapes would spill under
+// it and are not compiled (fold_tile_ok).
 template <int KIND, int WM, int WN, int PREC>
-__global__ __launch_bounds__(256) void fgemm_kernel(const GemmArgs a) {
+__global__ __launch_bounds__(256, PREC == 0 ? 2 : 1) void fgemm_kernel(const GemmArgs a) {
   constexpr bool DA = KIND != KIND_F2;   // DFT operand on the A side (rows i), data on the B side
   constexpr int BM = 32 * WM, BN = 32 * WN;
   constexpr int BK = PREC == 0 ? 16 : 32;
@@ -803,17 +806,19 @@ __global__ __launch_bounds__(256) void fgemm_kernel(const GemmArgs a) {
             }
             // K tail and the unpaired middle term (assigned after the products: padding is not read)
             const int kb = gx_k[r] + 4 * v;
+            if (kb + 4 > k_hi || (kmid >= kb && kmid < kb + 4)) {
 #pragma unroll
-            for (int e = 0; e < 4; ++e) {
-              if (kb + e >= k_hi) {
-                xr[e] = 0.f;
-                xi[e] = 0.f;
-                yr[e] = 0.f;
-                yi[e] = 0.f;
-              }
-              if (kb + e == kmid) {
-                yr[e] = 0.f;
-                yi[e] = 0.f;
+              for (int e = 0; e < 4; ++e) {
+                if (kb + e >= k_hi) {
+                  xr[e] = 0.f;
+                  xi[e] = 0.f;
+                  yr[e] = 0.f;
+                  yi[e] = 0.f;
+                }
+                if (kb + e == kmid) {
+                  yr[e] = 0.f;
+                  yi[e] = 0.f;
+                }
               }
             }
             er[v] = xr + yr;
@@ -1104,10 +1109,11 @@ __global__ __launch_bounds__(256) void fgemm_kernel(const GemmArgs a) {
   }
 }
 
-// Folded tile shapes: the 4 x 4 tiles (and B4's 3 x 3 under BF16X3) would spill their
-// accumulators and are not compiled.
+// Folded tile shapes compiled: those that keep their accumulators in registers. FP32 (two
+// workgroups per CU): 64 x 64, 64 x 32, 32 x 64. BF16X3: all but 128 x 128 (and B4's 96 x 96).
 constexpr bool fold_tile_ok(int kind, int prec, int wm, int wn) {
-  return !(wm == 4 && wn == 4) && !(kind == KIND_B4 && prec == 1 && wm == 3 && wn == 3);
+  if (prec == 0) return wm * wn <= 4 && wm <= 2 && wn <= 2;
+  return !(wm == 4 && wn == 4) && !(kind == KIND_B4 && wm == 3 && wn == 3);
 }
 
 template <int KIND, int WM, int WN, int PREC>
