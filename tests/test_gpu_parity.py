@@ -29,6 +29,10 @@ CASES = {
     "c2-odd": ("c2", dict(n_pupil=50, n_focal=124, n_wavelengths=4, noll=tuple(range(2, 10)))),
     # degenerate: no Zernike terms, a 4 x 4 detector
     "tiny-noz": ("c1", dict(n_pupil=16, n_focal=8, noll=())),
+    # odd pupil and focal sizes (unpaired middle samples on both sides of the symmetric fold),
+    # Q = 3, and the paper's Q = 1 sampling with an obstructed, odd pupil
+    "odd-q3": ("c1", dict(n_pupil=33, n_focal=39, oversample=3, noll=tuple(range(2, 12)))),
+    "odd-q1": ("c2", dict(n_pupil=31, n_focal=37, oversample=1, n_wavelengths=3, noll=tuple(range(2, 9)))),
 }
 
 
@@ -318,7 +322,7 @@ def test_intrapixel_gradient_rejects_large_oversampling():
 
 
 @pytest.mark.parametrize("prec", ["fp32", "bf16x3"])
-@pytest.mark.parametrize("case", ["c3-small", "c5-small", "c2-odd", "tiny-noz"])
+@pytest.mark.parametrize("case", ["c3-small", "c5-small", "c2-odd", "tiny-noz", "odd-q3", "odd-q1"])
 def test_dense_and_folded_mft_agree_with_the_oracle(case, prec):
     """The dense complex products (DLX_FLAG_DENSE_MFT) and the symmetric fold (default) compute the
     same evaluation: each matches the oracle, and the two agree to rounding. The cases cover odd and
