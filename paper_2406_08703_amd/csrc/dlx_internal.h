@@ -84,8 +84,8 @@ struct GemmArgs {
   // B3: seed weights G of the chunk's frames [nf][No][ldg]
   const float* seedw;
   long long seedw_by_frame;
-  // dense outputs (F1: T, F2: E, B3: U^T), indexed by local PSF;
-  // E is FP32, the others are split BF16 under BF16X3
+  // dense outputs (F1: T, F2: E, B3: U^T), indexed by local PSF; E is FP32, the others are
+  // split BF16 under BF16X3 in the dense kernels and FP32 in the folded ones
   void* out;
   long long out_plane;
   long long out_by_psf;
@@ -113,7 +113,7 @@ struct TileShape {
 };
 
 // Tile shapes compiled for every stage and precision (the autotuner's candidates).
-constexpr TileShape kTileShapes[] = {{4, 4}, {3, 3}, {2, 2}, {4, 2}, {2, 4}, {2, 1}, {1, 2}};
+constexpr TileShape kTileShapes[] = {{4, 4}, {3, 3}, {2, 2}, {4, 2}, {2, 4}, {2, 1}, {1, 2}, {1, 1}};
 
 hipError_t launch_gemm(int kind, int prec, TileShape ts, const GemmArgs& a, int n_wg, hipStream_t st);
 bool tile_supported(int kind, int prec, bool fold, TileShape ts);

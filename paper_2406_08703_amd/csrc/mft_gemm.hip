@@ -1142,6 +1142,7 @@ hipError_t launch_kind(TileShape ts, const GemmArgs& a, int n_wg, hipStream_t st
   DLX_TILE(2, 4)
   DLX_TILE(2, 1)
   DLX_TILE(1, 2)
+  DLX_TILE(1, 1)
 #undef DLX_TILE
   return hipErrorInvalidValue;
 }
