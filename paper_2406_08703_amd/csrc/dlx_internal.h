@@ -113,7 +113,7 @@ struct TileShape {
 };
 
 // Tile shapes compiled for every stage and precision (the autotuner's candidates).
-constexpr TileShape kTileShapes[] = {{4, 4}, {3, 3}, {2, 2}, {4, 2}, {2, 4}, {2, 1}, {1, 2}, {1, 1}};
+constexpr TileShape kTileShapes[] = {{4, 4}, {3, 3}, {2, 2}, {4, 2}, {2, 4}, {2, 1}, {1, 2}, {1, 1}, {4, 1}, {1, 4}};
 
 hipError_t launch_gemm(int kind, int prec, TileShape ts, const GemmArgs& a, int n_wg, hipStream_t st);
 bool tile_supported(int kind, int prec, bool fold, TileShape ts);

@@ -1110,9 +1110,10 @@ __global__ __launch_bounds__(256, PREC == 0 ? 2 : 1) void fgemm_kernel(const Gem
 }
 
 // Folded tile shapes compiled: those that keep their accumulators in registers. FP32 (two
-// workgroups per CU): 64 x 64, 64 x 32, 32 x 64. BF16X3: all but 128 x 128 (and B4's 96 x 96).
+// workgroups per CU): up to four 32 x 32 blocks, except B4's 128 x 32 and 32 x 128. BF16X3: all
+// but 128 x 128 (and B4's 96 x 96).
 constexpr bool fold_tile_ok(int kind, int prec, int wm, int wn) {
-  if (prec == 0) return wm * wn <= 4 && wm <= 2 && wn <= 2;
+  if (prec == 0) return wm * wn <= 4 && !(kind == KIND_B4 && wm != wn && wm * wn == 4);
   return !(wm == 4 && wn == 4) && !(kind == KIND_B4 && wm == 3 && wn == 3);
 }
 
@@ -1143,6 +1144,8 @@ hipError_t launch_kind(TileShape ts, const GemmArgs& a, int n_wg, hipStream_t st
   DLX_TILE(2, 1)
   DLX_TILE(1, 2)
   DLX_TILE(1, 1)
+  DLX_TILE(4, 1)
+  DLX_TILE(1, 4)
 #undef DLX_TILE
   return hipErrorInvalidValue;
 }
