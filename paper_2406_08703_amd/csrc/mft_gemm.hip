@@ -29,6 +29,11 @@
 // row tilt; B3: the adjoint seed w phi G E from the stored field E and the
 // frame's seed weights G) and into the epilogues (F1: the column tilt; F2:
 // the focal-field scale; B4: the phase gradient and position sums).
+//
+// Two kernels implement the stages: cgemm_kernel computes the dense complex
+// products, fgemm_kernel (the default) the symmetric fold of each product
+// (pair sums and differences over half the depth and half the DFT rows; see
+// dlx_internal.h), with the same loader and epilogue work.
 #include <type_traits>
 
 #include "dlx_internal.h"
@@ -579,7 +584,6 @@ __global__ __launch_bounds__(256, PREC == 0 ? 2 : 1) void fgemm_kernel(const Gem
   constexpr int D_EL = ND * RD * LDK, X_EL = NX * RX * LDK;
   constexpr int UNITS_D = RD * 4, UNITS_X = RX * 4;
   constexpr int D_U = (UNITS_D + 255) / 256, X_U = (UNITS_X + 255) / 256;
-  constexpr bool kW = KIND == KIND_F1 || KIND == KIND_B3;   // loader product with a second source
   using el_t = typename std::conditional<PREC == 0, float, unsigned short>::type;
   __shared__ __attribute__((aligned(16))) el_t smem[D_EL + X_EL];
   __shared__ double sred[8];
