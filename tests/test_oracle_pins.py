@@ -651,3 +651,31 @@ def test_per_pixel_kernel_gradient_central_differences_and_euler():
         assert abs(fd - g[idx]) <= 1e-6 * max(abs(g[idx]), 1e-3 * np.abs(g).max()), idx
     euler = np.sum(np.asarray(p["flat"], np.float64)[None] * base["r"] * base["binned"])
     assert abs(np.sum(Kp * g) - euler) <= 1e-10 * np.sum(np.abs(Kp * g))
+
+
+@pytest.mark.parametrize("ni,no", [(8, 6), (7, 9), (33, 39), (16, 5), (1, 4)])
+def test_centred_grid_dft_folds_to_pair_sums_and_differences(ni, no):
+    """The identity the GPU path's symmetric fold rests on, on the oracle's own grids (Section 3's
+    pixel-centred samples): reversing either index of the DFT matrix conjugates it, so the product
+    with any X equals, row a and its mirror, P +- iR with P = Re(M) (X + X_rev) and R = Im(M) (X - X_rev)
+    over half the depth; the middle sample of an odd length enters once."""
+    rng = np.random.default_rng(ni * 100 + no)
+    lam = 6e-7
+    x = O.pixel_grid(ni, 0.5 / ni)
+    u = O.pixel_grid(no, 1.5e-7)
+    M = O.dft_matrix(x, u, lam)
+    assert np.max(np.abs(M[:, ::-1] - np.conj(M))) < 1e-13
+    assert np.max(np.abs(M[::-1, :] - np.conj(M))) < 1e-13
+    X = rng.normal(size=(ni, 3)) + 1j * rng.normal(size=(ni, 3))
+    hk, ha = (ni + 1) // 2, (no + 1) // 2
+    Xm = X[::-1].copy()
+    if ni % 2:
+        Xm[hk - 1] = 0.0   # the middle sample is its own mirror
+    Xe, Xo = X[:hk] + Xm[:hk], X[:hk] - Xm[:hk]
+    P = M[:ha, :hk].real @ Xe
+    R = M[:ha, :hk].imag @ Xo
+    dense = M @ X
+    scale = np.max(np.abs(dense))
+    assert np.max(np.abs((P + 1j * R) - dense[:ha])) < 1e-12 * scale
+    mirror = no - 1 - np.arange(ha)
+    assert np.max(np.abs((P - 1j * R) - dense[mirror])) < 1e-12 * scale
