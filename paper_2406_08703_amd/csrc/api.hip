@@ -30,6 +30,9 @@ hipError_t launch_loss(dlx_plan* p, int f0, int nf, int chunk, const float* mode
                        const float* data, const float* flat, int kind, double mu, double sigma, float* r, double* gflat,
                        const float* const* seed_intrapixel_or_none, hipStream_t st);
 hipError_t launch_loss_final(dlx_plan* p, int n_chunks, double* loss, hipStream_t st);
+hipError_t launch_bin_loss(dlx_plan* p, int f0, int nf, int chunk, const float* sources, const float* intrapixel,
+                           const float* flat, const float* data, int kind, double mu, double sigma, float* binned,
+                           float* model, float* r, double* gflat, hipStream_t st);
 hipError_t launch_grad_reduce(dlx_plan* p, const float* Z, const float* Bm, double* gz, double* gmap, double* gsrc,
                               double* loss, int loss_chunks, double* gK, hipStream_t st);
 hipError_t launch_kgrad(dlx_plan* p, int f0, int nf, const float* sources, const float* flat, const float* resid,
@@ -112,10 +115,11 @@ void layout(dlx_plan* p, Pool& pool) {
   }
   p->d_gpart = pool.take<float>((size_t)p->b4_groups_max * p->ksplit_cap * Ni * Ni);
   p->d_gopd = pool.take<double>(Ni * Ni);
-  p->d_flux = pool.take<double>((size_t)p->F * p->S * p->seed_blocks);
+  const size_t pix64 = ((size_t)p->Nd * p->Nd + 63) / 64;   // bin_loss_kernel's pixel blocks
+  p->d_flux = pool.take<double>((size_t)p->F * p->S * std::max<size_t>(p->seed_blocks, pix64));
   p->d_kpart = pool.take<double>((size_t)p->F * p->seed_blocks * p->Q * p->Q);
   p->d_pos = pool.take<double>((size_t)p->n_psf * p->ksplit_cap * p->tiles_b4_cap * 2);
-  p->d_lossblk = pool.take<double>((size_t)p->loss_blocks * p->n_chunks);
+  p->d_lossblk = pool.take<double>(std::max<size_t>(p->loss_blocks, pix64) * p->n_chunks);
   p->d_tmp2 = pool.take<double>(std::max<size_t>(1, Ni * (size_t)p->Nmap));
   p->d_zpart = pool.take<double>((size_t)std::max(1, zproj_chunks((long long)Ni * Ni, p->Nz)) * std::max(1, p->Nz));
   p->d_status = pool.take<int>(1);
@@ -1134,11 +1138,18 @@ dlx_status dlx_eval(dlx_plan* p, const dlx_eval_args* a, void* stream) {
       if (a->grad_intrapixel) DLX_HIP(launch_kgrad(p, f0, nf, a->sources, a->flat, a->dloss_dmodel, a->grad_intrapixel, st));
       if (p->seed_pass) DLX_HIP(launch_seed_apply(p, f0, nf, a->sources, st));
     } else {
-      {
+      if (p->frames_per_chunk == 1) {
+        // one frame per chunk: binning, model, loss, residual, seed weights and flux partials in one
+        // pass (with several frames per chunk the frames would serialise inside each block)
         Stage sg(p, st, DLX_STAGE_BIN, nc);
-        DLX_HIP(launch_intensity(p, f0, nf, a->sources, a->intrapixel, a->flat, a->binned, a->model, st));
-      }
-      {  // loss, residual and the adjoint seed weights in one pass over the pixels
+        DLX_HIP(launch_bin_loss(p, f0, nf, c, a->sources, a->intrapixel, a->flat, a->data, (int)a->loss_kind,
+                                a->prior_mu, a->prior_sigma, a->binned, a->model, a->dloss_dmodel, a->grad_flat, st));
+      } else {
+        {
+          Stage sg(p, st, DLX_STAGE_BIN, nc);
+          DLX_HIP(launch_intensity(p, f0, nf, a->sources, a->intrapixel, a->flat, a->binned, a->model, st));
+        }
+        // loss, residual and the adjoint seed weights in one pass over the pixels
         Stage sg(p, st, DLX_STAGE_LOSS, nc);
         DLX_HIP(launch_loss(p, f0, nf, c, a->model, a->binned, a->data, a->flat, (int)a->loss_kind, a->prior_mu,
                             a->prior_sigma, a->dloss_dmodel, a->grad_flat, &a->intrapixel, st));

@@ -192,6 +192,9 @@ struct dlx_plan {
   int* d_status = nullptr;
   int loss_blocks = 0;
   int seed_blocks = 0;   // pixel blocks of the seed-weight kernel
+  // partial counts of the last launches that wrote them (flux partials per (frame, star); loss
+  // partials per chunk): seed kernels and loss_kernel use 256-pixel blocks, bin_loss_kernel 64
+  int flux_blocks = 0, lossblk_chunk = 0;
   bool seed_pass = false; // form Y = w phi G E in a separate pass (large frames) instead of in B3's loader
   // stage timing (diagnostics)
   bool profiling = false;

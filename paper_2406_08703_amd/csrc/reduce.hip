@@ -28,6 +28,51 @@ long long kstride(const dlx_plan* p) { return p->k_per_pixel ? (long long)p->Q *
 // columns c < h in place and move c >= h to c + s (s = 0: natural order).
 __device__ __forceinline__ int fcol(int c, int h, int s) { return c < h ? c : c + s; }
 
+// sum over a detector pixel's Q x Q focal samples of K |E|^2 for one PSF: e points at the pixel's
+// first focal row; its Q columns start at stored column cb, or (split) straddle the fold's split
+// and are mapped one by one from c0.
+template <int QT>
+__device__ __forceinline__ float pixel_power(const float* e, long long plane, int ld, int Q, int c0, int cb, bool split,
+                                             int fh, int fs, const float* kp) {
+  float part = 0.f;
+  if (split) {   // rare (one pixel column): kept rolled so it costs the common path no registers
+#pragma unroll 1
+    for (int a = 0; a < Q; ++a)
+#pragma unroll 1
+      for (int b = 0; b < Q; ++b) {
+        const int c = fcol(c0 + b, fh, fs);
+        const float er = e[(long long)a * ld + c], ei = e[plane + (long long)a * ld + c];
+        float v = er * er + ei * ei;
+        if (kp) v *= kp[a * Q + b];
+        part += v;
+      }
+  } else if constexpr (QT == 4 || QT == 2) {
+    e += cb;
+    typedef float vq __attribute__((ext_vector_type(QT)));
+#pragma unroll
+    for (int a = 0; a < QT; ++a) {
+      const vq vr = *reinterpret_cast<const vq*>(e + (long long)a * ld);
+      const vq vi = *reinterpret_cast<const vq*>(e + plane + (long long)a * ld);
+#pragma unroll
+      for (int b = 0; b < QT; ++b) {
+        float v = vr[b] * vr[b] + vi[b] * vi[b];
+        if (kp) v *= kp[a * QT + b];
+        part += v;
+      }
+    }
+  } else {
+    e += cb;
+    for (int a = 0; a < Q; ++a)
+      for (int b = 0; b < Q; ++b) {
+        const float er = e[(long long)a * ld + b], ei = e[plane + (long long)a * ld + b];
+        float v = er * er + ei * ei;
+        if (kp) v *= kp[a * Q + b];
+        part += v;
+      }
+  }
+  return part;
+}
+
 template <int QT>
 __global__ void intensity_kernel(const float* E, long long plane, long long by_psf, int ld, int f0, int F, int S, int L,
                                  int Qr, int Nd, const float* sources, const WlInfo* wl, const float* intrapixel,
@@ -54,42 +99,7 @@ __global__ void intensity_kernel(const float* E, long long plane, long long by_p
       for (int l = y; l < L; l += kLanes) {
         const long long lb = ((long long)(f - f0) * S + s) * L + l;
         const float* e = E + lb * by_psf + (long long)(Q * pr) * ld;
-        float part = 0.f;
-        if (split) {   // rare (one pixel column): kept rolled so it costs the common path no registers
-#pragma unroll 1
-          for (int a = 0; a < Q; ++a)
-#pragma unroll 1
-            for (int b = 0; b < Q; ++b) {
-              const int c = fcol(c0 + b, fh, fs);
-              const float er = e[(long long)a * ld + c], ei = e[plane + (long long)a * ld + c];
-              float v = er * er + ei * ei;
-              if (kp) v *= kp[a * Q + b];
-              part += v;
-            }
-        } else if constexpr (QT == 4 || QT == 2) {
-          e += cb;
-          typedef float vq __attribute__((ext_vector_type(QT)));
-#pragma unroll
-          for (int a = 0; a < QT; ++a) {
-            const vq vr = *reinterpret_cast<const vq*>(e + (long long)a * ld);
-            const vq vi = *reinterpret_cast<const vq*>(e + plane + (long long)a * ld);
-#pragma unroll
-            for (int b = 0; b < QT; ++b) {
-              float v = vr[b] * vr[b] + vi[b] * vi[b];
-              if (kp) v *= kp[a * QT + b];
-              part += v;
-            }
-          }
-        } else {
-          e += cb;
-          for (int a = 0; a < Q; ++a)
-            for (int b = 0; b < Q; ++b) {
-              const float er = e[(long long)a * ld + b], ei = e[plane + (long long)a * ld + b];
-              float v = er * er + ei * ei;
-              if (kp) v *= kp[a * Q + b];
-              part += v;
-            }
-        }
+        const float part = pixel_power<QT>(e, plane, ld, Q, c0, cb, split, fh, fs, kp);
         acc += (double)wl[l].w * (double)part;
       }
     }
@@ -124,6 +134,119 @@ __device__ __forceinline__ double block_sum(double v, double* sh) {
     for (int i = 0; i < (int)(blockDim.x >> 6); ++i) t += sh[i];
   __syncthreads();
   return t;
+}
+
+
+// The fused evaluation's binning and loss in one pass (in place of intensity_kernel followed by
+// loss_kernel<true>): a block of 64 x kLanes threads covers 64 detector pixels and every frame of
+// the chunk. For each pixel and frame the kLanes wavelength lanes form the per-star binned values
+// (as intensity_kernel); the first wave then forms, as loss_kernel<true> does, the model, the loss
+// terms, the residual r, the seed weights G = K flat r and, per star, the block's flux partial
+// sum of flat r bs at flux[(f S + s) gridDim.x + block]. The flat-field gradient sums over the
+// frames in a register; the loss partial of the block goes to blk[block].
+template <int QT>
+__global__ void bin_loss_kernel(const float* E, long long plane, long long by_psf, int ld, int f0, int nf, int S, int L,
+                                int Qr, int Nd, const float* sources, const WlInfo* wl, const float* intrapixel,
+                                long long kst, int fh, int fs, const float* flat, const float* data, int kind,
+                                double mu, double inv_s2, float* bs, float* binned, float* model, float* r_out,
+                                double* grad_flat, int accumulate, double* blk, int* status, float* G, int ldg,
+                                long long g_by_frame, double* flux) {
+  __shared__ double sh[kLanes][64];
+  const int Q = QT > 0 ? QT : Qr;
+  const long long npix = (long long)Nd * Nd;
+  const int x = threadIdx.x, y = threadIdx.y;
+  const long long p = (long long)blockIdx.x * 64 + x;
+  const bool live = p < npix;
+  const int pr = live ? (int)(p / Nd) : 0, pc = live ? (int)(p - (long long)pr * Nd) : 0;
+  const float* kp = intrapixel ? intrapixel + (live ? p : 0) * kst : nullptr;
+  const int c0 = Q * pc;
+  const bool split = fs != 0 && c0 < fh && c0 + Q > fh;
+  const int cb = fcol(c0, fh, fs);
+  const float fp = live ? flat[p] : 0.f;
+  double gf = 0.0, lsum = 0.0;
+  int flags = 0;
+  for (int fl = 0; fl < nf; ++fl) {
+    const int f = f0 + fl;
+    double total = 0.0;
+    for (int s = 0; s < S; ++s) {
+      double acc = 0.0;
+      if (live) {
+        for (int l = y; l < L; l += kLanes) {
+          const long long lb = ((long long)fl * S + s) * L + l;
+          const float* e = E + lb * by_psf + (long long)(Q * pr) * ld;
+          acc += (double)wl[l].w * (double)pixel_power<QT>(e, plane, ld, Q, c0, cb, split, fh, fs, kp);
+        }
+      }
+      sh[y][x] = acc;
+      __syncthreads();
+      if (y == 0 && live) {
+        double v = 0.0;
+#pragma unroll
+        for (int k = 0; k < kLanes; ++k) v += sh[k][x];
+        bs[((long long)fl * S + s) * npix + p] = (float)v;
+        total += (double)sources[((long long)f * S + s) * 3 + 2] * v;
+      }
+      __syncthreads();
+    }
+    float h = 0.f;
+    if (y == 0 && live) {
+      const float bv = (float)total;
+      const float mv = fp * bv;
+      const long long q = (long long)f * npix + p;
+      binned[q] = bv;
+      model[q] = mv;
+      double m = mv;
+      const double d = data[q];
+      const double b = bv;
+      if (!isfinite(m) || !isfinite(d)) flags |= 1;
+      double ell, r;
+      if (kind == DLX_LOSS_POISSON) {
+        if (m <= 0.0) {
+          if (d > 0.0) flags |= 2;
+          m = 1e-30;
+        }
+        ell = m - (d != 0.0 ? d * log(m) : 0.0);
+        r = 1.0 - d / m;
+      } else {
+        const double w = d > 1.0 ? d : 1.0;
+        const double dm = m - d;
+        ell = 0.5 * dm * dm / w;
+        r = dm / w;
+      }
+      lsum += ell;
+      const float rf = (float)r;
+      r_out[q] = rf;
+      gf += r * b;
+      h = fp * rf;
+      float* g = G + fl * g_by_frame + (long long)(Q * pr) * ldg;
+      for (int a = 0; a < Q; ++a)
+        for (int bb = 0; bb < Q; ++bb)
+          g[(long long)a * ldg + fcol(Q * pc + bb, fh, fs)] = intrapixel ? h * intrapixel[p * kst + a * Q + bb] : h;
+    }
+    if (y == 0) {   // the first wave: this frame's flux partials of the block, per star
+      for (int s = 0; s < S; ++s) {
+        double v = live ? (double)h * (double)bs[((long long)fl * S + s) * npix + p] : 0.0;
+#pragma unroll
+        for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+        if (x == 0) flux[((long long)f * S + s) * gridDim.x + blockIdx.x] = v;
+      }
+    }
+  }
+  if (y == 0) {
+    if (live) {
+      if (accumulate) {
+        grad_flat[p] += gf;
+      } else {
+        const double dfl = (double)fp - mu;
+        lsum += 0.5 * dfl * dfl * inv_s2;
+        grad_flat[p] = gf + dfl * inv_s2;
+      }
+    }
+    if (flags) atomicOr(status, flags);  // bit 0: non-finite, bit 1: domain
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) lsum += __shfl_xor(lsum, o, 64);
+    if (x == 0) blk[blockIdx.x] = lsum;
+  }
 }
 
 // Outputs of the adjoint seed, when the loss kernel also forms it (fused
@@ -585,6 +708,7 @@ int seed_block_count(long long npix) { return (int)((npix + kSeedThreads - 1) / 
 
 hipError_t launch_seed(dlx_plan* p, int f0, int nf, const float* flat, const float* resid, const float* intrapixel,
                        hipStream_t st) {
+  p->flux_blocks = p->seed_blocks;
   hipLaunchKernelGGL(seed_weight_kernel, dim3(p->seed_blocks, nf), dim3(kSeedThreads), 0, st, resid, flat, intrapixel,
                      kstride(p), p->d_bs, f0, p->Q, p->Nd, p->S, p->ldNo, p->hNo(), p->sNo(), (long long)p->No * p->ldNo,
                      p->d_G, p->seed_blocks, p->d_flux);
@@ -610,6 +734,7 @@ hipError_t launch_window(dlx_plan* p, const float* flat, float* binned, float* m
 
 hipError_t launch_seed_gather(dlx_plan* p, const float* flat, const float* resid, const float* intrapixel,
                               hipStream_t st) {
+  p->flux_blocks = p->seed_blocks;
   hipLaunchKernelGGL(seed_gather_kernel, dim3(p->seed_blocks), dim3(kSeedThreads), 0, st, resid, flat, intrapixel,
                      p->d_bs, p->d_win, p->F_img, p->Nd_img, p->Nd, p->Q, p->S, p->ldNo, p->hNo(), p->sNo(), p->d_G,
                      p->d_flux);
@@ -654,7 +779,9 @@ hipError_t launch_loss(dlx_plan* p, int f0, int nf, int chunk, const float* mode
   const int nb = loss_block_count(npix);
   const double inv_s2 = 1.0 / (sigma * sigma);
   double* blk = p->d_lossblk + (long long)chunk * nb;
+  p->lossblk_chunk = nb;
   if (seed_intrapixel_or_none) {
+    p->flux_blocks = nb;
     const SeedOut so{*seed_intrapixel_or_none, kstride(p), p->d_bs, p->Q, p->Nd, p->S, p->ldNo, p->hNo(), p->sNo(),
                      (long long)p->No * p->ldNo, p->d_G, p->d_flux};
     hipLaunchKernelGGL(loss_kernel<true>, dim3(nb), dim3(kLossThreads), 0, st, model, binned, data, flat, f0, f0 + nf,
@@ -666,8 +793,38 @@ hipError_t launch_loss(dlx_plan* p, int f0, int nf, int chunk, const float* mode
   return hipGetLastError();
 }
 
+int bin_loss_block_count(long long npix) { return (int)((npix + 63) / 64); }
+
+// dlx_eval's binning, loss, residual, seed weights and flux partials of frames [f0, f0 + nf) in
+// one launch (ordinary frames; the integer-dither mode keeps its windows and gather). One block
+// per 64 pixels; its loss partials at slot `chunk`, its flux partials per (frame, star).
+hipError_t launch_bin_loss(dlx_plan* p, int f0, int nf, int chunk, const float* sources, const float* intrapixel,
+                           const float* flat, const float* data, int kind, double mu, double sigma, float* binned,
+                           float* model, float* r, double* gflat, hipStream_t st) {
+  const long long npix = (long long)p->Nd * p->Nd;
+  const int nb = bin_loss_block_count(npix);
+  const double inv_s2 = 1.0 / (sigma * sigma);
+  double* blk = p->d_lossblk + (long long)chunk * nb;
+  const long long plane = (long long)p->chunk_psf * p->No * p->ldNo, by = (long long)p->No * p->ldNo;
+  const dim3 grid(nb), blkdim(64, kLanes);
+  p->flux_blocks = nb;
+  p->lossblk_chunk = nb;
+#define DLX_BIN_LOSS(QT)                                                                                           \
+  hipLaunchKernelGGL(bin_loss_kernel<QT>, grid, blkdim, 0, st, p->d_Y, plane, by, p->ldNo, f0, nf, p->S, p->L,  \
+                     p->Q, p->Nd, sources, p->d_wl, intrapixel, kstride(p), p->hNo(), p->sNo(), flat, data, kind, \
+                     mu, inv_s2, p->d_bs, binned, model, r, gflat, chunk > 0 ? 1 : 0, blk, p->d_status, p->d_G,    \
+                     p->ldNo, (long long)p->No * p->ldNo, p->d_flux)
+  switch (p->Q) {
+    case 2: DLX_BIN_LOSS(2); break;
+    case 4: DLX_BIN_LOSS(4); break;
+    default: DLX_BIN_LOSS(0); break;
+  }
+#undef DLX_BIN_LOSS
+  return hipGetLastError();
+}
+
 hipError_t launch_loss_final(dlx_plan* p, int n_chunks, double* loss, hipStream_t st) {
-  hipLaunchKernelGGL(final_sum_kernel, dim3(1), dim3(1024), 0, st, p->d_lossblk, p->loss_blocks * n_chunks, loss);
+  hipLaunchKernelGGL(final_sum_kernel, dim3(1), dim3(1024), 0, st, p->d_lossblk, p->lossblk_chunk * n_chunks, loss);
   return hipGetLastError();
 }
 
@@ -708,8 +865,8 @@ hipError_t launch_grad_reduce(dlx_plan* p, const float* Z, const float* Bm, doub
   // one kernel per pixel: launch_kgrad already wrote gK in full
   if (p->k_per_pixel) gK = nullptr;
   hipLaunchKernelGGL(finalize_kernel, dim3(p->Nz + FS + (loss ? 1 : 0) + (gK ? Q2 : 0)), dim3(256), 0, st,
-                     p->d_zpart, p->Nz, nch, gz, p->d_flux, p->seed_blocks, p->d_pos, p->tiles_b4 * p->b4_ksplit, p->L,
-                     FS, gsrc, p->d_lossblk, p->loss_blocks * loss_chunks, loss, p->d_kpart, p->F * p->seed_blocks, Q2,
+                     p->d_zpart, p->Nz, nch, gz, p->d_flux, p->flux_blocks, p->d_pos, p->tiles_b4 * p->b4_ksplit, p->L,
+                     FS, gsrc, p->d_lossblk, p->lossblk_chunk * loss_chunks, loss, p->d_kpart, p->F * p->seed_blocks, Q2,
                      gK);
   return hipGetLastError();
 }
