@@ -312,10 +312,11 @@ class BatchPlan:
 
     def __init__(self, geoms, transmissions, zbases, map_bases=None, intrapixels=None, precision: str = "fp32",
                  workspace_limit: int = 0, device="cuda", autotune: bool = True, store_fields: bool = False,
-                 dense_mft: bool = False):
+                 dense_mft: bool = False, pixel_kernel: bool = False):
         if not torch.cuda.is_available():
             raise RuntimeError("libdlx needs a ROCm GPU")
         self.geoms = list(geoms)
+        self.pixel_kernel = pixel_kernel
         n = len(self.geoms)
         if n < 1:
             raise ValueError("need at least one problem")
@@ -331,7 +332,8 @@ class BatchPlan:
         prec = {"fp32": _c.DLX_FP32, "bf16x3": _c.DLX_BF16X3}[precision]
         with torch.cuda.device(self.device):
             flags = ((0 if autotune else _c.DLX_FLAG_NO_AUTOTUNE) | (_c.DLX_FLAG_STORE_FIELDS if store_fields else 0)
-                     | (_c.DLX_FLAG_DENSE_MFT if dense_mft else 0))
+                     | (_c.DLX_FLAG_DENSE_MFT if dense_mft else 0)
+                     | (_c.DLX_FLAG_PIXEL_KERNEL if pixel_kernel else 0))
             self.plan = _c.dlx_plan_create(descs, n, prec, flags, int(workspace_limit))
         self.precision = precision
         self.offsets = [_c.dlx_plan_offsets(self.plan, k) for k in range(_c.dlx_plan_problems(self.plan))]
@@ -347,7 +349,9 @@ class BatchPlan:
         return {"transmission": (g.n_pupil, g.n_pupil), "zernike_basis": (g.n_zernike, g.n_pupil, g.n_pupil),
                 "map_basis": (g.n_pupil, g.n_map), "zernike_coeffs": (g.n_zernike,),
                 "phase_map": (g.n_map, g.n_map), "sources": g.sources_shape,
-                "flat": (g.n_det, g.n_det), "intrapixel": (g.oversample, g.oversample),
+                "flat": (g.n_det, g.n_det),
+                "intrapixel": ((g.n_det, g.n_det, g.oversample, g.oversample) if self.pixel_kernel
+                               else (g.oversample, g.oversample)),
                 "images": (g.n_frames, g.n_det, g.n_det), "loss": (1,)}[field]
 
     def total(self, field: str) -> int:
@@ -386,14 +390,18 @@ class BatchPlan:
             out.append(flat[o:o + n].view(shp))
         return out
 
-    def buffers(self) -> dict:
-        """Packed device outputs of one evaluation."""
+    def buffers(self, intrapixel_grad: bool = False) -> dict:
+        """Packed device outputs of one evaluation (with ``intrapixel_grad`` also dL/dK, FP64, packed
+        like the intra-pixel kernels)."""
         dv, f32, f64 = self.device, torch.float32, torch.float64
         e = lambda field, dt: torch.empty(max(self.total(field), 1), dtype=dt, device=dv)
+        if intrapixel_grad and self.intrapixel is None:
+            raise ValueError("dL/dK needs the intra-pixel kernels")
         return dict(binned=e("images", f32), model=e("images", f32), r=e("images", f32), loss=e("loss", f64),
                     grad_flat=e("flat", f64), grad_zernike=e("zernike_coeffs", f64),
                     grad_map=e("phase_map", f64) if self.map_basis is not None else None,
-                    grad_sources=e("sources", f64))
+                    grad_sources=e("sources", f64),
+                    grad_intrapixel=e("intrapixel", f64) if intrapixel_grad else None)
 
     def eval_args(self, coeffs, phase_map, sources, flat, data, out: dict, kind="poisson", prior_mu=1.0,
                   prior_sigma=0.1) -> _c.dlx_eval_args:
@@ -415,6 +423,7 @@ class BatchPlan:
             _ptr(out["loss"])
         a.grad_flat, a.grad_zernike = _ptr(out["grad_flat"]), _ptr(out["grad_zernike"])
         a.grad_map, a.grad_sources = _ptr(out["grad_map"]), _ptr(out["grad_sources"])
+        a.grad_intrapixel = _ptr(out.get("grad_intrapixel"))
         return a
 
     def evaluate(self, args: _c.dlx_eval_args) -> None:

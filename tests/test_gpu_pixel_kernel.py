@@ -94,3 +94,57 @@ def test_pixel_kernel_is_refused_in_integer_dither_mode():
     with pytest.raises(C.DlxError) as e:
         plan_for(w, pixel_kernel=True)
     assert e.value.status == C.DLX_ERR_UNSUPPORTED
+
+
+@pytest.mark.parametrize("pixel_kernel", [False, True])
+def test_batch_plan_intrapixel_gradient_matches_oracle(pixel_kernel):
+    """dL/dK through a multi-problem plan: three uneven problems (Q 2 to 4), each with its own
+    intra-pixel kernel (one per pixel with pixel_kernel), packed at the plan's offsets."""
+    import dataclasses
+    import torch
+    from paper_2406_08703_amd import BatchPlan
+    from synth import make_c4_workloads
+    from tests.gpu_helpers import geometry
+    print(f"batch dL/dK pixel_kernel={pixel_kernel}", flush=True)
+    rng = np.random.default_rng(31)
+    ws, refs, gks = [], [], []
+    for w in make_c4_workloads(3, scale=0.25):
+        P = w.problem
+        n, Q = P.n_det, P.oversample
+        K = 1.0 + 0.02 * rng.normal(size=(n, n, Q, Q) if pixel_kernel else (Q, Q))
+        w = dataclasses.replace(w, intrapixel=K.astype(np.float32))
+        prob = oracle_problem(w)
+        _, m = O.forward(prob, w.coeffs_true, None, w.sources_true, w.flat_true)
+        w = w.with_data(m)
+        p = w.eval_params()
+        ref = O.value_and_grad(prob, p["coeffs"], None, p["sources"], p["flat"], w.data, "poisson", w.prior_mu,
+                               w.prior_sigma)
+        gks.append(O.intrapixel_grad(prob, p["coeffs"], None, p["sources"], p["flat"], ref["r"]))
+        ws.append(w)
+        refs.append(ref)
+    t = lambda a: torch.from_numpy(np.ascontiguousarray(a, dtype=np.float32))
+    bp = BatchPlan([geometry(w) for w in ws], [t(w.transmission) for w in ws], [t(w.zbasis) for w in ws],
+                   intrapixels=[t(w.intrapixel) for w in ws], pixel_kernel=pixel_kernel)
+    eps = [w.eval_params() for w in ws]
+    c = bp.pack("zernike_coeffs", [t(e["coeffs"]) for e in eps])
+    s = bp.pack("sources", [t(e["sources"]) for e in eps])
+    fl = bp.pack("flat", [t(e["flat"]) for e in eps])
+    d = bp.pack("images", [t(w.data) for w in ws])
+    out = bp.buffers(intrapixel_grad=True)
+    bp.evaluate(bp.eval_args(c, None, s, fl, d, out, "poisson", ws[0].prior_mu, ws[0].prior_sigma))
+    assert bp.sync() == 0
+    gk = bp.unpack("intrapixel", out["grad_intrapixel"])
+    models = bp.unpack("images", out["model"])
+    for k, w in enumerate(ws):
+        assert rel_l2(models[k].cpu().numpy(), refs[k]["model"]) < TOL
+        got = gk[k].cpu().numpy()
+        Q = w.problem.oversample
+        flat = np.asarray(eps[k]["flat"], np.float64)
+        scale = np.sum(np.abs(flat[None] * refs[k]["r"]) * refs[k]["binned"]) / (Q * Q)
+        if pixel_kernel:
+            scale = np.max(np.sum(np.abs(flat[None] * refs[k]["r"]) * refs[k]["binned"], axis=0)) / (Q * Q)
+        err = np.max(np.abs(got - gks[k])) / scale
+        print(f"problem {k} Q={Q}: dL/dK cond={err:.2e}", flush=True)
+        assert got.shape == gks[k].shape
+        assert err < TOL
+    bp.close()
