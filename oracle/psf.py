@@ -19,9 +19,14 @@ with dLux I", arXiv 2406.08703):
 
 The MFT is a direct DFT evaluated at arbitrary output coordinates, so the
 oracle is that definition written out with explicit DFT matrices (no FFT),
-one PSF at a time, in FP64. Readings where the paper is silent
-(normalisation, centring, sign of the kernel, binning, intra-pixel kernel,
-prior form, chi-squared data term, bicubic map) are listed in the design doc.
+one PSF at a time, in FP64. Where the paper is silent this module reads it
+as follows: the pupil is normalised to unit power and the field scaled by
+dx du / lambda (Parseval on a full-period grid); grids are pixel-centred;
+the kernel is exp(-2 pi i x u / lambda); binning sums the Q x Q focal
+samples of a pixel, weighted by the intra-pixel kernel; the prior is the
+Gaussian (F - mu)^2 / (2 sigma^2); the chi-squared data term is
+(m - d)^2 / (2 max(d, 1)); the bicubic map's interpolation matrix (an input)
+uses Keys' kernel with a = -1/2.
 
 Pins (tests/test_oracle_pins.py): brute-force DFT, FFT equivalence,
 Parseval, Airy and annular-Airy closed forms, shift theorem, piston and

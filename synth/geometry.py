@@ -5,7 +5,7 @@ way the paper's listing in Section 3 builds its transmission and basis with
 coordinate, circle, combine and Zernike-basis utilities. Nothing here
 propagates a field.
 
-Conventions (the paper is silent on them; see the readings in the design doc):
+Conventions (the paper is silent on them):
 * grids are pixel-centred: sample ``i`` of an ``n``-point grid of pitch ``p``
   sits at ``(i - (n - 1) / 2) * p``;
 * a pupil array is indexed ``[row, col] = [y, x]``;
