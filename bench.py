@@ -199,7 +199,7 @@ def main():
         args.warmup = 5 if small_cfg else 1
     if args.gpus != 1:
         print(f"bench.py measures one GPU; --gpus {args.gpus} is not supported (the path shards by frame "
-              "with one all-reduce of the flat-field gradient, which this build does not run).", file=sys.stderr)
+              "with one all-reduce of the flat-field gradient, which this benchmark does not run).", file=sys.stderr)
         sys.exit(2)
 
     if args.config == "c4":

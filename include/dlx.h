@@ -54,7 +54,7 @@ typedef enum {
   DLX_ERR_HIP = 4,         /* a HIP runtime call failed (no device, launch failure) */
   DLX_ERR_NONFINITE = 5,   /* device saw a NaN or Inf in the model or data */
   DLX_ERR_DOMAIN = 6,      /* model <= 0 where the Poisson loss needs m > 0 (clamped to 1e-30) */
-  DLX_ERR_UNSUPPORTED = 7  /* valid request this build does not implement */
+  DLX_ERR_UNSUPPORTED = 7  /* valid request the library does not implement */
 } dlx_status;
 
 /* Arithmetic of the matrix Fourier transforms. DLX_FP32: FP32 MFMA with FP32

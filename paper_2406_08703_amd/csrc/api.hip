@@ -579,7 +579,7 @@ const char* dlx_status_string(dlx_status s) {
     case DLX_ERR_HIP: return "DLX_ERR_HIP: a HIP runtime call failed";
     case DLX_ERR_NONFINITE: return "DLX_ERR_NONFINITE: non-finite model or data";
     case DLX_ERR_DOMAIN: return "DLX_ERR_DOMAIN: model <= 0 under the Poisson loss (clamped)";
-    case DLX_ERR_UNSUPPORTED: return "DLX_ERR_UNSUPPORTED: not implemented in this build";
+    case DLX_ERR_UNSUPPORTED: return "DLX_ERR_UNSUPPORTED: not implemented by the library";
   }
   return "unknown dlx_status";
 }
