@@ -611,7 +611,7 @@ def bench_dither(args):
                        dense_mft=args.dense_mft)
         plan.set_phase_screen(dev(w.phase_screen))
         s = dev(ep["sources"] if dith else w.per_frame_sources(ep["sources"]))
-        roof = None
+        roof, stages = None, None
         if dith:   # eager pass with per-stage HIP events for the roofline of the dominant GEMM
             from paper_2406_08703_amd import EvalBuffers, evaluate
             eb = EvalBuffers(plan)
@@ -625,6 +625,7 @@ def bench_dither(args):
             gemm = {k: dict(ms_per_step=t / args.steps, launches=la, psfs=ps, avg_launch_ms=t / la)
                     for k, (t, la, ps) in st.items() if la and stage_flops(P, k)}
             roof = gemm_roofline(P, gemm, plan.tiles, args.precision, "p0", not args.dense_mft)
+            stages = {k: round(t / args.steps, 5) for k, (t, la, ps) in st.items() if la}
             del eb
         cap = CapturedEval(plan, c, None, s, fl, d, "poisson", w.prior_mu, w.prior_sigma)
         for _ in range(args.warmup):
@@ -640,7 +641,7 @@ def bench_dither(args):
                       8.0 * (ho_ * P.n_pupil * hi_ + no * ho_ * hi_ + hi_ * no * ho_ + hi_ * P.n_pupil * ho_) * psfs)
         results[mode] = dict(ms=wall * 1e3 / args.steps, per=per, psfs=psfs, flops=flops, exec_flops=exec_flops,
                              loss=loss,
-                             tiles=plan.tiles, roofline=roof)
+                             tiles=plan.tiles, roofline=roof, stages=stages)
         log(f"{mode}: {args.steps} replays in {wall:.4f} s ({psfs} PSFs of {no}x{no} per step)")
         cap = None
         plan.close()
@@ -701,6 +702,7 @@ def bench_dither(args):
                           "frac_fp32_mfma_peak_executed": round(r["exec_flops"] / (ms * 1e-3) / 1e12 /
                                                                 FP32_MFMA_PEAK_TFLOPS, 4)},
            "mode": "graph", "step_ms": step_stats(r["per"]), "tiles": {k: f"{v[0]}x{v[1]}" for k, v in r["tiles"].items()},
+           "stage_ms_per_step": r["stages"],
            "per_frame_path_ms_per_step": round(results["per-frame"]["ms"], 4),
            "speedup_vs_per_frame_path": round(results["per-frame"]["ms"] / ms, 3),
            "loss_rel_diff_vs_per_frame_path": float(f"{loss_rel:.3e}"),

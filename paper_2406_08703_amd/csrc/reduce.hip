@@ -15,9 +15,10 @@ namespace {
 //   bs[f][s][p] = sum_l w_l sum_{a,b<Q} K[a][b] |E_{f,s,l}[Qp_r + a][Qp_c + b]|^2   (per source, no flux)
 //   binned[f][p] = sum_s phi_s bs[f][s][p],  model[f][p] = flat[p] * binned[f][p]
 // (binned and model may each be null: the adjoint only needs bs). Block (64,
-// kLanes): 64 detector pixels x kLanes wavelength lanes; lane y sums
-// wavelengths y, y + kLanes, ... and the lanes are added in a fixed order
-// (deterministic). QT > 0 fixes Q at compile time (vector loads along the
+// kLanes): 64 detector pixels x kLanes rows; wavelength lane k sums
+// wavelengths k, k + kLanes, ... and the lanes are added in a fixed order
+// (deterministic), the rows taking the (star, lane) items of several stars at
+// once (bin_stars). QT > 0 fixes Q at compile time (vector loads along the
 // pixel's rows).
 constexpr int kLanes = 8;
 
@@ -73,12 +74,57 @@ __device__ __forceinline__ float pixel_power(const float* e, long long plane, in
   return part;
 }
 
+// Per-star binned values of one pixel p of one frame: for every star s,
+//   v_s = sum over the kLanes lanes k (in order) of acc_{s,k} = sum_{l = k, k + kLanes, ...} w_l P_{s,l}
+// (l in order, P the pixel power above), stored to bs_frame[s npix + p]; returns sum_s phi_s v_s
+// (in star order) on the block's first row. The (star, lane) items of up to kItems / min(L, kLanes)
+// stars are spread over the block's kLanes rows at once, so that with few wavelengths every row
+// still loads (lanes k >= L would only add zeros); the sums do not depend on the grouping.
+constexpr int kItems = 64;
+
+template <int QT>
+__device__ __forceinline__ double bin_stars(double (*sh)[64], const float* E, long long plane, long long by_psf,
+                                            int ld, long long psf0, int S, int L, int Q, int pr, int c0, int cb,
+                                            bool split, int fh, int fs, const float* kp, const WlInfo* wl,
+                                            const float* src, bool live, float* bs_frame, long long npix,
+                                            long long p) {
+  const int x = threadIdx.x, y = threadIdx.y;
+  const int kl = L < kLanes ? L : kLanes;
+  const int sg = kItems / kl;
+  double total = 0.0;
+  for (int s0 = 0; s0 < S; s0 += sg) {
+    const int ns = S - s0 < sg ? S - s0 : sg;
+    for (int j = y; j < ns * kl; j += kLanes) {
+      const int sl = j / kl, k = j - sl * kl;
+      double acc = 0.0;
+      if (live)
+        for (int l = k; l < L; l += kLanes) {
+          const float* e = E + (psf0 + (long long)(s0 + sl) * L + l) * by_psf + (long long)(Q * pr) * ld;
+          acc += (double)wl[l].w * (double)pixel_power<QT>(e, plane, ld, Q, c0, cb, split, fh, fs, kp);
+        }
+      sh[j][x] = acc;
+    }
+    __syncthreads();
+    for (int sl = y; sl < ns; sl += kLanes) {
+      double v = 0.0;
+      for (int k = 0; k < kl; ++k) v += sh[sl * kl + k][x];
+      if (live) bs_frame[(long long)(s0 + sl) * npix + p] = (float)v;
+      sh[sl * kl][x] = v;   // only this thread reads the star's items
+    }
+    __syncthreads();
+    if (y == 0)
+      for (int sl = 0; sl < ns; ++sl) total += (double)src[(long long)(s0 + sl) * 3 + 2] * sh[sl * kl][x];
+    __syncthreads();
+  }
+  return total;
+}
+
 template <int QT>
 __global__ void intensity_kernel(const float* E, long long plane, long long by_psf, int ld, int f0, int F, int S, int L,
                                  int Qr, int Nd, const float* sources, const WlInfo* wl, const float* intrapixel,
                                  long long kst, int fh, int fs, const float* flat, float* bs, float* binned,
                                  float* model) {
-  __shared__ double sh[kLanes][64];
+  __shared__ double sh[kItems][64];
   const int Q = QT > 0 ? QT : Qr;
   const long long npix = (long long)Nd * Nd;
   const long long p = (long long)blockIdx.x * 64 + threadIdx.x;
@@ -92,28 +138,9 @@ __global__ void intensity_kernel(const float* E, long long plane, long long by_p
   const int c0 = Q * pc;
   const bool split = fs != 0 && c0 < fh && c0 + Q > fh;
   const int cb = fcol(c0, fh, fs);
-  double total = 0.0;
-  for (int s = 0; s < S; ++s) {
-    double acc = 0.0;
-    if (live) {
-      for (int l = y; l < L; l += kLanes) {
-        const long long lb = ((long long)(f - f0) * S + s) * L + l;
-        const float* e = E + lb * by_psf + (long long)(Q * pr) * ld;
-        const float part = pixel_power<QT>(e, plane, ld, Q, c0, cb, split, fh, fs, kp);
-        acc += (double)wl[l].w * (double)part;
-      }
-    }
-    sh[y][threadIdx.x] = acc;
-    __syncthreads();
-    if (y == 0 && live) {
-      double v = 0.0;
-#pragma unroll
-      for (int k = 0; k < kLanes; ++k) v += sh[k][threadIdx.x];
-      bs[((long long)(f - f0) * S + s) * npix + p] = (float)v;
-      total += (double)sources[((long long)f * S + s) * 3 + 2] * v;
-    }
-    __syncthreads();
-  }
+  const double total = bin_stars<QT>(sh, E, plane, by_psf, ld, (long long)(f - f0) * S * L, S, L, Q, pr, c0, cb,
+                                     split, fh, fs, kp, wl, sources + (long long)(f < F ? f : 0) * S * 3, live,
+                                     bs + (long long)(f - f0) * S * npix, npix, p);
   if (y == 0 && live) {
     const float bv = (float)total;
     if (binned) binned[(long long)f * npix + p] = bv;
@@ -151,7 +178,7 @@ __global__ void bin_loss_kernel(const float* E, long long plane, long long by_ps
                                 double mu, double inv_s2, float* bs, float* binned, float* model, float* r_out,
                                 double* grad_flat, int accumulate, double* blk, int* status, float* G, int ldg,
                                 long long g_by_frame, double* flux) {
-  __shared__ double sh[kLanes][64];
+  __shared__ double sh[kItems][64];
   const int Q = QT > 0 ? QT : Qr;
   const long long npix = (long long)Nd * Nd;
   const int x = threadIdx.x, y = threadIdx.y;
@@ -167,27 +194,9 @@ __global__ void bin_loss_kernel(const float* E, long long plane, long long by_ps
   int flags = 0;
   for (int fl = 0; fl < nf; ++fl) {
     const int f = f0 + fl;
-    double total = 0.0;
-    for (int s = 0; s < S; ++s) {
-      double acc = 0.0;
-      if (live) {
-        for (int l = y; l < L; l += kLanes) {
-          const long long lb = ((long long)fl * S + s) * L + l;
-          const float* e = E + lb * by_psf + (long long)(Q * pr) * ld;
-          acc += (double)wl[l].w * (double)pixel_power<QT>(e, plane, ld, Q, c0, cb, split, fh, fs, kp);
-        }
-      }
-      sh[y][x] = acc;
-      __syncthreads();
-      if (y == 0 && live) {
-        double v = 0.0;
-#pragma unroll
-        for (int k = 0; k < kLanes; ++k) v += sh[k][x];
-        bs[((long long)fl * S + s) * npix + p] = (float)v;
-        total += (double)sources[((long long)f * S + s) * 3 + 2] * v;
-      }
-      __syncthreads();
-    }
+    const double total = bin_stars<QT>(sh, E, plane, by_psf, ld, (long long)fl * S * L, S, L, Q, pr, c0, cb, split,
+                                       fh, fs, kp, wl, sources + (long long)f * S * 3, live,
+                                       bs + (long long)fl * S * npix, npix, p);
     float h = 0.f;
     if (y == 0 && live) {
       const float bv = (float)total;
