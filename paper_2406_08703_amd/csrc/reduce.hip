@@ -47,6 +47,10 @@ __device__ __forceinline__ float pixel_power(const float* e, long long plane, in
         if (kp) v *= kp[a * Q + b];
         part += v;
       }
+  } else if constexpr (QT == 1) {
+    const float er = e[cb], ei = e[plane + cb];
+    part = er * er + ei * ei;
+    if (kp) part *= kp[0];
   } else if constexpr (QT == 4 || QT == 2) {
     e += cb;
     typedef float vq __attribute__((ext_vector_type(QT)));
@@ -94,15 +98,28 @@ __device__ __forceinline__ double bin_stars(double (*sh)[64], const float* E, lo
   double total = 0.0;
   for (int s0 = 0; s0 < S; s0 += sg) {
     const int ns = S - s0 < sg ? S - s0 : sg;
-    for (int j = y; j < ns * kl; j += kLanes) {
-      const int sl = j / kl, k = j - sl * kl;
-      double acc = 0.0;
-      if (live)
-        for (int l = k; l < L; l += kLanes) {
-          const float* e = E + (psf0 + (long long)(s0 + sl) * L + l) * by_psf + (long long)(Q * pr) * ld;
-          acc += (double)wl[l].w * (double)pixel_power<QT>(e, plane, ld, Q, c0, cb, split, fh, fs, kp);
+    if (L <= kLanes) {   // one wavelength per item: unrolled so that several items' loads are in flight
+#pragma unroll 4
+      for (int j = y; j < ns * kl; j += kLanes) {
+        const int sl = j / kl, k = j - sl * kl;
+        double acc = 0.0;
+        if (live) {
+          const float* e = E + (psf0 + (long long)(s0 + sl) * L + k) * by_psf + (long long)(Q * pr) * ld;
+          acc += (double)wl[k].w * (double)pixel_power<QT>(e, plane, ld, Q, c0, cb, split, fh, fs, kp);
         }
-      sh[j][x] = acc;
+        sh[j][x] = acc;
+      }
+    } else {
+      for (int j = y; j < ns * kl; j += kLanes) {
+        const int sl = j / kl, k = j - sl * kl;
+        double acc = 0.0;
+        if (live)
+          for (int l = k; l < L; l += kLanes) {
+            const float* e = E + (psf0 + (long long)(s0 + sl) * L + l) * by_psf + (long long)(Q * pr) * ld;
+            acc += (double)wl[l].w * (double)pixel_power<QT>(e, plane, ld, Q, c0, cb, split, fh, fs, kp);
+          }
+        sh[j][x] = acc;
+      }
     }
     __syncthreads();
     for (int sl = y; sl < ns; sl += kLanes) {
@@ -705,6 +722,7 @@ hipError_t launch_intensity(dlx_plan* p, int f0, int nf, const float* sources, c
                      p->Q, p->Nd, sources, p->d_wl, intrapixel, kstride(p), p->hNo(), p->sNo(), flat, p->d_bs,   \
                      binned, model)
   switch (p->Q) {
+    case 1: DLX_INTENSITY(1); break;
     case 2: DLX_INTENSITY(2); break;
     case 4: DLX_INTENSITY(4); break;
     default: DLX_INTENSITY(0); break;
@@ -824,6 +842,7 @@ hipError_t launch_bin_loss(dlx_plan* p, int f0, int nf, int chunk, const float* 
                      mu, inv_s2, p->d_bs, binned, model, r, gflat, chunk > 0 ? 1 : 0, blk, p->d_status, p->d_G,    \
                      p->ldNo, (long long)p->No * p->ldNo, p->d_flux)
   switch (p->Q) {
+    case 1: DLX_BIN_LOSS(1); break;
     case 2: DLX_BIN_LOSS(2); break;
     case 4: DLX_BIN_LOSS(4); break;
     default: DLX_BIN_LOSS(0); break;
