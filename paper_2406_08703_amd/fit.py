@@ -116,23 +116,23 @@ def fit_staged(ev: Evaluator, st: FitState, epochs_psf=100, epochs_prf=50, lr_po
     for e in range(epochs_psf):
         scale(((opt["pos"], lr_pos), (opt["lf"], lr_logflux), (opt["c"], lr_nm)), e, epochs_psf)
         L, gp, glf, gc, _ = ev(st)
-        hist.append(float(L))
+        hist.append(L.clone())   # on the device: no host wait per epoch
         opt["pos"].step(st.pos_px, gp)
         opt["lf"].step(st.log_flux, glf)
         if gc.numel():
             opt["c"].step(st.coeffs_nm, gc)
         if log_every and e % log_every == 0:
-            print(f"psf epoch {e}: loss {hist[-1]:.6e}", flush=True)
+            print(f"psf epoch {e}: loss {float(hist[-1]):.6e}", flush=True)
     oflat = _Adam(st.flat, lr_flat)
     for e in range(epochs_prf):
         scale(((oflat, lr_flat),), e, epochs_prf)
         L, _, _, _, gF = ev(st)
-        hist.append(float(L))
+        hist.append(L.clone())
         oflat.step(st.flat, gF)
         if log_every and e % log_every == 0:
-            print(f"prf epoch {e}: loss {hist[-1]:.6e}", flush=True)
-    hist.append(float(ev(st)[0]))
-    return hist
+            print(f"prf epoch {e}: loss {float(hist[-1]):.6e}", flush=True)
+    hist.append(ev(st)[0].clone())
+    return torch.stack(hist).cpu().tolist()
 
 
 def laplace_hessian(ev: Evaluator, st: FitState, h_px=0.05, h_logflux=5e-3, h_nm=0.25):
