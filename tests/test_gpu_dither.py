@@ -25,6 +25,12 @@ CASES = {
     # the paper's Q = 1 sampling, ragged sizes
     "q1": dict(n_pupil=36, n_det=37, oversample=1, margin=4, n_sources=4, wavelengths=(545e-9, 595e-9, 645e-9),
                dithers=((0, 0), (4, 4), (4, -4), (-4, 4), (-4, -4)), intra=False),
+    # more stars than the binning kernel takes at once: 23 stars of 3 wavelengths (21 per pass), and
+    # 10 stars of 9 wavelengths (8 per pass, two wavelengths on the first lane)
+    "q1-23stars": dict(n_pupil=24, n_det=41, oversample=1, margin=2, n_sources=23,
+                       wavelengths=(545e-9, 595e-9, 645e-9), dithers=((0, 0), (2, -2), (-1, 2)), intra=False),
+    "q2-10stars-9wl": dict(n_pupil=24, n_det=40, oversample=2, margin=2, n_sources=10,
+                           wavelengths=tuple(np.linspace(500e-9, 700e-9, 9)), dithers=((0, 0), (2, 1)), intra=False),
 }
 
 
@@ -121,16 +127,34 @@ def test_dither_mode_bf16x3_matches_oracle(name):
     compare(got, ref, tol_grad=TOL_BF16X3, tol_resid=TOL_BF16X3, tol_img=TOL_BF16X3, fscale=fscale)
 
 
-def test_dither_mode_equals_per_frame_path_on_gpu():
+@pytest.mark.parametrize("name", ["q2-k", "q2-10stars-9wl"])
+def test_dither_mode_equals_per_frame_path_on_gpu(name):
     # the same frames through the ordinary path, with the dithers added to the positions
-    print("dither vs per-frame", flush=True)
-    w, _ = case("q2-k")
+    from paper_2406_08703_amd import dlx as C
+    print(f"dither vs per-frame {name}", flush=True)
+    w, _ = case(name)
     pd = plan_for(w)
     a = run(w, pd, True)
     pd.close()
     pf = plan_for(w, dither=False)
-    b = run(w, pf, True, sources=w.per_frame_sources(w.eval_params()["sources"]))
+    srcs = w.per_frame_sources(w.eval_params()["sources"])
+    b = run(w, pf, True, sources=srcs)
     pf.close()
+    if name == "q2-10stars-9wl":
+        # one frame per chunk (a 12 MiB workspace holds one of this case's 7.9 MB frames): the fused
+        # binning-and-loss launch instead of binning and loss launches over both frames
+        p1 = plan_for(w, dither=False, workspace_limit=12 << 20)
+        C.dlx_plan_profile(p1.plan, True)
+        c1 = run(w, p1, True, sources=srcs)
+        launches = C.dlx_plan_stage_times(p1.plan)["BIN"][1]
+        C.dlx_plan_profile(p1.plan, False)
+        p1.close()
+        assert launches == w.n_frames
+        for k in ("binned", "model", "r"):
+            assert np.array_equal(c1[k], b[k]), k
+        # the frame sums and the prior add in another order
+        assert rel_l2(c1["grad_flat"], b["grad_flat"]) < 1e-12
+        assert abs(c1["loss"] - b["loss"]) <= 1e-12 * abs(b["loss"])
     for k in ("binned", "model", "r", "grad_flat", "grad_coeffs"):
         assert rel_l2(a[k], b[k]) < 1e-5, k
     # to first order the loss moves by sum r dm: an elementwise model error eps (FP32 rounding of the
