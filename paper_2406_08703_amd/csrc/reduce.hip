@@ -122,15 +122,24 @@ __device__ __forceinline__ double bin_stars(double (*sh)[64], const float* E, lo
       }
     }
     __syncthreads();
-    for (int sl = y; sl < ns; sl += kLanes) {
-      double v = 0.0;
-      for (int k = 0; k < kl; ++k) v += sh[sl * kl + k][x];
-      if (live) bs_frame[(long long)(s0 + sl) * npix + p] = (float)v;
-      sh[sl * kl][x] = v;   // only this thread reads the star's items
+    if (ns == 1) {   // one star in the pass (ns is the same for the whole block)
+      if (y == 0) {
+        double v = 0.0;
+        for (int k = 0; k < kl; ++k) v += sh[k][x];
+        if (live) bs_frame[(long long)s0 * npix + p] = (float)v;
+        total += (double)src[(long long)s0 * 3 + 2] * v;
+      }
+    } else {
+      for (int sl = y; sl < ns; sl += kLanes) {
+        double v = 0.0;
+        for (int k = 0; k < kl; ++k) v += sh[sl * kl + k][x];
+        if (live) bs_frame[(long long)(s0 + sl) * npix + p] = (float)v;
+        sh[sl * kl][x] = v;   // only this thread reads the star's items
+      }
+      __syncthreads();
+      if (y == 0)
+        for (int sl = 0; sl < ns; ++sl) total += (double)src[(long long)(s0 + sl) * 3 + 2] * sh[sl * kl][x];
     }
-    __syncthreads();
-    if (y == 0)
-      for (int sl = 0; sl < ns; ++sl) total += (double)src[(long long)(s0 + sl) * 3 + 2] * sh[sl * kl][x];
     __syncthreads();
   }
   return total;
