@@ -89,34 +89,36 @@ __global__ void pupil_kernel(const float* A, const double* opd, const float* scr
                              int n_norm, const WlInfo* wl, int Ni, int ldp, int h, float* P0T, long long plane,
                              long long by_wl) {
   __shared__ float tr[32][33], ti[32][33];
-  __shared__ double snorm;
+  __shared__ double sparts[256];   // n_norm <= 256
   const int tx = threadIdx.x, ty = threadIdx.y;  // 32 x 8
   const int m0 = blockIdx.y * 32, n0 = blockIdx.x * 32;
   const int l = blockIdx.z;
-  if (tx == 0 && ty == 0) {
-    double s2 = 0.0;
-    for (int i = 0; i < n_norm; ++i) s2 += norm_part[i];
-    snorm = s2 > 0.0 ? 1.0 / sqrt(s2) : 0.0;
-  }
-  __syncthreads();
-  const double nrm = snorm;
+  // the partial sums of A^2 are read in parallel, next to the pixels' loads and phases
+  for (int i = ty * 32 + tx; i < n_norm; i += 256) sparts[i] = norm_part[i];
   const double inv = 1.0 / wl[l].lam;
+  double cs[4], sn[4], av[4];
+#pragma unroll
   for (int q = 0; q < 4; ++q) {
     const int m = m0 + ty + 8 * q, n = n0 + tx;
-    float re = 0.f, im = 0.f;
+    cs[q] = sn[q] = av[q] = 0.0;
     if (m < Ni && n < Ni) {
       const long long p = (long long)m * Ni + n;
       // phase in cycles: the OPD's plus the static screen's (achromatic, radians)
       const double t0 = opd[p] * inv + (double)screen[p] * 0.15915494309189533577;
       const double fr = t0 - rint(t0);
-      double sn, cs;
-      sincospi(2.0 * fr, &sn, &cs);
-      const double amp = (double)A[p] * nrm;
-      re = (float)(amp * cs);
-      im = (float)(amp * sn);
+      sincospi(2.0 * fr, &sn[q], &cs[q]);
+      av[q] = (double)A[p];
     }
-    tr[ty + 8 * q][tx] = re;
-    ti[ty + 8 * q][tx] = im;
+  }
+  __syncthreads();
+  double s2 = 0.0;   // every thread adds the partials in the same order
+  for (int i = 0; i < n_norm; ++i) s2 += sparts[i];
+  const double nrm = s2 > 0.0 ? 1.0 / sqrt(s2) : 0.0;
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    const double amp = av[q] * nrm;
+    tr[ty + 8 * q][tx] = (float)(amp * cs[q]);
+    ti[ty + 8 * q][tx] = (float)(amp * sn[q]);
   }
   __syncthreads();
   for (int q = 0; q < 4; ++q) {
