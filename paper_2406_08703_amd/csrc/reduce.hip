@@ -640,24 +640,59 @@ __global__ void zproj_partial_kernel(const float* Z, const double* gopd, int Nz,
   }
 }
 
-// tmp2[m][k] = sum_n gopd[m][n] B[n][k]
-__global__ void map_grad1_kernel(const double* gopd, const float* Bm, int Ni, int Nmap, double* tmp2) {
+// The bicubic-map gradient B^T gopd B in two products over the pupil index, each output a
+// fixed-order FP64 sum: block of kMapWaves waves, lane = output column k (64 at a time), wave w
+// sums the terms w, w + kMapWaves, ... and the wave sums are added in wave order.
+constexpr int kMapWaves = 16;
+
+// tmp2[m][k] = sum_n gopd[m][n] B[n][k]   (block m)
+__global__ __launch_bounds__(64 * kMapWaves) void map_grad1_kernel(const double* gopd, const float* Bm, int Ni, int Nmap, double* tmp2) {
+  __shared__ double sh[kMapWaves][64];
   const int m = blockIdx.x;
-  const int k = threadIdx.x;
-  if (k >= Nmap) return;
-  double acc = 0.0;
-  for (int n = 0; n < Ni; ++n) acc += gopd[(long long)m * Ni + n] * (double)Bm[(long long)n * Nmap + k];
-  tmp2[(long long)m * Nmap + k] = acc;
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const double* g = gopd + (long long)m * Ni;
+  for (int k0 = 0; k0 < Nmap; k0 += 64) {
+    const int k = k0 + lane;
+    double acc = 0.0;
+    if (k < Nmap) {
+#pragma unroll 4
+      for (int n = w; n < Ni; n += kMapWaves) acc += g[n] * (double)Bm[(long long)n * Nmap + k];
+    }
+    sh[w][lane] = acc;
+    __syncthreads();
+    if (w == 0 && k < Nmap) {
+      double t = 0.0;
+#pragma unroll
+      for (int i = 0; i < kMapWaves; ++i) t += sh[i][lane];
+      tmp2[(long long)m * Nmap + k] = t;
+    }
+    __syncthreads();
+  }
 }
 
-// grad_C[j][k] = sum_m B[m][j] tmp2[m][k]
-__global__ void map_grad2_kernel(const double* tmp2, const float* Bm, int Ni, int Nmap, double* grad) {
+// grad_C[j][k] = sum_m B[m][j] tmp2[m][k]   (block j)
+__global__ __launch_bounds__(64 * kMapWaves) void map_grad2_kernel(const double* tmp2, const float* Bm, int Ni, int Nmap, double* grad) {
+  __shared__ double sh[kMapWaves][64];
   const int j = blockIdx.x;
-  const int k = threadIdx.x;
-  if (k >= Nmap) return;
-  double acc = 0.0;
-  for (int m = 0; m < Ni; ++m) acc += (double)Bm[(long long)m * Nmap + j] * tmp2[(long long)m * Nmap + k];
-  grad[(long long)j * Nmap + k] = acc;
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  for (int k0 = 0; k0 < Nmap; k0 += 64) {
+    const int k = k0 + lane;
+    double acc = 0.0;
+    if (k < Nmap) {
+#pragma unroll 4
+      for (int m = w; m < Ni; m += kMapWaves)
+        acc += (double)Bm[(long long)m * Nmap + j] * tmp2[(long long)m * Nmap + k];
+    }
+    sh[w][lane] = acc;
+    __syncthreads();
+    if (w == 0 && k < Nmap) {
+      double t = 0.0;
+#pragma unroll
+      for (int i = 0; i < kMapWaves; ++i) t += sh[i][lane];
+      grad[(long long)j * Nmap + k] = t;
+    }
+    __syncthreads();
+  }
 }
 
 // The last reductions of an evaluation in one launch, 256 threads per block,
@@ -892,10 +927,10 @@ hipError_t launch_grad_reduce(dlx_plan* p, const float* Z, const float* Bm, doub
                        p->d_gopd, p->Nz, npix, chunk, p->d_zpart);
   }
   if (p->Nmap > 0) {
-    hipLaunchKernelGGL(map_grad1_kernel, dim3(p->Ni), dim3((p->Nmap + 63) / 64 * 64), 0, st, p->d_gopd, Bm, p->Ni,
-                       p->Nmap, p->d_tmp2);
-    hipLaunchKernelGGL(map_grad2_kernel, dim3(p->Nmap), dim3((p->Nmap + 63) / 64 * 64), 0, st, p->d_tmp2, Bm, p->Ni,
-                       p->Nmap, gmap);
+    hipLaunchKernelGGL(map_grad1_kernel, dim3(p->Ni), dim3(64 * kMapWaves), 0, st, p->d_gopd, Bm, p->Ni, p->Nmap,
+                       p->d_tmp2);
+    hipLaunchKernelGGL(map_grad2_kernel, dim3(p->Nmap), dim3(64 * kMapWaves), 0, st, p->d_tmp2, Bm, p->Ni, p->Nmap,
+                       gmap);
   }
   const int FS = p->F * p->S;
   const int Q2 = p->Q * p->Q;

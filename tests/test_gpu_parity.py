@@ -33,6 +33,8 @@ CASES = {
     # Q = 3, and the paper's Q = 1 sampling with an obstructed, odd pupil
     "odd-q3": ("c1", dict(n_pupil=33, n_focal=39, oversample=3, noll=tuple(range(2, 12)))),
     "odd-q1": ("c2", dict(n_pupil=31, n_focal=37, oversample=1, n_wavelengths=3, noll=tuple(range(2, 9)))),
+    # a 70 x 70 bicubic map: more map columns than the map-gradient kernels take in one pass (64)
+    "c5-map70": ("c5", dict(n_pupil=72, n_focal=48, n_wavelengths=1, n_frames=1, noll=tuple(range(2, 8)), n_map=70)),
 }
 
 
