@@ -109,9 +109,9 @@ __device__ __forceinline__ double bin_stars(double (*sh)[64], const float* E, lo
         }
         sh[j][x] = acc;
       }
-    } else {
-      for (int j = y; j < ns * kl; j += kLanes) {
-        const int sl = j / kl, k = j - sl * kl;
+    } else {   // kl == kLanes: the item's star and lane are j / kLanes and j % kLanes
+      for (int j = y; j < ns * kLanes; j += kLanes) {
+        const int sl = j / kLanes, k = j % kLanes;
         double acc = 0.0;
         if (live)
           for (int l = k; l < L; l += kLanes) {
@@ -125,14 +125,18 @@ __device__ __forceinline__ double bin_stars(double (*sh)[64], const float* E, lo
     if (ns == 1) {   // one star in the pass (ns is the same for the whole block)
       if (y == 0) {
         double v = 0.0;
-        for (int k = 0; k < kl; ++k) v += sh[k][x];
+#pragma unroll
+        for (int k = 0; k < kLanes; ++k)
+          if (k < kl) v += sh[k][x];
         if (live) bs_frame[(long long)s0 * npix + p] = (float)v;
         total += (double)src[(long long)s0 * 3 + 2] * v;
       }
     } else {
       for (int sl = y; sl < ns; sl += kLanes) {
         double v = 0.0;
-        for (int k = 0; k < kl; ++k) v += sh[sl * kl + k][x];
+#pragma unroll
+        for (int k = 0; k < kLanes; ++k)
+          if (k < kl) v += sh[sl * kl + k][x];
         if (live) bs_frame[(long long)(s0 + sl) * npix + p] = (float)v;
         sh[sl * kl][x] = v;   // only this thread reads the star's items
       }
