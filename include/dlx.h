@@ -109,9 +109,9 @@ dlx_status dlx_validate(const dlx_problem_desc* probs, int32_t n_probs);
  * workspace for the first frame chunk and keeps the fastest.
  * DLX_FLAG_NO_AUTOTUNE keeps the built-in size heuristic instead.
  * The adjoint seed w phi G E is formed inside the first adjoint product's
- * operand loader unless a frame's seed weights G exceed 4 MiB, in which case
- * a separate elementwise pass forms it first; DLX_FLAG_SEED_PASS forces the
- * separate pass (same results, bit for bit). */
+ * operand loader; a plan with DLX_FLAG_DENSE_MFT forms it in a separate
+ * elementwise pass instead when a frame's seed weights G exceed 4 MiB, and
+ * DLX_FLAG_SEED_PASS forces the separate pass (same results, bit for bit). */
 enum {
   DLX_FLAG_NO_AUTOTUNE = 1,
   DLX_FLAG_SEED_PASS = 2,
@@ -158,8 +158,8 @@ enum {
  * dlx_psf_backward / dlx_eval then packs the problems' arrays one after the
  * other, problem k starting at the element offsets dlx_plan_offsets reports
  * (loss_out holds one loss per problem). flags: an OR of DLX_FLAG_NO_AUTOTUNE,
- * DLX_FLAG_SEED_PASS, DLX_FLAG_STORE_FIELDS and DLX_FLAG_PIXEL_KERNEL (other bits:
- * DLX_ERR_INVALID_ARG). Results do not depend on the tiles chosen
+ * DLX_FLAG_SEED_PASS, DLX_FLAG_STORE_FIELDS, DLX_FLAG_PIXEL_KERNEL and
+ * DLX_FLAG_DENSE_MFT (other bits: DLX_ERR_INVALID_ARG). Results do not depend on the tiles chosen
  * except for the order of FP32/FP64 partial sums in the gradient
  * reductions. workspace_limit_bytes: 0 = no limit;
  * otherwise the frame-chunk size is reduced until the workspace fits, and
