@@ -195,7 +195,7 @@ struct dlx_plan {
   // partial counts of the last launches that wrote them (flux partials per (frame, star); loss
   // partials per chunk): seed kernels and loss_kernel use 256-pixel blocks, bin_loss_kernel 64
   int flux_blocks = 0, lossblk_chunk = 0;
-  bool seed_pass = false; // form Y = w phi G E in a separate pass (large frames) instead of in B3's loader
+  bool seed_pass = false; // form Y = w phi G E in a separate pass (dense plans with large frames, or on request) instead of in B3's loader
   // stage timing (diagnostics)
   bool profiling = false;
   std::vector<hipEvent_t> ev_pool;
