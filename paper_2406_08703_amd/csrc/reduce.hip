@@ -29,6 +29,10 @@ long long kstride(const dlx_plan* p) { return p->k_per_pixel ? (long long)p->Q *
 // columns c < h in place and move c >= h to c + s (s = 0: natural order).
 __device__ __forceinline__ int fcol(int c, int h, int s) { return c < h ? c : c + s; }
 
+// |E|^2 of one focal sample at Q = 1, with the rounding fixed (one fused multiply-add) so that the
+// one-pixel and four-pixel binning kernels agree bit for bit.
+__device__ __forceinline__ float q1_power(float er, float ei) { return __fmaf_rn(er, er, ei * ei); }
+
 // sum over a detector pixel's Q x Q focal samples of K |E|^2 for one PSF: e points at the pixel's
 // first focal row; its Q columns start at stored column cb, or (split) straddle the fold's split
 // and are mapped one by one from c0.
@@ -49,7 +53,7 @@ __device__ __forceinline__ float pixel_power(const float* e, long long plane, in
       }
   } else if constexpr (QT == 1) {
     const float er = e[cb], ei = e[plane + cb];
-    part = er * er + ei * ei;
+    part = q1_power(er, ei);
     if (kp) part *= kp[0];
   } else if constexpr (QT == 4 || QT == 2) {
     e += cb;
@@ -105,7 +109,7 @@ __device__ __forceinline__ double bin_stars(double (*sh)[64], const float* E, lo
         double acc = 0.0;
         if (live) {
           const float* e = E + (psf0 + (long long)(s0 + sl) * L + k) * by_psf + (long long)(Q * pr) * ld;
-          acc += (double)wl[k].w * (double)pixel_power<QT>(e, plane, ld, Q, c0, cb, split, fh, fs, kp);
+          acc = fma((double)wl[k].w, (double)pixel_power<QT>(e, plane, ld, Q, c0, cb, split, fh, fs, kp), acc);
         }
         sh[j][x] = acc;
       }
@@ -116,7 +120,7 @@ __device__ __forceinline__ double bin_stars(double (*sh)[64], const float* E, lo
         if (live)
           for (int l = k; l < L; l += kLanes) {
             const float* e = E + (psf0 + (long long)(s0 + sl) * L + l) * by_psf + (long long)(Q * pr) * ld;
-            acc += (double)wl[l].w * (double)pixel_power<QT>(e, plane, ld, Q, c0, cb, split, fh, fs, kp);
+            acc = fma((double)wl[l].w, (double)pixel_power<QT>(e, plane, ld, Q, c0, cb, split, fh, fs, kp), acc);
           }
         sh[j][x] = acc;
       }
@@ -129,7 +133,7 @@ __device__ __forceinline__ double bin_stars(double (*sh)[64], const float* E, lo
         for (int k = 0; k < kLanes; ++k)
           if (k < kl) v += sh[k][x];
         if (live) bs_frame[(long long)s0 * npix + p] = (float)v;
-        total += (double)src[(long long)s0 * 3 + 2] * v;
+        total = fma((double)src[(long long)s0 * 3 + 2], v, total);
       }
     } else {
       for (int sl = y; sl < ns; sl += kLanes) {
@@ -142,7 +146,7 @@ __device__ __forceinline__ double bin_stars(double (*sh)[64], const float* E, lo
       }
       __syncthreads();
       if (y == 0)
-        for (int sl = 0; sl < ns; ++sl) total += (double)src[(long long)(s0 + sl) * 3 + 2] * sh[sl * kl][x];
+        for (int sl = 0; sl < ns; ++sl) total = fma((double)src[(long long)(s0 + sl) * 3 + 2], sh[sl * kl][x], total);
     }
     __syncthreads();
   }
@@ -175,6 +179,92 @@ __global__ void intensity_kernel(const float* E, long long plane, long long by_p
     const float bv = (float)total;
     if (binned) binned[(long long)f * npix + p] = bv;
     if (model) model[(long long)f * npix + p] = flat[p] * bv;
+  }
+}
+
+// intensity_kernel at Q = 1 with four adjacent pixels per thread and 16-byte loads (a block covers
+// 256 pixels). Launched when N_det and, for a folded plan, the fold's split h are multiples of 4, so
+// that the four pixels of a thread share a row and sit contiguous and 16-byte aligned in the stored
+// row. Per pixel the arithmetic and the order of every sum are those of intensity_kernel<1>.
+constexpr int kItemsV = 16;
+
+__global__ __launch_bounds__(64 * kLanes) void intensity_q1v_kernel(
+    const float* E, long long plane, long long by_psf, int ld, int f0, int F, int S, int L, int Nd,
+    const float* sources, const WlInfo* wl, const float* intrapixel, long long kst, int fh, int fs,
+    const float* flat, float* bs, float* binned, float* model) {
+  typedef float f4v __attribute__((ext_vector_type(4)));
+  __shared__ double sh[kItemsV][4][64];
+  const long long npix = (long long)Nd * Nd;
+  const int x = threadIdx.x, y = threadIdx.y;
+  const long long p = ((long long)blockIdx.x * 64 + x) * 4;   // first of the thread's four pixels
+  const int f = f0 + blockIdx.y;
+  const bool live = p < npix && f < F;
+  const int pr = live ? (int)(p / Nd) : 0, pc = live ? (int)(p - (long long)pr * Nd) : 0;
+  const int cb = fcol(pc, fh, fs);
+  float kv[4] = {1.f, 1.f, 1.f, 1.f};
+  if (intrapixel && live)
+#pragma unroll
+    for (int i = 0; i < 4; ++i) kv[i] = intrapixel[(p + i) * kst];
+  const float* src = sources + (long long)(f < F ? f : 0) * S * 3;
+  float* bsf = bs + (long long)(f - f0) * S * npix;
+  const long long psf0 = (long long)(f - f0) * S * L;
+  const int kl = L < kLanes ? L : kLanes;
+  const int sg = kItemsV / kl > 0 ? kItemsV / kl : 1;
+  double total[4] = {0.0, 0.0, 0.0, 0.0};
+  for (int s0 = 0; s0 < S; s0 += sg) {
+    const int ns = S - s0 < sg ? S - s0 : sg;
+    for (int j = y; j < ns * kl; j += kLanes) {
+      const int sl = j / kl, k = j - sl * kl;
+      double acc[4] = {0.0, 0.0, 0.0, 0.0};
+      if (live)
+        for (int l = k; l < L; l += kLanes) {
+          const float* e = E + (psf0 + (long long)(s0 + sl) * L + l) * by_psf + (long long)pr * ld + cb;
+          const f4v vr = *reinterpret_cast<const f4v*>(e);
+          const f4v vi = *reinterpret_cast<const f4v*>(e + plane);
+          const double w = (double)wl[l].w;
+#pragma unroll
+          for (int i = 0; i < 4; ++i) {
+            float part = q1_power(vr[i], vi[i]);
+            if (intrapixel) part *= kv[i];
+            acc[i] = fma(w, (double)part, acc[i]);
+          }
+        }
+#pragma unroll
+      for (int i = 0; i < 4; ++i) sh[j][i][x] = acc[i];
+    }
+    __syncthreads();
+    for (int sl = y; sl < ns; sl += kLanes) {
+      double v[4] = {0.0, 0.0, 0.0, 0.0};
+      for (int k = 0; k < kl; ++k)
+#pragma unroll
+        for (int i = 0; i < 4; ++i) v[i] += sh[sl * kl + k][i][x];
+      if (live) {
+        f4v o;
+#pragma unroll
+        for (int i = 0; i < 4; ++i) o[i] = (float)v[i];
+        *reinterpret_cast<f4v*>(bsf + (long long)(s0 + sl) * npix + p) = o;
+      }
+#pragma unroll
+      for (int i = 0; i < 4; ++i) sh[sl * kl][i][x] = v[i];   // only this thread reads the star's items
+    }
+    __syncthreads();
+    if (y == 0)
+      for (int sl = 0; sl < ns; ++sl) {
+        const double phi = (double)src[(long long)(s0 + sl) * 3 + 2];
+#pragma unroll
+        for (int i = 0; i < 4; ++i) total[i] = fma(phi, sh[sl * kl][i][x], total[i]);
+      }
+    __syncthreads();
+  }
+  if (y == 0 && live) {
+    f4v bv;
+#pragma unroll
+    for (int i = 0; i < 4; ++i) bv[i] = (float)total[i];
+    if (binned) *reinterpret_cast<f4v*>(binned + (long long)f * npix + p) = bv;
+    if (model) {
+      const f4v fl = *reinterpret_cast<const f4v*>(flat + p);
+      *reinterpret_cast<f4v*>(model + (long long)f * npix + p) = fl * bv;
+    }
   }
 }
 
@@ -769,6 +859,13 @@ hipError_t launch_intensity(dlx_plan* p, int f0, int nf, const float* sources, c
   hipLaunchKernelGGL(intensity_kernel<QT>, grid, blk, 0, st, p->d_Y, plane, by, p->ldNo, f0, p->F, p->S, p->L, \
                      p->Q, p->Nd, sources, p->d_wl, intrapixel, kstride(p), p->hNo(), p->sNo(), flat, p->d_bs,   \
                      binned, model)
+  if (p->Q == 1 && p->Nd % 4 == 0 && (!p->fold || p->hNo() % 4 == 0)) {
+    const dim3 grid4((unsigned)((npix / 4 + 63) / 64), nf);
+    hipLaunchKernelGGL(intensity_q1v_kernel, grid4, blk, 0, st, p->d_Y, plane, by, p->ldNo, f0, p->F, p->S, p->L,
+                       p->Nd, sources, p->d_wl, intrapixel, kstride(p), p->hNo(), p->sNo(), flat, p->d_bs, binned,
+                       model);
+    return hipGetLastError();
+  }
   switch (p->Q) {
     case 1: DLX_INTENSITY(1); break;
     case 2: DLX_INTENSITY(2); break;

@@ -25,6 +25,9 @@ CASES = {
     # the paper's Q = 1 sampling, ragged sizes
     "q1": dict(n_pupil=36, n_det=37, oversample=1, margin=4, n_sources=4, wavelengths=(545e-9, 595e-9, 645e-9),
                dithers=((0, 0), (4, 4), (4, -4), (-4, 4), (-4, -4)), intra=False),
+    # Q = 1 on a 48-pixel enlarged plane (a multiple of 8): the four-pixel binning kernel
+    "q1-vec": dict(n_pupil=24, n_det=44, oversample=1, margin=2, n_sources=5, wavelengths=(545e-9, 595e-9, 645e-9),
+                   dithers=((0, 0), (2, -2), (-1, 2)), intra=False),
     # more stars than the binning kernel takes at once: 23 stars of 3 wavelengths (21 per pass), and
     # 10 stars of 9 wavelengths (8 per pass, two wavelengths on the first lane)
     "q1-23stars": dict(n_pupil=24, n_det=41, oversample=1, margin=2, n_sources=23,

@@ -33,6 +33,8 @@ CASES = {
     # Q = 3, and the paper's Q = 1 sampling with an obstructed, odd pupil
     "odd-q3": ("c1", dict(n_pupil=33, n_focal=39, oversample=3, noll=tuple(range(2, 12)))),
     "odd-q1": ("c2", dict(n_pupil=31, n_focal=37, oversample=1, n_wavelengths=3, noll=tuple(range(2, 9)))),
+    # Q = 1 with a detector width and fold split that are multiples of 4: the four-pixel binning kernel
+    "q1-vec": ("c2", dict(n_pupil=32, n_focal=40, oversample=1, n_wavelengths=3, noll=tuple(range(2, 9)))),
     # a 70 x 70 bicubic map: more map columns than the map-gradient kernels take in one pass (64)
     "c5-map70": ("c5", dict(n_pupil=72, n_focal=48, n_wavelengths=1, n_frames=1, noll=tuple(range(2, 8)), n_map=70)),
 }
@@ -109,6 +111,17 @@ def test_forward_loss_gradient_match_oracle(case):
     got = run_gpu(w)
     assert got["status"] == 0
     compare(got, oracle_eval(case, "eval", "poisson"))
+
+
+def test_q1_four_pixel_binning_equals_one_pixel_binning():
+    # the separate forward call bins four pixels per thread at this size; the fused evaluation (one
+    # frame per chunk) bins one pixel per thread together with the loss: the same bits
+    from tests.gpu_helpers import run_eval, run_gpu
+    w, _ = workload("q1-vec")
+    assert w.problem.oversample == 1 and w.problem.n_det % 8 == 0
+    a, b = run_gpu(w), run_eval(w)
+    for k in ("binned", "model"):
+        assert np.array_equal(a[k], b[k]), k
 
 
 def test_chi2_variant_matches_oracle():
