@@ -298,7 +298,7 @@ __global__ void bin_loss_kernel(const float* E, long long plane, long long by_ps
                                 double mu, double inv_s2, float* bs, float* binned, float* model, float* r_out,
                                 double* grad_flat, int accumulate, double* blk, int* status, float* G, int ldg,
                                 long long g_by_frame, double* flux) {
-  __shared__ double sh[kItems][64];
+  __shared__ double sh[kLanes][64];
   const int Q = QT > 0 ? QT : Qr;
   const long long npix = (long long)Nd * Nd;
   const int x = threadIdx.x, y = threadIdx.y;
@@ -314,9 +314,29 @@ __global__ void bin_loss_kernel(const float* E, long long plane, long long by_ps
   int flags = 0;
   for (int fl = 0; fl < nf; ++fl) {
     const int f = f0 + fl;
-    const double total = bin_stars<QT>(sh, E, plane, by_psf, ld, (long long)fl * S * L, S, L, Q, pr, c0, cb, split,
-                                       fh, fs, kp, wl, sources + (long long)f * S * 3, live,
-                                       bs + (long long)fl * S * npix, npix, p);
+    // one star per pass (one-frame chunks run with eight or more wavelengths in practice, where
+    // bin_stars' grouping gains nothing); the arithmetic and the order of the sums are bin_stars'
+    double total = 0.0;
+    for (int s = 0; s < S; ++s) {
+      double acc = 0.0;
+      if (live) {
+        for (int l = y; l < L; l += kLanes) {
+          const float* e = E + (((long long)fl * S + s) * L + l) * by_psf + (long long)(Q * pr) * ld;
+          acc = fma((double)wl[l].w, (double)pixel_power<QT>(e, plane, ld, Q, c0, cb, split, fh, fs, kp), acc);
+        }
+      }
+      sh[y][x] = acc;
+      __syncthreads();
+      if (y == 0) {
+        double v = 0.0;
+#pragma unroll
+        for (int k = 0; k < kLanes; ++k)
+          if (k < L) v += sh[k][x];
+        if (live) bs[((long long)fl * S + s) * npix + p] = (float)v;
+        total = fma((double)sources[((long long)f * S + s) * 3 + 2], v, total);
+      }
+      __syncthreads();
+    }
     float h = 0.f;
     if (y == 0 && live) {
       const float bv = (float)total;
