@@ -17,9 +17,12 @@ pytestmark = pytest.mark.gpu
 
 @functools.lru_cache(maxsize=None)
 def pixel_case(name):
-    # Q = 3 (c3-like: binary, sub-pixel dithers, 3 frames) and Q = 4 (odd 31-pixel detector)
+    # Q = 3 (c3-like: binary, sub-pixel dithers, 3 frames), Q = 4 (odd 31-pixel detector) and Q = 1 on a
+    # 40-pixel detector (the four-pixel binning kernel)
     if name == "q3":
         w = make_workload("c3", n_pupil=80, n_focal=150, n_wavelengths=3, n_frames=3, noll=tuple(range(2, 14)))
+    elif name == "q1":
+        w = make_workload("c2", n_pupil=32, n_focal=40, oversample=1, n_wavelengths=3, noll=tuple(range(2, 9)))
     else:
         w = make_workload("c2", n_pupil=50, n_focal=124, n_wavelengths=4, noll=tuple(range(2, 10)))
     P = w.problem
@@ -46,7 +49,7 @@ def _plan(w, limit=0):
 
 
 @pytest.mark.parametrize("fused", [False, True])
-@pytest.mark.parametrize("name,chunked", [("q3", False), ("q3", True), ("q4", False)])
+@pytest.mark.parametrize("name,chunked", [("q3", False), ("q3", True), ("q4", False), ("q1", False)])
 def test_pixel_kernel_matches_oracle(name, chunked, fused):
     import torch
     from paper_2406_08703_amd import evaluate
