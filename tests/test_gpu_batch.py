@@ -85,7 +85,7 @@ def test_batch_eval_matches_oracle_per_problem():
         P = w.problem
         print(f"problem {k}: Ni={P.n_pupil} No={P.n_focal} Q={P.oversample} nl={len(P.wavelengths)} "
               f"nz={P.n_zernike} ns={P.n_sources}", flush=True)
-        compare(got[k], ref, tol_grad=TOL)
+        compare(got[k], ref, tol_grad=TOL, q=P.oversample)
 
 
 def test_batch_graph_replays_match_eager_bitwise():
@@ -105,4 +105,4 @@ def test_batch_bf16x3_matches_oracle_per_problem():
     got = run_batch("bf16x3", graph=True)[0]
     for k, (w, ref) in enumerate(batch()):
         compare(got[k], ref, tol_grad=TOL_BF16X3, tol_resid=TOL_BF16X3, tol_img=TOL_BF16X3,
-                sources=w.eval_params()["sources"])
+                sources=w.eval_params()["sources"], q=w.problem.oversample, prec="bf16x3")

@@ -114,7 +114,7 @@ def test_dither_mode_matches_oracle(name, fused, dense):
     got = run(w, plan, fused)
     plan.close()
     assert got["grad_sources"].shape == (w.problem.n_sources, 3)
-    compare(got, ref, tol_grad=TOL)
+    compare(got, ref, tol_grad=TOL, q=w.problem.oversample)
 
 
 @pytest.mark.parametrize("name", list(CASES))
@@ -127,7 +127,8 @@ def test_dither_mode_bf16x3_matches_oracle(name):
     # the flux gradient sums terms of both signs over all frames: scale by the size of its terms
     rm = np.sum(np.abs(ref["r"] * ref["model"]))
     fscale = rm / np.asarray(w.eval_params()["sources"], np.float64)[:, 2]
-    compare(got, ref, tol_grad=TOL_BF16X3, tol_resid=TOL_BF16X3, tol_img=TOL_BF16X3, fscale=fscale)
+    compare(got, ref, tol_grad=TOL_BF16X3, tol_resid=TOL_BF16X3, tol_img=TOL_BF16X3, fscale=fscale,
+            q=w.problem.oversample, prec="bf16x3")
 
 
 @pytest.mark.parametrize("name", ["q2-k", "q2-10stars-9wl"])

@@ -76,7 +76,7 @@ def test_pixel_kernel_matches_oracle(name, chunked, fused):
     plan.close()
     got = {k: (v if isinstance(v, float) else v.detach().cpu().numpy().astype(np.float64)) for k, v in got.items()}
     got["grad_map"] = None
-    compare(got, ref, sources=p["sources"])
+    compare(got, ref, sources=p["sources"], q=w.problem.oversample)
     gK = gK.cpu().numpy()
     assert gK.shape == gK_ref.shape
     # dL/dK_p[a,b] sums flat_p r_fp I_f(p,a,b) over frames, terms of both signs; an error eps of the

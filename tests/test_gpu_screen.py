@@ -44,7 +44,7 @@ def test_screened_separate_calls_match_oracle():
     got = run_gpu(w, plan=plan)
     plan.close()
     assert got["status"] == 0
-    compare(got, ref, sources=w.eval_params()["sources"])
+    compare(got, ref, sources=w.eval_params()["sources"], q=w.problem.oversample)
 
 
 def test_screened_fused_and_graph_match_oracle_and_clearing_restores_bits():
@@ -61,7 +61,7 @@ def test_screened_fused_and_graph_match_oracle_and_clearing_restores_bits():
     plan.set_phase_screen(dev(scr))          # after the capture: the replay must see it
     fused = run_eval(w, plan=plan)
     assert fused["status"] == 0
-    compare(fused, ref, sources=p["sources"])
+    compare(fused, ref, sources=p["sources"], q=w.problem.oversample)
     o = cap.replay()
     torch.cuda.synchronize()
     assert plan.sync() == 0
@@ -112,7 +112,7 @@ def test_batch_plan_screen_applies_to_its_problem_only():
         g = {n: v[k].cpu().numpy().astype(np.float64) for n, v in views.items()}
         g["loss"] = float(g["loss"][0])
         g["grad_map"] = None
-        compare(g, refs[k], sources=eps[k]["sources"])
+        compare(g, refs[k], sources=eps[k]["sources"], q=ws[k].problem.oversample)
     from paper_2406_08703_amd import dlx as C
     with pytest.raises(C.DlxError):
         C.dlx_plan_set_phase_screen(bp.plan, 3, None)
@@ -139,7 +139,7 @@ def test_fresnel_defocus_row_matches_oracle_and_its_gradient_is_the_row_entry():
                            w.prior_sigma)
     got = run_eval(w)
     assert got["status"] == 0
-    compare(got, ref, sources=p["sources"])
+    compare(got, ref, sources=p["sources"], q=w.problem.oversample)
     g = ref["grad_coeffs"][-1]
     assert abs(got["grad_coeffs"][-1] - g) <= TOL * np.linalg.norm(ref["grad_coeffs"])
     assert abs(g) > 0   # the defocus moves the loss
