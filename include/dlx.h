@@ -242,6 +242,35 @@ dlx_status dlx_loss_grad(dlx_plan* plan, const float* model, const float* binned
                          const float* flat, dlx_loss_kind kind, double prior_mu, double prior_sigma,
                          double* loss_out, float* dloss_dmodel, double* grad_flat, void* stream);
 
+/* Largest frame, in pixels (n_det^2), that dlx_loss_grad_noalloc accepts. */
+#define DLX_NOALLOC_MAX_PIXELS 4194304
+
+/* For callers that cannot allocate device memory -- code under HIP graph
+ * capture, serving loops or harnesses that forbid hipMalloc: dlx_loss_grad
+ * without a plan. Arguments, outputs and arithmetic are those of
+ * dlx_loss_grad for n_frames images of n_det x n_det pixels (the same
+ * kernels: the results equal, bit for bit, dlx_loss_grad's on a plan of that
+ * many frames and pixels), with n_det^2 <= DLX_NOALLOC_MAX_PIXELS.
+ * It allocates nothing. Its FP64 per-block loss partials and its status word
+ * sit in a fixed library array of 128 KiB + 256 B on each device it runs on,
+ * held until the process ends; every call on a device shares that device's
+ * array, so calls that overlap on one device (two streams or two threads)
+ * race and must be serialised by the caller. The status word is left zero by
+ * every call.
+ *   status_out  device int32[1] receiving this call's device flags, or NULL:
+ *               0, or bit 0 (a non-finite model or data value,
+ *               DLX_ERR_NONFINITE) | bit 1 (model <= 0 where the Poisson loss
+ *               needs m > 0, clamped to 1e-30: DLX_ERR_DOMAIN).
+ * Asynchronous on `stream`, which must belong to the current device.
+ * Errors, returned before any device work: DLX_ERR_INVALID_ARG (a null
+ * pointer other than status_out, n_frames or n_det < 1, a bad loss kind or
+ * prior), DLX_ERR_UNSUPPORTED (n_det^2 > DLX_NOALLOC_MAX_PIXELS); DLX_ERR_HIP
+ * if a launch fails. */
+dlx_status dlx_loss_grad_noalloc(int32_t n_frames, int32_t n_det, const float* model, const float* binned,
+                                 const float* data, const float* flat, dlx_loss_kind kind, double prior_mu,
+                                 double prior_sigma, double* loss_out, float* dloss_dmodel, double* grad_flat,
+                                 int32_t* status_out, void* stream);
+
 /* Gradient through the optics given r = dL/dm (Sections 3-4). The inputs are
  * those of dlx_psf_forward; the focal fields are recomputed (one chunk of
  * frames at a time in the plan's workspace), unless the plan was created with

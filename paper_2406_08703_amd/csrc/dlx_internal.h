@@ -115,6 +115,10 @@ struct TileShape {
 // Tile shapes compiled for every stage and precision (the autotuner's candidates).
 constexpr TileShape kTileShapes[] = {{4, 4}, {3, 3}, {2, 2}, {4, 2}, {2, 4}, {2, 1}, {1, 2}, {1, 1}, {4, 1}, {1, 4}};
 
+int loss_block_count(long long npix);
+hipError_t launch_loss_plain(int nf, long long npix, const float* model, const float* binned, const float* data,
+                             const float* flat, int kind, double mu, double sigma, float* r, double* gflat,
+                             double* blk, int* status, double* loss, hipStream_t st);
 hipError_t launch_gemm(int kind, int prec, TileShape ts, const GemmArgs& a, int n_wg, hipStream_t st);
 bool tile_supported(int kind, int prec, bool fold, TileShape ts);
 

@@ -1016,6 +1016,18 @@ hipError_t launch_bin_loss(dlx_plan* p, int f0, int nf, int chunk, const float* 
   return hipGetLastError();
 }
 
+// dlx_loss_grad's two launches (loss_kernel without the seed, then final_sum_kernel) over
+// caller-given buffers: blk holds loss_block_count(npix) doubles, status one int (OR-ed flags).
+hipError_t launch_loss_plain(int nf, long long npix, const float* model, const float* binned, const float* data,
+                             const float* flat, int kind, double mu, double sigma, float* r, double* gflat,
+                             double* blk, int* status, double* loss, hipStream_t st) {
+  const int nb = loss_block_count(npix);
+  hipLaunchKernelGGL(loss_kernel<false>, dim3(nb), dim3(kLossThreads), 0, st, model, binned, data, flat, 0, nf, npix,
+                     kind, mu, 1.0 / (sigma * sigma), r, gflat, 0, blk, status, SeedOut{});
+  hipLaunchKernelGGL(final_sum_kernel, dim3(1), dim3(1024), 0, st, blk, nb, loss);
+  return hipGetLastError();
+}
+
 hipError_t launch_loss_final(dlx_plan* p, int n_chunks, double* loss, hipStream_t st) {
   hipLaunchKernelGGL(final_sum_kernel, dim3(1), dim3(1024), 0, st, p->d_lossblk, p->lossblk_chunk * n_chunks, loss);
   return hipGetLastError();

@@ -40,7 +40,9 @@ EXPORTS = ("dlx_validate", "dlx_plan_create", "dlx_plan_destroy", "dlx_plan_work
            "dlx_plan_sync",
            "dlx_psf_forward", "dlx_loss_grad", "dlx_psf_backward", "dlx_eval", "dlx_graph_capture",
            "dlx_graph_launch", "dlx_plan_profile", "dlx_plan_stage_times", "dlx_status_string",
-           "dlx_plan_offsets", "dlx_plan_problems", "dlx_plan_set_phase_screen")
+           "dlx_plan_offsets", "dlx_plan_problems", "dlx_plan_set_phase_screen", "dlx_loss_grad_noalloc")
+
+DLX_NOALLOC_MAX_PIXELS = 4194304
 
 OFFSET_FIELDS = ("transmission", "zernike_basis", "map_basis", "zernike_coeffs", "phase_map", "sources", "flat",
                  "intrapixel", "images", "loss")
@@ -131,6 +133,9 @@ def lib() -> ctypes.CDLL:
         L.dlx_plan_problems.argtypes = [_vp]
         L.dlx_plan_set_phase_screen.restype = ctypes.c_int
         L.dlx_plan_set_phase_screen.argtypes = [_vp, ctypes.c_int32, _vp, _vp]
+        L.dlx_loss_grad_noalloc.restype = ctypes.c_int
+        L.dlx_loss_grad_noalloc.argtypes = [ctypes.c_int32, ctypes.c_int32, _vp, _vp, _vp, _vp, ctypes.c_int,
+                                            ctypes.c_double, ctypes.c_double, _vp, _vp, _vp, _vp, _vp]
         _LIB = L
     return _LIB
 
@@ -233,6 +238,14 @@ def dlx_loss_grad(plan, model, binned, data, flat, kind, prior_mu, prior_sigma, 
     _chk(lib().dlx_loss_grad(_p(plan), _p(model), _p(binned), _p(data), _p(flat), int(kind), float(prior_mu),
                              float(prior_sigma), _p(loss_out), _p(dloss_dmodel), _p(grad_flat), _p(stream)),
          "dlx_loss_grad")
+
+
+def dlx_loss_grad_noalloc(n_frames, n_det, model, binned, data, flat, kind, prior_mu, prior_sigma, loss_out,
+                          dloss_dmodel, grad_flat, status_out=0, stream=0) -> None:
+    """dlx_loss_grad without a plan or any device allocation (a fixed library buffer per device)."""
+    _chk(lib().dlx_loss_grad_noalloc(int(n_frames), int(n_det), _p(model), _p(binned), _p(data), _p(flat), int(kind),
+                                     float(prior_mu), float(prior_sigma), _p(loss_out), _p(dloss_dmodel),
+                                     _p(grad_flat), _p(status_out), _p(stream)), "dlx_loss_grad_noalloc")
 
 
 def dlx_psf_backward(plan, transmission, zernike_basis, map_basis, zernike_coeffs, phase_map, sources, flat,

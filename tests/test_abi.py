@@ -131,3 +131,16 @@ def test_validate_integer_dither_mode():
     with pytest.raises(dlx.DlxError) as e:
         dlx.dlx_plan_create(beyond)
     assert e.value.status == dlx.DLX_ERR_INVALID_ARG
+
+
+def test_no_alloc_loss_rejects_bad_arguments_before_any_device_work():
+    L = dlx.lib()
+    nd_big = int(dlx.DLX_NOALLOC_MAX_PIXELS ** 0.5) + 1
+    good = (1, 1, 1, 1, dlx.DLX_LOSS_POISSON, 1.0, 0.05, 1, 1, 1, None, None)
+    assert L.dlx_loss_grad_noalloc(1, nd_big, *good) == dlx.DLX_ERR_UNSUPPORTED
+    assert L.dlx_loss_grad_noalloc(0, 16, *good) == dlx.DLX_ERR_INVALID_ARG
+    assert L.dlx_loss_grad_noalloc(1, 0, *good) == dlx.DLX_ERR_INVALID_ARG
+    assert L.dlx_loss_grad_noalloc(1, 16, None, *good[1:]) == dlx.DLX_ERR_INVALID_ARG
+    assert L.dlx_loss_grad_noalloc(1, 16, 1, 1, 1, 1, 9, 1.0, 0.05, 1, 1, 1, None, None) == dlx.DLX_ERR_INVALID_ARG
+    assert L.dlx_loss_grad_noalloc(1, 16, 1, 1, 1, 1, 0, 1.0, 0.0, 1, 1, 1, None, None) == dlx.DLX_ERR_INVALID_ARG
+
