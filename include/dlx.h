@@ -107,7 +107,13 @@ dlx_status dlx_validate(const dlx_problem_desc* probs, int32_t n_probs);
 /* Plan flags. By default dlx_plan_create autotunes: for each MFT stage it
  * times every compiled output-tile shape on the plan's own (zeroed)
  * workspace for the first frame chunk and keeps the fastest.
- * DLX_FLAG_NO_AUTOTUNE keeps the built-in size heuristic instead.
+ * DLX_FLAG_NO_AUTOTUNE keeps the built-in size heuristic instead. Tuned
+ * tiles are kept per problem shape and device for the process; when the
+ * environment variable DLX_TUNE_CACHE names a file, that file is the cache
+ * instead (looked up at plan creation, one line appended per newly tuned
+ * shape, naming the device by its architecture and compute-unit count), so
+ * tuning carries across processes. Lines that do not parse, or whose tiles
+ * are not compiled for their stage, are ignored.
  * The adjoint seed w phi G E is formed inside the first adjoint product's
  * operand loader; a plan with DLX_FLAG_DENSE_MFT forms it in a separate
  * elementwise pass instead when a frame's seed weights G exceed 4 MiB, and

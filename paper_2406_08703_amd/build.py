@@ -31,7 +31,8 @@ def _hipcc() -> str:
 
 
 def sources() -> list[str]:
-    return sorted(os.path.join(CSRC, f) for f in os.listdir(CSRC) if f.endswith(".hip"))
+    """The HIP sources and the plain C++ host sources (the validation layer) of the library."""
+    return sorted(os.path.join(CSRC, f) for f in os.listdir(CSRC) if f.endswith((".hip", ".cpp")))
 
 
 def build(verbose: bool = False, jobs: int = 8) -> str:

@@ -47,7 +47,6 @@ using namespace dlx;
 namespace {
 
 constexpr size_t kDefaultChunkBudget = size_t(8) << 30;  // bytes of per-chunk intermediates
-constexpr int kMaxSide = 16384;
 constexpr int kTargetWG = 1024;
 constexpr int kMaxKgradQ = 4;   // the intra-pixel gradient kernel is compiled for Q <= 4
 // A frame's seed weights larger than this (bytes) are applied in a separate
@@ -420,7 +419,11 @@ hipError_t autotune(dlx_plan* p) {
 }
 
 // Tuned tiles per problem shape and device, shared by every plan of the
-// process, so plans of a shape already seen skip the timing runs.
+// process, so plans of a shape already seen skip the timing runs. With the
+// environment variable DLX_TUNE_CACHE naming a file, that file is the cache
+// instead: tuned shapes are looked up in it and appended to it, one line each,
+// so the choice carries across processes (lines whose tiles are not compiled
+// for their stage, or that do not parse, are ignored).
 using TuneKey = std::array<long long, 12>;
 std::mutex g_tune_mu;
 struct Tuned {
@@ -436,26 +439,101 @@ TuneKey tune_key(const dlx_plan* p) {
           (p->seed_pass ? 1 : 0) | (p->fold ? 2 : 0)};
 }
 
+// "dlx-tune-v1 <arch> <CUs> <prec Ni No Q L S F frames_per_chunk Nz Nmap flags>" of the cache file:
+// the device is named by its architecture and compute-unit count, not by its index.
+bool disk_key(const dlx_plan* p, char* buf, size_t n) {
+  int dev = 0;
+  hipDeviceProp_t prop;
+  if (hipGetDevice(&dev) != hipSuccess || hipGetDeviceProperties(&prop, dev) != hipSuccess) return false;
+  char arch[64];
+  int k = 0;
+  for (const char* c = prop.gcnArchName; *c && *c != ':' && k < 63; ++c) arch[k++] = *c;
+  arch[k] = 0;
+  const TuneKey t = tune_key(p);
+  const int w = std::snprintf(buf, n, "dlx-tune-v1 %s %d %lld %lld %lld %lld %lld %lld %lld %lld %lld %lld %lld",
+                              arch, prop.multiProcessorCount, t[1], t[2], t[3], t[4], t[5], t[6], t[7], t[8], t[9],
+                              t[10], t[11]);
+  return w > 0 && (size_t)w < n;
+}
+
+bool tuned_valid(const dlx_plan* p, const Tuned& t) {
+  const int kinds[4] = {KIND_F1, KIND_F2, KIND_B3, KIND_B4};
+  for (int i = 0; i < 4; ++i)
+    if (!tile_supported(kinds[i], p->bf16(), p->fold, t.tiles[i])) return false;
+  return t.b4_ksplit == 0 || t.b4_ksplit == 1 || t.b4_ksplit == 2 || t.b4_ksplit == 4;
+}
+
+bool disk_lookup(const dlx_plan* p, const char* path, Tuned* out) {
+  char key[256];
+  if (!disk_key(p, key, sizeof key)) return false;
+  std::FILE* f = std::fopen(path, "r");
+  if (!f) return false;
+  const size_t kl = std::strlen(key);
+  char line[512];
+  bool found = false;
+  while (std::fgets(line, sizeof line, f)) {   // the last valid line for the key wins
+    if (std::strncmp(line, key, kl) != 0 || std::strncmp(line + kl, " : ", 3) != 0) continue;
+    int v[9];
+    if (std::sscanf(line + kl + 3, "%d %d %d %d %d %d %d %d %d", &v[0], &v[1], &v[2], &v[3], &v[4], &v[5], &v[6],
+                    &v[7], &v[8]) != 9)
+      continue;
+    Tuned t{{TileShape{v[0], v[1]}, TileShape{v[2], v[3]}, TileShape{v[4], v[5]}, TileShape{v[6], v[7]}}, v[8]};
+    if (!tuned_valid(p, t)) continue;
+    *out = t;
+    found = true;
+  }
+  std::fclose(f);
+  return found;
+}
+
+void disk_store(const dlx_plan* p, const char* path, const Tuned& t) {
+  char key[256];
+  if (!disk_key(p, key, sizeof key)) return;
+  std::FILE* f = std::fopen(path, "a");
+  if (!f) return;   // an unwritable cache only costs the next process its tuning
+  std::fprintf(f, "%s : %d %d %d %d %d %d %d %d %d\n", key, t.tiles[0].wm, t.tiles[0].wn, t.tiles[1].wm,
+               t.tiles[1].wn, t.tiles[2].wm, t.tiles[2].wn, t.tiles[3].wm, t.tiles[3].wn, t.b4_ksplit);
+  std::fclose(f);
+}
+
+void apply_tuned(dlx_plan* p, const Tuned& t) {
+  p->ts_f1 = t.tiles[0];
+  p->ts_f2 = t.tiles[1];
+  p->ts_b3 = t.tiles[2];
+  p->ts_b4 = t.tiles[3];
+  p->b4_ksplit_tuned = t.b4_ksplit;
+  derive_tiles(p, p->b4_ksplit_tuned);
+  p->tuned = true;
+}
+
 hipError_t autotune_cached(dlx_plan* p) {
+  const char* path = std::getenv("DLX_TUNE_CACHE");
+  const bool disk = path && path[0];
   const TuneKey key = tune_key(p);
   {
     std::lock_guard<std::mutex> lock(g_tune_mu);
-    auto it = g_tune.find(key);
-    if (it != g_tune.end()) {
-      p->ts_f1 = it->second.tiles[0];
-      p->ts_f2 = it->second.tiles[1];
-      p->ts_b3 = it->second.tiles[2];
-      p->ts_b4 = it->second.tiles[3];
-      p->b4_ksplit_tuned = it->second.b4_ksplit;
-      derive_tiles(p, p->b4_ksplit_tuned);
-      p->tuned = true;
-      return hipSuccess;
+    Tuned t;
+    if (disk) {
+      if (disk_lookup(p, path, &t)) {
+        apply_tuned(p, t);
+        return hipSuccess;
+      }
+    } else {
+      auto it = g_tune.find(key);
+      if (it != g_tune.end()) {
+        apply_tuned(p, it->second);
+        return hipSuccess;
+      }
     }
   }
   const hipError_t e = autotune(p);
   if (e == hipSuccess) {
     std::lock_guard<std::mutex> lock(g_tune_mu);
-    g_tune[key] = Tuned{{p->ts_f1, p->ts_f2, p->ts_b3, p->ts_b4}, p->b4_ksplit_tuned};
+    const Tuned t{{p->ts_f1, p->ts_f2, p->ts_b3, p->ts_b4}, p->b4_ksplit_tuned};
+    if (disk)
+      disk_store(p, path, t);
+    else
+      g_tune[key] = t;
   }
   return e;
 }
@@ -569,51 +647,6 @@ T* at(T* base, long long off) {
 }  // namespace
 
 extern "C" {
-
-const char* dlx_status_string(dlx_status s) {
-  switch (s) {
-    case DLX_OK: return "DLX_OK";
-    case DLX_ERR_INVALID_ARG: return "DLX_ERR_INVALID_ARG: null pointer, non-positive size or bad enum";
-    case DLX_ERR_SHAPE: return "DLX_ERR_SHAPE: inconsistent sizes";
-    case DLX_ERR_OOM: return "DLX_ERR_OOM: workspace does not fit";
-    case DLX_ERR_HIP: return "DLX_ERR_HIP: a HIP runtime call failed";
-    case DLX_ERR_NONFINITE: return "DLX_ERR_NONFINITE: non-finite model or data";
-    case DLX_ERR_DOMAIN: return "DLX_ERR_DOMAIN: model <= 0 under the Poisson loss (clamped)";
-    case DLX_ERR_UNSUPPORTED: return "DLX_ERR_UNSUPPORTED: not implemented by the library";
-  }
-  return "unknown dlx_status";
-}
-
-dlx_status dlx_validate(const dlx_problem_desc* probs, int32_t n_probs) {
-  if (!probs || n_probs < 1) return DLX_ERR_INVALID_ARG;
-  for (int i = 0; i < n_probs; ++i) {
-    const dlx_problem_desc& d = probs[i];
-    if (d.n_pupil < 2 || d.n_focal < 1 || d.oversample < 1 || d.n_wavelengths < 1 || d.n_sources < 1 ||
-        d.n_frames < 1 || d.n_zernike < 0 || d.n_map < 0)
-      return DLX_ERR_INVALID_ARG;
-    if (!(d.diameter_m > 0.0) || !(d.focal_pixel_rad > 0.0) || !std::isfinite(d.diameter_m) ||
-        !std::isfinite(d.focal_pixel_rad))
-      return DLX_ERR_INVALID_ARG;
-    if (!d.wavelengths_m || !d.spectral_weights) return DLX_ERR_INVALID_ARG;
-    for (int l = 0; l < d.n_wavelengths; ++l) {
-      if (!(d.wavelengths_m[l] > 0.0) || !std::isfinite(d.wavelengths_m[l])) return DLX_ERR_INVALID_ARG;
-      if (!std::isfinite(d.spectral_weights[l])) return DLX_ERR_INVALID_ARG;
-    }
-    if (d.n_focal % d.oversample != 0) return DLX_ERR_SHAPE;
-    if (d.n_pupil > kMaxSide || d.n_focal > kMaxSide) return DLX_ERR_SHAPE;
-    if (d.frame_dithers) {
-      if (d.dither_margin < 0) return DLX_ERR_INVALID_ARG;
-      if ((long long)d.n_focal + 2LL * d.oversample * d.dither_margin > kMaxSide) return DLX_ERR_SHAPE;
-      for (int f = 0; f < d.n_frames; ++f)
-        for (int c = 0; c < 2; ++c) {
-          const int v = d.frame_dithers[2 * f + c];
-          if (v > d.dither_margin || v < -d.dither_margin) return DLX_ERR_INVALID_ARG;
-        }
-    }
-    if ((long long)d.n_frames * d.n_sources * d.n_wavelengths > (1LL << 24)) return DLX_ERR_SHAPE;
-  }
-  return DLX_OK;
-}
 
 dlx_status dlx_plan_create(const dlx_problem_desc* probs, int32_t n_probs, dlx_precision precision, int32_t flags,
                            size_t workspace_limit_bytes, dlx_plan** out) {

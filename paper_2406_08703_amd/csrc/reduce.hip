@@ -879,7 +879,11 @@ hipError_t launch_intensity(dlx_plan* p, int f0, int nf, const float* sources, c
   hipLaunchKernelGGL(intensity_kernel<QT>, grid, blk, 0, st, p->d_Y, plane, by, p->ldNo, f0, p->F, p->S, p->L, \
                      p->Q, p->Nd, sources, p->d_wl, intrapixel, kstride(p), p->hNo(), p->sNo(), flat, p->d_bs,   \
                      binned, model)
-  if (p->Q == 1 && p->Nd % 4 == 0 && (!p->fold || p->hNo() % 4 == 0)) {
+  // the four-pixel kernel moves flat, binned and model in 16-byte vectors: caller pointers must be
+  // 16-byte aligned (packed multi-problem arrays are not after a problem with an odd pixel count)
+  const bool aligned16 = ((reinterpret_cast<uintptr_t>(flat) | reinterpret_cast<uintptr_t>(binned) |
+                           reinterpret_cast<uintptr_t>(model)) & 15) == 0;
+  if (p->Q == 1 && p->Nd % 4 == 0 && (!p->fold || p->hNo() % 4 == 0) && aligned16) {
     const dim3 grid4((unsigned)((npix / 4 + 63) / 64), nf);
     hipLaunchKernelGGL(intensity_q1v_kernel, grid4, blk, 0, st, p->d_Y, plane, by, p->ldNo, f0, p->F, p->S, p->L,
                        p->Nd, sources, p->d_wl, intrapixel, kstride(p), p->hNo(), p->sNo(), flat, p->d_bs, binned,

@@ -111,6 +111,25 @@ def binary_phase_screen(n: int, rng: np.random.Generator, n_waves: int = 6, max_
     return np.where(f > 0, np.pi, 0.0).astype(np.float32)
 
 
+def fresnel_defocus_basis(n_pupil: int, diameter: float, focal_length: float) -> np.ndarray:
+    """Pupil OPD per metre of detector defocus, -(x^2 + y^2) / (2 f^2), as FP32 [n_pupil, n_pupil].
+
+    Section 1 names the Fresnel regime of a slightly defocused detector: a quadratic phase factor
+    before the Fourier transform and another after it. For a detector displaced by delta past the
+    focus of a system of focal length f, the factor before the transform is the pupil optical path
+    difference -delta (x^2 + y^2) / (2 f^2) (paraxial, delta << f). Appended to the aberration
+    basis (rows [N_z, n, n]) with coefficient delta in metres, it models the defocused detector, and
+    the gradient with respect to delta is that row's entry of the Zernike gradient. The factor after
+    the transform has unit modulus on the focal grid and changes neither |E|^2 nor the gradient, so
+    it is not an input; the change of the angular pixel scale by delta / f is neglected at this
+    order."""
+    if focal_length <= 0:
+        raise ValueError("focal_length must be positive")
+    x = pixel_centres(n_pupil, diameter / n_pupil)
+    r2 = x[None, :] ** 2 + x[:, None] ** 2
+    return (-r2 / (2.0 * focal_length ** 2)).astype(np.float32)
+
+
 def keys_weight(t: np.ndarray, a: float = -0.5) -> np.ndarray:
     """Keys (1981) cubic convolution kernel with parameter ``a``."""
     t = np.abs(t)

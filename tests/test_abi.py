@@ -1,5 +1,6 @@
 """C-ABI checks that need no GPU: the library loads, exports every declared
 symbol, and rejects bad arguments before touching the device."""
+import ctypes
 import os
 import re
 
@@ -144,3 +145,41 @@ def test_no_alloc_loss_rejects_bad_arguments_before_any_device_work():
     assert L.dlx_loss_grad_noalloc(1, 16, 1, 1, 1, 1, 9, 1.0, 0.05, 1, 1, 1, None, None) == dlx.DLX_ERR_INVALID_ARG
     assert L.dlx_loss_grad_noalloc(1, 16, 1, 1, 1, 1, 0, 1.0, 0.0, 1, 1, 1, None, None) == dlx.DLX_ERR_INVALID_ARG
 
+
+def test_validation_layer_under_address_sanitizer(tmp_path):
+    """The host validation layer built on its own with AddressSanitizer and UBSan (g++, host code
+    only), driven over good and malformed problem descriptions."""
+    import shutil
+    import subprocess
+    gxx = shutil.which("g++")
+    if gxx is None:
+        pytest.skip("g++ not available")
+    exe = tmp_path / "validate_asan"
+    src = os.path.join(ROOT, "paper_2406_08703_amd", "csrc", "validate.cpp")
+    drv = os.path.join(ROOT, "tests", "native", "validate_driver.cpp")
+    cmd = [gxx, "-std=c++17", "-O1", "-g", "-fno-omit-frame-pointer", "-fsanitize=address,undefined",
+           "-fno-sanitize-recover=all", "-I", os.path.join(ROOT, "include"), src, drv, "-o", str(exe)]
+    r = subprocess.run(cmd, capture_output=True, text=True)
+    assert r.returncode == 0, r.stderr
+    run = subprocess.run([str(exe)], capture_output=True, text=True,
+                         env=dict(os.environ, ASAN_OPTIONS="detect_leaks=1:verify_asan_link_order=0"))
+    assert run.returncode == 0, run.stdout + run.stderr
+    assert "validation driver ok" in run.stdout
+
+
+def test_plan_create_reports_oom_for_a_limit_below_one_frame():
+    # the workspace limit is checked against the fixed arrays plus one frame before any device call
+    d, keep = _desc(n_pupil=256, n_focal=512, oversample=4, n_frames=4)
+    out = ctypes.c_void_p()
+    s = dlx.lib().dlx_plan_create(ctypes.byref(d), 1, dlx.DLX_FP32, 0, 1 << 20, ctypes.byref(out))
+    assert s == dlx.DLX_ERR_OOM and not out.value
+
+
+def test_plan_create_reports_oom_when_stored_fields_do_not_fit_the_limit():
+    # stored fields need every frame in one chunk: a limit that holds one frame but not four fails
+    d, keep = _desc(n_pupil=64, n_focal=64, oversample=2, n_frames=4)
+    out = ctypes.c_void_p()
+    # fixed arrays 96 KiB and 116 KiB per frame at this size: room for one or two frames, not four
+    s = dlx.lib().dlx_plan_create(ctypes.byref(d), 1, dlx.DLX_FP32, dlx.DLX_FLAG_STORE_FIELDS, 300000,
+                                  ctypes.byref(out))
+    assert s == dlx.DLX_ERR_OOM and not out.value

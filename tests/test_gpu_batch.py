@@ -106,3 +106,47 @@ def test_batch_bf16x3_matches_oracle_per_problem():
     for k, (w, ref) in enumerate(batch()):
         compare(got[k], ref, tol_grad=TOL_BF16X3, tol_resid=TOL_BF16X3, tol_img=TOL_BF16X3,
                 sources=w.eval_params()["sources"], q=w.problem.oversample, prec="bf16x3")
+
+
+def test_q1_problem_packed_after_an_odd_sized_problem():
+    """A Q = 1 problem whose detector width allows the four-pixel binning kernel, packed after a
+    problem with an odd pixel count: its flat and image arrays start at offsets that are not 16-byte
+    aligned, so binning takes the one-pixel kernel; both problems must match the oracle."""
+    import torch
+    from paper_2406_08703_amd import BatchPlan
+    from synth import make_workload
+    from tests.gpu_helpers import geometry
+    print("batch: q1 problem after an odd problem", flush=True)
+    ws = [make_workload("c1", n_pupil=24, n_focal=21, oversample=3, noll=tuple(range(2, 8))),
+          make_workload("c2", n_pupil=32, n_focal=40, oversample=1, n_wavelengths=3, n_frames=2,
+                        noll=tuple(range(2, 9)))]
+    assert (ws[0].problem.n_det ** 2) % 4 != 0 and ws[1].problem.n_det % 8 == 0
+    refs = []
+    for k, w in enumerate(ws):
+        prob = oracle_problem(w)
+        _, m = O.forward(prob, w.coeffs_true, None, w.sources_true, w.flat_true)
+        ws[k] = w = w.with_data(m)
+        p = w.eval_params()
+        refs.append(O.value_and_grad(prob, p["coeffs"], None, p["sources"], p["flat"], w.data, "poisson",
+                                     w.prior_mu, w.prior_sigma))
+    t = lambda a: torch.from_numpy(np.ascontiguousarray(a, dtype=np.float32))
+    bp = BatchPlan([geometry(w) for w in ws], [t(w.transmission) for w in ws], [t(w.zbasis) for w in ws])
+    assert bp.offsets[1]["flat"] % 4 != 0 and bp.offsets[1]["images"] % 4 != 0
+    eps = [w.eval_params() for w in ws]
+    c = bp.pack("zernike_coeffs", [t(e["coeffs"]) for e in eps])
+    s = bp.pack("sources", [t(e["sources"]) for e in eps])
+    fl = bp.pack("flat", [t(e["flat"]) for e in eps])
+    d = bp.pack("images", [t(w.data) for w in ws])
+    out = bp.buffers()
+    bp.evaluate(bp.eval_args(c, None, s, fl, d, out, "poisson", ws[0].prior_mu, ws[0].prior_sigma))
+    assert bp.sync() == 0
+    views = {n: bp.unpack(f, out[k]) for n, k, f in (
+        ("binned", "binned", "images"), ("model", "model", "images"), ("r", "r", "images"),
+        ("loss", "loss", "loss"), ("grad_flat", "grad_flat", "flat"),
+        ("grad_coeffs", "grad_zernike", "zernike_coeffs"), ("grad_sources", "grad_sources", "sources"))}
+    for k, w in enumerate(ws):
+        g = {n: v[k].cpu().numpy().astype(np.float64) for n, v in views.items()}
+        g["loss"] = float(g["loss"][0])
+        g["grad_map"] = None
+        compare(g, refs[k], q=w.problem.oversample)
+    bp.close()

@@ -123,7 +123,10 @@ def pixel_errors(got, want, q, kind="poisson", min_counts=1.0):
             shape = dm * 3.0 * q * np.sqrt(np.max(m) / m[sel])
             rnd = 4.0 * EPS32 * (2.0 - r)
             dr = np.abs(np.asarray(got["r"][f], np.float64)[sel] - r)
-            e = max(e, float(np.max((dr - rnd).clip(min=0.0) / shape)))
+            excess = (dr - rnd).clip(min=0.0)
+            # d = 0 gives r = 1 exactly whatever m is (shape 0): any excess there is a failure
+            ratio = np.divide(excess, shape, out=np.where(excess > 0, np.inf, 0.0), where=shape > 0)
+            e = max(e, float(np.max(ratio)))
             worst_scale = max(worst_scale, float(np.max(dr / np.maximum(np.abs(r), 1.0))))
         out["r"] = e
         out["r_abs_over_max1r"] = worst_scale

@@ -120,7 +120,7 @@ def test_batch_plan_screen_applies_to_its_problem_only():
 
 
 def test_fresnel_defocus_row_matches_oracle_and_its_gradient_is_the_row_entry():
-    from paper_2406_08703_amd.optics import fresnel_defocus_basis
+    from synth import fresnel_defocus_basis
     from tests.gpu_helpers import run_eval
     print("fresnel defocus", flush=True)
     w = make_workload("c2", n_pupil=64, n_focal=96, n_wavelengths=3, noll=tuple(range(2, 9)))

@@ -559,7 +559,7 @@ def test_fresnel_defocus_basis_matches_angular_spectrum_propagation():
     # periodic DFT of the pupil, so propagating it a distance delta by its angular spectrum (paraxial
     # transfer function exp(-i pi lambda delta kappa^2) in this sign convention, where a +alpha tilt images
     # at +alpha) is exact, and must equal the focal field of the pupil with the defocus OPD added.
-    from paper_2406_08703_amd.optics import fresnel_defocus_basis
+    from synth import fresnel_defocus_basis
     D, ni, lam, f = 0.5, 33, 600e-9, 8.0
     npad = 66
     dx = D / ni
