@@ -123,8 +123,26 @@ enum {
   DLX_FLAG_SEED_PASS = 2,
   DLX_FLAG_STORE_FIELDS = 4,
   DLX_FLAG_PIXEL_KERNEL = 8,
-  DLX_FLAG_DENSE_MFT = 16
+  DLX_FLAG_DENSE_MFT = 16,
+  DLX_FLAG_GROUPED = 32
 };
+
+/* DLX_FLAG_GROUPED (plans of several problems): dlx_eval runs each stage as
+ * ONE launch over every problem -- the OPD and tilts, the pupil fields, the
+ * four MFT products, the binning with the loss, and the three final
+ * reductions -- instead of each problem's own launch sequence on the plan's
+ * concurrent streams. A device table maps every workgroup of a launch to its
+ * problem and its tile; the per-problem arguments live in device memory, and
+ * a call passes only its packed arrays' base pointers, so the launches
+ * replay from a captured graph. The MFT tile of each stage (shared by all
+ * problems) and B4's split and PSFs per group are tuned over the whole batch
+ * at plan creation. It applies when every problem has one frame, no bicubic
+ * map and no integer dithers, with the symmetric fold and without
+ * DLX_FLAG_SEED_PASS, DLX_FLAG_STORE_FIELDS or DLX_FLAG_PIXEL_KERNEL, and to
+ * calls without grad_intrapixel; otherwise the problems run on the streams.
+ * dlx_psf_forward, dlx_loss_grad and dlx_psf_backward always run per problem.
+ * Results equal the per-problem form's up to the order of partial sums in
+ * the gradient reductions (the images are the same bits). */
 
 /* The MFT products use the symmetry of the pixel-centred grids (Section 3's
  * coordinates are centred on the optical axis, so every sample x has a
@@ -164,8 +182,8 @@ enum {
  * dlx_psf_backward / dlx_eval then packs the problems' arrays one after the
  * other, problem k starting at the element offsets dlx_plan_offsets reports
  * (loss_out holds one loss per problem). flags: an OR of DLX_FLAG_NO_AUTOTUNE,
- * DLX_FLAG_SEED_PASS, DLX_FLAG_STORE_FIELDS, DLX_FLAG_PIXEL_KERNEL and
- * DLX_FLAG_DENSE_MFT (other bits: DLX_ERR_INVALID_ARG). Results do not depend on the tiles chosen
+ * DLX_FLAG_SEED_PASS, DLX_FLAG_STORE_FIELDS, DLX_FLAG_PIXEL_KERNEL,
+ * DLX_FLAG_DENSE_MFT and DLX_FLAG_GROUPED (other bits: DLX_ERR_INVALID_ARG). Results do not depend on the tiles chosen
  * except for the order of FP32/FP64 partial sums in the gradient
  * reductions. workspace_limit_bytes: 0 = no limit;
  * otherwise the frame-chunk size is reduced until the workspace fits, and

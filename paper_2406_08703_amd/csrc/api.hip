@@ -40,6 +40,7 @@ hipError_t launch_kgrad(dlx_plan* p, int f0, int nf, const float* sources, const
 int loss_block_count(long long npix);
 int seed_block_count(long long npix);
 int zproj_chunks(long long npix, int Nz);
+int bin_loss_block_count(long long npix);
 }  // namespace dlx
 
 using namespace dlx;
@@ -234,7 +235,7 @@ void set_fold(const dlx_plan* p, GemmArgs& a, int mirror_n, int k_full, int out_
 }
 
 // F1: T = M_l P for every PSF of frames [f0, f0 + nf)
-hipError_t run_f1(dlx_plan* p, int f0, int nf, hipStream_t st) {
+GemmArgs args_f1(dlx_plan* p, int f0, int nf) {
   GemmArgs a = base_args(p, f0, nf);
   a.M = p->fold ? p->hNo() : p->No;
   a.N = p->Ni;
@@ -248,13 +249,18 @@ hipError_t run_f1(dlx_plan* p, int f0, int nf, hipStream_t st) {
   a.out_by_psf = op_T(p).by_psf;
   a.ldo = p->ldNi;
   set_tiles(a, p->ts_f1);
+  return a;
+}
+
+hipError_t run_f1(dlx_plan* p, int f0, int nf, hipStream_t st) {
+  const GemmArgs a = args_f1(p, f0, nf);
   return launch_gemm(KIND_F1, p->bf16(), p->ts_f1, a, wg_count(a), st);
 }
 
 GemmArgs e_args(dlx_plan* p, int f0, int nf, TileShape ts);
 
 // F2 over frames [f0, f0 + nf): E = c T M^T into the Y buffer.
-hipError_t run_f2(dlx_plan* p, int f0, int nf, hipStream_t st) {
+GemmArgs args_f2(dlx_plan* p, int f0, int nf) {
   GemmArgs a = e_args(p, f0, nf, p->ts_f2);
   a.n_items = nf * p->S * p->L;
   if (p->fold) {
@@ -267,12 +273,17 @@ hipError_t run_f2(dlx_plan* p, int f0, int nf, hipStream_t st) {
   a.out_plane = (long long)p->chunk_psf * p->No * p->ldNo;
   a.out_by_psf = (long long)p->No * p->ldNo;
   a.ldo = p->ldNo;
+  return a;
+}
+
+hipError_t run_f2(dlx_plan* p, int f0, int nf, hipStream_t st) {
+  const GemmArgs a = args_f2(p, f0, nf);
   return launch_gemm(KIND_F2, p->bf16(), p->ts_f2, a, wg_count(a), st);
 }
 
 // B3 over frames [f0, f0 + nf): U^T = conj(M)^T Y^T with the seed Y = w phi G E
 // formed in the loader from E and the seed weights G.
-hipError_t run_b3(dlx_plan* p, int f0, int nf, const float* sources, hipStream_t st) {
+GemmArgs args_b3(dlx_plan* p, int f0, int nf, const float* sources) {
   GemmArgs a = base_args(p, f0, nf);
   a.M = p->fold ? p->hNi() : p->Ni;
   a.N = p->No;
@@ -290,11 +301,16 @@ hipError_t run_b3(dlx_plan* p, int f0, int nf, const float* sources, hipStream_t
   a.out_by_psf = op_UT(p).by_psf;
   a.ldo = p->ldNo;
   set_tiles(a, p->ts_b3);
+  return a;
+}
+
+hipError_t run_b3(dlx_plan* p, int f0, int nf, const float* sources, hipStream_t st) {
+  const GemmArgs a = args_b3(p, f0, nf, sources);
   return launch_gemm(KIND_B3, p->bf16(), p->ts_b3, a, wg_count(a), st);
 }
 
 // B4 over frames [f0, f0 + nf) of chunk c: W = c M^H U, phase gradient and position sums.
-hipError_t run_b4(dlx_plan* p, int c, int f0, int nf, hipStream_t st) {
+GemmArgs args_b4(dlx_plan* p, int c, int f0, int nf) {
   const int nc = nf * p->S * p->L;
   GemmArgs a = base_args(p, f0, nf);
   a.M = p->fold ? p->hNi() : p->Ni;
@@ -312,6 +328,11 @@ hipError_t run_b4(dlx_plan* p, int c, int f0, int nf, hipStream_t st) {
   a.accumulate = c > 0;
   a.red = p->d_pos;
   set_tiles(a, p->ts_b4);
+  return a;
+}
+
+hipError_t run_b4(dlx_plan* p, int c, int f0, int nf, hipStream_t st) {
+  const GemmArgs a = args_b4(p, c, f0, nf);
   return launch_gemm(KIND_B4, p->bf16(), p->ts_b4, a, wg_count(a), st);
 }
 
@@ -557,6 +578,452 @@ extern "C" dlx_status dlx_plan_create(const dlx_problem_desc* probs, int32_t n_p
 
 namespace {
 
+// ---- grouped launches: every stage of dlx_eval as one launch over all problems of the plan.
+// Used when every problem has one frame, no bicubic map and no integer dithers, and the plan folds
+// its products with the seed formed in B3's loader (no flags beyond NO_AUTOTUNE). Per-problem
+// arguments and block tables sit in device memory, built at plan creation; each call passes only
+// the base pointers of its packed arrays, so a captured graph replays with the call's pointers.
+}  // namespace
+
+namespace dlx {
+struct GroupPlan {
+  void* dmem = nullptr;         // GEMM arguments, block tables and the tuning star table
+  void* dmem_small = nullptr;   // the small stages' arguments and block tables
+  TileShape ts[4];     // F1, F2, B3, B4, shared by every problem
+  int b4_ks = 1;       // B4's split of K (each problem keeps at least 64 per range)
+  int b4_psfs = 32;    // PSFs per B4 group: one launch fills the chip with every problem's tiles, so
+                       // a problem needs few groups, and few dL/dOPD partial planes to write and reduce
+  std::vector<int> b4_groups_cap;   // each problem's group count its partial-plane buffer holds
+  GemmArgs* d_gargs[4] = {};
+  int2* d_gtab[4] = {};
+  int n_wg[4] = {}, cap_wg[4] = {};
+  PrepArgs* d_prep = nullptr;
+  GroupBlock* d_prep_tab = nullptr;
+  int n_prep = 0;
+  PupilArgs* d_pupil = nullptr;
+  GroupBlock* d_pupil_tab = nullptr;
+  int n_pupil = 0;
+  BinLossArgs* d_bl = nullptr;
+  GroupBlock* d_bl_tab[4] = {};   // problems by the compiled oversampling of their binning: 1, 2, 4, other
+  int n_bl[4] = {}, qt_of[4] = {1, 2, 4, 0};
+  GradArgs* d_grad = nullptr;
+  GroupBlock *d_gopd_tab = nullptr, *d_z_tab = nullptr, *d_fin_tab = nullptr;
+  int n_gopd = 0, n_z = 0, n_fin = 0;
+  float* d_tune_src = nullptr;
+};
+}  // namespace dlx
+
+namespace {
+
+constexpr int kGroupKinds[4] = {KIND_F1, KIND_F2, KIND_B3, KIND_B4};
+
+bool group_eligible(const dlx_problem_desc* probs, int n, int32_t flags) {
+  if (!(flags & DLX_FLAG_GROUPED)) return false;
+  if (flags & (DLX_FLAG_SEED_PASS | DLX_FLAG_STORE_FIELDS | DLX_FLAG_PIXEL_KERNEL | DLX_FLAG_DENSE_MFT)) return false;
+  for (int k = 0; k < n; ++k)
+    if (probs[k].frame_dithers || probs[k].n_frames != 1 || probs[k].n_map != 0) return false;
+  return true;
+}
+
+int b4_split_for(const dlx_plan* q, int ks) {
+  while (ks > 1 && q->hNo() / ks < 64) ks /= 2;
+  return ks;
+}
+
+int bin_class(int Q) { return Q == 1 ? 0 : Q == 2 ? 1 : Q == 4 ? 2 : 3; }
+
+// Stage s's tiles on every sub-plan (B4 with its split), as the grouped launch and the per-problem
+// calls of the plan use them.
+void group_apply_tiles(dlx_plan* p, int s) {
+  GroupPlan& g = *p->group;
+  for (size_t k = 0; k < p->subs.size(); ++k) {
+    dlx_plan* q = p->subs[k];
+    TileShape* t = s == 0 ? &q->ts_f1 : s == 1 ? &q->ts_f2 : s == 2 ? &q->ts_b3 : &q->ts_b4;
+    *t = g.ts[s];
+    if (s == 3) {
+      const int groups = std::min(g.b4_groups_cap[k], ceil_div(q->chunk_psf, g.b4_psfs));
+      q->b4_gsize = ceil_div(q->chunk_psf, groups);
+      q->b4_groups_max = ceil_div(q->chunk_psf, q->b4_gsize);
+      q->b4_ksplit_tuned = b4_split_for(q, g.b4_ks);
+      derive_tiles(q, q->b4_ksplit_tuned);
+    }
+  }
+}
+
+GemmArgs group_stage_args(dlx_plan* q, int s) {
+  switch (s) {
+    case 0: return args_f1(q, 0, q->F);
+    case 1: return args_f2(q, 0, q->F);
+    case 2: return args_b3(q, 0, q->F, nullptr);
+    default: return args_b4(q, 0, 0, q->F);
+  }
+}
+
+// Arguments and block table of GEMM stage s for the current tiles, uploaded (problems in order of
+// decreasing work, so the largest start first).
+hipError_t group_stage_upload(dlx_plan* p, int s) {
+  GroupPlan& g = *p->group;
+  group_apply_tiles(p, s);
+  const int n = (int)p->subs.size();
+  std::vector<GemmArgs> args(n);
+  std::vector<int2> tab;
+  for (int k : p->order) {
+    GemmArgs a = group_stage_args(p->subs[k], s);
+    a.sources = nullptr;
+    a.src_off = p->offs[k].sources;
+    args[k] = a;
+    const int nw = wg_count(a);
+    for (int w = 0; w < nw; ++w) tab.push_back(make_int2(k, w));
+  }
+  if ((int)tab.size() > g.cap_wg[s]) return hipErrorInvalidValue;
+  hipError_t e = hipMemcpy(g.d_gargs[s], args.data(), sizeof(GemmArgs) * n, hipMemcpyHostToDevice);
+  if (e == hipSuccess && !tab.empty())
+    e = hipMemcpy(g.d_gtab[s], tab.data(), sizeof(int2) * tab.size(), hipMemcpyHostToDevice);
+  g.n_wg[s] = (int)tab.size();
+  return e;
+}
+
+hipError_t group_gemm(dlx_plan* p, int s, const float* sources, hipStream_t st) {
+  const GroupPlan& g = *p->group;
+  return launch_gemm_group(kGroupKinds[s], p->bf16(), g.ts[s], g.d_gargs[s], g.d_gtab[s], g.n_wg[s], sources, st);
+}
+
+// Time every compiled tile shape of each stage (and B4's splits) as one grouped launch on the
+// zeroed workspaces, keep the fastest.
+hipError_t group_autotune(dlx_plan* p) {
+  GroupPlan& g = *p->group;
+  hipEvent_t t0, t1;
+  hipError_t e = hipEventCreate(&t0);
+  if (e != hipSuccess) return e;
+  if ((e = hipEventCreate(&t1)) != hipSuccess) {
+    (void)hipEventDestroy(t0);
+    return e;
+  }
+  const char* env = std::getenv("DLX_TUNE_LOG");
+  const bool log = env && env[0] == '1';
+  for (int s = 0; s < 4 && e == hipSuccess; ++s) {
+    TileShape best = g.ts[s];
+    int best_ks = g.b4_ks;
+    float best_ms = 1e30f;
+    const int n_ks = s == 3 ? 3 : 1;
+    for (int ci = 0; ci < (int)(sizeof(kTileShapes) / sizeof(kTileShapes[0])) * n_ks && e == hipSuccess; ++ci) {
+      const TileShape cand = kTileShapes[ci / n_ks];
+      if (!tile_supported(kGroupKinds[s], p->bf16(), true, cand)) continue;
+      g.ts[s] = cand;
+      if (s == 3) g.b4_ks = 1 << (ci % n_ks);
+      if ((e = group_stage_upload(p, s)) != hipSuccess) break;
+      if ((e = group_gemm(p, s, g.d_tune_src, nullptr)) != hipSuccess) break;   // warm-up
+      if ((e = hipEventRecord(t0, nullptr)) != hipSuccess) break;
+      for (int r = 0; r < 2 && e == hipSuccess; ++r) e = group_gemm(p, s, g.d_tune_src, nullptr);
+      if (e != hipSuccess) break;
+      if ((e = hipEventRecord(t1, nullptr)) != hipSuccess) break;
+      if ((e = hipEventSynchronize(t1)) != hipSuccess) break;
+      float ms = 0.f;
+      if ((e = hipEventElapsedTime(&ms, t0, t1)) != hipSuccess) break;
+      if (log)
+        std::fprintf(stderr, "dlx group tune: stage %d tile %dx%d ksplit %d: %.4f ms per launch\n", kGroupKinds[s],
+                     cand.bm(), cand.bn(), g.b4_ks, ms / 2);
+      if (ms < best_ms) {
+        best_ms = ms;
+        best = cand;
+        best_ks = g.b4_ks;
+      }
+    }
+    g.ts[s] = best;
+    g.b4_ks = best_ks;
+    if (s == 3 && e == hipSuccess) {   // then B4's PSFs per group, with its tile and split
+      const int cands[4] = {8, 16, 32, 64};
+      int best_gp = g.b4_psfs;
+      best_ms = 1e30f;
+      for (int gp : cands) {
+        g.b4_psfs = gp;
+        if ((e = group_stage_upload(p, s)) != hipSuccess) break;
+        if ((e = group_gemm(p, s, g.d_tune_src, nullptr)) != hipSuccess) break;
+        if ((e = hipEventRecord(t0, nullptr)) != hipSuccess) break;
+        for (int r = 0; r < 2 && e == hipSuccess; ++r) e = group_gemm(p, s, g.d_tune_src, nullptr);
+        if (e != hipSuccess) break;
+        if ((e = hipEventRecord(t1, nullptr)) != hipSuccess) break;
+        if ((e = hipEventSynchronize(t1)) != hipSuccess) break;
+        float ms = 0.f;
+        if ((e = hipEventElapsedTime(&ms, t0, t1)) != hipSuccess) break;
+        if (log) std::fprintf(stderr, "dlx group tune: B4 %d PSFs per group: %.4f ms per launch\n", gp, ms / 2);
+        if (ms < best_ms) {
+          best_ms = ms;
+          best_gp = gp;
+        }
+      }
+      g.b4_psfs = best_gp;
+    }
+    if (e == hipSuccess) e = group_stage_upload(p, s);
+  }
+  (void)hipEventDestroy(t0);
+  (void)hipEventDestroy(t1);
+  if (e == hipSuccess) e = hipDeviceSynchronize();
+  return e;
+}
+
+// Arguments and block tables of the small stages (after the tiles are final: the dL/dOPD reduction
+// follows B4's groups and split).
+hipError_t group_small_upload(dlx_plan* p) {
+  GroupPlan& g = *p->group;
+  const int n = (int)p->subs.size();
+  std::vector<PrepArgs> prep(n);
+  std::vector<PupilArgs> pupil(n);
+  std::vector<BinLossArgs> bl(n);
+  std::vector<GradArgs> grad(n);
+  std::vector<GroupBlock> t_prep, t_pupil, t_bl[4], t_gopd, t_z, t_fin;
+  for (int k : p->order) {
+    const dlx_plan* q = p->subs[k];
+    const dlx_offsets& o = p->offs[k];
+    const long long npix = (long long)q->Ni * q->Ni;
+    PrepArgs& a = prep[k];
+    a.Nz = q->Nz;
+    a.Ni = q->Ni;
+    a.nb_opd = (int)((npix + 255) / 256);
+    a.n_norm = q->n_norm_part;
+    a.L = q->L;
+    a.ldt = q->ldNi;
+    a.npix = npix;
+    a.n_tilt = (long long)q->n_psf * q->ldNi;
+    a.tplane = a.n_tilt;
+    a.opd = q->d_opd;
+    a.norm_part = q->d_norm;
+    a.wl = q->d_wl;
+    a.x = q->d_x;
+    a.tx = q->d_tx;
+    a.ty = q->d_ty;
+    a.o_trans = o.transmission;
+    a.o_z = o.zernike_basis;
+    a.o_c = o.zernike_coeffs;
+    a.o_src = o.sources;
+    const int nb_prep = a.nb_opd + a.n_norm + (int)((a.n_tilt + 255) / 256);
+    for (int b = 0; b < nb_prep; ++b) t_prep.push_back(GroupBlock{k, b, 0, 0});
+
+    PupilArgs& u = pupil[k];
+    u.opd = q->d_opd;
+    u.screen = q->d_screen;
+    u.norm_part = q->d_norm;
+    u.n_norm = q->n_norm_part;
+    u.Ni = q->Ni;
+    u.ldp = q->ldNi;
+    u.h = q->hNi();
+    u.wl = q->d_wl;
+    u.P0T = q->d_P0T;
+    u.plane = (long long)q->Ni * q->ldNi;
+    u.by_wl = 2LL * q->Ni * q->ldNi;
+    u.o_trans = o.transmission;
+    for (int l = 0; l < q->L; ++l)
+      for (int y = 0; y < (q->ldNi + 31) / 32; ++y)
+        for (int x = 0; x < (q->Ni + 31) / 32; ++x) t_pupil.push_back(GroupBlock{k, x, y, l});
+
+    BinLossArgs& b = bl[k];
+    b.E = q->d_Y;
+    b.plane = (long long)q->chunk_psf * q->No * q->ldNo;
+    b.by_psf = (long long)q->No * q->ldNo;
+    b.ld = q->ldNo;
+    b.S = q->S;
+    b.L = q->L;
+    b.Q = q->Q;
+    b.Nd = q->Nd;
+    b.fh = q->hNo();
+    b.fs = q->sNo();
+    b.ldg = q->ldNo;
+    b.nb = bin_loss_block_count((long long)q->Nd * q->Nd);
+    b.wl = q->d_wl;
+    b.kst = 0;
+    b.g_by_frame = (long long)q->No * q->ldNo;
+    b.bs = q->d_bs;
+    b.blk = q->d_lossblk;
+    b.status = q->d_status;
+    b.G = q->d_G;
+    b.flux = q->d_flux;
+    b.o_src = o.sources;
+    b.o_flat = o.flat;
+    b.o_k = o.intrapixel;
+    b.o_img = o.images;
+    const int cls = bin_class(q->Q);
+    for (int x = 0; x < b.nb; ++x) t_bl[cls].push_back(GroupBlock{k, x, 0, 0});
+
+    GradArgs& r = grad[k];
+    r.gpart = q->d_gpart;
+    r.G = q->b4_groups_max * q->b4_ksplit;
+    r.npix = npix;
+    r.gopd = q->d_gopd;
+    r.Nz = q->Nz;
+    r.nchunks = q->Nz > 0 ? zproj_chunks(npix, q->Nz) : 1;
+    r.zchunk = ((npix + r.nchunks - 1) / r.nchunks + 1023) / 1024 * 1024;
+    r.zpart = q->d_zpart;
+    r.flux = q->d_flux;
+    r.flux_blocks = b.nb;
+    r.tiles_b4 = q->tiles_b4 * q->b4_ksplit;
+    r.L = q->L;
+    r.FS = q->F * q->S;
+    r.nloss = b.nb;
+    r.pos = q->d_pos;
+    r.lossblk = q->d_lossblk;
+    r.o_z = o.zernike_basis;
+    r.o_c = o.zernike_coeffs;
+    r.o_src = o.sources;
+    r.o_loss = o.loss;
+    for (int x = 0; x < (int)((npix + 255) / 256); ++x) t_gopd.push_back(GroupBlock{k, x, 0, 0});
+    if (q->Nz > 0)
+      for (int y = 0; y < r.nchunks; ++y)
+        for (int x = 0; x < (q->Nz + 7) / 8; ++x) t_z.push_back(GroupBlock{k, x, y, 0});
+    for (int x = 0; x < q->Nz + r.FS + 1; ++x) t_fin.push_back(GroupBlock{k, x, 0, 0});
+  }
+  // one device buffer for all of it
+  auto bytes = [](size_t n, size_t sz) { return (n * sz + 255) & ~size_t(255); };
+  size_t total = bytes(n, sizeof(PrepArgs)) + bytes(n, sizeof(PupilArgs)) + bytes(n, sizeof(BinLossArgs)) +
+                 bytes(n, sizeof(GradArgs)) + bytes(t_prep.size(), sizeof(GroupBlock)) +
+                 bytes(t_pupil.size(), sizeof(GroupBlock)) + bytes(t_gopd.size(), sizeof(GroupBlock)) +
+                 bytes(t_z.size(), sizeof(GroupBlock)) + bytes(t_fin.size(), sizeof(GroupBlock));
+  for (int c = 0; c < 4; ++c) total += bytes(t_bl[c].size(), sizeof(GroupBlock));
+  char* base = nullptr;
+  hipError_t e = hipMalloc(reinterpret_cast<void**>(&base), total);
+  if (e != hipSuccess) return e;
+  g.dmem_small = base;
+  size_t off = 0;
+  auto put = [&](const void* src, size_t nbytes) -> char* {
+    char* d = base + off;
+    off += (nbytes + 255) & ~size_t(255);
+    if (nbytes && e == hipSuccess) e = hipMemcpy(d, src, nbytes, hipMemcpyHostToDevice);
+    return d;
+  };
+  g.d_prep = reinterpret_cast<PrepArgs*>(put(prep.data(), n * sizeof(PrepArgs)));
+  g.d_pupil = reinterpret_cast<PupilArgs*>(put(pupil.data(), n * sizeof(PupilArgs)));
+  g.d_bl = reinterpret_cast<BinLossArgs*>(put(bl.data(), n * sizeof(BinLossArgs)));
+  g.d_grad = reinterpret_cast<GradArgs*>(put(grad.data(), n * sizeof(GradArgs)));
+  g.d_prep_tab = reinterpret_cast<GroupBlock*>(put(t_prep.data(), t_prep.size() * sizeof(GroupBlock)));
+  g.d_pupil_tab = reinterpret_cast<GroupBlock*>(put(t_pupil.data(), t_pupil.size() * sizeof(GroupBlock)));
+  g.d_gopd_tab = reinterpret_cast<GroupBlock*>(put(t_gopd.data(), t_gopd.size() * sizeof(GroupBlock)));
+  g.d_z_tab = reinterpret_cast<GroupBlock*>(put(t_z.data(), t_z.size() * sizeof(GroupBlock)));
+  g.d_fin_tab = reinterpret_cast<GroupBlock*>(put(t_fin.data(), t_fin.size() * sizeof(GroupBlock)));
+  for (int c = 0; c < 4; ++c) {
+    g.d_bl_tab[c] = reinterpret_cast<GroupBlock*>(put(t_bl[c].data(), t_bl[c].size() * sizeof(GroupBlock)));
+    g.n_bl[c] = (int)t_bl[c].size();
+  }
+  g.n_prep = (int)t_prep.size();
+  g.n_pupil = (int)t_pupil.size();
+  g.n_gopd = (int)t_gopd.size();
+  g.n_z = (int)t_z.size();
+  g.n_fin = (int)t_fin.size();
+  return e;
+}
+
+void group_free(GroupPlan* g) {
+  if (!g) return;
+  if (g->dmem) (void)hipFree(g->dmem);
+  if (g->dmem_small) (void)hipFree(g->dmem_small);
+  delete g;
+}
+
+// Build the grouped launches of a multi-problem plan whose sub-plans exist (created without
+// tuning): device buffers for the GEMM arguments and tables (sized for the smallest tile and the
+// largest B4 split), then the tiles (tuned unless `tune` is false), then the small stages.
+dlx_status group_build(dlx_plan* p, bool tune) {
+  for (const dlx_plan* q : p->subs)
+    if (q->n_chunks != 1 || q->F != 1 || q->seed_pass || !q->fold || q->Nmap != 0 || q->dither) return DLX_OK;
+  GroupPlan* g = new (std::nothrow) GroupPlan();
+  if (!g) return DLX_ERR_OOM;
+  p->group = g;
+  const int n = (int)p->subs.size();
+  const dlx_plan* q0 = p->subs[0];
+  for (int s = 0; s < 4; ++s) g->ts[s] = s == 0 ? q0->ts_f1 : s == 1 ? q0->ts_f2 : s == 2 ? q0->ts_b3 : q0->ts_b4;
+  g->b4_ks = 1;
+  for (const dlx_plan* q : p->subs) g->b4_groups_cap.push_back(q->b4_groups_max);
+  long long total_src = 0;
+  for (int k = 0; k < n; ++k) {
+    dlx_plan* q = p->subs[k];
+    total_src = std::max<long long>(total_src, p->offs[k].sources + 3LL * q->F * q->S);
+    const int fm = q->hNo(), fi = q->hNi();
+    const int items = q->chunk_psf;
+    g->cap_wg[0] += ceil_div(fm, 32) * ceil_div(q->Ni, 32) * items;
+    g->cap_wg[1] += ceil_div(q->No, 32) * ceil_div(fm, 32) * items;
+    g->cap_wg[2] += ceil_div(fi, 32) * ceil_div(q->No, 32) * items;
+    g->cap_wg[3] += ceil_div(fi, 32) * ceil_div(q->Ni, 32) * q->b4_groups_max * 4;
+  }
+  size_t total = 0;
+  auto bytes = [](size_t c, size_t sz) { return (c * sz + 255) & ~size_t(255); };
+  for (int s = 0; s < 4; ++s) total += bytes(n, sizeof(GemmArgs)) + bytes(g->cap_wg[s], sizeof(int2));
+  total += bytes(total_src, sizeof(float));
+  if (hipMalloc(&g->dmem, total) != hipSuccess) {
+    group_free(g);
+    p->group = nullptr;
+    return DLX_ERR_OOM;
+  }
+  char* c = static_cast<char*>(g->dmem);
+  for (int s = 0; s < 4; ++s) {
+    g->d_gargs[s] = reinterpret_cast<GemmArgs*>(c);
+    c += bytes(n, sizeof(GemmArgs));
+    g->d_gtab[s] = reinterpret_cast<int2*>(c);
+    c += bytes(g->cap_wg[s], sizeof(int2));
+  }
+  g->d_tune_src = reinterpret_cast<float*>(c);
+  hipError_t e = hipMemset(g->d_tune_src, 0, sizeof(float) * total_src);
+  for (int s = 0; s < 4 && e == hipSuccess; ++s) e = group_stage_upload(p, s);
+  if (e == hipSuccess && tune) e = group_autotune(p);
+  if (e == hipSuccess) e = group_small_upload(p);
+  if (e == hipSuccess) e = hipDeviceSynchronize();
+  if (e != hipSuccess) {
+    group_free(g);
+    p->group = nullptr;
+    return DLX_ERR_HIP;
+  }
+  return DLX_OK;
+}
+
+// dlx_eval over every problem, one launch per stage.
+dlx_status group_eval(dlx_plan* p, const dlx_eval_args* a, hipStream_t st) {
+  const GroupPlan& g = *p->group;
+  GroupCall call;
+  call.transmission = a->transmission;
+  call.zbasis = a->zernike_basis;
+  call.coeffs = a->zernike_coeffs;
+  call.sources = a->sources;
+  call.flat = a->flat;
+  call.intrapixel = a->intrapixel;
+  call.data = a->data;
+  call.binned = a->binned;
+  call.model = a->model;
+  call.r = a->dloss_dmodel;
+  call.loss = a->loss;
+  call.grad_flat = a->grad_flat;
+  call.grad_zernike = a->grad_zernike;
+  call.grad_sources = a->grad_sources;
+  call.kind = (int)a->loss_kind;
+  call.mu = a->prior_mu;
+  call.inv_s2 = 1.0 / (a->prior_sigma * a->prior_sigma);
+  for (dlx_plan* q : p->subs) q->fields_valid = false;
+  {
+    Stage sg(p, st, DLX_STAGE_PREP, p->n_psf);
+    DLX_HIP(launch_prep_group(g.d_prep, g.d_prep_tab, g.n_prep, call, st));
+    DLX_HIP(launch_pupil_group(g.d_pupil, g.d_pupil_tab, g.n_pupil, call, st));
+  }
+  {
+    Stage sg(p, st, DLX_STAGE_F1, p->n_psf);
+    DLX_HIP(group_gemm(p, 0, nullptr, st));
+  }
+  {
+    Stage sg(p, st, DLX_STAGE_F2, p->n_psf);
+    DLX_HIP(group_gemm(p, 1, nullptr, st));
+  }
+  {
+    Stage sg(p, st, DLX_STAGE_BIN, p->n_psf);
+    for (int c = 0; c < 4; ++c) DLX_HIP(launch_bin_loss_group(g.qt_of[c], g.d_bl, g.d_bl_tab[c], g.n_bl[c], call, st));
+  }
+  {
+    Stage sg(p, st, DLX_STAGE_B3, p->n_psf);
+    DLX_HIP(group_gemm(p, 2, a->sources, st));
+  }
+  {
+    Stage sg(p, st, DLX_STAGE_B4, p->n_psf);
+    DLX_HIP(group_gemm(p, 3, nullptr, st));
+  }
+  Stage sg(p, st, DLX_STAGE_GRAD, p->n_psf);
+  DLX_HIP(launch_grad_group(g.d_grad, g.d_gopd_tab, g.n_gopd, g.d_z_tab, g.n_z, g.d_fin_tab, g.n_fin, call, st));
+  return DLX_OK;
+}
+
 constexpr int kSideStreams = 4;
 
 // One plan per problem; problem k's arrays sit at offs[k] in every packed array.
@@ -565,10 +1032,15 @@ dlx_status create_multi(const dlx_problem_desc* probs, int32_t n, dlx_precision 
   dlx_plan* p = new (std::nothrow) dlx_plan();
   if (!p) return DLX_ERR_OOM;
   p->prec = prec;
+  p->n_psf = 0;
+  // grouped launches tune the shared tiles over all problems at once: the sub-plans skip their own
+  const bool grouped = group_eligible(probs, n, flags);
+  const bool tune = !(flags & DLX_FLAG_NO_AUTOTUNE);
   dlx_offsets o{};
   for (int k = 0; k < n; ++k) {
     dlx_plan* sub = nullptr;
-    const dlx_status s = dlx_plan_create(&probs[k], 1, prec, flags, limit, &sub);
+    const dlx_status s = dlx_plan_create(&probs[k], 1, prec, grouped ? (flags | DLX_FLAG_NO_AUTOTUNE) : flags, limit,
+                                         &sub);
     if (s != DLX_OK) {
       dlx_plan_destroy(p);
       return s;
@@ -576,6 +1048,7 @@ dlx_status create_multi(const dlx_problem_desc* probs, int32_t n, dlx_precision 
     p->subs.push_back(sub);
     p->offs.push_back(o);
     p->pool_bytes += sub->pool_bytes;
+    p->n_psf += sub->n_psf;
     const dlx_problem_desc& d = probs[k];
     const long long ni2 = (long long)d.n_pupil * d.n_pupil, nd = d.n_focal / d.oversample;
     o.transmission += ni2;
@@ -615,6 +1088,22 @@ dlx_status create_multi(const dlx_problem_desc* probs, int32_t n, dlx_precision 
   if (!ok) {
     dlx_plan_destroy(p);
     return DLX_ERR_HIP;
+  }
+  if (grouped) {
+    dlx_status s = group_build(p, tune);
+    if (s == DLX_OK && !p->group && tune) {   // a problem needs more than one chunk: tune each on its own
+      for (dlx_plan* q : p->subs) {
+        if (autotune_cached(q) != hipSuccess || hipMemset(q->d_status, 0, sizeof(int)) != hipSuccess) {
+          s = DLX_ERR_HIP;
+          break;
+        }
+      }
+      if (s == DLX_OK && hipDeviceSynchronize() != hipSuccess) s = DLX_ERR_HIP;
+    }
+    if (s != DLX_OK) {
+      dlx_plan_destroy(p);
+      return s;
+    }
   }
   *out = p;
   return DLX_OK;
@@ -656,7 +1145,7 @@ dlx_status dlx_plan_create(const dlx_problem_desc* probs, int32_t n_probs, dlx_p
   if (v != DLX_OK) return v;
   if (precision != DLX_FP32 && precision != DLX_BF16X3) return DLX_ERR_INVALID_ARG;
   if ((flags & ~(DLX_FLAG_NO_AUTOTUNE | DLX_FLAG_SEED_PASS | DLX_FLAG_STORE_FIELDS | DLX_FLAG_PIXEL_KERNEL |
-                 DLX_FLAG_DENSE_MFT)) != 0)
+                 DLX_FLAG_DENSE_MFT | DLX_FLAG_GROUPED)) != 0)
     return DLX_ERR_INVALID_ARG;
   if (n_probs > 1) return create_multi(probs, n_probs, precision, flags, workspace_limit_bytes, out);
   const dlx_problem_desc& d = probs[0];
@@ -809,6 +1298,10 @@ dlx_status dlx_plan_destroy(dlx_plan* p) {
   if (!p) return DLX_OK;
   if (p->multi() || !p->side.empty()) {
     dlx_status s = DLX_OK;
+    if (hipDeviceSynchronize() != hipSuccess) s = DLX_ERR_HIP;
+    group_free(p->group);
+    p->group = nullptr;
+    for (hipEvent_t ev : p->ev_pool) (void)hipEventDestroy(ev);
     for (dlx_plan* sub : p->subs)
       if (dlx_plan_destroy(sub) != DLX_OK) s = DLX_ERR_HIP;
     for (hipStream_t st : p->side)
@@ -866,7 +1359,7 @@ dlx_status dlx_plan_profile(dlx_plan* p, int32_t enable) {
       const dlx_status s = dlx_plan_profile(sub, enable);
       if (s != DLX_OK) return s;
     }
-    return DLX_OK;
+    if (!p->group) return DLX_OK;   // grouped launches record their stages on the plan itself
   }
   if (enable && p->ev_pool.empty()) {
     p->ev_pool.resize(kEventPool);
@@ -901,6 +1394,17 @@ dlx_status dlx_plan_stage_times(dlx_plan* p, double* total_ms, int64_t* launches
         total_ms[i] += ms[i];
         launches[i] += la[i];
         psfs[i] += ps[i];
+      }
+    }
+    if (p->group) {   // the grouped launches' own stages
+      DLX_HIP(flush_records(p));
+      for (int i = 0; i < DLX_N_STAGES; ++i) {
+        total_ms[i] += p->stage_ms[i];
+        launches[i] += p->stage_launches[i];
+        psfs[i] += p->stage_psfs[i];
+        p->stage_ms[i] = 0.0;
+        p->stage_launches[i] = 0;
+        p->stage_psfs[i] = 0;
       }
     }
     return DLX_OK;
@@ -1104,6 +1608,15 @@ dlx_status dlx_eval(dlx_plan* p, const dlx_eval_args* a, void* stream) {
     if (!a->transmission || !a->sources || !a->flat || !a->data || !a->binned || !a->model || !a->dloss_dmodel ||
         !a->loss || !a->grad_flat || !a->grad_sources)
       return DLX_ERR_INVALID_ARG;
+    if (a->loss_kind != DLX_LOSS_POISSON && a->loss_kind != DLX_LOSS_CHI2) return DLX_ERR_INVALID_ARG;
+    if (!(a->prior_sigma > 0.0) || !std::isfinite(a->prior_sigma) || !std::isfinite(a->prior_mu))
+      return DLX_ERR_INVALID_ARG;
+    if (p->group && !a->grad_intrapixel) {
+      bool zok = true;   // every problem with Zernike terms needs the basis, coefficients and gradient
+      for (const dlx_plan* q : p->subs) zok = zok && (q->Nz == 0 || (a->zernike_basis && a->zernike_coeffs && a->grad_zernike));
+      if (!zok) return DLX_ERR_INVALID_ARG;
+      return group_eval(p, a, reinterpret_cast<hipStream_t>(stream));
+    }
     return run_multi(p, reinterpret_cast<hipStream_t>(stream), [&](int k, dlx_plan* q, hipStream_t s) {
       const dlx_offsets& o = p->offs[k];
       dlx_eval_args b = *a;

@@ -103,6 +103,9 @@ struct GemmArgs {
   int mirror_n;
   int kodd;
   int out_h, out_s;
+  // grouped launches of a multi-problem plan: offset of the problem's star table in the call's
+  // packed sources (the launch passes the base; `sources` above is unused there)
+  long long src_off;
 };
 
 // Tile shape of one GEMM launch: 4 waves (2 x 2), each WM x WN blocks of 16 x 16.
@@ -115,12 +118,106 @@ struct TileShape {
 // Tile shapes compiled for every stage and precision (the autotuner's candidates).
 constexpr TileShape kTileShapes[] = {{4, 4}, {3, 3}, {2, 2}, {4, 2}, {2, 4}, {2, 1}, {1, 2}, {1, 1}, {4, 1}, {1, 4}};
 
+// ---- grouped launches of a multi-problem plan: one launch per stage over every problem
+// Entry of a grouped launch's block table: the problem and the block's coordinates in the
+// problem's own grid.
+struct GroupBlock {
+  int k, x, y, z;
+};
+
+// Base pointers of one call's packed caller arrays (problem k's arrays start at its element
+// offsets, dlx_offsets), and the loss's scalars.
+struct GroupCall {
+  const float* transmission;
+  const float* zbasis;
+  const float* coeffs;
+  const float* sources;
+  const float* flat;
+  const float* intrapixel;
+  const float* data;
+  float* binned;
+  float* model;
+  float* r;
+  double* loss;
+  double* grad_flat;
+  double* grad_zernike;
+  double* grad_sources;
+  int kind;
+  double mu, inv_s2;
+};
+
+// Per-problem arguments of the grouped small kernels (plan-owned pointers, sizes, and the
+// offsets of the problem's arrays in the call's packed arrays).
+struct PrepArgs {   // OPD, A^2 partial sums, tilt vectors (prep_kernel)
+  int Nz, Ni, nb_opd, n_norm, L, ldt;
+  long long npix, n_tilt, tplane;
+  double* opd;
+  double* norm_part;
+  const WlInfo* wl;
+  const double* x;
+  float* tx;
+  float* ty;
+  long long o_trans, o_z, o_c, o_src;
+};
+struct PupilArgs {   // per-wavelength pupil fields (pupil_kernel)
+  const double* opd;
+  const float* screen;
+  const double* norm_part;
+  int n_norm, Ni, ldp, h;
+  const WlInfo* wl;
+  float* P0T;
+  long long plane, by_wl, o_trans;
+};
+struct BinLossArgs {   // binning, model, loss, residual, seed weights of a one-frame problem (bin_loss_kernel)
+  const float* E;
+  long long plane, by_psf;
+  int ld, S, L, Q, Nd, fh, fs, ldg, nb;
+  const WlInfo* wl;
+  long long kst, g_by_frame;
+  float* bs;
+  double* blk;
+  int* status;
+  float* G;
+  double* flux;
+  long long o_src, o_flat, o_k, o_img;
+};
+struct GradArgs {   // dL/dOPD, its Zernike projection and the final sums (gopd, zproj, finalize)
+  const float* gpart;
+  int G;
+  long long npix;
+  double* gopd;
+  int Nz, nchunks;
+  long long zchunk;
+  double* zpart;
+  const double* flux;
+  int flux_blocks, tiles_b4, L, FS, nloss;
+  const double* pos;
+  const double* lossblk;
+  long long o_z, o_c, o_src, o_loss;
+};
+
+hipError_t launch_prep_group(const PrepArgs* args, const GroupBlock* tab, int n_blocks, const GroupCall& call,
+                             hipStream_t st);
+hipError_t launch_pupil_group(const PupilArgs* args, const GroupBlock* tab, int n_blocks, const GroupCall& call,
+                              hipStream_t st);
+// qt: the compiled oversampling of the bin_loss_kernel instance (1, 2, 4, or 0 = any)
+hipError_t launch_bin_loss_group(int qt, const BinLossArgs* args, const GroupBlock* tab, int n_blocks,
+                                 const GroupCall& call, hipStream_t st);
+hipError_t launch_grad_group(const GradArgs* args, const GroupBlock* gopd_tab, int n_gopd, const GroupBlock* z_tab,
+                             int n_z, const GroupBlock* fin_tab, int n_fin, const GroupCall& call, hipStream_t st);
+
 int loss_block_count(long long npix);
 hipError_t launch_loss_plain(int nf, long long npix, const float* model, const float* binned, const float* data,
                              const float* flat, int kind, double mu, double sigma, float* r, double* gflat,
                              double* blk, int* status, double* loss, hipStream_t st);
 hipError_t launch_gemm(int kind, int prec, TileShape ts, const GemmArgs& a, int n_wg, hipStream_t st);
+// One folded stage over many problems: n_wg workgroups, tab[g] = (problem, its logical workgroup),
+// args = per-problem arguments in device memory, sources = the call's packed star table.
+hipError_t launch_gemm_group(int kind, int prec, TileShape ts, const GemmArgs* args, const int2* tab, int n_wg,
+                             const float* sources, hipStream_t st);
 bool tile_supported(int kind, int prec, bool fold, TileShape ts);
+
+struct GroupPlan;
 
 }  // namespace dlx
 
@@ -133,6 +230,8 @@ struct dlx_plan {
   hipEvent_t fork = nullptr;
   std::vector<hipEvent_t> joins;
   bool multi() const { return !subs.empty(); }
+  // grouped launches (one per stage over every problem) when every problem qualifies; null otherwise
+  dlx::GroupPlan* group = nullptr;
   // problem. In integer-dither mode the MFT stages see one frame of an enlarged
   // detector (F = 1, Nd = N_det + 2 margin, No = Q Nd) and the images are
   // F_img windows of N_det_img pixels; otherwise F_img = F and Nd_img = Nd.

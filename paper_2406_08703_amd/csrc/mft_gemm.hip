@@ -570,8 +570,10 @@ __device__ __forceinline__ f4 rev4(f4 v) { return f4{v[3], v[2], v[1], v[0]}; }
 // FP32: at least two workgroups per CU. The register bound keeps B4's 64 x 64 tile at two waves
 // per SIMD (its epilogue's registers would leave one); the larger FP32 shapes would spill under
 // it and are not compiled (fold_tile_ok).
+// The folded stage for the workgroup at logical index `lin` of its problem's own grid; `src` is the
+// problem's [F][S][3] star table (read by B3 for w phi).
 template <int KIND, int WM, int WN, int PREC>
-__global__ __launch_bounds__(256, PREC == 0 ? 2 : 1) void fgemm_kernel(const GemmArgs a) {
+__device__ __forceinline__ void fgemm_body(const GemmArgs& a, int lin, const float* src) {
   constexpr bool DA = KIND != KIND_F2;   // DFT operand on the A side (rows i), data on the B side
   constexpr int BM = 32 * WM, BN = 32 * WN;
   constexpr int BK = PREC == 0 ? 16 : 32;
@@ -592,7 +594,6 @@ __global__ __launch_bounds__(256, PREC == 0 ? 2 : 1) void fgemm_kernel(const Gem
 
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int wr = wave >> 1, wc = wave & 1;
-  const int lin = xcd_remap(blockIdx.x, gridDim.x);
   const int tiles = a.tiles_m * a.tiles_n;
   const int item = lin / tiles;
   if (item >= a.n_items) return;
@@ -649,7 +650,7 @@ __global__ __launch_bounds__(256, PREC == 0 ? 2 : 1) void fgemm_kernel(const Gem
     if constexpr (KIND == KIND_B3) {
       if (a.seedw) {
         const int fs = gb / a.L;
-        wphi = a.wl[wl].w * a.sources[fs * 3 + 2];
+        wphi = a.wl[wl].w * src[fs * 3 + 2];
         gwb = a.seedw + (long long)(fs / a.S - a.frame0) * a.seedw_by_frame;
       }
     }
@@ -1113,6 +1114,23 @@ __global__ __launch_bounds__(256, PREC == 0 ? 2 : 1) void fgemm_kernel(const Gem
   }
 }
 
+template <int KIND, int WM, int WN, int PREC>
+__global__ __launch_bounds__(256, PREC == 0 ? 2 : 1) void fgemm_kernel(const GemmArgs a) {
+  fgemm_body<KIND, WM, WN, PREC>(a, xcd_remap(blockIdx.x, gridDim.x), a.sources);
+}
+
+// One launch of a folded stage over the problems of a multi-problem plan: workgroup g (in XCD order)
+// runs logical workgroup tab[g].y of problem tab[g].x, whose arguments are args[tab[g].x]; the
+// problem's star table is sources + args[k].src_off (sources: the call's packed table).
+template <int KIND, int WM, int WN, int PREC>
+__global__ __launch_bounds__(256, PREC == 0 ? 2 : 1) void fgemm_group_kernel(const GemmArgs* __restrict__ args,
+                                                                            const int2* __restrict__ tab,
+                                                                            const float* sources) {
+  const int2 e = tab[xcd_remap(blockIdx.x, gridDim.x)];
+  const GemmArgs& a = args[e.x];
+  fgemm_body<KIND, WM, WN, PREC>(a, e.y, sources ? sources + a.src_off : nullptr);
+}
+
 // Folded tile shapes compiled: those that keep their accumulators in registers. FP32 (two
 // workgroups per CU): up to four 32 x 32 blocks, except B4's 128 x 32 and 32 x 128. BF16X3: all
 // but 128 x 128 (and B4's 96 x 96).
@@ -1165,7 +1183,52 @@ hipError_t launch_prec(int kind, TileShape ts, const GemmArgs& a, int n_wg, hipS
   }
 }
 
+template <int KIND, int PREC>
+hipError_t launch_group_kind(TileShape ts, const GemmArgs* args, const int2* tab, int n_wg, const float* sources,
+                             hipStream_t st) {
+  const dim3 grid(n_wg), block(256);
+#define DLX_TILE(WM_, WN_)                                                                                   \
+  if (ts.wm == WM_ && ts.wn == WN_) {                                                                        \
+    if constexpr (fold_tile_ok(KIND, PREC, WM_, WN_)) {                                                      \
+      hipLaunchKernelGGL((fgemm_group_kernel<KIND, WM_, WN_, PREC>), grid, block, 0, st, args, tab, sources); \
+      return hipGetLastError();                                                                              \
+    }                                                                                                        \
+    return hipErrorInvalidValue;                                                                             \
+  }
+  DLX_TILE(4, 4)
+  DLX_TILE(3, 3)
+  DLX_TILE(2, 2)
+  DLX_TILE(4, 2)
+  DLX_TILE(2, 4)
+  DLX_TILE(2, 1)
+  DLX_TILE(1, 2)
+  DLX_TILE(1, 1)
+  DLX_TILE(4, 1)
+  DLX_TILE(1, 4)
+#undef DLX_TILE
+  return hipErrorInvalidValue;
+}
+
+template <int PREC>
+hipError_t launch_group_prec(int kind, TileShape ts, const GemmArgs* args, const int2* tab, int n_wg,
+                             const float* sources, hipStream_t st) {
+  switch (kind) {
+    case KIND_F1: return launch_group_kind<KIND_F1, PREC>(ts, args, tab, n_wg, sources, st);
+    case KIND_F2: return launch_group_kind<KIND_F2, PREC>(ts, args, tab, n_wg, sources, st);
+    case KIND_B3: return launch_group_kind<KIND_B3, PREC>(ts, args, tab, n_wg, sources, st);
+    case KIND_B4: return launch_group_kind<KIND_B4, PREC>(ts, args, tab, n_wg, sources, st);
+    default: return hipErrorInvalidValue;
+  }
+}
+
 }  // namespace
+
+hipError_t launch_gemm_group(int kind, int prec, TileShape ts, const GemmArgs* args, const int2* tab, int n_wg,
+                             const float* sources, hipStream_t st) {
+  if (n_wg <= 0) return hipSuccess;
+  return prec == 0 ? launch_group_prec<0>(kind, ts, args, tab, n_wg, sources, st)
+                   : launch_group_prec<1>(kind, ts, args, tab, n_wg, sources, st);
+}
 
 bool tile_supported(int kind, int prec, bool fold, TileShape ts) {
   for (const TileShape& t : kTileShapes)

@@ -85,14 +85,14 @@ __global__ void map_tmp_kernel(const float* C, const float* Bm, float* tmp, int 
 // P0T_l[n][m] = A[m][n] / sqrt(sum A^2) * exp(i 2 pi OPD[m][n] / lambda_l), one block per
 // (32 x 32 tile, wavelength), transposed through LDS. Row n stores column m at m for m < h and at
 // m + ldp - Ni for h <= m < Ni (the folded layout; h = Ni: natural), zeros elsewhere.
-__global__ void pupil_kernel(const float* A, const double* opd, const float* screen, const double* norm_part,
-                             int n_norm, const WlInfo* wl, int Ni, int ldp, int h, float* P0T, long long plane,
-                             long long by_wl) {
+__device__ __forceinline__ void pupil_body(int bx, int by, int l, const float* A, const double* opd,
+                                           const float* screen, const double* norm_part, int n_norm,
+                                           const WlInfo* wl, int Ni, int ldp, int h, float* P0T, long long plane,
+                                           long long by_wl) {
   __shared__ float tr[32][33], ti[32][33];
   __shared__ double sparts[256];   // n_norm <= 256
   const int tx = threadIdx.x, ty = threadIdx.y;  // 32 x 8
-  const int m0 = blockIdx.y * 32, n0 = blockIdx.x * 32;
-  const int l = blockIdx.z;
+  const int m0 = by * 32, n0 = bx * 32;
   // the partial sums of A^2 are read in parallel, next to the pixels' loads and phases
   for (int i = ty * 32 + tx; i < n_norm; i += 256) sparts[i] = norm_part[i];
   const double inv = 1.0 / wl[l].lam;
@@ -133,6 +133,22 @@ __global__ void pupil_kernel(const float* A, const double* opd, const float* scr
   }
 }
 
+__global__ __launch_bounds__(256) void pupil_kernel(const float* A, const double* opd, const float* screen,
+                                                    const double* norm_part, int n_norm, const WlInfo* wl, int Ni,
+                                                    int ldp, int h, float* P0T, long long plane, long long by_wl) {
+  pupil_body(blockIdx.x, blockIdx.y, blockIdx.z, A, opd, screen, norm_part, n_norm, wl, Ni, ldp, h, P0T, plane, by_wl);
+}
+
+// The pupil fields of every problem of a multi-problem plan in one launch (block table entries:
+// problem, tile column, tile row, wavelength).
+__global__ __launch_bounds__(256) void pupil_group_kernel(const PupilArgs* __restrict__ args,
+                                                          const GroupBlock* __restrict__ tab, const float* A) {
+  const GroupBlock e = tab[blockIdx.x];
+  const PupilArgs& a = args[e.k];
+  pupil_body(e.x, e.y, e.z, A + a.o_trans, a.opd, a.screen, a.norm_part, a.n_norm, a.wl, a.Ni, a.ldp, a.h, a.P0T,
+             a.plane, a.by_wl);
+}
+
 // Tilt vectors of all PSFs, psf = (f S + s) L + l: element t = psf * ldt + n.
 __device__ void tilt_at(long long t, const float* sources, const WlInfo* wl, const double* x, int L, int Ni, int ldt,
                         float* tx, float* ty, long long plane) {
@@ -169,11 +185,11 @@ __device__ void tilt_at(long long t, const float* sources, const WlInfo* wl, con
 //   [nb_opd, nb_opd + n_norm): partial sums of A^2 (grid-stride over the pixels),
 //                             one per block, added by the pupil kernel in order;
 //   the rest:                 the tilt vectors tx, ty of every PSF.
-__global__ void prep_kernel(const float* Z, const float* c, int Nz, long long npix, int Ni, const float* Bm,
-                            const float* tmp, int Nmap, double* opd, int nb_opd, const float* A, double* norm_part,
-                            int n_norm, const float* sources, const WlInfo* wl, const double* x, int L, int ldt,
-                            long long n_tilt, float* tx, float* ty, long long tplane) {
-  const int b = blockIdx.x;
+__device__ __forceinline__ void prep_body(int b, const float* Z, const float* c, int Nz, long long npix, int Ni,
+                                          const float* Bm, const float* tmp, int Nmap, double* opd, int nb_opd,
+                                          const float* A, double* norm_part, int n_norm, const float* sources,
+                                          const WlInfo* wl, const double* x, int L, int ldt, long long n_tilt,
+                                          float* tx, float* ty, long long tplane) {
   if (b < nb_opd) {
     const long long p = (long long)b * blockDim.x + threadIdx.x;
     if (p >= npix) return;
@@ -212,6 +228,26 @@ __global__ void prep_kernel(const float* Z, const float* c, int Nz, long long np
     const long long t = (long long)(b - nb_opd - n_norm) * blockDim.x + threadIdx.x;
     if (t < n_tilt) tilt_at(t, sources, wl, x, L, Ni, ldt, tx, ty, tplane);
   }
+}
+
+__global__ __launch_bounds__(256) void prep_kernel(const float* Z, const float* c, int Nz, long long npix, int Ni,
+                                                   const float* Bm, const float* tmp, int Nmap, double* opd,
+                                                   int nb_opd, const float* A, double* norm_part, int n_norm,
+                                                   const float* sources, const WlInfo* wl, const double* x, int L,
+                                                   int ldt, long long n_tilt, float* tx, float* ty, long long tplane) {
+  prep_body(blockIdx.x, Z, c, Nz, npix, Ni, Bm, tmp, Nmap, opd, nb_opd, A, norm_part, n_norm, sources, wl, x, L, ldt,
+            n_tilt, tx, ty, tplane);
+}
+
+// prep_kernel's three jobs for every problem of a multi-problem plan in one launch (block table
+// entries: problem, block of that problem's prep grid); no bicubic map.
+__global__ __launch_bounds__(256) void prep_group_kernel(const PrepArgs* __restrict__ args,
+                                                         const GroupBlock* __restrict__ tab, GroupCall call) {
+  const GroupBlock e = tab[blockIdx.x];
+  const PrepArgs& a = args[e.k];
+  prep_body(e.x, a.Nz ? call.zbasis + a.o_z : nullptr, a.Nz ? call.coeffs + a.o_c : nullptr, a.Nz, a.npix, a.Ni,
+            nullptr, nullptr, 0, a.opd, a.nb_opd, call.transmission + a.o_trans, a.norm_part, a.n_norm,
+            call.sources + a.o_src, a.wl, a.x, a.L, a.ldt, a.n_tilt, a.tx, a.ty, a.tplane);
 }
 
 }  // namespace
@@ -264,6 +300,20 @@ hipError_t launch_prep(dlx_plan* p, const float* A, const float* Z, const float*
   hipLaunchKernelGGL(pupil_kernel, dim3((p->Ni + 31) / 32, (p->ldNi + 31) / 32, p->L), dim3(32, 8), 0, st, A,
                      p->d_opd, p->d_screen, p->d_norm, p->n_norm_part, p->d_wl, p->Ni, p->ldNi,
                      p->fold ? p->hNi() : p->Ni, p->d_P0T, (long long)p->Ni * p->ldNi, p0_by_wl);
+  return hipGetLastError();
+}
+
+hipError_t launch_prep_group(const PrepArgs* args, const GroupBlock* tab, int n_blocks, const GroupCall& call,
+                             hipStream_t st) {
+  if (n_blocks <= 0) return hipSuccess;
+  hipLaunchKernelGGL(prep_group_kernel, dim3(n_blocks), dim3(256), 0, st, args, tab, call);
+  return hipGetLastError();
+}
+
+hipError_t launch_pupil_group(const PupilArgs* args, const GroupBlock* tab, int n_blocks, const GroupCall& call,
+                              hipStream_t st) {
+  if (n_blocks <= 0) return hipSuccess;
+  hipLaunchKernelGGL(pupil_group_kernel, dim3(n_blocks), dim3(32, 8), 0, st, args, tab, call.transmission);
   return hipGetLastError();
 }
 

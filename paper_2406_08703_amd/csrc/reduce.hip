@@ -292,17 +292,19 @@ __device__ __forceinline__ double block_sum(double v, double* sh) {
 // sum of flat r bs at flux[(f S + s) gridDim.x + block]. The flat-field gradient sums over the
 // frames in a register; the loss partial of the block goes to blk[block].
 template <int QT>
-__global__ void bin_loss_kernel(const float* E, long long plane, long long by_psf, int ld, int f0, int nf, int S, int L,
-                                int Qr, int Nd, const float* sources, const WlInfo* wl, const float* intrapixel,
-                                long long kst, int fh, int fs, const float* flat, const float* data, int kind,
-                                double mu, double inv_s2, float* bs, float* binned, float* model, float* r_out,
-                                double* grad_flat, int accumulate, double* blk, int* status, float* G, int ldg,
-                                long long g_by_frame, double* flux) {
+__device__ __forceinline__ void bin_loss_body(int bx, int nbx, const float* E, long long plane, long long by_psf,
+                                              int ld, int f0, int nf, int S, int L, int Qr, int Nd,
+                                              const float* sources, const WlInfo* wl, const float* intrapixel,
+                                              long long kst, int fh, int fs, const float* flat, const float* data,
+                                              int kind, double mu, double inv_s2, float* bs, float* binned,
+                                              float* model, float* r_out, double* grad_flat, int accumulate,
+                                              double* blk, int* status, float* G, int ldg, long long g_by_frame,
+                                              double* flux) {
   __shared__ double sh[kLanes][64];
   const int Q = QT > 0 ? QT : Qr;
   const long long npix = (long long)Nd * Nd;
   const int x = threadIdx.x, y = threadIdx.y;
-  const long long p = (long long)blockIdx.x * 64 + x;
+  const long long p = (long long)bx * 64 + x;
   const bool live = p < npix;
   const int pr = live ? (int)(p / Nd) : 0, pc = live ? (int)(p - (long long)pr * Nd) : 0;
   const float* kp = intrapixel ? intrapixel + (live ? p : 0) * kst : nullptr;
@@ -377,7 +379,7 @@ __global__ void bin_loss_kernel(const float* E, long long plane, long long by_ps
         double v = live ? (double)h * (double)bs[((long long)fl * S + s) * npix + p] : 0.0;
 #pragma unroll
         for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
-        if (x == 0) flux[((long long)f * S + s) * gridDim.x + blockIdx.x] = v;
+        if (x == 0) flux[((long long)f * S + s) * nbx + bx] = v;
       }
     }
   }
@@ -394,8 +396,34 @@ __global__ void bin_loss_kernel(const float* E, long long plane, long long by_ps
     if (flags) atomicOr(status, flags);  // bit 0: non-finite, bit 1: domain
 #pragma unroll
     for (int o = 32; o > 0; o >>= 1) lsum += __shfl_xor(lsum, o, 64);
-    if (x == 0) blk[blockIdx.x] = lsum;
+    if (x == 0) blk[bx] = lsum;
   }
+}
+
+template <int QT>
+__global__ void bin_loss_kernel(const float* E, long long plane, long long by_psf, int ld, int f0, int nf, int S, int L,
+                                int Qr, int Nd, const float* sources, const WlInfo* wl, const float* intrapixel,
+                                long long kst, int fh, int fs, const float* flat, const float* data, int kind,
+                                double mu, double inv_s2, float* bs, float* binned, float* model, float* r_out,
+                                double* grad_flat, int accumulate, double* blk, int* status, float* G, int ldg,
+                                long long g_by_frame, double* flux) {
+  bin_loss_body<QT>(blockIdx.x, gridDim.x, E, plane, by_psf, ld, f0, nf, S, L, Qr, Nd, sources, wl, intrapixel, kst,
+                    fh, fs, flat, data, kind, mu, inv_s2, bs, binned, model, r_out, grad_flat, accumulate, blk, status,
+                    G, ldg, g_by_frame, flux);
+}
+
+// bin_loss_kernel over the one-frame problems of a multi-problem plan in one launch (block table
+// entries: problem, pixel block); each problem's arrays at its offsets in the call's packed arrays.
+template <int QT>
+__global__ void bin_loss_group_kernel(const BinLossArgs* __restrict__ args, const GroupBlock* __restrict__ tab,
+                                      GroupCall call) {
+  const GroupBlock e = tab[blockIdx.x];
+  const BinLossArgs& a = args[e.k];
+  const long long im = a.o_img;
+  bin_loss_body<QT>(e.x, a.nb, a.E, a.plane, a.by_psf, a.ld, 0, 1, a.S, a.L, a.Q, a.Nd, call.sources + a.o_src, a.wl,
+                    call.intrapixel ? call.intrapixel + a.o_k : nullptr, a.kst, a.fh, a.fs, call.flat + a.o_flat,
+                    call.data + im, call.kind, call.mu, call.inv_s2, a.bs, call.binned + im, call.model + im,
+                    call.r + im, call.grad_flat + a.o_flat, 0, a.blk, a.status, a.G, a.ldg, a.g_by_frame, a.flux);
 }
 
 // Outputs of the adjoint seed, when the loss kernel also forms it (fused
@@ -624,7 +652,7 @@ __global__ void seed_gather_kernel(const float* resid, const float* flat, const 
 // With one kernel per pixel (gpix non-null) the pixel sum is dropped: the block runs every frame
 // of the chunk (grid.y = 1) and writes gpix[p][a][b], or adds to it for a chunk after the first.
 template <int QT>
-__global__ void kgrad_kernel(const float* E, long long plane, long long by_psf, int ld, int f0, int S, int L,
+__global__ __launch_bounds__(kSeedThreads) void kgrad_kernel(const float* E, long long plane, long long by_psf, int ld, int f0, int S, int L,
                              int Nd, const float* sources, const WlInfo* wl, const float* flat, const float* resid,
                              const int* win, int F_img, int Nd_img, int fh, int fs, double* part, double* gpix,
                              int nf_pix, int accumulate) {
@@ -700,8 +728,8 @@ __global__ void kgrad_kernel(const float* E, long long plane, long long by_psf, 
 }
 
 // gopd[p] = sum_g gpart[g][p]
-__global__ void gopd_reduce_kernel(const float* gpart, int G, long long npix, double* gopd) {
-  const long long p = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+__device__ __forceinline__ void gopd_body(int bx, const float* gpart, int G, long long npix, double* gopd) {
+  const long long p = (long long)bx * blockDim.x + threadIdx.x;
   if (p >= npix) return;
   double acc = 0.0;
 #pragma unroll 8
@@ -709,15 +737,19 @@ __global__ void gopd_reduce_kernel(const float* gpart, int G, long long npix, do
   gopd[p] = acc;
 }
 
+__global__ void gopd_reduce_kernel(const float* gpart, int G, long long npix, double* gopd) {
+  gopd_body(blockIdx.x, gpart, G, npix, gopd);
+}
+
 // Zernike projection dL/dc_j = sum_p Z_j[p] gopd[p], in two deterministic passes:
 // block (term group of 8, pixel chunk) writes part[chunk][j]; zproj_final sums chunks.
 constexpr int kZGroup = 8;
 
-__global__ void zproj_partial_kernel(const float* Z, const double* gopd, int Nz, long long npix, long long chunk,
-                                     double* part) {
+__device__ __forceinline__ void zproj_body(int bx, int by, const float* Z, const double* gopd, int Nz, long long npix,
+                                           long long chunk, double* part) {
   __shared__ double sh[4][kZGroup];
-  const int j0 = blockIdx.x * kZGroup;
-  const long long p_begin = (long long)blockIdx.y * chunk;
+  const int j0 = bx * kZGroup;
+  const long long p_begin = (long long)by * chunk;
   const long long p_end = p_begin + chunk < npix ? p_begin + chunk : npix;
   double acc[kZGroup];
 #pragma unroll
@@ -750,8 +782,13 @@ __global__ void zproj_partial_kernel(const float* Z, const double* gopd, int Nz,
   __syncthreads();
   if (threadIdx.x < kZGroup && j0 + (int)threadIdx.x < Nz) {
     const int q = threadIdx.x;
-    part[(long long)blockIdx.y * Nz + j0 + q] = sh[0][q] + sh[1][q] + sh[2][q] + sh[3][q];
+    part[(long long)by * Nz + j0 + q] = sh[0][q] + sh[1][q] + sh[2][q] + sh[3][q];
   }
+}
+
+__global__ void zproj_partial_kernel(const float* Z, const double* gopd, int Nz, long long npix, long long chunk,
+                                     double* part) {
+  zproj_body(blockIdx.x, blockIdx.y, Z, gopd, Nz, npix, chunk, part);
 }
 
 // The bicubic-map gradient B^T gopd B in two products over the pupil index, each output a
@@ -816,12 +853,11 @@ __global__ __launch_bounds__(64 * kMapWaves) void map_grad2_kernel(const double*
 //                            wavelengths and tiles, flux partials over pixel blocks;
 //   block Nz + F S (if loss): L = sum of the loss block partials;
 //   the last Q^2 blocks (if gK): dL/dK[a][b] = sum of the intra-pixel partials.
-__global__ void finalize_kernel(const double* zpart, int Nz, int nchunks, double* gz, const double* flux,
-                                int seed_blocks, const double* pos, int tiles_b4, int L, int FS, double* gsrc,
-                                const double* lossblk, int nloss, double* loss, const double* kpart, int nkpart,
-                                int Q2, double* gK) {
+__device__ __forceinline__ void finalize_body(int b, const double* zpart, int Nz, int nchunks, double* gz,
+                                              const double* flux, int seed_blocks, const double* pos, int tiles_b4,
+                                              int L, int FS, double* gsrc, const double* lossblk, int nloss,
+                                              double* loss, const double* kpart, int nkpart, int Q2, double* gK) {
   __shared__ double sh[3][4];
-  const int b = blockIdx.x;
   const int w = threadIdx.x >> 6;
   double v0 = 0.0, v1 = 0.0, v2 = 0.0;
   if (b < Nz) {
@@ -866,6 +902,40 @@ __global__ void finalize_kernel(const double* zpart, int Nz, int nchunks, double
       gK[b - Nz - FS - (loss ? 1 : 0)] = t;
     }
   }
+}
+
+__global__ void finalize_kernel(const double* zpart, int Nz, int nchunks, double* gz, const double* flux,
+                                int seed_blocks, const double* pos, int tiles_b4, int L, int FS, double* gsrc,
+                                const double* lossblk, int nloss, double* loss, const double* kpart, int nkpart,
+                                int Q2, double* gK) {
+  finalize_body(blockIdx.x, zpart, Nz, nchunks, gz, flux, seed_blocks, pos, tiles_b4, L, FS, gsrc, lossblk, nloss,
+                loss, kpart, nkpart, Q2, gK);
+}
+
+// The last reductions of every problem of a multi-problem plan, each a grouped launch (block
+// table entries: problem and the block in that problem's own grid): gopd_reduce_kernel,
+// zproj_partial_kernel and finalize_kernel (with the loss, without dL/dK).
+__global__ __launch_bounds__(256) void gopd_group_kernel(const GradArgs* __restrict__ args,
+                                                         const GroupBlock* __restrict__ tab) {
+  const GroupBlock e = tab[blockIdx.x];
+  const GradArgs& a = args[e.k];
+  gopd_body(e.x, a.gpart, a.G, a.npix, a.gopd);
+}
+
+__global__ __launch_bounds__(256) void zproj_group_kernel(const GradArgs* __restrict__ args,
+                                                          const GroupBlock* __restrict__ tab, const float* Z) {
+  const GroupBlock e = tab[blockIdx.x];
+  const GradArgs& a = args[e.k];
+  zproj_body(e.x, e.y, Z + a.o_z, a.gopd, a.Nz, a.npix, a.zchunk, a.zpart);
+}
+
+__global__ __launch_bounds__(256) void finalize_group_kernel(const GradArgs* __restrict__ args,
+                                                             const GroupBlock* __restrict__ tab, GroupCall call) {
+  const GroupBlock e = tab[blockIdx.x];
+  const GradArgs& a = args[e.k];
+  finalize_body(e.x, a.zpart, a.Nz, a.nchunks, a.Nz ? call.grad_zernike + a.o_c : nullptr, a.flux, a.flux_blocks,
+                a.pos, a.tiles_b4, a.L, a.FS, call.grad_sources + a.o_src, a.lossblk, a.nloss, call.loss + a.o_loss,
+                nullptr, 0, 0, nullptr);
 }
 
 }  // namespace
@@ -1017,6 +1087,27 @@ hipError_t launch_bin_loss(dlx_plan* p, int f0, int nf, int chunk, const float* 
     default: DLX_BIN_LOSS(0); break;
   }
 #undef DLX_BIN_LOSS
+  return hipGetLastError();
+}
+
+hipError_t launch_bin_loss_group(int qt, const BinLossArgs* args, const GroupBlock* tab, int n_blocks,
+                                 const GroupCall& call, hipStream_t st) {
+  if (n_blocks <= 0) return hipSuccess;
+  const dim3 grid(n_blocks), blk(64, kLanes);
+  switch (qt) {
+    case 1: hipLaunchKernelGGL(bin_loss_group_kernel<1>, grid, blk, 0, st, args, tab, call); break;
+    case 2: hipLaunchKernelGGL(bin_loss_group_kernel<2>, grid, blk, 0, st, args, tab, call); break;
+    case 4: hipLaunchKernelGGL(bin_loss_group_kernel<4>, grid, blk, 0, st, args, tab, call); break;
+    default: hipLaunchKernelGGL(bin_loss_group_kernel<0>, grid, blk, 0, st, args, tab, call); break;
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_grad_group(const GradArgs* args, const GroupBlock* gopd_tab, int n_gopd, const GroupBlock* z_tab,
+                             int n_z, const GroupBlock* fin_tab, int n_fin, const GroupCall& call, hipStream_t st) {
+  if (n_gopd > 0) hipLaunchKernelGGL(gopd_group_kernel, dim3(n_gopd), dim3(256), 0, st, args, gopd_tab);
+  if (n_z > 0) hipLaunchKernelGGL(zproj_group_kernel, dim3(n_z), dim3(256), 0, st, args, z_tab, call.zbasis);
+  if (n_fin > 0) hipLaunchKernelGGL(finalize_group_kernel, dim3(n_fin), dim3(256), 0, st, args, fin_tab, call);
   return hipGetLastError();
 }
 

@@ -33,6 +33,7 @@ DLX_FLAG_SEED_PASS = 2
 DLX_FLAG_STORE_FIELDS = 4
 DLX_FLAG_PIXEL_KERNEL = 8
 DLX_FLAG_DENSE_MFT = 16
+DLX_FLAG_GROUPED = 32
 
 # Every symbol include/dlx.h declares.
 

@@ -304,7 +304,8 @@ class BatchPlan:
     (dlx_plan_offsets). ``pack`` builds such a tensor from per-problem
     tensors and ``unpack`` returns per-problem views of one. One call
     evaluates every problem; the library spreads them over concurrent
-    streams joined back into the caller's stream.
+    streams joined back into the caller's stream, or, with ``grouped``, runs
+    each stage as one launch over every problem (DLX_FLAG_GROUPED).
     """
 
     _FIELDS = ("transmission", "zernike_basis", "map_basis", "zernike_coeffs", "phase_map", "sources", "flat",
@@ -312,7 +313,7 @@ class BatchPlan:
 
     def __init__(self, geoms, transmissions, zbases, map_bases=None, intrapixels=None, precision: str = "fp32",
                  workspace_limit: int = 0, device="cuda", autotune: bool = True, store_fields: bool = False,
-                 dense_mft: bool = False, pixel_kernel: bool = False):
+                 dense_mft: bool = False, pixel_kernel: bool = False, grouped: bool = False):
         if not torch.cuda.is_available():
             raise RuntimeError("libdlx needs a ROCm GPU")
         self.geoms = list(geoms)
@@ -333,7 +334,8 @@ class BatchPlan:
         with torch.cuda.device(self.device):
             flags = ((0 if autotune else _c.DLX_FLAG_NO_AUTOTUNE) | (_c.DLX_FLAG_STORE_FIELDS if store_fields else 0)
                      | (_c.DLX_FLAG_DENSE_MFT if dense_mft else 0)
-                     | (_c.DLX_FLAG_PIXEL_KERNEL if pixel_kernel else 0))
+                     | (_c.DLX_FLAG_PIXEL_KERNEL if pixel_kernel else 0)
+                     | (_c.DLX_FLAG_GROUPED if grouped else 0))
             self.plan = _c.dlx_plan_create(descs, n, prec, flags, int(workspace_limit))
         self.precision = precision
         self.offsets = [_c.dlx_plan_offsets(self.plan, k) for k in range(_c.dlx_plan_problems(self.plan))]

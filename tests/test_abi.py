@@ -82,10 +82,10 @@ def test_plan_create_rejects_bad_precision_and_flags():
         dlx.dlx_plan_create(d, precision=7)
     assert e.value.status == dlx.DLX_ERR_INVALID_ARG
     with pytest.raises(dlx.DlxError) as e:
-        dlx.dlx_plan_create(d, flags=32)   # an undefined bit
+        dlx.dlx_plan_create(d, flags=64)   # an undefined bit
     assert e.value.status == dlx.DLX_ERR_INVALID_ARG
     assert (dlx.DLX_FLAG_NO_AUTOTUNE | dlx.DLX_FLAG_SEED_PASS | dlx.DLX_FLAG_STORE_FIELDS
-            | dlx.DLX_FLAG_PIXEL_KERNEL | dlx.DLX_FLAG_DENSE_MFT) == 31
+            | dlx.DLX_FLAG_PIXEL_KERNEL | dlx.DLX_FLAG_DENSE_MFT | dlx.DLX_FLAG_GROUPED) == 63
 
 
 def test_calls_on_null_plan_are_rejected():

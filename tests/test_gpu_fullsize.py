@@ -216,20 +216,21 @@ def c4_reference():
     return ws, refs
 
 
+@pytest.mark.parametrize("grouped", [False, True])
 @pytest.mark.parametrize("prec", ["fp32", "bf16x3"])
-def test_fullsize_batched_configuration_sampled_problems(prec):
+def test_fullsize_batched_configuration_sampled_problems(prec, grouped):
     """All 128 problems of the batched configuration in one plan, replayed from its graph as
     benchmarked; sampled problems are checked against the oracle."""
     import torch
     from paper_2406_08703_amd import BatchPlan
     from tests.gpu_helpers import geometry
     from tests.test_gpu_parity import compare
-    print(f"full size c4 {prec}", flush=True)
+    print(f"full size c4 {prec} grouped={grouped}", flush=True)
     ws, refs = c4_reference()
     picks = list(refs)
     t = lambda a: torch.from_numpy(np.ascontiguousarray(a, dtype=np.float32))
     bp = BatchPlan([geometry(w) for w in ws], [t(w.transmission) for w in ws], [t(w.zbasis) for w in ws],
-                   precision=prec)
+                   precision=prec, grouped=grouped)
     eps = [w.eval_params() for w in ws]
     c = bp.pack("zernike_coeffs", [t(e["coeffs"]) for e in eps])
     s = bp.pack("sources", [t(e["sources"]) for e in eps])

@@ -16,12 +16,13 @@ def _plan(w):
 
 
 def test_tune_cache_file_is_written_read_and_validated(tmp_path, monkeypatch):
-    from synth import make_workload
+    from synth import make_workload, standin_image
     from tests.gpu_helpers import run_eval
     from tests.helpers import rel_l2
     print("tune cache", flush=True)
     # a shape no other test uses, so nothing is cached for it yet
     w = make_workload("c2", n_pupil=44, n_focal=52, n_wavelengths=2, noll=tuple(range(2, 7)))
+    w = w.with_data(standin_image(w))
     path = tmp_path / "tune.txt"
     monkeypatch.setenv("DLX_TUNE_CACHE", str(path))
     plan = _plan(w)
