@@ -637,7 +637,12 @@ __device__ __forceinline__ void fgemm_body(const GemmArgs& a, int lin, const flo
   }
   const int nk = k_hi > k_lo ? (k_hi - k_lo + BK - 1) / BK : 0;
 
-  for (int lb = p_begin; lb < p_end; ++lb) {
+  // Items run wavelength-major: item it is the chunk's PSF (it % nfs) L + it / nfs, so consecutive
+  // items (and the contiguous workgroup ranges of one XCD) share a wavelength's DFT matrix (and, for
+  // F1, its pupil field) in that XCD's L2. The PSF index itself is (frame S + star) L + wavelength.
+  const int nfs = a.n_chunk_psf / a.L;
+  for (int it = p_begin; it < p_end; ++it) {
+    const int lb = (it % nfs) * a.L + it / nfs;
     const int gb = a.psf0 + lb;
     const int wl = gb % a.L;
     const el_t* Db = static_cast<const el_t*>(OD.base) + (long long)wl * OD.by_wl + (long long)lb * OD.by_psf;
