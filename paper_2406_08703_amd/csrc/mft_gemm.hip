@@ -598,7 +598,13 @@ __device__ __forceinline__ void fgemm_body(const GemmArgs& a, int lin, const flo
   const int item = lin / tiles;
   if (item >= a.n_items) return;
   const int tile = lin - item * tiles;
-  const int tm = tile / a.tiles_n, tn = tile - tm * a.tiles_n;
+  // In the adjoint products the DFT side's tile index varies fastest, so that the workgroups that read
+  // one block of a PSF's data rows (E and G for B3, U^T for B4) run next to each other and share it in
+  // L2. F1 and F2 keep the DFT tile fixed while the data tiles vary: F2's data rows (T) are already
+  // shared by the workgroups of one row tile, and F1's (the pupil field) by every PSF of a wavelength.
+  constexpr bool DFT_FAST = KIND == KIND_B3 || KIND == KIND_B4;
+  const int tm = DFT_FAST ? tile % a.tiles_m : tile / a.tiles_n;
+  const int tn = DFT_FAST ? tile / a.tiles_m : tile - tm * a.tiles_n;
   const int row0 = tm * BM, col0 = tn * BN;
   const int M = a.M, N = a.N, K = a.K;
   const int rowD0 = DA ? row0 : col0, rowX0 = DA ? col0 : row0;
