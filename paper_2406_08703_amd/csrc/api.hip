@@ -10,6 +10,7 @@
 #include <cstdlib>
 #include <cstring>
 #include <new>
+#include <utility>
 
 #include "dlx_internal.h"
 
@@ -659,23 +660,56 @@ GemmArgs group_stage_args(dlx_plan* q, int s) {
   }
 }
 
+// Block table of a grouped GEMM launch, in dispatch order. Workgroup g goes to XCD g mod 8 and each
+// XCD takes its workgroups in order, so the table is laid out as eight queues, entry j of queue x at
+// position 8 j + x. Every problem's logical workgroups are cut into eight contiguous ranges whose
+// sizes differ by at most one, one range per queue: each XCD then gets an equal share of every
+// problem (tiles differ in depth from problem to problem, not within one), and the tiles of a range,
+// which share operands, stay on one L2. The ranges that take a problem's remainder start at the
+// first queue that is one entry short, so queue x always ends with ceil((n - x) / 8) entries.
+// Returns an empty table if that count does not hold (not expected).
+std::vector<int2> xcd_queue_table(const std::vector<std::pair<int, int>>& problem_wgs) {
+  constexpr int kXcds = 8;
+  std::vector<int2> q[kXcds];
+  long long n = 0;
+  for (const auto& pw : problem_wgs) {
+    const int nw = pw.second, base = nw / kXcds, extra = nw % kXcds;
+    const int start = (int)(n % kXcds);
+    int w = 0;
+    for (int j = 0; j < kXcds; ++j) {
+      const int x = (start + j) % kXcds;
+      const int cnt = base + (j < extra ? 1 : 0);
+      for (int i = 0; i < cnt; ++i) q[x].push_back(make_int2(pw.first, w++));
+    }
+    n += nw;
+  }
+  std::vector<int2> tab((size_t)n);
+  for (int x = 0; x < kXcds; ++x) {
+    if ((long long)q[x].size() != (n - x + kXcds - 1) / kXcds) return {};
+    for (size_t j = 0; j < q[x].size(); ++j) tab[j * kXcds + x] = q[x][j];
+  }
+  return tab;
+}
+
 // Arguments and block table of GEMM stage s for the current tiles, uploaded (problems in order of
-// decreasing work, so the largest start first).
+// decreasing work, so the largest start first on every XCD).
 hipError_t group_stage_upload(dlx_plan* p, int s) {
   GroupPlan& g = *p->group;
   group_apply_tiles(p, s);
   const int n = (int)p->subs.size();
   std::vector<GemmArgs> args(n);
-  std::vector<int2> tab;
+  std::vector<std::pair<int, int>> wgs;
+  long long n_wg = 0;
   for (int k : p->order) {
     GemmArgs a = group_stage_args(p->subs[k], s);
     a.sources = nullptr;
     a.src_off = p->offs[k].sources;
     args[k] = a;
-    const int nw = wg_count(a);
-    for (int w = 0; w < nw; ++w) tab.push_back(make_int2(k, w));
+    wgs.emplace_back(k, wg_count(a));
+    n_wg += wg_count(a);
   }
-  if ((int)tab.size() > g.cap_wg[s]) return hipErrorInvalidValue;
+  const std::vector<int2> tab = xcd_queue_table(wgs);
+  if ((long long)tab.size() != n_wg || n_wg > g.cap_wg[s]) return hipErrorInvalidValue;
   hipError_t e = hipMemcpy(g.d_gargs[s], args.data(), sizeof(GemmArgs) * n, hipMemcpyHostToDevice);
   if (e == hipSuccess && !tab.empty())
     e = hipMemcpy(g.d_gtab[s], tab.data(), sizeof(int2) * tab.size(), hipMemcpyHostToDevice);

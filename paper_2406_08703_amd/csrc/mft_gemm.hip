@@ -1130,14 +1130,15 @@ __global__ __launch_bounds__(256, PREC == 0 ? 2 : 1) void fgemm_kernel(const Gem
   fgemm_body<KIND, WM, WN, PREC>(a, xcd_remap(blockIdx.x, gridDim.x), a.sources);
 }
 
-// One launch of a folded stage over the problems of a multi-problem plan: workgroup g (in XCD order)
-// runs logical workgroup tab[g].y of problem tab[g].x, whose arguments are args[tab[g].x]; the
-// problem's star table is sources + args[k].src_off (sources: the call's packed table).
+// One launch of a folded stage over the problems of a multi-problem plan: workgroup g runs logical
+// workgroup tab[g].y of problem tab[g].x, whose arguments are args[tab[g].x]; the problem's star
+// table is sources + args[k].src_off (sources: the call's packed table). The table is already in
+// dispatch order (the host lays it out as one queue per XCD), so no remap is applied here.
 template <int KIND, int WM, int WN, int PREC>
 __global__ __launch_bounds__(256, PREC == 0 ? 2 : 1) void fgemm_group_kernel(const GemmArgs* __restrict__ args,
                                                                             const int2* __restrict__ tab,
                                                                             const float* sources) {
-  const int2 e = tab[xcd_remap(blockIdx.x, gridDim.x)];
+  const int2 e = tab[blockIdx.x];
   const GemmArgs& a = args[e.x];
   fgemm_body<KIND, WM, WN, PREC>(a, e.y, sources ? sources + a.src_off : nullptr);
 }
