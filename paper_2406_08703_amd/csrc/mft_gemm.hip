@@ -647,17 +647,22 @@ __device__ __forceinline__ void fgemm_body(const GemmArgs& a, int lin, const flo
   // items (and the contiguous workgroup ranges of one XCD) share a wavelength's DFT matrix (and, for
   // F1, its pupil field) in that XCD's L2. The PSF index itself is (frame S + star) L + wavelength.
   const int nfs = a.n_chunk_psf / a.L;
-  for (int it = p_begin; it < p_end; ++it) {
+  const int ldx = OX.ld;
+  // The PSF whose tiles the loader fetches: its operand bases, its row tilt (F1) and, for B3, the
+  // seed weights and w phi. B4 workgroups run several PSFs; there the last k-stage of one PSF
+  // already fetches the first tile of the next, so a new PSF does not start on an empty pipeline.
+  const el_t* Db = nullptr;
+  const float* Xb = nullptr;
+  const float* tyl = nullptr;
+  float wphi = 1.f;
+  const float* gwb = nullptr;
+  auto set_loader = [&](int it) {
     const int lb = (it % nfs) * a.L + it / nfs;
     const int gb = a.psf0 + lb;
     const int wl = gb % a.L;
-    const el_t* Db = static_cast<const el_t*>(OD.base) + (long long)wl * OD.by_wl + (long long)lb * OD.by_psf;
-    const float* Xb = static_cast<const float*>(OX.base) + (long long)wl * OX.by_wl + (long long)lb * OX.by_psf;
-    const int ldx = OX.ld;
-    const float* txb = a.tx + (long long)gb * a.ldt;
-    const float* tyb = a.ty + (long long)gb * a.ldt;
-    float wphi = 1.f;
-    const float* gwb = nullptr;
+    Db = static_cast<const el_t*>(OD.base) + (long long)wl * OD.by_wl + (long long)lb * OD.by_psf;
+    Xb = static_cast<const float*>(OX.base) + (long long)wl * OX.by_wl + (long long)lb * OX.by_psf;
+    tyl = a.ty + (long long)gb * a.ldt;
     if constexpr (KIND == KIND_B3) {
       if (a.seedw) {
         const int fs = gb / a.L;
@@ -665,6 +670,205 @@ __device__ __forceinline__ void fgemm_body(const GemmArgs& a, int lin, const flo
         gwb = a.seedw + (long long)(fs / a.S - a.frame0) * a.seedw_by_frame;
       }
     }
+  };
+
+  // ------------------------------------------------------------ staging registers
+  u4 gd[D_U][ND];
+  int gd_k[D_U];
+  u4 xn[X_U][2 * V], xm[X_U][2 * V];   // re, im at the natural chunk and at the mirror chunk
+  u4 w0[X_U][V], w1[X_U][V];           // F1: ty re, im at k; B3: G at k and at the mirror
+  int gx_k[X_U];
+
+  auto load_tile = [&](int k0) {
+#pragma unroll
+    for (int r = 0; r < D_U; ++r) {
+      const int q = tid + 256 * r;
+      const int row = q >> 2, kq = q & 3;
+      const int gi = rowD0 + row;
+      const int gk = k0 + CH * kq;
+      gd_k[r] = gk;
+#pragma unroll
+      for (int pl = 0; pl < ND; ++pl) gd[r][pl] = u4{0u, 0u, 0u, 0u};
+      if (q < UNITS_D && gi < nD && gk < k_hi) {
+        const el_t* p = Db + (long long)gi * OD.ld + gk;
+#pragma unroll
+        for (int pl = 0; pl < ND; ++pl) gd[r][pl] = *reinterpret_cast<const u4*>(p + pl * OD.plane);
+      }
+    }
+#pragma unroll
+    for (int r = 0; r < X_U; ++r) {
+      const int q = tid + 256 * r;
+      const int row = q >> 2, kq = q & 3;
+      const int gj = rowX0 + row;
+      const int gk = k0 + CH * kq;
+      gx_k[r] = gk;
+#pragma unroll
+      for (int v = 0; v < 2 * V; ++v) {
+        xn[r][v] = u4{0u, 0u, 0u, 0u};
+        xm[r][v] = u4{0u, 0u, 0u, 0u};
+      }
+#pragma unroll
+      for (int v = 0; v < V; ++v) {
+        w0[r][v] = u4{0u, 0u, 0u, 0u};
+        w1[r][v] = u4{0u, 0u, 0u, 0u};
+      }
+      if (q < UNITS_X && gj < nX && gk < k_hi) {
+        const float* p = Xb + (long long)gj * ldx + gk;
+        const float* pm = Xb + (long long)gj * ldx + (ldx - CH - gk);
+#pragma unroll
+        for (int v = 0; v < V; ++v) {
+          xn[r][v] = *reinterpret_cast<const u4*>(p + 4 * v);
+          xn[r][V + v] = *reinterpret_cast<const u4*>(p + OX.plane + 4 * v);
+          xm[r][v] = *reinterpret_cast<const u4*>(pm + 4 * v);
+          xm[r][V + v] = *reinterpret_cast<const u4*>(pm + OX.plane + 4 * v);
+        }
+        if constexpr (KIND == KIND_F1) {
+#pragma unroll
+          for (int v = 0; v < V; ++v) {
+            w0[r][v] = *reinterpret_cast<const u4*>(tyl + gk + 4 * v);
+            w1[r][v] = *reinterpret_cast<const u4*>(tyl + a.tilt_plane + gk + 4 * v);
+          }
+        } else if constexpr (KIND == KIND_B3) {
+          const f4 one = f4{1.f, 1.f, 1.f, 1.f};
+#pragma unroll
+          for (int v = 0; v < V; ++v) {
+            w0[r][v] = gwb ? *reinterpret_cast<const u4*>(gwb + (long long)gj * ldx + gk + 4 * v)
+                           : __builtin_bit_cast(u4, one);
+            w1[r][v] = gwb ? *reinterpret_cast<const u4*>(gwb + (long long)gj * ldx + (ldx - CH - gk) + 4 * v)
+                           : __builtin_bit_cast(u4, one);
+          }
+        }
+      }
+    }
+  };
+
+  auto store_tile = [&]() {
+    // DFT operand: as the dense kernel (K tail masked, conjugated for the adjoint)
+#pragma unroll
+    for (int r = 0; r < D_U; ++r) {
+      const int q = tid + 256 * r;
+      if (q < UNITS_D) {
+        const int row = q >> 2, kq = q & 3;
+        if constexpr (PREC == 0) {
+          f4 vr = __builtin_bit_cast(f4, gd[r][0]), vi = __builtin_bit_cast(f4, gd[r][1]);
+          const int gk = gd_k[r];
+          if (gk + 4 > k_hi) {
+#pragma unroll
+            for (int e = 0; e < 4; ++e)
+              if (gk + e >= k_hi) {
+                vr[e] = 0.f;
+                vi[e] = 0.f;
+              }
+          }
+          if (conj_d) vi = -vi;
+          *reinterpret_cast<f4*>(&Ds[row * LDK + 4 * (kq ^ lds_swz(row))]) = vr;
+          *reinterpret_cast<f4*>(&Ds[(RD + row) * LDK + 4 * (kq ^ lds_swz(row))]) = vi;
+        } else {
+          u4* pl = gd[r];
+          const int gk = gd_k[r];
+          if (gk + 8 > k_hi) {
+#pragma unroll
+            for (int e = 0; e < 8; ++e)
+              if (gk + e >= k_hi) {
+                const unsigned int mask = (e & 1) ? 0x0000ffffu : 0xffff0000u;
+#pragma unroll
+                for (int c = 0; c < 4; ++c) pl[c][e >> 1] &= mask;
+              }
+          }
+          if (conj_d) {
+            pl[2] ^= u4{0x80008000u, 0x80008000u, 0x80008000u, 0x80008000u};
+            pl[3] ^= u4{0x80008000u, 0x80008000u, 0x80008000u, 0x80008000u};
+          }
+#pragma unroll
+          for (int c = 0; c < 4; ++c)
+            *reinterpret_cast<u4*>(&Ds[(c * RD + row) * LDK + 8 * (kq ^ lds_swz(row))]) = pl[c];
+        }
+      }
+    }
+    // data operand: loader product at k and at the mirror, then sum and difference
+#pragma unroll
+    for (int r = 0; r < X_U; ++r) {
+      const int q = tid + 256 * r;
+      if (q < UNITS_X) {
+        const int row = q >> 2, kq = q & 3;
+        f4 er[V], ei[V], odr[V], odi[V];
+#pragma unroll
+        for (int v = 0; v < V; ++v) {
+          f4 xr = __builtin_bit_cast(f4, xn[r][v]), xi = __builtin_bit_cast(f4, xn[r][V + v]);
+          // the mirror of natural element 4v + e is element 3 - e of mirror vector V - 1 - v
+          f4 yr = rev4(__builtin_bit_cast(f4, xm[r][V - 1 - v]));
+          f4 yi = rev4(__builtin_bit_cast(f4, xm[r][2 * V - 1 - v]));
+          if constexpr (KIND == KIND_F1) {
+            // P[k] = P0[k] ty[k]; at the mirror row the tilt is conj(ty[k])
+            const f4 tr = __builtin_bit_cast(f4, w0[r][v]), ti = __builtin_bit_cast(f4, w1[r][v]);
+            const f4 ar = xr * tr - xi * ti, ai = xr * ti + xi * tr;
+            const f4 br = yr * tr + yi * ti, bi = yi * tr - yr * ti;
+            xr = ar;
+            xi = ai;
+            yr = br;
+            yi = bi;
+          } else if constexpr (KIND == KIND_B3) {
+            const f4 g = wphi * __builtin_bit_cast(f4, w0[r][v]);
+            const f4 gm = wphi * rev4(__builtin_bit_cast(f4, w1[r][V - 1 - v]));
+            xr = g * xr;
+            xi = g * xi;
+            yr = gm * yr;
+            yi = gm * yi;
+          }
+          // K tail and the unpaired middle term (assigned after the products: padding is not read)
+          const int kb = gx_k[r] + 4 * v;
+          if (kb + 4 > k_hi || (kmid >= kb && kmid < kb + 4)) {
+#pragma unroll
+            for (int e = 0; e < 4; ++e) {
+              if (kb + e >= k_hi) {
+                xr[e] = 0.f;
+                xi[e] = 0.f;
+                yr[e] = 0.f;
+                yi[e] = 0.f;
+              }
+              if (kb + e == kmid) {
+                yr[e] = 0.f;
+                yi[e] = 0.f;
+              }
+            }
+          }
+          er[v] = xr + yr;
+          ei[v] = xi + yi;
+          odr[v] = xr - yr;
+          odi[v] = xi - yi;
+        }
+        if constexpr (PREC == 0) {
+          const int o = 4 * (kq ^ lds_swz(row));
+          *reinterpret_cast<f4*>(&Xs[(0 * RX + row) * LDK + o]) = er[0];
+          *reinterpret_cast<f4*>(&Xs[(1 * RX + row) * LDK + o]) = ei[0];
+          *reinterpret_cast<f4*>(&Xs[(2 * RX + row) * LDK + o]) = odr[0];
+          *reinterpret_cast<f4*>(&Xs[(3 * RX + row) * LDK + o]) = odi[0];
+        } else {
+          // planes: Xe re hi, lo; Xe im hi, lo; Xo re hi, lo; Xo im hi, lo (8 k each, two per word)
+          unsigned int w[8][4];
+#pragma unroll
+          for (int e = 0; e < 4; ++e) {
+            const int v = e >> 1, c = 2 * (e & 1);
+            split_pair(er[v][c], er[v][c + 1], w[0][e], w[1][e]);
+            split_pair(ei[v][c], ei[v][c + 1], w[2][e], w[3][e]);
+            split_pair(odr[v][c], odr[v][c + 1], w[4][e], w[5][e]);
+            split_pair(odi[v][c], odi[v][c + 1], w[6][e], w[7][e]);
+          }
+          const int o = 8 * (kq ^ lds_swz(row));
+#pragma unroll
+          for (int pl = 0; pl < 8; ++pl)
+            *reinterpret_cast<u4*>(&Xs[(pl * RX + row) * LDK + o]) = u4{w[pl][0], w[pl][1], w[pl][2], w[pl][3]};
+        }
+      }
+    }
+  };
+
+  for (int it = p_begin; it < p_end; ++it) {
+    const int lb = (it % nfs) * a.L + it / nfs;
+    const int gb = a.psf0 + lb;
+    const int wl = gb % a.L;
+    const float* txb = a.tx + (long long)gb * a.ldt;
+    const float* tyb = a.ty + (long long)gb * a.ldt;
 
     f4 pr_[WM][WN], pi_[WM][WN], rr_[WM][WN], ri_[WM][WN];
 #pragma unroll
@@ -676,204 +880,21 @@ __device__ __forceinline__ void fgemm_body(const GemmArgs& a, int lin, const flo
         rr_[bm][bn] = f4{0.f, 0.f, 0.f, 0.f};
         ri_[bm][bn] = f4{0.f, 0.f, 0.f, 0.f};
       }
+    if (KIND != KIND_B4 || it == p_begin) {   // later B4 PSFs were fetched by the previous PSF
+      set_loader(it);
+      if (nk > 0) load_tile(k_lo);
+    }
 
-    // ------------------------------------------------------------ staging registers
-    u4 gd[D_U][ND];
-    int gd_k[D_U];
-    u4 xn[X_U][2 * V], xm[X_U][2 * V];   // re, im at the natural chunk and at the mirror chunk
-    u4 w0[X_U][V], w1[X_U][V];           // F1: ty re, im at k; B3: G at k and at the mirror
-    int gx_k[X_U];
-
-    auto load_tile = [&](int k0) {
-#pragma unroll
-      for (int r = 0; r < D_U; ++r) {
-        const int q = tid + 256 * r;
-        const int row = q >> 2, kq = q & 3;
-        const int gi = rowD0 + row;
-        const int gk = k0 + CH * kq;
-        gd_k[r] = gk;
-#pragma unroll
-        for (int pl = 0; pl < ND; ++pl) gd[r][pl] = u4{0u, 0u, 0u, 0u};
-        if (q < UNITS_D && gi < nD && gk < k_hi) {
-          const el_t* p = Db + (long long)gi * OD.ld + gk;
-#pragma unroll
-          for (int pl = 0; pl < ND; ++pl) gd[r][pl] = *reinterpret_cast<const u4*>(p + pl * OD.plane);
-        }
-      }
-#pragma unroll
-      for (int r = 0; r < X_U; ++r) {
-        const int q = tid + 256 * r;
-        const int row = q >> 2, kq = q & 3;
-        const int gj = rowX0 + row;
-        const int gk = k0 + CH * kq;
-        gx_k[r] = gk;
-#pragma unroll
-        for (int v = 0; v < 2 * V; ++v) {
-          xn[r][v] = u4{0u, 0u, 0u, 0u};
-          xm[r][v] = u4{0u, 0u, 0u, 0u};
-        }
-#pragma unroll
-        for (int v = 0; v < V; ++v) {
-          w0[r][v] = u4{0u, 0u, 0u, 0u};
-          w1[r][v] = u4{0u, 0u, 0u, 0u};
-        }
-        if (q < UNITS_X && gj < nX && gk < k_hi) {
-          const float* p = Xb + (long long)gj * ldx + gk;
-          const float* pm = Xb + (long long)gj * ldx + (ldx - CH - gk);
-#pragma unroll
-          for (int v = 0; v < V; ++v) {
-            xn[r][v] = *reinterpret_cast<const u4*>(p + 4 * v);
-            xn[r][V + v] = *reinterpret_cast<const u4*>(p + OX.plane + 4 * v);
-            xm[r][v] = *reinterpret_cast<const u4*>(pm + 4 * v);
-            xm[r][V + v] = *reinterpret_cast<const u4*>(pm + OX.plane + 4 * v);
-          }
-          if constexpr (KIND == KIND_F1) {
-#pragma unroll
-            for (int v = 0; v < V; ++v) {
-              w0[r][v] = *reinterpret_cast<const u4*>(tyb + gk + 4 * v);
-              w1[r][v] = *reinterpret_cast<const u4*>(tyb + a.tilt_plane + gk + 4 * v);
-            }
-          } else if constexpr (KIND == KIND_B3) {
-            const f4 one = f4{1.f, 1.f, 1.f, 1.f};
-#pragma unroll
-            for (int v = 0; v < V; ++v) {
-              w0[r][v] = gwb ? *reinterpret_cast<const u4*>(gwb + (long long)gj * ldx + gk + 4 * v)
-                             : __builtin_bit_cast(u4, one);
-              w1[r][v] = gwb ? *reinterpret_cast<const u4*>(gwb + (long long)gj * ldx + (ldx - CH - gk) + 4 * v)
-                             : __builtin_bit_cast(u4, one);
-            }
-          }
-        }
-      }
-    };
-
-    auto store_tile = [&]() {
-      // DFT operand: as the dense kernel (K tail masked, conjugated for the adjoint)
-#pragma unroll
-      for (int r = 0; r < D_U; ++r) {
-        const int q = tid + 256 * r;
-        if (q < UNITS_D) {
-          const int row = q >> 2, kq = q & 3;
-          if constexpr (PREC == 0) {
-            f4 vr = __builtin_bit_cast(f4, gd[r][0]), vi = __builtin_bit_cast(f4, gd[r][1]);
-            const int gk = gd_k[r];
-            if (gk + 4 > k_hi) {
-#pragma unroll
-              for (int e = 0; e < 4; ++e)
-                if (gk + e >= k_hi) {
-                  vr[e] = 0.f;
-                  vi[e] = 0.f;
-                }
-            }
-            if (conj_d) vi = -vi;
-            *reinterpret_cast<f4*>(&Ds[row * LDK + 4 * (kq ^ lds_swz(row))]) = vr;
-            *reinterpret_cast<f4*>(&Ds[(RD + row) * LDK + 4 * (kq ^ lds_swz(row))]) = vi;
-          } else {
-            u4* pl = gd[r];
-            const int gk = gd_k[r];
-            if (gk + 8 > k_hi) {
-#pragma unroll
-              for (int e = 0; e < 8; ++e)
-                if (gk + e >= k_hi) {
-                  const unsigned int mask = (e & 1) ? 0x0000ffffu : 0xffff0000u;
-#pragma unroll
-                  for (int c = 0; c < 4; ++c) pl[c][e >> 1] &= mask;
-                }
-            }
-            if (conj_d) {
-              pl[2] ^= u4{0x80008000u, 0x80008000u, 0x80008000u, 0x80008000u};
-              pl[3] ^= u4{0x80008000u, 0x80008000u, 0x80008000u, 0x80008000u};
-            }
-#pragma unroll
-            for (int c = 0; c < 4; ++c)
-              *reinterpret_cast<u4*>(&Ds[(c * RD + row) * LDK + 8 * (kq ^ lds_swz(row))]) = pl[c];
-          }
-        }
-      }
-      // data operand: loader product at k and at the mirror, then sum and difference
-#pragma unroll
-      for (int r = 0; r < X_U; ++r) {
-        const int q = tid + 256 * r;
-        if (q < UNITS_X) {
-          const int row = q >> 2, kq = q & 3;
-          f4 er[V], ei[V], odr[V], odi[V];
-#pragma unroll
-          for (int v = 0; v < V; ++v) {
-            f4 xr = __builtin_bit_cast(f4, xn[r][v]), xi = __builtin_bit_cast(f4, xn[r][V + v]);
-            // the mirror of natural element 4v + e is element 3 - e of mirror vector V - 1 - v
-            f4 yr = rev4(__builtin_bit_cast(f4, xm[r][V - 1 - v]));
-            f4 yi = rev4(__builtin_bit_cast(f4, xm[r][2 * V - 1 - v]));
-            if constexpr (KIND == KIND_F1) {
-              // P[k] = P0[k] ty[k]; at the mirror row the tilt is conj(ty[k])
-              const f4 tr = __builtin_bit_cast(f4, w0[r][v]), ti = __builtin_bit_cast(f4, w1[r][v]);
-              const f4 ar = xr * tr - xi * ti, ai = xr * ti + xi * tr;
-              const f4 br = yr * tr + yi * ti, bi = yi * tr - yr * ti;
-              xr = ar;
-              xi = ai;
-              yr = br;
-              yi = bi;
-            } else if constexpr (KIND == KIND_B3) {
-              const f4 g = wphi * __builtin_bit_cast(f4, w0[r][v]);
-              const f4 gm = wphi * rev4(__builtin_bit_cast(f4, w1[r][V - 1 - v]));
-              xr = g * xr;
-              xi = g * xi;
-              yr = gm * yr;
-              yi = gm * yi;
-            }
-            // K tail and the unpaired middle term (assigned after the products: padding is not read)
-            const int kb = gx_k[r] + 4 * v;
-            if (kb + 4 > k_hi || (kmid >= kb && kmid < kb + 4)) {
-#pragma unroll
-              for (int e = 0; e < 4; ++e) {
-                if (kb + e >= k_hi) {
-                  xr[e] = 0.f;
-                  xi[e] = 0.f;
-                  yr[e] = 0.f;
-                  yi[e] = 0.f;
-                }
-                if (kb + e == kmid) {
-                  yr[e] = 0.f;
-                  yi[e] = 0.f;
-                }
-              }
-            }
-            er[v] = xr + yr;
-            ei[v] = xi + yi;
-            odr[v] = xr - yr;
-            odi[v] = xi - yi;
-          }
-          if constexpr (PREC == 0) {
-            const int o = 4 * (kq ^ lds_swz(row));
-            *reinterpret_cast<f4*>(&Xs[(0 * RX + row) * LDK + o]) = er[0];
-            *reinterpret_cast<f4*>(&Xs[(1 * RX + row) * LDK + o]) = ei[0];
-            *reinterpret_cast<f4*>(&Xs[(2 * RX + row) * LDK + o]) = odr[0];
-            *reinterpret_cast<f4*>(&Xs[(3 * RX + row) * LDK + o]) = odi[0];
-          } else {
-            // planes: Xe re hi, lo; Xe im hi, lo; Xo re hi, lo; Xo im hi, lo (8 k each, two per word)
-            unsigned int w[8][4];
-#pragma unroll
-            for (int e = 0; e < 4; ++e) {
-              const int v = e >> 1, c = 2 * (e & 1);
-              split_pair(er[v][c], er[v][c + 1], w[0][e], w[1][e]);
-              split_pair(ei[v][c], ei[v][c + 1], w[2][e], w[3][e]);
-              split_pair(odr[v][c], odr[v][c + 1], w[4][e], w[5][e]);
-              split_pair(odi[v][c], odi[v][c + 1], w[6][e], w[7][e]);
-            }
-            const int o = 8 * (kq ^ lds_swz(row));
-#pragma unroll
-            for (int pl = 0; pl < 8; ++pl)
-              *reinterpret_cast<u4*>(&Xs[(pl * RX + row) * LDK + o]) = u4{w[pl][0], w[pl][1], w[pl][2], w[pl][3]};
-          }
-        }
-      }
-    };
-
-    if (nk > 0) load_tile(k_lo);
     for (int kt = 0; kt < nk; ++kt) {
       __syncthreads();
       store_tile();
       __syncthreads();
-      if (kt + 1 < nk) load_tile(k_lo + (kt + 1) * BK);
+      if (kt + 1 < nk) {
+        load_tile(k_lo + (kt + 1) * BK);
+      } else if (KIND == KIND_B4 && it + 1 < p_end) {
+        set_loader(it + 1);
+        load_tile(k_lo);
+      }
 
       if constexpr (PREC == 0) {
         constexpr int WD = DA ? WM : WN, WX = DA ? WN : WM;
@@ -1145,10 +1166,10 @@ __global__ __launch_bounds__(256, PREC == 0 ? 2 : 1) void fgemm_group_kernel(con
 
 // Folded tile shapes compiled: those that keep their accumulators in registers. FP32 (two
 // workgroups per CU): up to four 32 x 32 blocks, except B4's 128 x 32 and 32 x 128. BF16X3: all
-// but 128 x 128 (and B4's 96 x 96).
+// but 128 x 128 (and B4's 96 x 96 and 64 x 128, whose epilogue and prefetched next tile spill).
 constexpr bool fold_tile_ok(int kind, int prec, int wm, int wn) {
   if (prec == 0) return wm * wn <= 4 && !(kind == KIND_B4 && wm != wn && wm * wn == 4);
-  return !(wm == 4 && wn == 4) && !(kind == KIND_B4 && wm == 3 && wn == 3);
+  return !(wm == 4 && wn == 4) && !(kind == KIND_B4 && ((wm == 3 && wn == 3) || (wm == 2 && wn == 4)));
 }
 
 template <int KIND, int WM, int WN, int PREC>
