@@ -846,7 +846,8 @@ hipError_t group_small_upload(dlx_plan* p) {
     u.plane = (long long)q->Ni * q->ldNi;
     u.by_wl = 2LL * q->Ni * q->ldNi;
     u.o_trans = o.transmission;
-    for (int l = 0; l < q->L; ++l)
+    u.L = q->L;
+    for (int l = 0; l < q->L; l += kPupilGroupWl)
       for (int y = 0; y < (q->ldNi + 31) / 32; ++y)
         for (int x = 0; x < (q->Ni + 31) / 32; ++x) t_pupil.push_back(GroupBlock{k, x, y, l});
 

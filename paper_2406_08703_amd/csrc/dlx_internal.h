@@ -159,11 +159,12 @@ struct PrepArgs {   // OPD, A^2 partial sums, tilt vectors (prep_kernel)
   float* ty;
   long long o_trans, o_z, o_c, o_src;
 };
+constexpr int kPupilGroupWl = 8;   // wavelengths per block of the grouped pupil launch
 struct PupilArgs {   // per-wavelength pupil fields (pupil_kernel)
   const double* opd;
   const float* screen;
   const double* norm_part;
-  int n_norm, Ni, ldp, h;
+  int n_norm, Ni, ldp, h, L;
   const WlInfo* wl;
   float* P0T;
   long long plane, by_wl, o_trans;

@@ -83,9 +83,10 @@ __global__ void map_tmp_kernel(const float* C, const float* Bm, float* tmp, int 
 }
 
 // P0T_l[n][m] = A[m][n] / sqrt(sum A^2) * exp(i 2 pi OPD[m][n] / lambda_l), one block per
-// (32 x 32 tile, wavelength), transposed through LDS. Row n stores column m at m for m < h and at
-// m + ldp - Ni for h <= m < Ni (the folded layout; h = Ni: natural), zeros elsewhere.
-__device__ __forceinline__ void pupil_body(int bx, int by, int l, const float* A, const double* opd,
+// (32 x 32 tile, nl consecutive wavelengths from l0), transposed through LDS; the tile's OPD,
+// screen and transmission are read once for all of its wavelengths. Row n stores column m at m for
+// m < h and at m + ldp - Ni for h <= m < Ni (the folded layout; h = Ni: natural), zeros elsewhere.
+__device__ __forceinline__ void pupil_body(int bx, int by, int l0, int nl, int L, const float* A, const double* opd,
                                            const float* screen, const double* norm_part, int n_norm,
                                            const WlInfo* wl, int Ni, int ldp, int h, float* P0T, long long plane,
                                            long long by_wl) {
@@ -93,20 +94,19 @@ __device__ __forceinline__ void pupil_body(int bx, int by, int l, const float* A
   __shared__ double sparts[256];   // n_norm <= 256
   const int tx = threadIdx.x, ty = threadIdx.y;  // 32 x 8
   const int m0 = by * 32, n0 = bx * 32;
-  // the partial sums of A^2 are read in parallel, next to the pixels' loads and phases
+  // the partial sums of A^2 are read in parallel, next to the pixels' loads
   for (int i = ty * 32 + tx; i < n_norm; i += 256) sparts[i] = norm_part[i];
-  const double inv = 1.0 / wl[l].lam;
-  double cs[4], sn[4], av[4];
+  double od[4], sc[4], av[4];
+  bool in[4];
 #pragma unroll
   for (int q = 0; q < 4; ++q) {
     const int m = m0 + ty + 8 * q, n = n0 + tx;
-    cs[q] = sn[q] = av[q] = 0.0;
-    if (m < Ni && n < Ni) {
+    in[q] = m < Ni && n < Ni;
+    od[q] = sc[q] = av[q] = 0.0;
+    if (in[q]) {
       const long long p = (long long)m * Ni + n;
-      // phase in cycles: the OPD's plus the static screen's (achromatic, radians)
-      const double t0 = opd[p] * inv + (double)screen[p] * 0.15915494309189533577;
-      const double fr = t0 - rint(t0);
-      sincospi(2.0 * fr, &sn[q], &cs[q]);
+      od[q] = opd[p];
+      sc[q] = (double)screen[p] * 0.15915494309189533577;   // the static screen in cycles (achromatic)
       av[q] = (double)A[p];
     }
   }
@@ -114,39 +114,52 @@ __device__ __forceinline__ void pupil_body(int bx, int by, int l, const float* A
   double s2 = 0.0;   // every thread adds the partials in the same order
   for (int i = 0; i < n_norm; ++i) s2 += sparts[i];
   const double nrm = s2 > 0.0 ? 1.0 / sqrt(s2) : 0.0;
+  const int l_end = l0 + nl < L ? l0 + nl : L;
+  for (int l = l0; l < l_end; ++l) {
+    const double inv = 1.0 / wl[l].lam;
 #pragma unroll
-  for (int q = 0; q < 4; ++q) {
-    const double amp = av[q] * nrm;
-    tr[ty + 8 * q][tx] = (float)(amp * cs[q]);
-    ti[ty + 8 * q][tx] = (float)(amp * sn[q]);
-  }
-  __syncthreads();
-  for (int q = 0; q < 4; ++q) {
-    const int n = n0 + ty + 8 * q, m = m0 + tx;  // output row n, column m
-    if (n < Ni && m < ldp) {
-      const bool in = m < Ni;
-      // the ldp - Ni padding columns m >= Ni fill the gap [h, h + ldp - Ni)
-      const int c = m < h ? m : (in ? m + (ldp - Ni) : h + (m - Ni));
-      P0T[l * by_wl + (long long)n * ldp + c] = in ? tr[tx][ty + 8 * q] : 0.f;
-      P0T[l * by_wl + plane + (long long)n * ldp + c] = in ? ti[tx][ty + 8 * q] : 0.f;
+    for (int q = 0; q < 4; ++q) {
+      double sn = 0.0, cs = 0.0;
+      if (in[q]) {
+        const double t0 = od[q] * inv + sc[q];   // phase in cycles
+        const double fr = t0 - rint(t0);
+        sincospi(2.0 * fr, &sn, &cs);
+      }
+      const double amp = av[q] * nrm;
+      tr[ty + 8 * q][tx] = (float)(amp * cs);
+      ti[ty + 8 * q][tx] = (float)(amp * sn);
     }
+    __syncthreads();
+    for (int q = 0; q < 4; ++q) {
+      const int n = n0 + ty + 8 * q, m = m0 + tx;  // output row n, column m
+      if (n < Ni && m < ldp) {
+        const bool inside = m < Ni;
+        // the ldp - Ni padding columns m >= Ni fill the gap [h, h + ldp - Ni)
+        const int c = m < h ? m : (inside ? m + (ldp - Ni) : h + (m - Ni));
+        P0T[l * by_wl + (long long)n * ldp + c] = inside ? tr[tx][ty + 8 * q] : 0.f;
+        P0T[l * by_wl + plane + (long long)n * ldp + c] = inside ? ti[tx][ty + 8 * q] : 0.f;
+      }
+    }
+    if (l + 1 < l_end) __syncthreads();   // the next wavelength rewrites the tile
   }
 }
 
 __global__ __launch_bounds__(256) void pupil_kernel(const float* A, const double* opd, const float* screen,
                                                     const double* norm_part, int n_norm, const WlInfo* wl, int Ni,
-                                                    int ldp, int h, float* P0T, long long plane, long long by_wl) {
-  pupil_body(blockIdx.x, blockIdx.y, blockIdx.z, A, opd, screen, norm_part, n_norm, wl, Ni, ldp, h, P0T, plane, by_wl);
+                                                    int ldp, int h, float* P0T, long long plane, long long by_wl,
+                                                    int nl, int L) {
+  pupil_body(blockIdx.x, blockIdx.y, blockIdx.z * nl, nl, L, A, opd, screen, norm_part, n_norm, wl, Ni, ldp, h, P0T,
+             plane, by_wl);
 }
 
 // The pupil fields of every problem of a multi-problem plan in one launch (block table entries:
-// problem, tile column, tile row, wavelength).
+// problem, tile column, tile row, first wavelength; kPupilGroupWl wavelengths per block).
 __global__ __launch_bounds__(256) void pupil_group_kernel(const PupilArgs* __restrict__ args,
                                                           const GroupBlock* __restrict__ tab, const float* A) {
   const GroupBlock e = tab[blockIdx.x];
   const PupilArgs& a = args[e.k];
-  pupil_body(e.x, e.y, e.z, A + a.o_trans, a.opd, a.screen, a.norm_part, a.n_norm, a.wl, a.Ni, a.ldp, a.h, a.P0T,
-             a.plane, a.by_wl);
+  pupil_body(e.x, e.y, e.z, kPupilGroupWl, a.L, A + a.o_trans, a.opd, a.screen, a.norm_part, a.n_norm, a.wl, a.Ni,
+             a.ldp, a.h, a.P0T, a.plane, a.by_wl);
 }
 
 // Tilt vectors of all PSFs, psf = (f S + s) L + l: element t = psf * ldt + n.
@@ -297,9 +310,14 @@ hipError_t launch_prep(dlx_plan* p, const float* A, const float* Z, const float*
                      Bm, p->d_maptmp, p->Nmap, p->d_opd, nb_opd, A, p->d_norm, p->n_norm_part, sources, p->d_wl,
                      p->d_x, p->L, p->ldNi, nt, p->d_tx, p->d_ty, nt);
   const long long p0_by_wl = 2LL * p->Ni * p->ldNi;
-  hipLaunchKernelGGL(pupil_kernel, dim3((p->Ni + 31) / 32, (p->ldNi + 31) / 32, p->L), dim3(32, 8), 0, st, A,
-                     p->d_opd, p->d_screen, p->d_norm, p->n_norm_part, p->d_wl, p->Ni, p->ldNi,
-                     p->fold ? p->hNi() : p->Ni, p->d_P0T, (long long)p->Ni * p->ldNi, p0_by_wl);
+  // wavelengths per block: up to 8 (each tile's loads and norm serve them all) while the launch
+  // keeps at least 2048 blocks
+  const long long tiles = (long long)((p->Ni + 31) / 32) * ((p->ldNi + 31) / 32);
+  int nl = 8;
+  while (nl > 1 && tiles * ((p->L + nl - 1) / nl) < 2048) nl /= 2;
+  hipLaunchKernelGGL(pupil_kernel, dim3((p->Ni + 31) / 32, (p->ldNi + 31) / 32, (p->L + nl - 1) / nl), dim3(32, 8), 0,
+                     st, A, p->d_opd, p->d_screen, p->d_norm, p->n_norm_part, p->d_wl, p->Ni, p->ldNi,
+                     p->fold ? p->hNi() : p->Ni, p->d_P0T, (long long)p->Ni * p->ldNi, p0_by_wl, nl, p->L);
   return hipGetLastError();
 }
 
