@@ -605,8 +605,8 @@ struct GroupPlan {
   GroupBlock* d_pupil_tab = nullptr;
   int n_pupil = 0;
   BinLossArgs* d_bl = nullptr;
-  GroupBlock* d_bl_tab[4] = {};   // problems by the compiled oversampling of their binning: 1, 2, 4, other
-  int n_bl[4] = {}, qt_of[4] = {1, 2, 4, 0};
+  GroupBlock* d_bl_tab[5] = {};   // problems by the compiled oversampling of their binning: 1, 2, 3, 4, other
+  int n_bl[5] = {}, qt_of[5] = {1, 2, 3, 4, 0};
   GradArgs* d_grad = nullptr;
   GroupBlock *d_gopd_tab = nullptr, *d_z_tab = nullptr, *d_fin_tab = nullptr;
   int n_gopd = 0, n_z = 0, n_fin = 0;
@@ -631,7 +631,7 @@ int b4_split_for(const dlx_plan* q, int ks) {
   return ks;
 }
 
-int bin_class(int Q) { return Q == 1 ? 0 : Q == 2 ? 1 : Q == 4 ? 2 : 3; }
+int bin_class(int Q) { return Q >= 1 && Q <= 4 ? Q - 1 : 4; }
 
 // Stage s's tiles on every sub-plan (B4 with its split), as the grouped launch and the per-problem
 // calls of the plan use them.
@@ -805,7 +805,7 @@ hipError_t group_small_upload(dlx_plan* p) {
   std::vector<PupilArgs> pupil(n);
   std::vector<BinLossArgs> bl(n);
   std::vector<GradArgs> grad(n);
-  std::vector<GroupBlock> t_prep, t_pupil, t_bl[4], t_gopd, t_z, t_fin;
+  std::vector<GroupBlock> t_prep, t_pupil, t_bl[5], t_gopd, t_z, t_fin;
   for (int k : p->order) {
     const dlx_plan* q = p->subs[k];
     const dlx_offsets& o = p->offs[k];
@@ -912,7 +912,7 @@ hipError_t group_small_upload(dlx_plan* p) {
                  bytes(n, sizeof(GradArgs)) + bytes(t_prep.size(), sizeof(GroupBlock)) +
                  bytes(t_pupil.size(), sizeof(GroupBlock)) + bytes(t_gopd.size(), sizeof(GroupBlock)) +
                  bytes(t_z.size(), sizeof(GroupBlock)) + bytes(t_fin.size(), sizeof(GroupBlock));
-  for (int c = 0; c < 4; ++c) total += bytes(t_bl[c].size(), sizeof(GroupBlock));
+  for (int c = 0; c < 5; ++c) total += bytes(t_bl[c].size(), sizeof(GroupBlock));
   char* base = nullptr;
   hipError_t e = hipMalloc(reinterpret_cast<void**>(&base), total);
   if (e != hipSuccess) return e;
@@ -933,7 +933,7 @@ hipError_t group_small_upload(dlx_plan* p) {
   g.d_gopd_tab = reinterpret_cast<GroupBlock*>(put(t_gopd.data(), t_gopd.size() * sizeof(GroupBlock)));
   g.d_z_tab = reinterpret_cast<GroupBlock*>(put(t_z.data(), t_z.size() * sizeof(GroupBlock)));
   g.d_fin_tab = reinterpret_cast<GroupBlock*>(put(t_fin.data(), t_fin.size() * sizeof(GroupBlock)));
-  for (int c = 0; c < 4; ++c) {
+  for (int c = 0; c < 5; ++c) {
     g.d_bl_tab[c] = reinterpret_cast<GroupBlock*>(put(t_bl[c].data(), t_bl[c].size() * sizeof(GroupBlock)));
     g.n_bl[c] = (int)t_bl[c].size();
   }
@@ -1044,7 +1044,7 @@ dlx_status group_eval(dlx_plan* p, const dlx_eval_args* a, hipStream_t st) {
   }
   {
     Stage sg(p, st, DLX_STAGE_BIN, p->n_psf);
-    for (int c = 0; c < 4; ++c) DLX_HIP(launch_bin_loss_group(g.qt_of[c], g.d_bl, g.d_bl_tab[c], g.n_bl[c], call, st));
+    for (int c = 0; c < 5; ++c) DLX_HIP(launch_bin_loss_group(g.qt_of[c], g.d_bl, g.d_bl_tab[c], g.n_bl[c], call, st));
   }
   {
     Stage sg(p, st, DLX_STAGE_B3, p->n_psf);

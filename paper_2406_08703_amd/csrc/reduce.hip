@@ -55,20 +55,44 @@ __device__ __forceinline__ float pixel_power(const float* e, long long plane, in
     const float er = e[cb], ei = e[plane + cb];
     part = q1_power(er, ei);
     if (kp) part *= kp[0];
-  } else if constexpr (QT == 4 || QT == 2) {
+  } else if constexpr (QT >= 2) {
+    // every load of the pixel (and its kernel weights) is issued before any arithmetic, so that
+    // they are in flight together; the weights' branch would otherwise wait for each row in turn
     e += cb;
-    typedef float vq __attribute__((ext_vector_type(QT)));
+    float er[QT][QT], ei[QT][QT], kw[QT * QT];
+    if constexpr (QT == 3) {   // three columns: not 8- or 16-byte aligned
 #pragma unroll
-    for (int a = 0; a < QT; ++a) {
-      const vq vr = *reinterpret_cast<const vq*>(e + (long long)a * ld);
-      const vq vi = *reinterpret_cast<const vq*>(e + plane + (long long)a * ld);
+      for (int a = 0; a < QT; ++a)
 #pragma unroll
-      for (int b = 0; b < QT; ++b) {
-        float v = vr[b] * vr[b] + vi[b] * vi[b];
-        if (kp) v *= kp[a * QT + b];
-        part += v;
+        for (int b = 0; b < QT; ++b) {
+          er[a][b] = e[(long long)a * ld + b];
+          ei[a][b] = e[plane + (long long)a * ld + b];
+        }
+    } else {
+      typedef float vq __attribute__((ext_vector_type(QT)));
+#pragma unroll
+      for (int a = 0; a < QT; ++a) {
+        const vq vr = *reinterpret_cast<const vq*>(e + (long long)a * ld);
+        const vq vi = *reinterpret_cast<const vq*>(e + plane + (long long)a * ld);
+#pragma unroll
+        for (int b = 0; b < QT; ++b) {
+          er[a][b] = vr[b];
+          ei[a][b] = vi[b];
+        }
       }
     }
+    if (kp) {
+#pragma unroll
+      for (int i = 0; i < QT * QT; ++i) kw[i] = kp[i];
+    }
+#pragma unroll
+    for (int a = 0; a < QT; ++a)
+#pragma unroll
+      for (int b = 0; b < QT; ++b) {
+        float v = er[a][b] * er[a][b] + ei[a][b] * ei[a][b];
+        if (kp) v *= kw[a * QT + b];
+        part += v;
+      }
   } else {
     e += cb;
     for (int a = 0; a < Q; ++a)
@@ -963,6 +987,7 @@ hipError_t launch_intensity(dlx_plan* p, int f0, int nf, const float* sources, c
   switch (p->Q) {
     case 1: DLX_INTENSITY(1); break;
     case 2: DLX_INTENSITY(2); break;
+    case 3: DLX_INTENSITY(3); break;
     case 4: DLX_INTENSITY(4); break;
     default: DLX_INTENSITY(0); break;
   }
@@ -1083,6 +1108,7 @@ hipError_t launch_bin_loss(dlx_plan* p, int f0, int nf, int chunk, const float* 
   switch (p->Q) {
     case 1: DLX_BIN_LOSS(1); break;
     case 2: DLX_BIN_LOSS(2); break;
+    case 3: DLX_BIN_LOSS(3); break;
     case 4: DLX_BIN_LOSS(4); break;
     default: DLX_BIN_LOSS(0); break;
   }
@@ -1097,6 +1123,7 @@ hipError_t launch_bin_loss_group(int qt, const BinLossArgs* args, const GroupBlo
   switch (qt) {
     case 1: hipLaunchKernelGGL(bin_loss_group_kernel<1>, grid, blk, 0, st, args, tab, call); break;
     case 2: hipLaunchKernelGGL(bin_loss_group_kernel<2>, grid, blk, 0, st, args, tab, call); break;
+    case 3: hipLaunchKernelGGL(bin_loss_group_kernel<3>, grid, blk, 0, st, args, tab, call); break;
     case 4: hipLaunchKernelGGL(bin_loss_group_kernel<4>, grid, blk, 0, st, args, tab, call); break;
     default: hipLaunchKernelGGL(bin_loss_group_kernel<0>, grid, blk, 0, st, args, tab, call); break;
   }
