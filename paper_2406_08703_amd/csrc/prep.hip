@@ -86,6 +86,7 @@ __global__ void map_tmp_kernel(const float* C, const float* Bm, float* tmp, int 
 // (32 x 32 tile, nl consecutive wavelengths from l0), transposed through LDS; the tile's OPD,
 // screen and transmission are read once for all of its wavelengths. Row n stores column m at m for
 // m < h and at m + ldp - Ni for h <= m < Ni (the folded layout; h = Ni: natural), zeros elsewhere.
+template <int NLMAX>   // nl <= NLMAX (1: the single-wavelength body, with no loop state)
 __device__ __forceinline__ void pupil_body(int bx, int by, int l0, int nl, int L, const float* A, const double* opd,
                                            const float* screen, const double* norm_part, int n_norm,
                                            const WlInfo* wl, int Ni, int ldp, int h, float* P0T, long long plane,
@@ -115,7 +116,10 @@ __device__ __forceinline__ void pupil_body(int bx, int by, int l0, int nl, int L
   for (int i = 0; i < n_norm; ++i) s2 += sparts[i];
   const double nrm = s2 > 0.0 ? 1.0 / sqrt(s2) : 0.0;
   const int l_end = l0 + nl < L ? l0 + nl : L;
-  for (int l = l0; l < l_end; ++l) {
+#pragma unroll
+  for (int i = 0; i < NLMAX; ++i) {
+    const int l = l0 + i;
+    if (l >= l_end) break;
     const double inv = 1.0 / wl[l].lam;
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
@@ -140,16 +144,17 @@ __device__ __forceinline__ void pupil_body(int bx, int by, int l0, int nl, int L
         P0T[l * by_wl + plane + (long long)n * ldp + c] = inside ? ti[tx][ty + 8 * q] : 0.f;
       }
     }
-    if (l + 1 < l_end) __syncthreads();   // the next wavelength rewrites the tile
+    if (i + 1 < NLMAX && l + 1 < l_end) __syncthreads();   // the next wavelength rewrites the tile
   }
 }
 
+template <int NLMAX>
 __global__ __launch_bounds__(256) void pupil_kernel(const float* A, const double* opd, const float* screen,
                                                     const double* norm_part, int n_norm, const WlInfo* wl, int Ni,
                                                     int ldp, int h, float* P0T, long long plane, long long by_wl,
                                                     int nl, int L) {
-  pupil_body(blockIdx.x, blockIdx.y, blockIdx.z * nl, nl, L, A, opd, screen, norm_part, n_norm, wl, Ni, ldp, h, P0T,
-             plane, by_wl);
+  pupil_body<NLMAX>(blockIdx.x, blockIdx.y, blockIdx.z * nl, nl, L, A, opd, screen, norm_part, n_norm, wl, Ni, ldp, h,
+                    P0T, plane, by_wl);
 }
 
 // The pupil fields of every problem of a multi-problem plan in one launch (block table entries:
@@ -158,7 +163,7 @@ __global__ __launch_bounds__(256) void pupil_group_kernel(const PupilArgs* __res
                                                           const GroupBlock* __restrict__ tab, const float* A) {
   const GroupBlock e = tab[blockIdx.x];
   const PupilArgs& a = args[e.k];
-  pupil_body(e.x, e.y, e.z, kPupilGroupWl, a.L, A + a.o_trans, a.opd, a.screen, a.norm_part, a.n_norm, a.wl, a.Ni,
+  pupil_body<kPupilGroupWl>(e.x, e.y, e.z, kPupilGroupWl, a.L, A + a.o_trans, a.opd, a.screen, a.norm_part, a.n_norm, a.wl, a.Ni,
              a.ldp, a.h, a.P0T, a.plane, a.by_wl);
 }
 
@@ -315,9 +320,15 @@ hipError_t launch_prep(dlx_plan* p, const float* A, const float* Z, const float*
   const long long tiles = (long long)((p->Ni + 31) / 32) * ((p->ldNi + 31) / 32);
   int nl = 8;
   while (nl > 1 && tiles * ((p->L + nl - 1) / nl) < 2048) nl /= 2;
-  hipLaunchKernelGGL(pupil_kernel, dim3((p->Ni + 31) / 32, (p->ldNi + 31) / 32, (p->L + nl - 1) / nl), dim3(32, 8), 0,
-                     st, A, p->d_opd, p->d_screen, p->d_norm, p->n_norm_part, p->d_wl, p->Ni, p->ldNi,
-                     p->fold ? p->hNi() : p->Ni, p->d_P0T, (long long)p->Ni * p->ldNi, p0_by_wl, nl, p->L);
+  const dim3 pgrid((p->Ni + 31) / 32, (p->ldNi + 31) / 32, (p->L + nl - 1) / nl);
+  if (nl == 1)
+    hipLaunchKernelGGL(pupil_kernel<1>, pgrid, dim3(32, 8), 0, st, A, p->d_opd, p->d_screen, p->d_norm,
+                       p->n_norm_part, p->d_wl, p->Ni, p->ldNi, p->fold ? p->hNi() : p->Ni, p->d_P0T,
+                       (long long)p->Ni * p->ldNi, p0_by_wl, nl, p->L);
+  else
+    hipLaunchKernelGGL(pupil_kernel<8>, pgrid, dim3(32, 8), 0, st, A, p->d_opd, p->d_screen, p->d_norm,
+                       p->n_norm_part, p->d_wl, p->Ni, p->ldNi, p->fold ? p->hNi() : p->Ni, p->d_P0T,
+                       (long long)p->Ni * p->ldNi, p0_by_wl, nl, p->L);
   return hipGetLastError();
 }
 
