@@ -41,7 +41,7 @@ def test_roofline_entry_from_launch_times():
 
 
 def test_traffic_lookup_matches_the_summary_and_guards_the_source(tmp_path, monkeypatch):
-    path = os.path.join(bench.ROOT, "profiles", "traffic_c2_fp32.txt")
+    path = os.path.join(bench.ROOT, "profiles", "traffic_c3_fp32.txt")
     lines = open(path).read().splitlines()
     fields = dict(l.split() for l in lines if l.split()[:1] and l.split()[0] in ("fetch_scale", "write_scale",
                                                                                  "kernel_source_sha256"))
@@ -50,7 +50,7 @@ def test_traffic_lookup_matches_the_summary_and_guards_the_source(tmp_path, monk
     want = round(1024 * (float(stage[4]) * float(fields["fetch_scale"]) + float(stage[5]) * float(fields["write_scale"])))
     src = os.path.join(bench.ROOT, "paper_2406_08703_amd", "csrc", "mft_gemm.hip")
     current = hashlib.sha256(open(src, "rb").read()).hexdigest()
-    got = bench.measured_traffic("c2", "fp32", "B3", (wm, wn))
+    got = bench.measured_traffic("c3", "fp32", "B3", (wm, wn))
     if fields["kernel_source_sha256"] == current:
         assert got == want
     else:
@@ -60,6 +60,6 @@ def test_traffic_lookup_matches_the_summary_and_guards_the_source(tmp_path, monk
     (root / "profiles").mkdir()
     (root / "paper_2406_08703_amd" / "csrc").mkdir(parents=True)
     (root / "paper_2406_08703_amd" / "csrc" / "mft_gemm.hip").write_text("// another kernel\n")
-    (root / "profiles" / "traffic_c2_fp32.txt").write_text("\n".join(lines) + "\n")
+    (root / "profiles" / "traffic_c3_fp32.txt").write_text("\n".join(lines) + "\n")
     monkeypatch.setattr(bench, "ROOT", str(root))
-    assert bench.measured_traffic("c2", "fp32", "B3", (wm, wn)) is None
+    assert bench.measured_traffic("c3", "fp32", "B3", (wm, wn)) is None
