@@ -225,6 +225,32 @@ def test_q1_four_pixel_binning_equals_one_pixel_binning():
         assert np.array_equal(a[k], b[k]), k
 
 
+@pytest.mark.parametrize("case", ["c3-small", "c5-small", "c2", "odd-q3"])
+def test_binning_kernels_agree_bitwise_at_every_compiled_oversampling(case):
+    # the separate forward call bins every frame of a chunk in one launch (intensity_kernel); a fused
+    # evaluation with one frame per chunk bins together with the loss (bin_loss_kernel). Q = 3
+    # (c3-small, odd-q3), 2 (c5-small) and 4 (c2) each have their own compiled path: the same bits
+    from paper_2406_08703_amd.dlx import DlxError
+    from tests.gpu_helpers import make_plan, run_eval, run_gpu
+    w, _ = workload(case)
+    # the smallest workspace limit a plan accepts holds one frame per chunk
+    full = make_plan(w, autotune=False)
+    lo, hi = 1 << 16, full.workspace_bytes
+    full.close()
+    while hi - lo > 4096:
+        mid = (lo + hi) // 2
+        try:
+            make_plan(w, workspace_limit=mid, autotune=False).close()
+            hi = mid
+        except DlxError:
+            lo = mid
+    plan = make_plan(w, workspace_limit=hi)
+    a, b = run_gpu(w, plan=plan), run_eval(w, plan=plan)
+    plan.close()
+    for k in ("binned", "model"):
+        assert np.array_equal(a[k], b[k]), k
+
+
 def test_chi2_variant_matches_oracle():
     from tests.gpu_helpers import run_gpu
     w, _ = workload("c3-small")
