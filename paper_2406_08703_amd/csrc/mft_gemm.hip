@@ -588,7 +588,8 @@ __device__ __forceinline__ void fgemm_body(const GemmArgs& a, int lin, const flo
   constexpr int D_U = (UNITS_D + 255) / 256, X_U = (UNITS_X + 255) / 256;
   using el_t = typename std::conditional<PREC == 0, float, unsigned short>::type;
   __shared__ __attribute__((aligned(16))) el_t smem[D_EL + X_EL];
-  __shared__ double sred[8];
+  constexpr int kPosSlots = KIND == KIND_B4 ? 32 : 1;
+  __shared__ double spos[kPosSlots][4][2];   // B4: per-PSF, per-wave position partials
   el_t* Ds = smem;
   el_t* Xs = smem + D_EL;
 
@@ -1108,15 +1109,23 @@ __device__ __forceinline__ void fgemm_body(const GemmArgs& a, int lin, const flo
         }
       px = wave_sum(px);
       py = wave_sum(py);
+      // the PSF's wave sums wait in an LDS slot; they are added (in wave order) and written when
+      // the slots are full or the group ends, so the workgroup does not synchronise after each PSF
+      const int slot = (it - p_begin) % kPosSlots;
       if (lane == 0) {
-        sred[2 * wave] = px;
-        sred[2 * wave + 1] = py;
+        spos[slot][wave][0] = px;
+        spos[slot][wave][1] = py;
       }
-      __syncthreads();
-      if (tid == 0) {
-        double* o = a.red + (((long long)gb * a.ksplit + item % a.ksplit) * tiles + tile) * 2;
-        o[0] = sred[0] + sred[2] + sred[4] + sred[6];
-        o[1] = sred[1] + sred[3] + sred[5] + sred[7];
+      if (slot == kPosSlots - 1 || it + 1 == p_end) {
+        __syncthreads();
+        if (tid <= slot) {
+          const int is = it - slot + tid;
+          const int gbs = a.psf0 + (is % nfs) * a.L + is / nfs;
+          double* o = a.red + (((long long)gbs * a.ksplit + item % a.ksplit) * tiles + tile) * 2;
+          o[0] = spos[tid][0][0] + spos[tid][1][0] + spos[tid][2][0] + spos[tid][3][0];
+          o[1] = spos[tid][0][1] + spos[tid][1][1] + spos[tid][2][1] + spos[tid][3][1];
+        }
+        if (it + 1 < p_end) __syncthreads();   // the next PSFs reuse the slots
       }
     }
   }
