@@ -106,7 +106,9 @@ dlx_status dlx_validate(const dlx_problem_desc* probs, int32_t n_probs);
 
 /* Plan flags. By default dlx_plan_create autotunes: for each MFT stage it
  * times every compiled output-tile shape on the plan's own (zeroed)
- * workspace for the first frame chunk and keeps the fastest.
+ * workspace for the first frame chunk and keeps the fastest (for the last
+ * adjoint product also its split of the contraction and the number of PSFs
+ * each workgroup sums over).
  * DLX_FLAG_NO_AUTOTUNE keeps the built-in size heuristic instead. Tuned
  * tiles are kept per problem shape and device for the process; when the
  * environment variable DLX_TUNE_CACHE names a file, that file is the cache

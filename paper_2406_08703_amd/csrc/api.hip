@@ -114,7 +114,7 @@ void layout(dlx_plan* p, Pool& pool) {
     p->d_Bbig = pool.take<float>((size_t)p->Nd * p->Nd);
     p->d_win = pool.take<int>(p->win.size());
   }
-  p->d_gpart = pool.take<float>((size_t)p->b4_groups_max * p->ksplit_cap * Ni * Ni);
+  p->d_gpart = pool.take<float>((size_t)p->b4_groups_alloc * p->ksplit_cap * Ni * Ni);
   p->d_gopd = pool.take<double>(Ni * Ni);
   const size_t pix64 = ((size_t)p->Nd * p->Nd + 63) / 64;   // bin_loss_kernel's pixel blocks
   p->d_flux = pool.take<double>((size_t)p->F * p->S * std::max<size_t>(p->seed_blocks, pix64));
@@ -400,15 +400,23 @@ hipError_t autotune(dlx_plan* p) {
   for (int kind : kinds) {
     TileShape* ts = stage_tile(p, kind);
     TileShape best = *ts;
-    int best_ks = 0;
+    int best_ks = 0, best_gs = p->b4_gsize;
     float best_ms = 1e30f;
-    // B4 also tries each split of its K (= No) into 1, 2 or 4 ranges of at least 64
-    const int n_ks = kind == KIND_B4 ? 3 : 1;
-    for (int ci = 0; ci < (int)(sizeof(kTileShapes) / sizeof(kTileShapes[0])) * n_ks && e == hipSuccess; ++ci) {
-      const TileShape& cand = kTileShapes[ci / n_ks];
-      const int ks = kind == KIND_B4 ? (1 << (ci % n_ks)) : 0;
+    // B4 also tries each split of its K (= No) into 1, 2 or 4 ranges of at least 64, and groups of
+    // the heuristic size, twice and four times it
+    const int n_ks = kind == KIND_B4 ? 3 : 1, n_gs = kind == KIND_B4 ? 3 : 1;
+    const int n_cand = (int)(sizeof(kTileShapes) / sizeof(kTileShapes[0])) * n_ks * n_gs;
+    for (int ci = 0; ci < n_cand && e == hipSuccess; ++ci) {
+      const TileShape& cand = kTileShapes[ci / (n_ks * n_gs)];
+      const int ks = kind == KIND_B4 ? (1 << (ci / n_gs % n_ks)) : 0;
       if (ks > 1 && (p->fold ? p->hNo() : p->No) / ks < 64) continue;
       if (!tile_supported(kind, p->bf16(), p->fold, cand)) continue;
+      if (kind == KIND_B4) {
+        const int gs = std::min(p->chunk_psf, p->b4_gsize_default << (ci % n_gs));
+        if (ci % n_gs > 0 && gs == std::min(p->chunk_psf, p->b4_gsize_default << (ci % n_gs - 1))) continue;
+        p->b4_gsize = gs;
+        p->b4_groups_max = ceil_div(p->chunk_psf, gs);
+      }
       *ts = cand;
       derive_tiles(p, ks);
       if ((e = run_stage_for_tuning(p, kind, nullptr)) != hipSuccess) break;   // warm-up
@@ -420,15 +428,20 @@ hipError_t autotune(dlx_plan* p) {
       float ms = 0.f;
       if ((e = hipEventElapsedTime(&ms, t0, t1)) != hipSuccess) break;
       if (log)
-        std::fprintf(stderr, "dlx tune: stage %d tile %dx%d ksplit %d: %.4f ms per launch\n", kind, cand.bm(),
-                     cand.bn(), p->b4_ksplit, ms / 2);
+        std::fprintf(stderr, "dlx tune: stage %d tile %dx%d ksplit %d group %d: %.4f ms per launch\n", kind,
+                     cand.bm(), cand.bn(), p->b4_ksplit, p->b4_gsize, ms / 2);
       if (ms < best_ms) {
         best_ms = ms;
         best = cand;
         best_ks = ks;
+        best_gs = p->b4_gsize;
       }
     }
     *ts = best;
+    if (kind == KIND_B4) {
+      p->b4_gsize = best_gs;
+      p->b4_groups_max = ceil_div(p->chunk_psf, best_gs);
+    }
     derive_tiles(p, best_ks);
     if (kind == KIND_B4) p->b4_ksplit_tuned = best_ks;
     if (e != hipSuccess) break;
@@ -451,6 +464,7 @@ std::mutex g_tune_mu;
 struct Tuned {
   std::array<TileShape, 4> tiles;   // F1, F2, B3, B4
   int b4_ksplit;
+  int b4_gsize;                     // PSFs per B4 group
 };
 std::map<TuneKey, Tuned> g_tune;
 
@@ -461,7 +475,7 @@ TuneKey tune_key(const dlx_plan* p) {
           (p->seed_pass ? 1 : 0) | (p->fold ? 2 : 0)};
 }
 
-// "dlx-tune-v1 <arch> <CUs> <prec Ni No Q L S F frames_per_chunk Nz Nmap flags>" of the cache file:
+// "dlx-tune-v2 <arch> <CUs> <prec Ni No Q L S F frames_per_chunk Nz Nmap flags>" of the cache file:
 // the device is named by its architecture and compute-unit count, not by its index.
 bool disk_key(const dlx_plan* p, char* buf, size_t n) {
   int dev = 0;
@@ -472,7 +486,7 @@ bool disk_key(const dlx_plan* p, char* buf, size_t n) {
   for (const char* c = prop.gcnArchName; *c && *c != ':' && k < 63; ++c) arch[k++] = *c;
   arch[k] = 0;
   const TuneKey t = tune_key(p);
-  const int w = std::snprintf(buf, n, "dlx-tune-v1 %s %d %lld %lld %lld %lld %lld %lld %lld %lld %lld %lld %lld",
+  const int w = std::snprintf(buf, n, "dlx-tune-v2 %s %d %lld %lld %lld %lld %lld %lld %lld %lld %lld %lld %lld",
                               arch, prop.multiProcessorCount, t[1], t[2], t[3], t[4], t[5], t[6], t[7], t[8], t[9],
                               t[10], t[11]);
   return w > 0 && (size_t)w < n;
@@ -482,6 +496,7 @@ bool tuned_valid(const dlx_plan* p, const Tuned& t) {
   const int kinds[4] = {KIND_F1, KIND_F2, KIND_B3, KIND_B4};
   for (int i = 0; i < 4; ++i)
     if (!tile_supported(kinds[i], p->bf16(), p->fold, t.tiles[i])) return false;
+  if (t.b4_gsize < 1 || ceil_div(p->chunk_psf, t.b4_gsize) > p->b4_groups_alloc) return false;
   return t.b4_ksplit == 0 || t.b4_ksplit == 1 || t.b4_ksplit == 2 || t.b4_ksplit == 4;
 }
 
@@ -495,11 +510,11 @@ bool disk_lookup(const dlx_plan* p, const char* path, Tuned* out) {
   bool found = false;
   while (std::fgets(line, sizeof line, f)) {   // the last valid line for the key wins
     if (std::strncmp(line, key, kl) != 0 || std::strncmp(line + kl, " : ", 3) != 0) continue;
-    int v[9];
-    if (std::sscanf(line + kl + 3, "%d %d %d %d %d %d %d %d %d", &v[0], &v[1], &v[2], &v[3], &v[4], &v[5], &v[6],
-                    &v[7], &v[8]) != 9)
+    int v[10];
+    if (std::sscanf(line + kl + 3, "%d %d %d %d %d %d %d %d %d %d", &v[0], &v[1], &v[2], &v[3], &v[4], &v[5],
+                    &v[6], &v[7], &v[8], &v[9]) != 10)
       continue;
-    Tuned t{{TileShape{v[0], v[1]}, TileShape{v[2], v[3]}, TileShape{v[4], v[5]}, TileShape{v[6], v[7]}}, v[8]};
+    Tuned t{{TileShape{v[0], v[1]}, TileShape{v[2], v[3]}, TileShape{v[4], v[5]}, TileShape{v[6], v[7]}}, v[8], v[9]};
     if (!tuned_valid(p, t)) continue;
     *out = t;
     found = true;
@@ -513,8 +528,8 @@ void disk_store(const dlx_plan* p, const char* path, const Tuned& t) {
   if (!disk_key(p, key, sizeof key)) return;
   std::FILE* f = std::fopen(path, "a");
   if (!f) return;   // an unwritable cache only costs the next process its tuning
-  std::fprintf(f, "%s : %d %d %d %d %d %d %d %d %d\n", key, t.tiles[0].wm, t.tiles[0].wn, t.tiles[1].wm,
-               t.tiles[1].wn, t.tiles[2].wm, t.tiles[2].wn, t.tiles[3].wm, t.tiles[3].wn, t.b4_ksplit);
+  std::fprintf(f, "%s : %d %d %d %d %d %d %d %d %d %d\n", key, t.tiles[0].wm, t.tiles[0].wn, t.tiles[1].wm,
+               t.tiles[1].wn, t.tiles[2].wm, t.tiles[2].wn, t.tiles[3].wm, t.tiles[3].wn, t.b4_ksplit, t.b4_gsize);
   std::fclose(f);
 }
 
@@ -524,6 +539,8 @@ void apply_tuned(dlx_plan* p, const Tuned& t) {
   p->ts_b3 = t.tiles[2];
   p->ts_b4 = t.tiles[3];
   p->b4_ksplit_tuned = t.b4_ksplit;
+  p->b4_gsize = t.b4_gsize;
+  p->b4_groups_max = ceil_div(p->chunk_psf, t.b4_gsize);
   derive_tiles(p, p->b4_ksplit_tuned);
   p->tuned = true;
 }
@@ -551,7 +568,7 @@ hipError_t autotune_cached(dlx_plan* p) {
   const hipError_t e = autotune(p);
   if (e == hipSuccess) {
     std::lock_guard<std::mutex> lock(g_tune_mu);
-    const Tuned t{{p->ts_f1, p->ts_f2, p->ts_b3, p->ts_b4}, p->b4_ksplit_tuned};
+    const Tuned t{{p->ts_f1, p->ts_f2, p->ts_b3, p->ts_b4}, p->b4_ksplit_tuned, p->b4_gsize};
     if (disk)
       disk_store(p, path, t);
     else
@@ -965,7 +982,7 @@ dlx_status group_build(dlx_plan* p, bool tune) {
   const dlx_plan* q0 = p->subs[0];
   for (int s = 0; s < 4; ++s) g->ts[s] = s == 0 ? q0->ts_f1 : s == 1 ? q0->ts_f2 : s == 2 ? q0->ts_b3 : q0->ts_b4;
   g->b4_ks = 1;
-  for (const dlx_plan* q : p->subs) g->b4_groups_cap.push_back(q->b4_groups_max);
+  for (const dlx_plan* q : p->subs) g->b4_groups_cap.push_back(q->b4_groups_alloc);
   long long total_src = 0;
   for (int k = 0; k < n; ++k) {
     dlx_plan* q = p->subs[k];
@@ -975,7 +992,7 @@ dlx_status group_build(dlx_plan* p, bool tune) {
     g->cap_wg[0] += ceil_div(fm, 32) * ceil_div(q->Ni, 32) * items;
     g->cap_wg[1] += ceil_div(q->No, 32) * ceil_div(fm, 32) * items;
     g->cap_wg[2] += ceil_div(fi, 32) * ceil_div(q->No, 32) * items;
-    g->cap_wg[3] += ceil_div(fi, 32) * ceil_div(q->Ni, 32) * q->b4_groups_max * 4;
+    g->cap_wg[3] += ceil_div(fi, 32) * ceil_div(q->Ni, 32) * q->b4_groups_alloc * 4;
   }
   size_t total = 0;
   auto bytes = [](size_t c, size_t sz) { return (c * sz + 255) & ~size_t(255); };
@@ -1269,6 +1286,10 @@ dlx_status dlx_plan_create(const dlx_problem_desc* probs, int32_t n_probs, dlx_p
     p->b4_gsize = ceil_div(p->chunk_psf, g);
     p->b4_groups_max = ceil_div(p->chunk_psf, p->b4_gsize);
     p->ts_b4 = choose_tile(mNi, p->Ni, p->b4_groups_max, 1, fo);
+    // the autotuner also tries twice and four times this group size (fewer partial planes to write
+    // and add up, fewer workgroups); the partial planes are sized for this one, the most groups
+    p->b4_gsize_default = p->b4_gsize;
+    p->b4_groups_alloc = p->b4_groups_max;
   }
   derive_tiles(p);
   // partial-sum buffers are sized for the smallest candidate tile (32 x 32) and the largest split

@@ -262,6 +262,7 @@ struct dlx_plan {
   // tiles
   dlx::TileShape ts_f1, ts_f2, ts_b3, ts_b4;
   int b4_gsize, b4_groups_max, b4_ksplit = 1;
+  int b4_gsize_default = 1, b4_groups_alloc = 1;   // B4: the heuristic group size; groups d_gpart holds
   int b4_ksplit_tuned = 0;   // B4's K split chosen by the autotuner (0: the heuristic)
   // device memory
   void* pool = nullptr;
@@ -285,7 +286,7 @@ struct dlx_plan {
   float* d_bs = nullptr;   // per-source binned sum_l w_l K|E|^2 [frames_per_chunk][S][Nd*Nd]
   float* d_Bbig = nullptr; // integer-dither mode: binned enlarged plane [Nd*Nd]
   int* d_win = nullptr;    // integer-dither mode: window corners [F_img][2]
-  float* d_gpart = nullptr;    // [b4_groups_max * b4_ksplit][Ni*Ni]
+  float* d_gpart = nullptr;    // [b4_groups_max * b4_ksplit][Ni*Ni], room for b4_groups_alloc groups
   double* d_gopd = nullptr;    // [Ni*Ni]
   double* d_flux = nullptr;    // flux gradient partials [F][S][seed blocks]
   double* d_kpart = nullptr;   // intra-pixel kernel gradient partials [F][seed blocks][Q*Q]

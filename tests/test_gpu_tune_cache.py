@@ -1,5 +1,5 @@
 """The autotuner's on-disk cache (DLX_TUNE_CACHE): a plan created with the variable set appends its
-tuned tiles to the file; a later plan of the same shape takes its tiles from the file (here a line
+tuned tiles (and B4's split and group size) to the file; a later plan of the same shape takes its tiles from the file (here a line
 edited by hand to tiles the tuner would not pick), ignores a line whose tiles are not compiled for
 their stage, and evaluates the same result whatever the tiles up to the order of partial sums."""
 import os
@@ -30,11 +30,11 @@ def test_tune_cache_file_is_written_read_and_validated(tmp_path, monkeypatch):
     ref = run_eval(w, plan=plan)
     plan.close()
     lines = path.read_text().splitlines()
-    assert len(lines) == 1 and lines[0].startswith("dlx-tune-v1 ") and " : " in lines[0]
+    assert len(lines) == 1 and lines[0].startswith("dlx-tune-v2 ") and " : " in lines[0]
     key, vals = lines[0].split(" : ")
-    assert len(vals.split()) == 9
-    # a hand-edited line: every stage on the 32 x 32 tile, B4 unsplit
-    path.write_text(f"{key} : 1 1 1 1 1 1 1 1 1\n")
+    assert len(vals.split()) == 10
+    # a hand-edited line: every stage on the 32 x 32 tile, B4 unsplit, B4 groups of its heuristic size
+    path.write_text(f"{key} : 1 1 1 1 1 1 1 1 1 1\n")
     plan = _plan(w)
     assert plan.tiles == {"F1": (32, 32), "F2": (32, 32), "B3": (32, 32), "B4": (32, 32)}
     got = run_eval(w, plan=plan)
@@ -42,7 +42,7 @@ def test_tune_cache_file_is_written_read_and_validated(tmp_path, monkeypatch):
     np.testing.assert_array_equal(got["model"], ref["model"])   # the images do not depend on the tiles
     assert rel_l2(got["grad_coeffs"], ref["grad_coeffs"]) < 1e-6
     # an uncompiled folded FP32 tile (128 x 128) is ignored: the shape is tuned again and appended
-    path.write_text(f"{key} : 4 4 1 1 1 1 1 1 1\nnot a cache line\n")
+    path.write_text(f"{key} : 4 4 1 1 1 1 1 1 1 1\nnot a cache line\n")
     plan = _plan(w)
     assert plan.tiles["F1"] != (128, 128)
     plan.close()
