@@ -168,8 +168,8 @@ enum {
  * dlx_psf_backward, which then runs only the adjoint products: 2 MFTs per
  * PSF for a forward + backward pair instead of 3 (the choice between
  * recomputing and storing E). The whole problem is then one frame chunk:
- * the workspace holds every PSF's T, E and U^T (for c3 of the benchmark,
- * 4096 PSFs of 768^2, about 45 GB); without workspace_limit_bytes the plan
+ * the workspace holds every PSF's T, E and U^T (for 4096 PSFs of 768^2
+ * focal samples from a 512^2 pupil, about 45 GB); without workspace_limit_bytes the plan
  * may use up to 80% of the free device memory, and DLX_ERR_OOM is returned
  * if the problem does not fit. The backward call must receive the same
  * parameter arrays, unchanged, as the forward call it follows; any other

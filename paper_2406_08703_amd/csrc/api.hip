@@ -1298,7 +1298,8 @@ dlx_status dlx_plan_create(const dlx_problem_desc* probs, int32_t n_probs, dlx_p
   p->loss_blocks = loss_block_count((long long)p->Nd_img * p->Nd_img);
   p->seed_blocks = seed_block_count((long long)p->Nd * p->Nd);
   // the dense B3 streams a frame's G slower than a separate pass once G outgrows an XCD's L2; the
-  // folded B3 (a quarter of the matrix work per G element read) does not, up to c5's 16.8 MB frames
+  // folded B3 (a quarter of the matrix work per G element read) does not, up to frames of 2048^2
+  // focal samples (16.8 MB of G)
   p->seed_pass = (flags & DLX_FLAG_SEED_PASS) ||
                  (!p->fold && sizeof(float) * (size_t)p->No * p->ldNo > kSeedFuseMaxBytes);
   {
