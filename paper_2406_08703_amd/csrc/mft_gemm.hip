@@ -21,9 +21,14 @@
 // The next K stage's global loads are issued before the MFMAs and consumed
 // only when stored to LDS after them (conjugation, K-tail masking, the F1
 // pupil-field product and the BF16 split happen there), so their latency
-// overlaps the matrix work. The complex product uses the four real products
-// Re = ArBr - AiBi, Im = ArBi + AiBr (no 3-multiply trick: it loses accuracy
-// on operands of very different size).
+// overlaps the matrix work. The folded FP32 kernels go one step further: two
+// LDS buffers, one barrier per stage, and the store of the next stage's tile
+// interleaved with the current stage's MFMAs, so the loader's arithmetic and
+// LDS writes issue while the matrix pipe is busy.
+//
+// The complex product uses the four real products Re = ArBr - AiBi,
+// Im = ArBi + AiBr (no 3-multiply trick: it loses accuracy on operands of
+// very different size).
 //
 // Stage-specific work is fused into the operand loaders (F1: P0^T times the
 // row tilt; B3: the adjoint seed w phi G E from the stored field E and the
@@ -587,11 +592,12 @@ __device__ __forceinline__ void fgemm_body(const GemmArgs& a, int lin, const flo
   constexpr int UNITS_D = RD * 4, UNITS_X = RX * 4;
   constexpr int D_U = (UNITS_D + 255) / 256, X_U = (UNITS_X + 255) / 256;
   using el_t = typename std::conditional<PREC == 0, float, unsigned short>::type;
-  __shared__ __attribute__((aligned(16))) el_t smem[D_EL + X_EL];
+  // FP32 runs a two-buffer pipeline (below); BF16X3 one LDS buffer
+  constexpr bool PIPE = PREC == 0;
+  constexpr int BUF_EL = D_EL + X_EL;
+  __shared__ __attribute__((aligned(16))) el_t smem[(PIPE ? 2 : 1) * BUF_EL];
   constexpr int kPosSlots = KIND == KIND_B4 ? 32 : 1;
   __shared__ double spos[kPosSlots][4][2];   // B4: per-PSF, per-wave position partials
-  el_t* Ds = smem;
-  el_t* Xs = smem + D_EL;
 
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int wr = wave >> 1, wc = wave & 1;
@@ -743,17 +749,84 @@ __device__ __forceinline__ void fgemm_body(const GemmArgs& a, int lin, const flo
     }
   };
 
-  auto store_tile = [&]() {
+  // The pipelined path's loader: every thread loads unconditionally from clamped addresses (rows
+  // past the operand repeat its last row, k past k_hi its last chunk), so the loads and the stores
+  // of a full tile carry no branches. Repeated rows only feed outputs that are never stored; the
+  // masked store zeroes the k past k_hi, as gd_k and gx_k keep the unclamped positions.
+  const int kc_last = k_hi > 0 ? ((k_hi - 1) / CH) * CH : 0;
+  auto load_tile_c = [&](int k0) {
+#pragma unroll
+    for (int r = 0; r < D_U; ++r) {
+      const int q = (tid + 256 * r) % UNITS_D;
+      const int row = q >> 2, kq = q & 3;
+      const int gi = min(rowD0 + row, nD - 1);
+      const int gk = k0 + CH * kq;
+      gd_k[r] = gk;
+      const el_t* p = Db + (long long)gi * OD.ld + min(gk, kc_last);
+#pragma unroll
+      for (int pl = 0; pl < ND; ++pl) gd[r][pl] = *reinterpret_cast<const u4*>(p + pl * OD.plane);
+    }
+#pragma unroll
+    for (int r = 0; r < X_U; ++r) {
+      const int q = (tid + 256 * r) % UNITS_X;
+      const int row = q >> 2, kq = q & 3;
+      const int gj = min(rowX0 + row, nX - 1);
+      const int gk = k0 + CH * kq;
+      const int gkc = min(gk, kc_last);
+      gx_k[r] = gk;
+      const float* p = Xb + (long long)gj * ldx + gkc;
+      const float* pm = Xb + (long long)gj * ldx + (ldx - CH - gkc);
+#pragma unroll
+      for (int v = 0; v < V; ++v) {
+        xn[r][v] = *reinterpret_cast<const u4*>(p + 4 * v);
+        xn[r][V + v] = *reinterpret_cast<const u4*>(p + OX.plane + 4 * v);
+        xm[r][v] = *reinterpret_cast<const u4*>(pm + 4 * v);
+        xm[r][V + v] = *reinterpret_cast<const u4*>(pm + OX.plane + 4 * v);
+      }
+      if constexpr (KIND == KIND_F1) {
+#pragma unroll
+        for (int v = 0; v < V; ++v) {
+          w0[r][v] = *reinterpret_cast<const u4*>(tyl + gkc + 4 * v);
+          w1[r][v] = *reinterpret_cast<const u4*>(tyl + a.tilt_plane + gkc + 4 * v);
+        }
+      } else if constexpr (KIND == KIND_B3) {
+        // without seed weights (the seed pass) G is 1: the data rows stand in as a valid address
+        const bool hg = gwb != nullptr;
+        const float* g = hg ? gwb : Xb;
+        const u4 one = __builtin_bit_cast(u4, f4{1.f, 1.f, 1.f, 1.f});
+#pragma unroll
+        for (int v = 0; v < V; ++v) {
+          const u4 g0 = *reinterpret_cast<const u4*>(g + (long long)gj * ldx + gkc + 4 * v);
+          const u4 g1 = *reinterpret_cast<const u4*>(g + (long long)gj * ldx + (ldx - CH - gkc) + 4 * v);
+          w0[r][v] = hg ? g0 : one;
+          w1[r][v] = hg ? g1 : one;
+        }
+      }
+    }
+  };
+
+  // Staged tile -> LDS buffer `buf`. MASK: zero the K tail and the unpaired middle term (a tile
+  // that reaches k_hi or kmid); without it the tile must lie wholly inside both. The pipelined path
+  // leaves the DFT operand unconjugated and negates the accumulators that take its imaginary part.
+  auto store_tile = [&](el_t* buf, auto mask_tag) {
+    // the loader products are rounded before the pair sums (no FMA contraction), as a separately
+    // formed seed or the dense kernel's loader would round them, whatever the masking
+#pragma clang fp contract(off)
+    constexpr bool MASK = decltype(mask_tag)::value;
+    el_t* Ds = buf;
+    el_t* Xs = buf + D_EL;
     // DFT operand: as the dense kernel (K tail masked, conjugated for the adjoint)
 #pragma unroll
     for (int r = 0; r < D_U; ++r) {
-      const int q = tid + 256 * r;
-      if (q < UNITS_D) {
+      // the pipelined loader gives threads past the tile's units a copy of a unit (q mod units):
+      // they store the same words to the same place, so no thread branches off
+      const int q = PIPE ? (tid + 256 * r) % UNITS_D : tid + 256 * r;
+      if (PIPE || UNITS_D % 256 == 0 || q < UNITS_D) {
         const int row = q >> 2, kq = q & 3;
         if constexpr (PREC == 0) {
           f4 vr = __builtin_bit_cast(f4, gd[r][0]), vi = __builtin_bit_cast(f4, gd[r][1]);
           const int gk = gd_k[r];
-          if (gk + 4 > k_hi) {
+          if (MASK && gk + 4 > k_hi) {
 #pragma unroll
             for (int e = 0; e < 4; ++e)
               if (gk + e >= k_hi) {
@@ -761,13 +834,13 @@ __device__ __forceinline__ void fgemm_body(const GemmArgs& a, int lin, const flo
                 vi[e] = 0.f;
               }
           }
-          if (conj_d) vi = -vi;
+          if (!PIPE && conj_d) vi = -vi;
           *reinterpret_cast<f4*>(&Ds[row * LDK + 4 * (kq ^ lds_swz(row))]) = vr;
           *reinterpret_cast<f4*>(&Ds[(RD + row) * LDK + 4 * (kq ^ lds_swz(row))]) = vi;
         } else {
           u4* pl = gd[r];
           const int gk = gd_k[r];
-          if (gk + 8 > k_hi) {
+          if (MASK && gk + 8 > k_hi) {
 #pragma unroll
             for (int e = 0; e < 8; ++e)
               if (gk + e >= k_hi) {
@@ -789,8 +862,8 @@ __device__ __forceinline__ void fgemm_body(const GemmArgs& a, int lin, const flo
     // data operand: loader product at k and at the mirror, then sum and difference
 #pragma unroll
     for (int r = 0; r < X_U; ++r) {
-      const int q = tid + 256 * r;
-      if (q < UNITS_X) {
+      const int q = PIPE ? (tid + 256 * r) % UNITS_X : tid + 256 * r;
+      if (PIPE || UNITS_X % 256 == 0 || q < UNITS_X) {
         const int row = q >> 2, kq = q & 3;
         f4 er[V], ei[V], odr[V], odi[V];
 #pragma unroll
@@ -818,7 +891,7 @@ __device__ __forceinline__ void fgemm_body(const GemmArgs& a, int lin, const flo
           }
           // K tail and the unpaired middle term (assigned after the products: padding is not read)
           const int kb = gx_k[r] + 4 * v;
-          if (kb + 4 > k_hi || (kmid >= kb && kmid < kb + 4)) {
+          if (MASK && (kb + 4 > k_hi || (kmid >= kb && kmid < kb + 4))) {
 #pragma unroll
             for (int e = 0; e < 4; ++e) {
               if (kb + e >= k_hi) {
@@ -864,6 +937,40 @@ __device__ __forceinline__ void fgemm_body(const GemmArgs& a, int lin, const flo
     }
   };
 
+  // Instruction interleave of one pipelined k-stage (sched_group_barrier masks: 0x008 MFMA,
+  // 0x002 VALU, 0x100 LDS read, 0x200 LDS write, 0x020 global read): the fragment reads, a
+  // quarter of the MFMAs alone while they arrive, then each MFMA followed by a little of the
+  // store's VALU work and LDS writes, then by the next stage's global loads.
+  auto pipe_schedule = [&]() {
+    if constexpr (PIPE) {
+      constexpr int WD = DA ? WM : WN, WX = DA ? WN : WM;
+      constexpr int NMF = WM * WN * 16;
+      constexpr int NDSR = 2 * WD + 4 * WX;
+      constexpr int NDSW = 2 * D_U + 4 * X_U;
+      constexpr int NVM = 2 * D_U + (KIND == KIND_F2 ? 4 : 6) * X_U;
+      constexpr int Q1 = NMF / 4, Q2 = NMF / 2, Q3 = NMF - Q1 - Q2;
+      __builtin_amdgcn_sched_group_barrier(0x100, NDSR, 0);
+#pragma unroll
+      for (int i = 0; i < Q1; ++i) __builtin_amdgcn_sched_group_barrier(0x008, 1, 0);
+#pragma unroll
+      for (int i = 0; i < Q2; ++i) {
+        __builtin_amdgcn_sched_group_barrier(0x008, 1, 0);
+        __builtin_amdgcn_sched_group_barrier(0x002, 2, 0);
+        if (i % (Q2 / NDSW) == Q2 / NDSW - 1) __builtin_amdgcn_sched_group_barrier(0x200, 1, 0);
+      }
+#pragma unroll
+      for (int i = 0; i < Q3; ++i) {
+        __builtin_amdgcn_sched_group_barrier(0x008, 1, 0);
+        __builtin_amdgcn_sched_group_barrier(0x002, 1, 0);
+        if (i < NVM) __builtin_amdgcn_sched_group_barrier(0x020, 1, 0);
+      }
+    }
+  };
+
+  // pipelined stream state: the tile count, the PSF the loader points at, the full k-stages
+  int ts = 0, lpsf = p_begin;
+  const int k_full = a.kodd ? min(k_hi, K - 1) : k_hi;
+  const int nfull = max(0, (k_full - k_lo) / BK);   // k-stages [0, nfull) hold full tiles
   for (int it = p_begin; it < p_end; ++it) {
     const int lb = (it % nfs) * a.L + it / nfs;
     const int gb = a.psf0 + lb;
@@ -881,22 +988,10 @@ __device__ __forceinline__ void fgemm_body(const GemmArgs& a, int lin, const flo
         rr_[bm][bn] = f4{0.f, 0.f, 0.f, 0.f};
         ri_[bm][bn] = f4{0.f, 0.f, 0.f, 0.f};
       }
-    if (KIND != KIND_B4 || it == p_begin) {   // later B4 PSFs were fetched by the previous PSF
-      set_loader(it);
-      if (nk > 0) load_tile(k_lo);
-    }
-
-    for (int kt = 0; kt < nk; ++kt) {
-      __syncthreads();
-      store_tile();
-      __syncthreads();
-      if (kt + 1 < nk) {
-        load_tile(k_lo + (kt + 1) * BK);
-      } else if (KIND == KIND_B4 && it + 1 < p_end) {
-        set_loader(it + 1);
-        load_tile(k_lo);
-      }
-
+    // the matrix work of one k-stage, from the operands in LDS buffer `buf`
+    auto mma = [&](const el_t* buf) {
+      const el_t* Ds = buf;
+      const el_t* Xs = buf + D_EL;
       if constexpr (PREC == 0) {
         constexpr int WD = DA ? WM : WN, WX = DA ? WN : WM;
         const int bd = DA ? wr : wc, bx = DA ? wc : wr;
@@ -1002,6 +1097,113 @@ __device__ __forceinline__ void fgemm_body(const GemmArgs& a, int lin, const flo
             }
           }
         }
+      }
+    };
+
+    if constexpr (!PIPE) {
+      if (KIND != KIND_B4 || it == p_begin) {   // later B4 PSFs were fetched by the previous PSF
+        set_loader(it);
+        if (nk > 0) load_tile(k_lo);
+      }
+      for (int kt = 0; kt < nk; ++kt) {
+        __syncthreads();
+        store_tile(smem, std::true_type{});
+        __syncthreads();
+        if (kt + 1 < nk) {
+          load_tile(k_lo + (kt + 1) * BK);
+        } else if (KIND == KIND_B4 && it + 1 < p_end) {
+          set_loader(it + 1);
+          load_tile(k_lo);
+        }
+        mma(smem);
+      }
+    } else if constexpr (KIND != KIND_B4) {
+      // Two LDS buffers and one barrier per k-stage: the MFMAs of stage kt read buffer kt & 1 while
+      // the tile of stage kt + 1, staged in registers, is stored into the other buffer and the
+      // loads of stage kt + 2 go out. For full tiles the store is branch-free and the scheduler
+      // is told to spread it, and the loads, between the MFMAs, so the pair sums and the LDS and
+      // global traffic issue while the matrix pipe is busy. (One workgroup runs one PSF here.)
+      set_loader(it);
+      load_tile_c(k_lo);
+      if (nfull > 0)
+        store_tile(smem, std::false_type{});
+      else
+        store_tile(smem, std::true_type{});
+      load_tile_c(k_lo + BK);
+      __syncthreads();
+      int kt = 0;
+      for (; kt + 1 < nfull; ++kt) {   // the next tile is full: one basic block per stage
+        mma(smem + (kt & 1) * BUF_EL);
+        store_tile(smem + ((kt + 1) & 1) * BUF_EL, std::false_type{});
+        load_tile_c(k_lo + (kt + 2) * BK);
+        pipe_schedule();
+        __syncthreads();
+      }
+      for (; kt < nk; ++kt) {   // the last one or two stages
+        mma(smem + (kt & 1) * BUF_EL);
+        if (kt + 1 < nk) {
+          store_tile(smem + ((kt + 1) & 1) * BUF_EL, std::true_type{});
+          load_tile_c(k_lo + (kt + 2) * BK);
+        }
+        __syncthreads();
+      }
+    } else if (nk > 0) {
+      // B4: the same pipeline over a stream of tiles that runs through the workgroup's PSFs and
+      // their k-stages (tile ts in buffer ts & 1), so the first tiles of a PSF are stored and
+      // fetched during the previous PSF's last stages.
+      if (it == p_begin) {   // prologue: tile 0 to LDS, tile 1 to registers
+        set_loader(it);
+        lpsf = it;
+        load_tile_c(k_lo);
+        if (nfull > 0)
+          store_tile(smem, std::false_type{});
+        else
+          store_tile(smem, std::true_type{});
+        if (nk > 1) {
+          load_tile_c(k_lo + BK);
+        } else if (it + 1 < p_end) {
+          set_loader(it + 1);
+          lpsf = it + 1;
+          load_tile_c(k_lo);
+        }
+        __syncthreads();
+      }
+      const int nfast = min(nfull - 1, nk - 2);   // next tile full, the tile after in this PSF
+      int kt = 0;
+      for (; kt < nfast; ++kt, ++ts) {   // one basic block per stage
+        mma(smem + (ts & 1) * BUF_EL);
+        store_tile(smem + ((ts + 1) & 1) * BUF_EL, std::false_type{});
+        load_tile_c(k_lo + (kt + 2) * BK);
+        pipe_schedule();
+        __syncthreads();
+      }
+      for (; kt < nk; ++kt, ++ts) {   // the PSF's last stages, with masking and the PSF switch
+        mma(smem + (ts & 1) * BUF_EL);
+        if (kt + 1 < nk || it + 1 < p_end) store_tile(smem + ((ts + 1) & 1) * BUF_EL, std::true_type{});
+        int lk = kt + 2, lp = it;   // the tile two ahead in the stream
+        while (lk >= nk) {
+          lk -= nk;
+          ++lp;
+        }
+        if (lp < p_end) {
+          if (lp != lpsf) {
+            set_loader(lp);
+            lpsf = lp;
+          }
+          load_tile_c(k_lo + lk * BK);
+        }
+        __syncthreads();
+      }
+    }
+    if constexpr (PIPE) {
+      if (conj_d) {   // the adjoint's conj(M): its imaginary part feeds R only
+#pragma unroll
+        for (int bm = 0; bm < WM; ++bm)
+#pragma unroll
+          for (int bn = 0; bn < WN; ++bn) {
+            rr_[bm][bn] = -rr_[bm][bn];
+            ri_[bm][bn] = -ri_[bm][bn];
+          }
       }
     }
 
