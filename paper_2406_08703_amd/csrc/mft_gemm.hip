@@ -947,8 +947,10 @@ __device__ __forceinline__ void fgemm_body(const GemmArgs& a, int lin, const flo
       constexpr int NMF = WM * WN * 16;
       constexpr int NDSR = 2 * WD + 4 * WX;
       constexpr int NDSW = 2 * D_U + 4 * X_U;
-      constexpr int NVM = 2 * D_U + (KIND == KIND_F2 ? 4 : 6) * X_U;
+      constexpr int NVM = 2 * D_U + (KIND == KIND_F1 || KIND == KIND_B3 ? 6 : 4) * X_U;
       constexpr int Q1 = NMF / 4, Q2 = NMF / 2, Q3 = NMF - Q1 - Q2;
+      constexpr int DSW_EVERY = Q2 / NDSW;   // MFMAs per LDS write in the middle half
+      static_assert(DSW_EVERY >= 1, "every LDS write needs a slot in the middle half");
       __builtin_amdgcn_sched_group_barrier(0x100, NDSR, 0);
 #pragma unroll
       for (int i = 0; i < Q1; ++i) __builtin_amdgcn_sched_group_barrier(0x008, 1, 0);
@@ -956,7 +958,7 @@ __device__ __forceinline__ void fgemm_body(const GemmArgs& a, int lin, const flo
       for (int i = 0; i < Q2; ++i) {
         __builtin_amdgcn_sched_group_barrier(0x008, 1, 0);
         __builtin_amdgcn_sched_group_barrier(0x002, 2, 0);
-        if (i % (Q2 / NDSW) == Q2 / NDSW - 1) __builtin_amdgcn_sched_group_barrier(0x200, 1, 0);
+        if (i % DSW_EVERY == DSW_EVERY - 1) __builtin_amdgcn_sched_group_barrier(0x200, 1, 0);
       }
 #pragma unroll
       for (int i = 0; i < Q3; ++i) {
