@@ -37,6 +37,11 @@ CASES = {
     "q1-vec": ("c2", dict(n_pupil=32, n_focal=40, oversample=1, n_wavelengths=3, noll=tuple(range(2, 9)))),
     # a 70 x 70 bicubic map: more map columns than the map-gradient kernels take in one pass (64)
     "c5-map70": ("c5", dict(n_pupil=72, n_focal=48, n_wavelengths=1, n_frames=1, noll=tuple(range(2, 8)), n_map=70)),
+    # short contractions with many PSFs: every folded depth below one 16-deep k-stage (pupil 24,
+    # focal 27), and one full stage plus a partial one holding the unpaired middle term (pupil 40,
+    # focal 39); 3 frames x 2 stars x 3 wavelengths
+    "k1-groups": ("c3", dict(n_pupil=24, n_focal=27, n_wavelengths=3, n_frames=3, noll=tuple(range(2, 12)))),
+    "k2-odd-groups": ("c3", dict(n_pupil=40, n_focal=39, n_wavelengths=3, n_frames=3, noll=tuple(range(2, 12)))),
 }
 
 
@@ -488,3 +493,43 @@ def test_dense_and_folded_mft_agree_with_the_oracle(case, prec):
         outs[dense] = got
     assert rel_l2(outs[False]["model"], outs[True]["model"]) < tol
     assert rel_l2(outs[False]["grad_coeffs"], outs[True]["grad_coeffs"]) < 10 * tol
+
+
+# Tiles, B4's K split and its PSFs per group forced through the tune cache (whatever the tuner would
+# pick): a 4-way split leaves splits with no k-stage at these depths, and one B4 group holding every
+# PSF makes each B4 workgroup run its tile stream through all of them, the next PSF's first tiles
+# stored and fetched during the last stages of the one before (one stage per PSF at k1-groups).
+FORCED = [  # F1, F2, B3, B4 tiles (32 WM x 32 WN), B4 K split
+    ((1, 1), (1, 1), (1, 1), (1, 1), 4),
+    ((2, 2), (2, 2), (2, 2), (2, 2), 2),
+    ((2, 1), (1, 2), (2, 1), (2, 1), 1),
+]
+
+
+@pytest.mark.parametrize("prec", ["fp32", "bf16x3"])
+@pytest.mark.parametrize("case", ["k1-groups", "k2-odd-groups"])
+def test_forced_tiles_splits_and_groups_match_oracle(case, prec, tmp_path, monkeypatch):
+    from tests.gpu_helpers import make_plan, run_eval
+    print(f"forced tiles {case} {prec}", flush=True)
+    w, _ = workload(case)
+    path = tmp_path / "tune.txt"
+    monkeypatch.setenv("DLX_TUNE_CACHE", str(path))
+    make_plan(w, prec).close()   # tunes and writes the shape's line
+    key = path.read_text().splitlines()[0].split(" : ")[0]
+    P = w.problem
+    n_psf = P.n_frames * P.n_sources * len(P.wavelengths)
+    want = oracle_eval(case, "eval", "poisson")
+    kw = dict(q=P.oversample) if prec == "fp32" else dict(
+        tol_grad=TOL_BF16X3, tol_resid=TOL_BF16X3, tol_img=TOL_BF16X3, sources=w.eval_params()["sources"],
+        q=P.oversample, prec="bf16x3")
+    for f1, f2, b3, b4, ks in FORCED:
+        vals = [*f1, *f2, *b3, *b4, ks, n_psf]
+        path.write_text(f"{key} : {' '.join(map(str, vals))}\n")
+        plan = make_plan(w, prec)
+        assert plan.tiles == {"F1": (32 * f1[0], 32 * f1[1]), "F2": (32 * f2[0], 32 * f2[1]),
+                              "B3": (32 * b3[0], 32 * b3[1]), "B4": (32 * b4[0], 32 * b4[1])}
+        got = run_eval(w, plan=plan)
+        plan.close()
+        assert got["status"] == 0
+        print(f"  tiles {vals}", flush=True)
+        compare(got, want, **kw)
