@@ -656,8 +656,9 @@ __device__ __forceinline__ void fgemm_body(const GemmArgs& a, int lin, const flo
   const int nfs = a.n_chunk_psf / a.L;
   const int ldx = OX.ld;
   // The PSF whose tiles the loader fetches: its operand bases, its row tilt (F1) and, for B3, the
-  // seed weights and w phi. B4 workgroups run several PSFs; there the last k-stage of one PSF
-  // already fetches the first tile of the next, so a new PSF does not start on an empty pipeline.
+  // seed weights and w phi. B4 workgroups run several PSFs; there the last k-stages of one PSF
+  // already store and fetch the first tiles of the next, so a new PSF does not start on an empty
+  // pipeline.
   const el_t* Db = nullptr;
   const float* Xb = nullptr;
   const float* tyl = nullptr;
@@ -937,12 +938,16 @@ __device__ __forceinline__ void fgemm_body(const GemmArgs& a, int lin, const flo
     }
   };
 
-  // Instruction interleave of one pipelined k-stage (sched_group_barrier masks: 0x008 MFMA,
-  // 0x002 VALU, 0x100 LDS read, 0x200 LDS write, 0x020 global read): the fragment reads, a
+  // Instruction interleave of one pipelined k-stage. F1 and B3 (sched_group_barrier masks: 0x008
+  // MFMA, 0x002 VALU, 0x100 LDS read, 0x200 LDS write, 0x020 global read): the fragment reads, a
   // quarter of the MFMAs alone while they arrive, then each MFMA followed by a little of the
-  // store's VALU work and LDS writes, then by the next stage's global loads.
+  // store's VALU work and LDS writes, then by the next stage's global loads. F2 and B4 take the
+  // compiler's own interleave for small GEMMs (iglp_opt 1), which measured faster for them; for
+  // B4 the groups above are not honoured by the scheduler at all.
   auto pipe_schedule = [&]() {
-    if constexpr (PIPE) {
+    if constexpr (PIPE && (KIND == KIND_F2 || KIND == KIND_B4)) {
+      __builtin_amdgcn_iglp_opt(1);
+    } else if constexpr (PIPE) {
       constexpr int WD = DA ? WM : WN, WX = DA ? WN : WM;
       constexpr int NMF = WM * WN * 16;
       constexpr int NDSR = 2 * WD + 4 * WX;
