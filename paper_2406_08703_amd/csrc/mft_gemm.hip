@@ -953,7 +953,10 @@ __device__ __forceinline__ void fgemm_body(const GemmArgs& a, int lin, const flo
       constexpr int NDSR = 2 * WD + 4 * WX;
       constexpr int NDSW = 2 * D_U + 4 * X_U;
       constexpr int NVM = 2 * D_U + (KIND == KIND_F1 || KIND == KIND_B3 ? 6 : 4) * X_U;
-      constexpr int Q1 = NMF / 4, Q2 = NMF / 2, Q3 = NMF - Q1 - Q2;
+      // B3 (the loader with the most VALU work) starts its store after two MFMAs
+      constexpr int Q1 = KIND == KIND_B3 ? 2 : NMF / 4;
+      constexpr int Q2 = KIND == KIND_B3 ? NMF * 3 / 4 - 2 : NMF / 2;
+      constexpr int Q3 = NMF - Q1 - Q2;
       constexpr int DSW_EVERY = Q2 / NDSW;   // MFMAs per LDS write in the middle half
       static_assert(DSW_EVERY >= 1, "every LDS write needs a slot in the middle half");
       __builtin_amdgcn_sched_group_barrier(0x100, NDSR, 0);
